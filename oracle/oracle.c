@@ -1,0 +1,1320 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU reference of the analytic phase-space-ring
+ * (PSR) source model dose path of Tian et al., "An analytic linear accelerator
+ * source model for Monte Carlo dose calculations. II" (arXiv:1503.01725).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header, table
+ * or constant generator with the GPU engine; both sides receive the same
+ * seeded inputs and each implements the counter-based Philox4x32-10 generator
+ * from its published definition (Salmon et al., SC'11).
+ *
+ * Everything is written in the order the paper (or, where the paper is silent,
+ * the documented reading) states it, with no blocking or fusion:
+ *   - PSR -> PSL conversion ............ Sec. 2.1.1, Eqs. (1)-(2), steps 1-4
+ *   - sampling areas ................... Sec. 2.1.2, Fig. 3, step S1
+ *   - particles per PSL ................ step S2, Eq. (3)
+ *   - history order .................... Sec. 2.1.3 (locations inner, energy outer)
+ *   - primary / scatter / electron ..... steps S3-S5, Eqs. (4)-(7)
+ *   - jaw rejection .................... Sec. 2.1.2 (upper jaw surfaces)
+ *   - transport physics ................ paper silent (Sec. 2.3 only names the
+ *                                        cut-offs); Klein-Nishina Compton with
+ *                                        Woodcock tracking, Bethe CSDA electrons
+ *                                        with Highland Gaussian multiple scattering
+ *   - PSR-indexed tally ................ Sec. 2.2.2 (index map + 2D array)
+ *   - commissioning .................... Sec. 2.2.3 Eq. (8), Sec. 2.2.4
+ *
+ * Parity pins live in tests/test_oracle_*.py.  Functions without an external
+ * pin say so in their comment ("parity unpinned").
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+#define OR_INF (1.0 / 0.0)
+
+/* Physical constants (CODATA 2018). */
+#define OR_ME 0.51099895000            /* electron rest energy, MeV */
+#define OR_RE 2.8179403262e-13         /* classical electron radius, cm */
+#define OR_NA 6.02214076e23            /* Avogadro, 1/mol */
+#define OR_ZA_WATER (10.0 / 18.0153)   /* Z/A of water, mol/g */
+#define OR_I_WATER 75.0e-6             /* mean excitation energy of water, MeV */
+#define OR_X0_WATER 36.08              /* radiation length of water, g/cm^2 */
+#define OR_MEV_PER_G_TO_GY 1.602176634e-10
+
+enum { OR_TAG_SRC = 1, OR_TAG_TR = 2 };
+enum { OR_ST_OK = 0, OR_ST_JAW = 1, OR_ST_MISSED = 2, OR_ST_INVALID = 3 };
+enum { OR_SUB_PRIMARY = 0, OR_SUB_SCATTER = 1, OR_SUB_ELECTRON = 2 };
+
+/* ledger[] slots */
+enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, L_N };
+/* counters[] slots */
+enum { C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS,
+       C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_N = 16 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
+/* easy as 1, 2, 3", SC'11): 10 rounds of the 4x32 Philox S-box with the     */
+/* Weyl key schedule.                                                         */
+/* ------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A stream of uniforms for one particle: key = seed, counter =
+ * (block, tag<<16 | sub, g_lo, g_hi).  Uniforms are consumed in order, four
+ * per Philox block; u = (x >> 8) * 2^-24, so u is in [0, 1) and exact in FP32. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t ctr[4];
+    uint32_t buf[4];
+    int left;
+} or_stream;
+
+static void stream_init(or_stream* s, uint64_t seed, uint64_t g, uint32_t tag, uint32_t sub)
+{
+    s->key[0] = (uint32_t)seed;
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->ctr[0] = 0;
+    s->ctr[1] = (tag << 16) | (sub & 0xFFFFu);
+    s->ctr[2] = (uint32_t)g;
+    s->ctr[3] = (uint32_t)(g >> 32);
+    s->left = 0;
+}
+
+static double stream_u01(or_stream* s)
+{
+    if (s->left == 0) {
+        or_philox4x32_10(s->ctr, s->key, s->buf);
+        s->ctr[0] += 1;
+        s->left = 4;
+    }
+    uint32_t x = s->buf[4 - s->left];
+    s->left -= 1;
+    return (double)(x >> 8) * (1.0 / 16777216.0);
+}
+
+/* test hook: n consecutive uniforms of stream (seed, g, tag, sub) */
+void or_stream_uniforms(uint64_t seed, uint64_t g, uint32_t tag, uint32_t sub, int n, double* out)
+{
+    or_stream s;
+    stream_init(&s, seed, g, tag, sub);
+    for (int i = 0; i < n; ++i) out[i] = stream_u01(&s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inputs                                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_ebin, n_ring, n_comp, n_psl;
+    double e_lo, e_width, ring_dr, psl_x0, psl_dx;
+    double z_target, z_plane, z_scatter, z_jaw_y, z_jaw_x;
+    double sigma_spot, sig_ea, sig_eb;
+    const double* w_psr;   /* [3][n_ebin][n_ring] */
+    const double* sc_c;    /* [n_ebin][n_ring][K] */
+    const double* sc_mu;
+    const double* sc_sa;
+    const double* sc_sb;
+} or_model;
+
+typedef struct {
+    double x1, x2, y1, y2;   /* jaw edges projected to the isocentre plane */
+    double gantry_deg, couch_deg;
+    double iso[3];
+} or_beam;
+
+typedef struct {
+    int32_t nx, ny, nz, pad;
+    double vox[3];
+    double origin[3];
+    const float* density;    /* [nz][ny][nx] */
+} or_phantom;
+
+typedef struct {
+    double e_cut_e, e_cut_g, step_frac;
+    int32_t ms_enable, pad;
+} or_params;
+
+typedef struct {
+    int64_t n_list;
+    const int32_t* beam;
+    const int32_t* stype;
+    const int32_t* ebin;
+    const int32_t* ix;
+    const int32_t* iy;
+    const int32_t* tag;      /* tally column (basis) carried by the particle */
+    const uint64_t* cum;     /* inclusive prefix of per-PSL counts */
+    uint64_t n_hist;         /* N = cum[n_list-1] */
+} or_plan;
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.1.1: PSR -> PSL conversion.                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Step 2 of Sec. 2.1.1: ring weight at radius r by linear interpolation between
+ * ring centres; inside the first centre the first ring's weight, between the
+ * last centre and the model's outer radius the last ring's weight, 0 beyond. */
+static double ring_weight_at(const double* w_ring, int n_ring, double dr, double r)
+{
+    double r_outer = (double)n_ring * dr;
+    if (r > r_outer) return 0.0;
+    double t = r / dr - 0.5;
+    if (t <= 0.0) return w_ring[0];
+    if (t >= (double)(n_ring - 1)) return w_ring[n_ring - 1];
+    int j = (int)floor(t);
+    double f = t - (double)j;
+    return (1.0 - f) * w_ring[j] + f * w_ring[j + 1];
+}
+
+/* Eq. (2) in discrete form (Sec. 2.1.1 steps 1-4): PSL weight = interpolated
+ * ring weight / (2 pi r) at the PSL centre, normalised so that the sum over all
+ * sub-sources, energies and locations is 1.  The normalising sum runs in the
+ * order (s, b, iy, ix).  Output w_psl[3][n_ebin][n_psl][n_psl]; returns the sum. */
+double or_psl_build(const or_model* m, double* w_psl)
+{
+    const int n = m->n_psl;
+    for (int s = 0; s < 3; ++s)
+        for (int b = 0; b < m->n_ebin; ++b) {
+            const double* wr = m->w_psr + ((size_t)s * m->n_ebin + b) * m->n_ring;
+            for (int iy = 0; iy < n; ++iy)
+                for (int ix = 0; ix < n; ++ix) {
+                    double xc = m->psl_x0 + ((double)ix + 0.5) * m->psl_dx;
+                    double yc = m->psl_x0 + ((double)iy + 0.5) * m->psl_dx;
+                    double r = sqrt(xc * xc + yc * yc);
+                    double w = ring_weight_at(wr, m->n_ring, m->ring_dr, r);
+                    w_psl[(((size_t)s * m->n_ebin + b) * n + iy) * n + ix] = w / ((2.0 * OR_PI) * r);
+                }
+        }
+    size_t total = (size_t)3 * m->n_ebin * n * n;
+    double sum = 0.0;
+    for (size_t i = 0; i < total; ++i) sum += w_psl[i];
+    for (size_t i = 0; i < total; ++i) w_psl[i] = w_psl[i] / sum;
+    return sum;
+}
+
+/* Step S4: cumulative component table P_{i,k} = sum_{j<=k} c_{i,j} / sum_j c_{i,j}
+ * for k = 0..K-2 (the last entry is 1 by definition).  Output [n_ebin][n_ring][K]. */
+void or_scatter_cdf(const or_model* m, double* P)
+{
+    const int K = m->n_comp;
+    for (int i = 0; i < m->n_ebin * m->n_ring; ++i) {
+        const double* c = m->sc_c + (size_t)i * K;
+        double tot = 0.0;
+        for (int k = 0; k < K; ++k) tot += c[k];
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            acc += c[k];
+            P[(size_t)i * K + k] = (k == K - 1) ? 1.0 : acc / tot;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.1.2 / Fig. 3 / step S1: sampling areas.                             */
+/* ------------------------------------------------------------------------ */
+#define OR_AREA_NSIGMA 4.0
+
+/* Largest angular width of a sub-source's direction model (rad). */
+static double sub_source_sigma_max(const or_model* m, int stype)
+{
+    if (stype == OR_SUB_ELECTRON) return fmax(m->sig_ea, m->sig_eb);
+    double smax = 0.0;
+    size_t n = (size_t)m->n_ebin * m->n_ring * m->n_comp;
+    for (size_t i = 0; i < n; ++i) {
+        smax = fmax(smax, m->sc_sa[i]);
+        smax = fmax(smax, m->sc_sb[i]);
+    }
+    return smax;
+}
+
+/* One axis of the sampling strip at the plane for jaw edges e1 < e2 given at
+ * the isocentre plane, jaw upper surface at height zj. */
+static void sampling_strip(const or_model* m, int stype, double e1, double e2, double zj,
+                           double* lo, double* hi)
+{
+    const double zt = m->z_target, zp = m->z_plane;
+    /* jaw edges at the height of the upper surface (faces focus on the target) */
+    double j1 = e1 * (zj - zt) / (zp - zt);
+    double j2 = e2 * (zj - zt) / (zp - zt);
+    if (stype == OR_SUB_PRIMARY) {
+        /* jaw opening seen from the focal spot, widened by the shadow of an
+         * n-sigma focal spot through the jaw edge */
+        double margin = OR_AREA_NSIGMA * m->sigma_spot * (zp - zj) / (zj - zt);
+        *lo = e1 - margin;
+        *hi = e2 + margin;
+        return;
+    }
+    /* The mean ray of a plane point comes from a source point on the axis at
+     * height zs (scatter source; electrons: zs -> -inf, vertical mean ray).
+     * The ray through the jaw edge lands at c = j (zp - zs)/(zj - zs); a
+     * deviation d from the mean direction moves the crossing point at the jaw
+     * by (zp - zj) tan(d), i.e. the plane point by that times (zp - zs)/(zj - zs). */
+    double c1, c2, magnify;
+    if (stype == OR_SUB_SCATTER) {
+        double zs = m->z_scatter;
+        magnify = (zp - zs) / (zj - zs);
+    } else {
+        magnify = 1.0;
+    }
+    c1 = j1 * magnify;
+    c2 = j2 * magnify;
+    double margin = (zp - zj) * tan(OR_AREA_NSIGMA * sub_source_sigma_max(m, stype)) * magnify;
+    *lo = c1 - margin;
+    *hi = c2 + margin;
+}
+
+/* PSL index box [ix0, ix1] x [iy0, iy1] (inclusive) of the PSLs whose squares
+ * overlap the sampling rectangle with positive area; the rectangle is the
+ * intersection of the x strip (X jaws) and the y strip (Y jaws). */
+void or_sampling_box(const or_model* m, const or_beam* bm, int stype, int32_t box[4])
+{
+    double xlo, xhi, ylo, yhi;
+    sampling_strip(m, stype, bm->x1, bm->x2, m->z_jaw_x, &xlo, &xhi);
+    sampling_strip(m, stype, bm->y1, bm->y2, m->z_jaw_y, &ylo, &yhi);
+    const double x0 = m->psl_x0, dx = m->psl_dx;
+    int ix0 = (int)floor((xlo - x0) / dx), ix1 = (int)ceil((xhi - x0) / dx) - 1;
+    int iy0 = (int)floor((ylo - x0) / dx), iy1 = (int)ceil((yhi - x0) / dx) - 1;
+    if (ix0 < 0) ix0 = 0;
+    if (iy0 < 0) iy0 = 0;
+    if (ix1 > m->n_psl - 1) ix1 = m->n_psl - 1;
+    if (iy1 > m->n_psl - 1) iy1 = m->n_psl - 1;
+    box[0] = ix0; box[1] = ix1; box[2] = iy0; box[3] = iy1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step S2 / Eq. (3): particles per PSL, and the history order of Sec. 2.1.3. */
+/* ------------------------------------------------------------------------ */
+static int psl_ring_of_centre(const or_model* m, int ix, int iy)
+{
+    double xc = m->psl_x0 + ((double)ix + 0.5) * m->psl_dx;
+    double yc = m->psl_x0 + ((double)iy + 0.5) * m->psl_dx;
+    int ring = (int)floor(sqrt(xc * xc + yc * yc) / m->ring_dr);
+    return ring < m->n_ring - 1 ? ring : m->n_ring - 1;
+}
+
+/* Systematic rounding of N * q_i / sum(q) inside one group of list entries
+ * [a, b): n_i = round(N*Q_i/S) - round(N*Q_{i-1}/S), Q the running prefix of q.
+ * The totals add to N exactly and each n_i is the floor or ceiling of its
+ * fractional share.  128-bit integer arithmetic. */
+static void systematic_counts(const uint64_t* q, int64_t a, int64_t b, uint64_t n_group,
+                              uint64_t* n_out)
+{
+    unsigned __int128 S = 0;
+    for (int64_t i = a; i < b; ++i) S += q[i];
+    if (S == 0) {
+        for (int64_t i = a; i < b; ++i) n_out[i] = 0;
+        return;
+    }
+    unsigned __int128 acc = 0, prev = 0;
+    for (int64_t i = a; i < b; ++i) {
+        acc += q[i];
+        unsigned __int128 cum = ((unsigned __int128)n_group * acc + S / 2) / S;
+        n_out[i] = (uint64_t)(cum - prev);
+        prev = cum;
+    }
+}
+
+/* Builds the list of in-area PSLs and their particle counts.
+ *
+ * Order (Sec. 2.1.3; S1 repeats S2-S5 per beam, S3->S5 are the sub-sources):
+ * beam, sub-source, energy bin, iy, ix -- location is the inner loop, energy
+ * the outer one.  With hist_per_basis > 0 (commissioning, Sec. 2.2.2) each
+ * (beam, basis) group receives hist_per_basis histories spread over its own
+ * PSLs and the order is beam, basis, sub-source, energy, iy, ix.  Otherwise
+ * Eq. (3) allocates n_hist over the whole list (the denominator sums the
+ * sampling areas of all beams).
+ *
+ * The tally tag of an entry is beam * n_basis + basis when a basis map is given,
+ * else 0.  Weights are quantised to q = llround(w * 2^40) before rounding.
+ *
+ * Outputs (caller-allocated, max_list entries): beam, stype, ebin, ix, iy, tag,
+ * w (FP64 weight), cum (inclusive prefix of counts); group_w / group_n are the
+ * per-(beam, basis) weight sum and history count (index beam * n_basis + basis,
+ * or [0] for the whole list).  Returns the list length or -1 if max_list is too
+ * small. */
+int64_t or_plan_build(const or_model* m, const double* w_psl, const or_beam* beams, int n_beams,
+                      uint64_t n_hist, const uint16_t* basis_map, int32_t n_basis,
+                      uint64_t hist_per_basis, int64_t max_list,
+                      int32_t* beam_o, int32_t* stype_o, int32_t* ebin_o, int32_t* ix_o,
+                      int32_t* iy_o, int32_t* tag_o, double* w_o, uint64_t* cum_o,
+                      double* group_w, uint64_t* group_n)
+{
+    const int n = m->n_psl;
+    int64_t len = 0;
+    int stratified = (hist_per_basis > 0 && basis_map != NULL);
+    int nb = basis_map ? n_basis : 1;
+    int* ring_of = (int*)malloc(sizeof(int) * (size_t)n * n);
+    for (int iy = 0; iy < n; ++iy)
+        for (int ix = 0; ix < n; ++ix) ring_of[iy * n + ix] = psl_ring_of_centre(m, ix, iy);
+    for (int beam = 0; beam < n_beams; ++beam) {
+        int32_t boxes[3][4];
+        for (int s = 0; s < 3; ++s) or_sampling_box(m, &beams[beam], s, boxes[s]);
+        int k_lo = 0, k_hi = stratified ? nb : 1;
+        for (int k = k_lo; k < k_hi; ++k)
+            for (int s = 0; s < 3; ++s)
+                for (int b = 0; b < m->n_ebin; ++b)
+                    for (int iy = boxes[s][2]; iy <= boxes[s][3]; ++iy)
+                        for (int ix = boxes[s][0]; ix <= boxes[s][1]; ++ix) {
+                            double w = w_psl[(((size_t)s * m->n_ebin + b) * n + iy) * n + ix];
+                            if (!(w > 0.0)) continue;
+                            int basis = 0;
+                            if (basis_map) {
+                                int ring = ring_of[iy * n + ix];
+                                basis = basis_map[((size_t)s * m->n_ebin + b) * m->n_ring + ring];
+                                if (stratified && basis != k) continue;
+                            }
+                            if (len >= max_list) { free(ring_of); return -1; }
+                            beam_o[len] = beam; stype_o[len] = s; ebin_o[len] = b;
+                            ix_o[len] = ix; iy_o[len] = iy;
+                            tag_o[len] = basis_map ? beam * nb + basis : 0;
+                            w_o[len] = w;
+                            len++;
+                        }
+    }
+    free(ring_of);
+    uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1));
+    uint64_t* cnt = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(len > 0 ? len : 1));
+    for (int64_t i = 0; i < len; ++i) q[i] = (uint64_t)llround(w_o[i] * 1099511627776.0);
+    if (stratified) {
+        for (int g = 0; g < n_beams * nb; ++g) { group_w[g] = 0.0; group_n[g] = 0; }
+        int64_t a = 0;
+        while (a < len) {
+            int64_t b = a;
+            while (b < len && tag_o[b] == tag_o[a]) ++b;
+            systematic_counts(q, a, b, hist_per_basis, cnt);
+            double wsum = 0.0;
+            for (int64_t i = a; i < b; ++i) wsum += w_o[i];
+            group_w[tag_o[a]] = wsum;
+            group_n[tag_o[a]] = hist_per_basis;
+            a = b;
+        }
+    } else {
+        systematic_counts(q, 0, len, n_hist, cnt);
+        double wsum = 0.0;
+        for (int64_t i = 0; i < len; ++i) wsum += w_o[i];
+        group_w[0] = wsum;
+        group_n[0] = n_hist;
+    }
+    uint64_t acc = 0;
+    for (int64_t i = 0; i < len; ++i) { acc += cnt[i]; cum_o[i] = acc; }
+    free(q);
+    free(cnt);
+    return len;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry helpers                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Beam frame -> patient frame rotation R = Rz(couch) * Ry(gantry). */
+static void beam_rotation(const or_beam* bm, double R[9])
+{
+    double g = bm->gantry_deg * OR_PI / 180.0, c = bm->couch_deg * OR_PI / 180.0;
+    double cg = cos(g), sg = sin(g), cc = cos(c), sc = sin(c);
+    /* Ry(g) = [[cg,0,sg],[0,1,0],[-sg,0,cg]];  Rz(c) = [[cc,-sc,0],[sc,cc,0],[0,0,1]] */
+    double Ry[9] = {cg, 0.0, sg, 0.0, 1.0, 0.0, -sg, 0.0, cg};
+    double Rz[9] = {cc, -sc, 0.0, sc, cc, 0.0, 0.0, 0.0, 1.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a = 0.0;
+            for (int k = 0; k < 3; ++k) a += Rz[i * 3 + k] * Ry[k * 3 + j];
+            R[i * 3 + j] = a;
+        }
+}
+
+/* Entry of the infinite line p + t d into the phantom box (slab method).
+ * *t_entry / *t_exit receive the parameters where the line enters and leaves;
+ * returns 1 if t_exit > t_entry (the line crosses the box), else 0. */
+static int ray_box_entry(const or_phantom* ph, const double p[3], const double d[3],
+                         double* t_entry, double* t_exit)
+{
+    double tmin = -OR_INF, tmax = OR_INF;
+    const int n[3] = {ph->nx, ph->ny, ph->nz};
+    for (int a = 0; a < 3; ++a) {
+        double lo = ph->origin[a], hi = ph->origin[a] + (double)n[a] * ph->vox[a];
+        if (d[a] != 0.0) {
+            double t1 = (lo - p[a]) / d[a], t2 = (hi - p[a]) / d[a];
+            double tn = fmin(t1, t2), tf = fmax(t1, t2);
+            if (tn > tmin) tmin = tn;
+            if (tf < tmax) tmax = tf;
+        } else if (p[a] < lo || p[a] > hi) {
+            tmax = -OR_INF;
+        }
+    }
+    *t_entry = tmin;
+    *t_exit = tmax;
+    return tmax > tmin;
+}
+
+/* Voxel index of a point, or -1 outside the phantom. */
+static int64_t voxel_of(const or_phantom* ph, const double p[3], int idx[3])
+{
+    const int n[3] = {ph->nx, ph->ny, ph->nz};
+    for (int a = 0; a < 3; ++a) {
+        double f = floor((p[a] - ph->origin[a]) / ph->vox[a]);
+        if (!(f >= 0.0 && f < (double)n[a])) return -1;
+        idx[a] = (int)f;
+    }
+    return ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
+}
+
+/* Voxel index of a point on or inside the box, clamped onto the grid. */
+static void voxel_clamped(const or_phantom* ph, const double p[3], int idx[3])
+{
+    const int n[3] = {ph->nx, ph->ny, ph->nz};
+    for (int a = 0; a < 3; ++a) {
+        double f = floor((p[a] - ph->origin[a]) / ph->vox[a]);
+        if (f < 0.0) f = 0.0;
+        if (f > (double)(n[a] - 1)) f = (double)(n[a] - 1);
+        idx[a] = (int)f;
+    }
+}
+
+/* Turns direction d by polar angle theta (given by cos) and azimuth phi. */
+static void rotate_direction(double d[3], double cos_t, double phi)
+{
+    double sin_t = sqrt(fmax(0.0, 1.0 - cos_t * cos_t));
+    double cp = cos(phi), sp = sin(phi);
+    double u = d[0], v = d[1], w = d[2];
+    double nu, nv, nw;
+    if (fabs(w) < 0.99999) {
+        double t = sqrt(1.0 - w * w);
+        nu = u * cos_t + sin_t * (u * w * cp - v * sp) / t;
+        nv = v * cos_t + sin_t * (v * w * cp + u * sp) / t;
+        nw = w * cos_t - sin_t * cp * t;
+    } else {
+        nu = sin_t * cp;
+        nv = sin_t * sp;
+        nw = (w > 0.0 ? 1.0 : -1.0) * cos_t;
+    }
+    double norm = sqrt(nu * nu + nv * nv + nw * nw);
+    d[0] = nu / norm; d[1] = nv / norm; d[2] = nw / norm;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Steps S3-S5: sampling one history.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t j, k, status, stype, beam, ebin, ix, iy, tag, pad;
+    double xb, yb;            /* position on the plane, beam frame */
+    double ub, vb, wb;        /* direction, beam frame (after the rotation by theta) */
+    double e;
+    double xs, ys;            /* focal-spot point (primary) */
+    double alpha, beta;       /* local direction angles (scatter, electron) */
+    double jaw_margin;        /* distance of the back-traced point to the nearest jaw edge */
+    double box_margin;        /* chord length of the line through the phantom box */
+    double x, y, z, u, v, w;  /* patient frame, at the phantom entry */
+} or_sample_rec;
+
+/* First index j with cum[j] > h (upper bound). */
+static int64_t upper_bound_u64(const uint64_t* cum, int64_t n, uint64_t h)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (cum[mid] > h) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+typedef struct {
+    const or_model* m;
+    const double* cdf;      /* [n_ebin][n_ring][K] */
+    const or_plan* plan;
+    const or_beam* beams;
+    double (*R)[9];         /* per-beam rotations */
+    const or_phantom* ph;
+} or_sampler;
+
+static void sample_history(const or_sampler* S, uint64_t seed, uint64_t g, or_sample_rec* rec)
+{
+    const or_model* m = S->m;
+    const or_plan* P = S->plan;
+    uint64_t h = g % P->n_hist;
+    int64_t j = upper_bound_u64(P->cum, P->n_list, h);
+    memset(rec, 0, sizeof(*rec));
+    rec->j = (int32_t)j;
+    rec->k = -1;
+    rec->stype = P->stype[j];
+    rec->beam = P->beam[j];
+    rec->ebin = P->ebin[j];
+    rec->ix = P->ix[j];
+    rec->iy = P->iy[j];
+    rec->tag = P->tag[j];
+    const or_beam* bm = &S->beams[rec->beam];
+
+    or_stream st;
+    stream_init(&st, seed, g, OR_TAG_SRC, 0);
+    double u0 = stream_u01(&st), u1 = stream_u01(&st), u2 = stream_u01(&st), u3 = stream_u01(&st);
+    double u4 = stream_u01(&st), u5 = stream_u01(&st);
+
+    /* uniform position inside the PSL and uniform energy inside the bin */
+    double x = (m->psl_x0 + (double)rec->ix * m->psl_dx) + m->psl_dx * u0;
+    double y = (m->psl_x0 + (double)rec->iy * m->psl_dx) + m->psl_dx * u1;
+    double e = (m->e_lo + (double)rec->ebin * m->e_width) + m->e_width * u2;
+    double r = sqrt(x * x + y * y);
+    double ct = 1.0, stt = 0.0;
+    if (r > 0.0) { ct = x / r; stt = y / r; }
+
+    /* Box-Muller pair */
+    double rad = sqrt(-2.0 * log(1.0 - u4));
+    double g1 = rad * cos(2.0 * OR_PI * u5), g2 = rad * sin(2.0 * OR_PI * u5);
+
+    double ul, vl, wl;
+    int invalid = 0;
+    if (rec->stype == OR_SUB_PRIMARY) {
+        /* Eq. (4): focal-spot point from a 2D Gaussian; Eq. (5): direction */
+        double zph = m->z_plane - m->z_target;
+        double xs = m->sigma_spot * g1, ys = m->sigma_spot * g2;
+        double dxr = r - xs;
+        double D = sqrt(dxr * dxr + ys * ys + zph * zph);
+        ul = dxr / D; vl = -ys / D; wl = zph / D;
+        rec->xs = xs; rec->ys = ys;
+    } else {
+        double alpha, beta;
+        if (rec->stype == OR_SUB_SCATTER) {
+            /* Eq. (6): PSR index from the sampled radius, component from the
+             * cumulative table (decision taken in FP32), then one Gaussian */
+            int ring = (int)floor(r / m->ring_dr);
+            if (ring > m->n_ring - 1) ring = m->n_ring - 1;
+            size_t base = ((size_t)rec->ebin * m->n_ring + ring) * m->n_comp;
+            int k = 0;
+            while (k < m->n_comp - 1 && !((float)u3 < (float)S->cdf[base + k])) ++k;
+            rec->k = k;
+            alpha = m->sc_mu[base + k] + m->sc_sa[base + k] * g1;
+            beta = m->sc_sb[base + k] * g2;
+        } else {
+            /* Eq. (7): zero-mean Gaussian angles */
+            alpha = m->sig_ea * g1;
+            beta = m->sig_eb * g2;
+        }
+        rec->alpha = alpha; rec->beta = beta;
+        if (fabs(alpha) >= 0.5 * OR_PI || fabs(beta) >= 0.5 * OR_PI) invalid = 1;
+        /* alpha = atan(u/w), beta = atan(v/w) */
+        double ta = tan(alpha), tb = tan(beta);
+        double nrm = sqrt(ta * ta + tb * tb + 1.0);
+        ul = ta / nrm; vl = tb / nrm; wl = 1.0 / nrm;
+    }
+    /* rotation of the local (radial, tangential) frame by theta = atan2(y, x) */
+    double u = ct * ul - stt * vl;
+    double v = stt * ul + ct * vl;
+    double w = wl;
+    rec->xb = x; rec->yb = y; rec->ub = u; rec->vb = v; rec->wb = w; rec->e = e;
+
+    if (invalid) { rec->status = OR_ST_INVALID; return; }
+
+    /* jaw rejection at the upper jaw surfaces (closed intervals) */
+    const double zt = m->z_target, zp = m->z_plane;
+    double yj = y + (v / w) * (m->z_jaw_y - zp);
+    double xj = x + (u / w) * (m->z_jaw_x - zp);
+    double ky = (m->z_jaw_y - zt) / (zp - zt), kx = (m->z_jaw_x - zt) / (zp - zt);
+    double y1 = bm->y1 * ky, y2 = bm->y2 * ky, x1 = bm->x1 * kx, x2 = bm->x2 * kx;
+    rec->jaw_margin = fmin(fmin(fabs(yj - y1), fabs(yj - y2)), fmin(fabs(xj - x1), fabs(xj - x2)));
+    if (!(yj >= y1 && yj <= y2 && xj >= x1 && xj <= x2)) { rec->status = OR_ST_JAW; return; }
+
+    /* beam frame -> patient frame; the plane is the isocentre plane */
+    const double* R = S->R[rec->beam];
+    double pb[3] = {x, y, 0.0}, db[3] = {u, v, w}, p[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        p[i] = bm->iso[i] + R[i * 3 + 0] * pb[0] + R[i * 3 + 1] * pb[1] + R[i * 3 + 2] * pb[2];
+        d[i] = R[i * 3 + 0] * db[0] + R[i * 3 + 1] * db[1] + R[i * 3 + 2] * db[2];
+    }
+    double t, t_exit;
+    int hit = ray_box_entry(S->ph, p, d, &t, &t_exit);
+    /* chord length through the box (negative: distance by which it misses) */
+    rec->box_margin = t_exit - t;
+    if (!hit) { rec->status = OR_ST_MISSED; return; }
+    rec->x = p[0] + t * d[0]; rec->y = p[1] + t * d[1]; rec->z = p[2] + t * d[2];
+    rec->u = d[0]; rec->v = d[1]; rec->w = d[2];
+    rec->status = OR_ST_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Photon physics: free-electron Klein-Nishina Compton scattering.            */
+/* ------------------------------------------------------------------------ */
+
+/* Total Klein-Nishina cross-section per electron (cm^2), textbook form. */
+double or_kn_sigma(double e)
+{
+    double k = e / OR_ME;
+    double a = 1.0 + 2.0 * k;
+    double l = log(a);
+    return 2.0 * OR_PI * OR_RE * OR_RE *
+           ((1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - l / k) + l / (2.0 * k) -
+            (1.0 + 3.0 * k) / (a * a));
+}
+
+/* Electron density of water at unit mass density (electrons / cm^3). */
+static double ne_water(void) { return OR_NA * OR_ZA_WATER; }
+
+/* Kahn's rejection method for the Klein-Nishina distribution of
+ * x = E/E' in [1, 1+2k]: with probability (1+2k)/(9+2k) propose x uniform and
+ * accept with 4(x-1)/x^2, otherwise propose x with density ~1/x^2 and accept
+ * with (cos^2 + 1/x)/2.  Three uniforms per trial. Returns x. */
+static double kahn_sample(or_stream* st, double k, uint64_t* trials)
+{
+    for (;;) {
+        double r1 = stream_u01(st), r2 = stream_u01(st), r3 = stream_u01(st);
+        if (trials) (*trials)++;
+        if (r1 <= (1.0 + 2.0 * k) / (9.0 + 2.0 * k)) {
+            double x = 1.0 + 2.0 * k * r2;
+            if (r3 <= 4.0 * (1.0 / x - 1.0 / (x * x))) return x;
+        } else {
+            double x = (1.0 + 2.0 * k) / (1.0 + 2.0 * k * r2);
+            double c = 1.0 - (x - 1.0) / k;
+            if (r3 <= 0.5 * (c * c + 1.0 / x)) return x;
+        }
+    }
+}
+
+/* test hook: n Klein-Nishina scattering cosines at energy e (stream g = i) */
+void or_kn_sample_cos(double e, uint64_t seed, int n, double* cos_out)
+{
+    double k = e / OR_ME;
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        double x = kahn_sample(&st, k, NULL);
+        cos_out[i] = 1.0 - (x - 1.0) / k;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Electron physics: Bethe collision stopping power (ICRU 37 form, no density */
+/* effect), CSDA range and its inverse, Highland multiple-scattering width.   */
+/* ------------------------------------------------------------------------ */
+
+/* Mass collision stopping power of water for electrons, MeV cm^2 / g. */
+double or_s_col(double t)
+{
+    double tau = t / OR_ME;
+    double gam = tau + 1.0;
+    double beta2 = 1.0 - 1.0 / (gam * gam);
+    double i_rel = OR_I_WATER / OR_ME;
+    double f_minus = 1.0 - beta2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * log(2.0)) / (gam * gam);
+    double bracket = log(tau * tau * (tau + 2.0) / (2.0 * i_rel * i_rel)) + f_minus;
+    return 2.0 * OR_PI * OR_RE * OR_RE * OR_ME * OR_NA * OR_ZA_WATER / beta2 * bracket;
+}
+
+/* Gauss-Legendre nodes/weights on [-1, 1] from Newton iteration on P_n. */
+#define OR_GL_N 8
+static double gl_x[OR_GL_N], gl_w[OR_GL_N];
+static void gl_init(void)
+{
+    const int n = OR_GL_N;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(OR_PI * ((double)i + 0.75) / ((double)n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabs(z - z1) < 1e-16) break;
+        }
+        gl_x[i] = z;
+        gl_w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+static double gl_integral_inv_s(double a, double b)
+{
+    double c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
+    for (int i = 0; i < OR_GL_N; ++i) s += gl_w[i] / or_s_col(c + h * gl_x[i]);
+    return s * h;
+}
+
+/* Range nodes: T_k log-spaced from t_cut upwards, C_k = int_{t_cut}^{T_k} dT/S. */
+#define OR_RNG_N 4000
+#define OR_RNG_TMAX 30.0
+typedef struct {
+    double t_cut, ratio;
+    double t[OR_RNG_N], c[OR_RNG_N];
+} or_range_table;
+
+static void range_table_init(or_range_table* rt, double t_cut)
+{
+    gl_init();
+    rt->t_cut = t_cut;
+    rt->ratio = pow(OR_RNG_TMAX / t_cut, 1.0 / (OR_RNG_N - 1));
+    rt->t[0] = t_cut;
+    rt->c[0] = 0.0;
+    for (int k = 1; k < OR_RNG_N; ++k) {
+        rt->t[k] = t_cut * pow(rt->ratio, (double)k);
+        rt->c[k] = rt->c[k - 1] + gl_integral_inv_s(rt->t[k - 1], rt->t[k]);
+    }
+}
+
+/* CSDA range above the cut-off: R(T) = int_{t_cut}^{T} dT'/S(T') (g/cm^2). */
+static double range_of(const or_range_table* rt, double t)
+{
+    if (t <= rt->t_cut) return 0.0;
+    int k = (int)floor(log(t / rt->t_cut) / log(rt->ratio));
+    if (k < 0) k = 0;
+    if (k > OR_RNG_N - 1) k = OR_RNG_N - 1;
+    while (k > 0 && rt->t[k] > t) --k;
+    while (k < OR_RNG_N - 1 && rt->t[k + 1] <= t) ++k;
+    return rt->c[k] + gl_integral_inv_s(rt->t[k], t);
+}
+
+/* Inverse of range_of by bracketing on the nodes, then safeguarded Newton. */
+static double range_inverse(const or_range_table* rt, double rr)
+{
+    if (rr <= 0.0) return rt->t_cut;
+    int lo = 0, hi = OR_RNG_N - 1;
+    if (rr >= rt->c[hi]) return rt->t[hi];
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (rt->c[mid] <= rr) lo = mid; else hi = mid;
+    }
+    double a = rt->t[lo], b = rt->t[hi];
+    double t = a + (b - a) * (rr - rt->c[lo]) / (rt->c[hi] - rt->c[lo]);
+    for (int it = 0; it < 60; ++it) {
+        double f = rt->c[lo] + gl_integral_inv_s(rt->t[lo], t) - rr;
+        if (f > 0.0) b = t; else a = t;
+        double tn = t - f * or_s_col(t);
+        if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
+        if (fabs(tn - t) <= 1e-15 * t) { t = tn; break; }
+        t = tn;
+    }
+    return t;
+}
+
+/* test hooks */
+static or_range_table g_test_rt;
+static double g_test_rt_cut = -1.0;
+static void ensure_test_rt(double t_cut)
+{
+    if (g_test_rt_cut != t_cut) { range_table_init(&g_test_rt, t_cut); g_test_rt_cut = t_cut; }
+}
+double or_range(double t, double t_cut) { ensure_test_rt(t_cut); return range_of(&g_test_rt, t); }
+double or_range_inv(double rr, double t_cut) { ensure_test_rt(t_cut); return range_inverse(&g_test_rt, rr); }
+
+/* Highland width (PDG) of the projected multiple-scattering angle for an
+ * electron of kinetic energy t over t_x radiation lengths; 0 where the
+ * logarithmic correction turns it negative. */
+double or_highland(double t, double t_x)
+{
+    if (!(t_x > 0.0)) return 0.0;
+    double betacp = t * (t + 2.0 * OR_ME) / (t + OR_ME);
+    double th = 13.6 / betacp * sqrt(t_x) * (1.0 + 0.038 * log(t_x));
+    return th > 0.0 ? th : 0.0;
+}
+
+/* Polar deflection for projected-angle width theta0: |theta| of a 2D Gaussian,
+ * theta = theta0 sqrt(-2 ln(1-u)), capped at pi. */
+static double ms_polar(double theta0, double u)
+{
+    double th = theta0 * sqrt(-2.0 * log(1.0 - u));
+    return th < OR_PI ? th : OR_PI;
+}
+
+/* test hook: n polar deflections for width theta0 (stream g = i) */
+void or_ms_sample(double theta0, uint64_t seed, int n, double* theta_out)
+{
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        double u = stream_u01(&st);
+        theta_out[i] = ms_polar(theta0, u);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Transport and tally                                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const or_phantom* ph;
+    const or_params* tp;
+    const or_range_table* rt;
+    double rho_max;
+    const int32_t* imap;       /* optional voxel -> row+1 */
+    int64_t n_cols;            /* tally columns in index-map mode */
+    double* grid;              /* this thread's energy array */
+    double ledger[L_N];
+    uint64_t cnt[C_N];
+} or_tracker;
+
+static void deposit(or_tracker* T, int64_t v, double e, int32_t tag)
+{
+    if (e == 0.0) return;
+    T->ledger[L_DEP] += e;
+    T->cnt[C_DEPOSITS]++;
+    if (T->imap) {
+        int32_t row = T->imap[v];
+        if (row > 0) T->grid[(int64_t)(row - 1) * T->n_cols + tag] += e;
+    } else {
+        T->grid[v] += e;
+    }
+}
+
+#define OR_MAX_E_STEPS 100000
+
+/* Condensed-history electron (CSDA + Highland Gaussian deflections).
+ * Steps end at voxel faces or after a fractional energy loss step_frac;
+ * the voxel index is carried explicitly and changes by one at each face. */
+static void transport_electron(or_tracker* T, double p[3], double d[3], double e,
+                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag)
+{
+    const or_phantom* ph = T->ph;
+    const double tcut = T->tp->e_cut_e, f = T->tp->step_frac;
+    const int n[3] = {ph->nx, ph->ny, ph->nz};
+    int idx[3];
+    voxel_clamped(ph, p, idx);
+    if (e < tcut) {
+        deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
+        T->cnt[C_E_LOCAL]++;
+        return;
+    }
+    or_stream st;
+    stream_init(&st, seed, g, OR_TAG_TR, sub);
+    for (int step = 0;; ++step) {
+        int64_t v = ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
+        if (step >= OR_MAX_E_STEPS) { deposit(T, v, e, tag); T->cnt[C_GUARD]++; return; }
+        double rho = (double)ph->density[v];
+        /* distance to the exit face of the current voxel */
+        double sb = OR_INF;
+        int axis = -1;
+        for (int a = 0; a < 3; ++a) {
+            double face;
+            if (d[a] > 0.0) face = ph->origin[a] + (double)(idx[a] + 1) * ph->vox[a];
+            else if (d[a] < 0.0) face = ph->origin[a] + (double)idx[a] * ph->vox[a];
+            else continue;
+            double t = (face - p[a]) / d[a];
+            if (t < sb) { sb = t; axis = a; }
+        }
+        if (sb < 0.0) sb = 0.0;
+        /* energy-loss limited step */
+        double r0 = range_of(T->rt, e);
+        double e_f = e * (1.0 - f);
+        int final = !(e_f > tcut);
+        double sf;
+        if (rho > 0.0) sf = (final ? r0 : r0 - range_of(T->rt, e_f)) / rho;
+        else sf = OR_INF;
+        T->cnt[C_E_STEPS]++;
+        if (sf <= sb) {
+            if (final) {
+                /* the residual range ends inside this voxel */
+                T->ledger[L_EPATH] += sf;
+                deposit(T, v, e, tag);
+                return;
+            }
+            double e_new = range_inverse(T->rt, r0 - rho * sf);
+            deposit(T, v, e - e_new, tag);
+            for (int a = 0; a < 3; ++a) p[a] += sf * d[a];
+            T->ledger[L_EPATH] += sf;
+            double e_old = e;
+            e = e_new;
+            if (e < tcut) { deposit(T, v, e, tag); return; }
+            if (T->tp->ms_enable) {
+                double th0 = or_highland(0.5 * (e_old + e), rho * sf / OR_X0_WATER);
+                double u1 = stream_u01(&st), u2 = stream_u01(&st);
+                rotate_direction(d, cos(ms_polar(th0, u1)), 2.0 * OR_PI * u2);
+            }
+        } else {
+            double e_new = range_inverse(T->rt, r0 - rho * sb);
+            deposit(T, v, e - e_new, tag);
+            for (int a = 0; a < 3; ++a) p[a] += sb * d[a];
+            T->ledger[L_EPATH] += sb;
+            T->cnt[C_E_BOUNDARY]++;
+            double e_old = e;
+            e = e_new;
+            idx[axis] += d[axis] > 0.0 ? 1 : -1;
+            if (idx[axis] < 0 || idx[axis] >= n[axis]) { T->ledger[L_ESC_E] += e; return; }
+            if (e < tcut) {
+                deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
+                return;
+            }
+            if (T->tp->ms_enable) {
+                double th0 = or_highland(0.5 * (e_old + e), rho * sb / OR_X0_WATER);
+                double u1 = stream_u01(&st), u2 = stream_u01(&st);
+                rotate_direction(d, cos(ms_polar(th0, u1)), 2.0 * OR_PI * u2);
+            }
+        }
+    }
+}
+
+typedef struct { double p[3], d[3], e; uint32_t sub; } or_electron;
+
+/* Woodcock (delta) tracking with the majorant mu_max(E) = n_e rho_max sigma_KN(E);
+ * a tentative collision is real with probability rho_voxel / rho_max.
+ * Compton electrons at or above the electron cut-off are transported, below it
+ * deposited on the spot; the photon is absorbed locally below its cut-off. */
+static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
+                             uint64_t seed, uint64_t g, int32_t tag)
+{
+    const or_phantom* ph = T->ph;
+    or_stream st;
+    stream_init(&st, seed, g, OR_TAG_TR, 0);
+    or_electron stack[64];
+    int n_e = 0;
+    uint32_t n_push = 0;
+    int collided = 0;
+    const double ne = ne_water();
+    for (;;) {
+        double mu_max = ne * T->rho_max * or_kn_sigma(e);
+        double s = -log(1.0 - stream_u01(&st)) / mu_max;
+        for (int a = 0; a < 3; ++a) p[a] += s * d[a];
+        int idx[3];
+        int64_t v = voxel_of(ph, p, idx);
+        if (v < 0) {
+            T->ledger[L_ESC_G] += e;
+            if (!collided) T->cnt[C_ESC_UNCOLLIDED]++;
+            break;
+        }
+        T->cnt[C_WC_STEPS]++;
+        double ur = stream_u01(&st);
+        if (!(ur < (double)ph->density[v] / T->rho_max)) continue;
+        collided = 1;
+        T->cnt[C_REAL]++;
+        double k = e / OR_ME;
+        double x = kahn_sample(&st, k, &T->cnt[C_KAHN_TRIALS]);
+        double cos_t = 1.0 - (x - 1.0) / k;
+        double phi = 2.0 * OR_PI * stream_u01(&st);
+        double e1 = e / x;
+        double te = e - e1;
+        double d1[3] = {d[0], d[1], d[2]};
+        rotate_direction(d1, cos_t, phi);
+        if (te >= T->tp->e_cut_e) {
+            /* electron direction from momentum conservation: p_e = E d - E' d' */
+            double pe[3], nrm = 0.0;
+            for (int a = 0; a < 3; ++a) { pe[a] = e * d[a] - e1 * d1[a]; nrm += pe[a] * pe[a]; }
+            nrm = sqrt(nrm);
+            or_electron* el = &stack[n_e++];
+            for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = pe[a] / nrm; }
+            el->e = te;
+            el->sub = 1 + n_push++;
+            T->cnt[C_E_PUSHED]++;
+        } else {
+            deposit(T, v, te, tag);
+            T->cnt[C_E_LOCAL]++;
+        }
+        e = e1;
+        for (int a = 0; a < 3; ++a) d[a] = d1[a];
+        if (e < T->tp->e_cut_g) { deposit(T, v, e, tag); break; }
+        if (n_e == 64) break;   /* cannot happen: at most E/e_cut_e pushes */
+    }
+    for (int i = 0; i < n_e; ++i)
+        transport_electron(T, stack[i].p, stack[i].d, stack[i].e, seed, g, stack[i].sub, tag);
+}
+
+static double phantom_rho_max(const or_phantom* ph)
+{
+    size_t n = (size_t)ph->nx * ph->ny * ph->nz;
+    double m = 0.0;
+    for (size_t i = 0; i < n; ++i) if (ph->density[i] > m) m = ph->density[i];
+    return m;
+}
+
+static void tracker_init(or_tracker* T, const or_phantom* ph, const or_params* tp,
+                         const or_range_table* rt, double rho_max, const int32_t* imap,
+                         int64_t n_cols, double* grid)
+{
+    memset(T, 0, sizeof(*T));
+    T->ph = ph; T->tp = tp; T->rt = rt; T->rho_max = rho_max;
+    T->imap = imap; T->n_cols = n_cols; T->grid = grid;
+}
+
+#define OR_MAX_THREADS 64
+static int n_threads_of(int req)
+{
+#ifdef _OPENMP
+    int nt = req > 0 ? req : omp_get_max_threads();
+    return nt < OR_MAX_THREADS ? nt : OR_MAX_THREADS;
+#else
+    (void)req;
+    return 1;
+#endif
+}
+
+/* Samples histories g = r*N + h for r in [rep0, rep0+n_rep), h in [h0, h1) and
+ * transports them.  Energy per replica is accumulated in FP64; sum/sum2 receive
+ * the sum over replicas of E_r and E_r^2 per tally cell (V voxels, or
+ * n_rows * n_cols cells in index-map mode).  ledger[8], counters[16]. */
+int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_beams,
+           const or_phantom* ph, const or_params* tp, uint64_t seed, uint32_t rep0,
+           uint32_t n_rep, uint64_t h0, uint64_t h1, const int32_t* imap, int64_t n_rows,
+           int64_t n_cols, double* sum, double* sum2, double* ledger, uint64_t* counters,
+           int n_threads)
+{
+    if (!plan->n_list || h1 > plan->n_hist || h0 > h1) return -1;
+    gl_init();
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)m->n_ebin * m->n_ring * m->n_comp);
+    or_scatter_cdf(m, cdf);
+    double (*R)[9] = malloc(sizeof(double[9]) * (size_t)n_beams);
+    for (int b = 0; b < n_beams; ++b) beam_rotation(&beams[b], R[b]);
+    or_sampler S = {m, cdf, plan, beams, R, ph};
+    or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
+    range_table_init(rt, tp->e_cut_e);
+    double rho_max = phantom_rho_max(ph);
+    int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
+    int nt = n_threads_of(n_threads);
+    double* grids = (double*)malloc(sizeof(double) * (size_t)cells * nt);
+    double* er = (double*)malloc(sizeof(double) * (size_t)cells);
+    double led[L_N] = {0};
+    uint64_t cnt[C_N] = {0};
+    for (int64_t c = 0; c < cells; ++c) { sum[c] = 0.0; sum2[c] = 0.0; }
+    for (uint32_t r = rep0; r < rep0 + n_rep; ++r) {
+        memset(grids, 0, sizeof(double) * (size_t)cells * nt);
+        or_tracker trk[OR_MAX_THREADS];
+#pragma omp parallel num_threads(nt)
+        {
+#ifdef _OPENMP
+            int tid = omp_get_thread_num();
+#else
+            int tid = 0;
+#endif
+            or_tracker* T = &trk[tid];
+            tracker_init(T, ph, tp, rt, rho_max, imap, n_cols, grids + (size_t)cells * tid);
+#pragma omp for schedule(static)
+            for (int64_t h = (int64_t)h0; h < (int64_t)h1; ++h) {
+                uint64_t g = (uint64_t)r * plan->n_hist + (uint64_t)h;
+                or_sample_rec rec;
+                sample_history(&S, seed, g, &rec);
+                T->cnt[C_HIST]++;
+                T->ledger[L_SRC] += rec.e;
+                if (rec.status == OR_ST_JAW) { T->ledger[L_JAW] += rec.e; continue; }
+                if (rec.status == OR_ST_INVALID) { T->ledger[L_INVALID] += rec.e; continue; }
+                if (rec.status == OR_ST_MISSED) { T->ledger[L_MISSED] += rec.e; continue; }
+                T->cnt[C_ENTERED]++;
+                double p[3] = {rec.x, rec.y, rec.z}, d[3] = {rec.u, rec.v, rec.w};
+                if (rec.stype == OR_SUB_ELECTRON)
+                    transport_electron(T, p, d, rec.e, seed, g, 0, rec.tag);
+                else
+                    transport_photon(T, p, d, rec.e, seed, g, rec.tag);
+            }
+        }
+        for (int64_t c = 0; c < cells; ++c) {
+            double a = 0.0;
+            for (int t = 0; t < nt; ++t) a += grids[(size_t)cells * t + c];
+            er[c] = a;
+        }
+        for (int64_t c = 0; c < cells; ++c) { sum[c] += er[c]; sum2[c] += er[c] * er[c]; }
+        for (int t = 0; t < nt; ++t) {
+            for (int i = 0; i < L_N; ++i) led[i] += trk[t].ledger[i];
+            for (int i = 0; i < C_N; ++i) cnt[i] += trk[t].cnt[i];
+        }
+    }
+    for (int i = 0; i < L_N; ++i) ledger[i] = led[i];
+    for (int i = 0; i < C_N; ++i) counters[i] = cnt[i];
+    free(cdf); free(R); free(rt); free(grids); free(er);
+    return 0;
+}
+
+/* Per-history sampling records for g in [g0, g0+n) (test hook). */
+int or_sample(const or_model* m, const or_plan* plan, const or_beam* beams, int n_beams,
+              const or_phantom* ph, uint64_t seed, uint64_t g0, int64_t n, or_sample_rec* out)
+{
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)m->n_ebin * m->n_ring * m->n_comp);
+    or_scatter_cdf(m, cdf);
+    double (*R)[9] = malloc(sizeof(double[9]) * (size_t)n_beams);
+    for (int b = 0; b < n_beams; ++b) beam_rotation(&beams[b], R[b]);
+    or_sampler S = {m, cdf, plan, beams, R, ph};
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) sample_history(&S, seed, g0 + (uint64_t)i, &out[i]);
+    free(cdf); free(R);
+    return 0;
+}
+
+/* Transports given particles (ptype 0 photon, 1 electron) that start on or in
+ * the phantom; energy per cell summed into edep.  Particle i uses history id
+ * hid[i] for its random streams. */
+int or_transport(const or_phantom* ph, const or_params* tp, uint64_t seed, int64_t n,
+                 const int32_t* ptype, const double* pos, const double* dir, const double* e,
+                 const uint64_t* hid, const int32_t* tag, const int32_t* imap, int64_t n_rows,
+                 int64_t n_cols, double* edep, double* ledger, uint64_t* counters, int n_threads)
+{
+    gl_init();
+    or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
+    range_table_init(rt, tp->e_cut_e);
+    double rho_max = phantom_rho_max(ph);
+    int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
+    int nt = n_threads_of(n_threads);
+    double* grids = (double*)calloc((size_t)cells * nt, sizeof(double));
+    or_tracker trk[OR_MAX_THREADS];
+#pragma omp parallel num_threads(nt)
+    {
+#ifdef _OPENMP
+        int tid = omp_get_thread_num();
+#else
+        int tid = 0;
+#endif
+        or_tracker* T = &trk[tid];
+        tracker_init(T, ph, tp, rt, rho_max, imap, n_cols, grids + (size_t)cells * tid);
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+            double d[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+            T->cnt[C_HIST]++;
+            T->ledger[L_SRC] += e[i];
+            if (ptype[i] == 1)
+                transport_electron(T, p, d, e[i], seed, hid[i], 0, tag ? tag[i] : 0);
+            else
+                transport_photon(T, p, d, e[i], seed, hid[i], tag ? tag[i] : 0);
+        }
+    }
+    for (int64_t c = 0; c < cells; ++c) {
+        double a = 0.0;
+        for (int t = 0; t < nt; ++t) a += grids[(size_t)cells * t + c];
+        edep[c] = a;
+    }
+    for (int i = 0; i < L_N; ++i) ledger[i] = 0.0;
+    for (int i = 0; i < C_N; ++i) counters[i] = 0;
+    for (int t = 0; t < nt; ++t) {
+        for (int i = 0; i < L_N; ++i) ledger[i] += trk[t].ledger[i];
+        for (int i = 0; i < C_N; ++i) counters[i] += trk[t].cnt[i];
+    }
+    free(rt); free(grids);
+    return 0;
+}
+
+/* Dose in Gy per model particle from summed replica energies (MeV):
+ * D = 1.602176634e-10 * mean_r(E) / (rho V) * weight_per_history, and the
+ * standard error of the replica mean. */
+void or_finalize(const or_phantom* ph, const double* sum, const double* sum2, uint32_t n_rep,
+                 double weight_per_history, double* dose, double* sigma)
+{
+    int64_t V = (int64_t)ph->nx * ph->ny * ph->nz;
+    double vol = ph->vox[0] * ph->vox[1] * ph->vox[2];
+    for (int64_t v = 0; v < V; ++v) {
+        double rho = (double)ph->density[v];
+        double k = rho > 0.0 ? OR_MEV_PER_G_TO_GY * weight_per_history / (rho * vol) : 0.0;
+        double mean = sum[v] / n_rep;
+        double var = n_rep > 1 ? (sum2[v] / n_rep - mean * mean) * n_rep / (n_rep - 1) : 0.0;
+        if (var < 0.0) var = 0.0;
+        dose[v] = k * mean;
+        sigma[v] = k * sqrt(var / n_rep);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 2.2.3-2.2.4: commissioning, min_{x>=0} ||Ax - b||^2 (Eq. 8) by        */
+/* gradient projection x+ = max(0, x - s grad F) with Armijo's rule.          */
+/* The trial step is the Barzilai-Borwein step of the previous iteration (the */
+/* first one 1/||A||_F^2); it is halved until F(x+) <= F(x) + sigma g.(x+ - x).*/
+/* Stops when the relative decrease of F is below delta and the projected     */
+/* gradient is below pg_tol * |g0|, or after max_iter iterations.             */
+/* A is m x n column-major.                                                   */
+/* ------------------------------------------------------------------------ */
+static double nnls_objective(const double* A, int64_t m, int64_t n, const double* b,
+                             const double* x, double* r)
+{
+    for (int64_t i = 0; i < m; ++i) r[i] = -b[i];
+    for (int64_t j = 0; j < n; ++j) {
+        double xj = x[j];
+        if (xj == 0.0) continue;
+        const double* col = A + j * m;
+        for (int64_t i = 0; i < m; ++i) r[i] += col[i] * xj;
+    }
+    double f = 0.0;
+    for (int64_t i = 0; i < m; ++i) f += r[i] * r[i];
+    return f;
+}
+
+static void nnls_gradient(const double* A, int64_t m, int64_t n, const double* r, double* g)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        const double* col = A + j * m;
+        double s = 0.0;
+        for (int64_t i = 0; i < m; ++i) s += col[i] * r[i];
+        g[j] = 2.0 * s;
+    }
+}
+
+static double projected_gradient_norm(const double* x, const double* g, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double pg = x[j] > 0.0 ? g[j] : (g[j] < 0.0 ? g[j] : 0.0);
+        s += pg * pg;
+    }
+    return sqrt(s);
+}
+
+/* report[0] = iterations, [1] = F, [2] = projected-gradient norm, [3] = converged */
+int or_nnls_gp(const double* A, int64_t m, int64_t n, const double* b, double* x,
+               double delta, double pg_tol, double armijo_sigma, double armijo_beta,
+               int64_t max_iter, double* report)
+{
+    double* r = (double*)malloc(sizeof(double) * (size_t)m);
+    double* g = (double*)malloc(sizeof(double) * (size_t)n);
+    double* xn = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gn = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int64_t j = 0; j < n; ++j) if (!(x[j] > 0.0)) x[j] = 0.0;
+    double f = nnls_objective(A, m, n, b, x, r);
+    nnls_gradient(A, m, n, r, g);
+    double g0 = 0.0;
+    for (int64_t j = 0; j < n; ++j) g0 += g[j] * g[j];
+    g0 = sqrt(g0);
+    double fro = 0.0;
+    for (int64_t i = 0; i < m * n; ++i) fro += A[i] * A[i];
+    double step = fro > 0.0 ? 1.0 / fro : 1.0;
+    int64_t it = 0;
+    int converged = 0;
+    double pg = projected_gradient_norm(x, g, n);
+    if (pg <= pg_tol * g0) converged = 1;
+    while (!converged && it < max_iter) {
+        ++it;
+        double s = step, fn = f;
+        int accepted = 0;
+        for (int ls = 0; ls < 200; ++ls) {
+            double dec = 0.0;
+            for (int64_t j = 0; j < n; ++j) {
+                double y = x[j] - s * g[j];
+                xn[j] = y > 0.0 ? y : 0.0;
+                dec += g[j] * (xn[j] - x[j]);
+            }
+            fn = nnls_objective(A, m, n, b, xn, r);
+            if (fn <= f + armijo_sigma * dec) { accepted = 1; break; }
+            s *= armijo_beta;
+        }
+        if (!accepted) break;
+        nnls_gradient(A, m, n, r, gn);
+        /* Barzilai-Borwein trial step for the next iteration */
+        double sxx = 0.0, sxg = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double dx = xn[j] - x[j], dg = gn[j] - g[j];
+            sxx += dx * dx;
+            sxg += dx * dg;
+        }
+        step = (sxg > 0.0) ? sxx / sxg : 2.0 * s;
+        double rel = (f - fn) / (f > 0.0 ? f : 1.0);
+        memcpy(x, xn, sizeof(double) * (size_t)n);
+        memcpy(g, gn, sizeof(double) * (size_t)n);
+        f = fn;
+        pg = projected_gradient_norm(x, g, n);
+        if (rel < delta && pg <= pg_tol * g0) converged = 1;
+        if (f == 0.0) converged = 1;
+    }
+    report[0] = (double)it;
+    report[1] = f;
+    report[2] = pg;
+    report[3] = (double)converged;
+    free(r); free(g); free(xn); free(gn);
+    return converged ? 0 : 1;
+}
