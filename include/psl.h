@@ -1,0 +1,312 @@
+/*
+ * psl.h -- C ABI of the MI355X (gfx950) Monte Carlo dose engine built around
+ * the analytic phase-space-ring (PSR) linac source model of Tian et al.,
+ * "An analytic linear accelerator source model for Monte Carlo dose
+ * calculations. II" (arXiv:1503.01725).
+ *
+ * Conventions
+ *   - Every call returns a psl_status; on failure psl_last_error() (thread
+ *     local) holds a message.  No C++ exception crosses this boundary.
+ *   - Units: cm, MeV, g/cm^3.  Doses are Gy per model particle.
+ *   - Handles (psl_model, psl_plan, psl_phantom, psl_tally) are owned by the
+ *     library and released with the matching *_free call.  A plan keeps a
+ *     pointer to its model, a tally to its phantom: free dependants first.
+ *   - Pointers documented as "device" are HIP device pointers owned by the
+ *     caller (for example torch tensors); the library never frees them.
+ *     Pointers documented as "host" are read (or written) before the call
+ *     returns.
+ *   - Calls taking a `stream` (a hipStream_t, NULL = default stream) are
+ *     asynchronous: they validate arguments on the host, enqueue work and
+ *     return.  Faults detected on the device (stack overflow, non-finite
+ *     energies) set a device status word that psl_tally_stats reports.
+ *   - Distinct handles may be used from different host threads; one handle
+ *     must not be used by two threads at once.
+ */
+#ifndef PSL_H
+#define PSL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSL_OK = 0,
+    PSL_EINVAL = -1,     /* bad argument (reported before any device work)    */
+    PSL_ENOMEM = -2,     /* device or host allocation failed                  */
+    PSL_EDEVICE = -3,    /* HIP runtime error                                 */
+    PSL_EOVERFLOW = -4,  /* a particle stack was too small; results invalid   */
+    PSL_ENOTCONV = -5    /* iterative solve hit its iteration limit           */
+} psl_status;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* psl_last_error(void);
+
+/* Opaque, library-owned handles. */
+typedef struct psl_model psl_model;
+typedef struct psl_plan psl_plan;
+typedef struct psl_phantom psl_phantom;
+typedef struct psl_tally psl_tally;
+
+/* ------------------------------------------------------------------------
+ * Source model (Sec. 2.1.1; Eqs. 4-7 for the direction models)
+ * ------------------------------------------------------------------------ */
+
+/* A PSR model: 3 sub-sources (0 primary photon, 1 scatter photon,
+ * 2 electron) x n_ebin energy bins x n_ring rings on the plane z = z_plane.
+ * Energy bin b covers [e_lo + b e_width, e_lo + (b+1) e_width); ring j covers
+ * [j ring_dr, (j+1) ring_dr).  The PSL grid is n_psl x n_psl squares of side
+ * psl_dx with edges at psl_x0 + k psl_dx in x and y.  Heights (beam frame,
+ * particles travel towards +z): focal spot z_target, scatter source
+ * z_scatter, upper surfaces of the Y and X jaws z_jaw_y and z_jaw_x; the plane
+ * is the isocentre plane.  All arrays are host memory, copied by psl_build. */
+typedef struct {
+    int32_t n_ebin, n_ring, n_comp, n_psl;
+    double e_lo, e_width, ring_dr, psl_x0, psl_dx;
+    double z_target, z_plane, z_scatter, z_jaw_y, z_jaw_x;
+    double sigma_spot;          /* focal-spot Gaussian width, Eq. (4)        */
+    double sig_ea, sig_eb;      /* electron angular widths, Eq. (7)          */
+    const double* w_psr;        /* [3][n_ebin][n_ring] PSR weights           */
+    const double* sc_c;         /* [n_ebin][n_ring][n_comp] mixture weights, Eq. (6) */
+    const double* sc_mu;        /* [n_ebin][n_ring][n_comp] alpha means (rad)     */
+    const double* sc_sa;        /* [n_ebin][n_ring][n_comp] alpha widths (rad)    */
+    const double* sc_sb;        /* [n_ebin][n_ring][n_comp] beta widths (rad)     */
+} psl_psr_desc;
+
+/* Converts the PSR model to its PSL representation once (Sec. 2.1.1, Eq. 2:
+ * interpolated ring weight / (2 pi r) at each PSL centre, normalised over all
+ * sub-sources, energies and locations), builds the scatter component table
+ * P_{i,k} (step S4) and uploads the sampling tables to the current device.
+ * Limits: n_psl <= 255, n_ebin <= 255, 1 <= n_comp <= 8.  Synchronous. */
+int psl_build(const psl_psr_desc* desc, psl_model** out);
+
+/* Copies the FP64 PSL weights [3][n_ebin][n_psl][n_psl] to host memory. */
+int psl_model_weights(const psl_model* model, double* w_psl_host);
+void psl_model_free(psl_model* model);
+
+/* ------------------------------------------------------------------------
+ * Plan: sampling areas (Sec. 2.1.2, Fig. 3, step S1) and particles per PSL
+ * (step S2, Eq. 3), with the history order of Sec. 2.1.3.
+ * ------------------------------------------------------------------------ */
+
+/* One beam: jaw edges projected to the isocentre plane (x1 < x2, y1 < y2),
+ * gantry angle (rotation about patient +y) and couch angle (about +z), and
+ * the isocentre in patient coordinates. */
+typedef struct {
+    double x1, x2, y1, y2;
+    double gantry_deg, couch_deg;
+    double iso[3];
+} psl_beam;
+
+/* Builds the list of in-area PSLs of all beams in the order beam, sub-source,
+ * energy bin, y, x (location innermost, energy outer; Sec. 2.1.3) and their
+ * particle counts.
+ *   basis_of_psr: NULL, or host [3][n_ebin][n_ring] basis id of each PSR (the
+ *     PSL takes the id of the ring its centre lies in).  A particle then
+ *     carries the tally column beam * n_basis + basis (Sec. 2.2.2), where
+ *     n_basis = 1 + the largest id.
+ *   hist_per_basis: 0 -> Eq. (3): n_hist histories spread over the whole list
+ *     in proportion to the PSL weights.  > 0 (needs basis_of_psr) ->
+ *     commissioning: each (beam, basis) receives hist_per_basis histories
+ *     spread over its own PSLs; the list order is then beam, basis, sub-source,
+ *     energy, y, x, and n_hist is ignored.
+ *   Counts are rounded systematically on a 2^-40 fixed-point prefix so that
+ *   they add up to the requested totals exactly.
+ * The plan refers to `model`, which must outlive it.  Synchronous. */
+int psl_plan_create(const psl_model* model, const psl_beam* beams, int32_t n_beams,
+                    uint64_t n_hist, uint32_t n_replica, const uint16_t* basis_of_psr,
+                    uint64_t hist_per_basis, psl_plan** out);
+
+typedef struct {
+    uint64_t n_hist;        /* histories per replica (N)                        */
+    uint32_t n_replica;
+    int32_t n_beams;
+    int64_t n_list;         /* in-area PSLs with positive weight                */
+    int32_t n_cols;         /* tally columns (1 without a basis map)            */
+    double s_area;          /* sum of in-area PSL weights (Eq. 3 denominator)   */
+    double e_max;           /* highest source energy of the model               */
+} psl_plan_info;
+int psl_plan_get_info(const psl_plan* plan, psl_plan_info* info);
+
+/* Host copies of the plan: the sampling box [ix0, ix1, iy0, iy1] of every
+ * (beam, sub-source) (int32 [n_beams][3][4]); and the list (any pointer may
+ * be NULL): int32 beam, stype, ebin, ix, iy, tag and uint64 inclusive prefix
+ * of counts, n_list entries each. */
+int psl_plan_boxes(const psl_plan* plan, int32_t* boxes);
+int psl_plan_list(const psl_plan* plan, int32_t* beam, int32_t* stype, int32_t* ebin,
+                  int32_t* ix, int32_t* iy, int32_t* tag, double* w, uint64_t* cum);
+
+/* Per-column particle weight (model particles per history): S_A/N for Eq. (3)
+ * plans, S_{beam,basis}/n_{beam,basis} for commissioning plans.  n_cols
+ * doubles, host memory. */
+int psl_plan_col_weight(const psl_plan* plan, double* w_host);
+
+/* Batches (Sec. 2.1.3): maximal runs of consecutive histories inside one
+ * (beam, sub-source, energy band) with at most max_batch histories, where
+ * band = energy bin / band_width.  psl_plan_set_batching fixes the split and
+ * returns the number of batches; psl_plan_get_batch reads one. */
+typedef struct {
+    uint64_t h0;            /* first history (within a replica)               */
+    uint32_t n;             /* histories in the batch                          */
+    int32_t stype;          /* sub-source: 0 primary, 1 scatter, 2 electron   */
+    int32_t beam;
+    int32_t band;
+} psl_batch;
+int psl_plan_set_batching(psl_plan* plan, uint32_t max_batch, int32_t band_width,
+                          int64_t* n_batches);
+int psl_plan_get_batch(const psl_plan* plan, int64_t index, psl_batch* batch);
+void psl_plan_free(psl_plan* plan);
+
+/* ------------------------------------------------------------------------
+ * Phantom
+ * ------------------------------------------------------------------------ */
+/* density_dev: device float32 [nz][ny][nx] mass densities (water-like medium
+ * scaled by density), x fastest; must stay valid while the phantom is used.
+ * vox: voxel size (cm); origin: patient coordinates of the outer corner of
+ * voxel (0,0,0).  The maximum density is found on the device.  Synchronous. */
+int psl_phantom_create(const float* density_dev, int32_t nx, int32_t ny, int32_t nz,
+                       const double vox[3], const double origin[3], psl_phantom** out);
+void psl_phantom_free(psl_phantom* phantom);
+
+/* ------------------------------------------------------------------------
+ * Particles (steps S3-S5)
+ * ------------------------------------------------------------------------ */
+
+/* Structure-of-arrays particle stack, all arrays device memory of `capacity`
+ * entries, caller-allocated.  tag bits 0-15: tally column; bits 16-23: random
+ * sub-stream id; bits 24-31: status (0 ok, 1 jaw-rejected, 2 missed the
+ * phantom, 3 invalid direction; dense sampling output only).  `count` is a
+ * device uint32.  `ptype` (host field) is 0 for photons, 1 for electrons and
+ * is set by sample_batch. */
+typedef struct {
+    float *x, *y, *z, *u, *v, *w, *e;
+    uint64_t* hid;
+    uint32_t* tag;
+    uint32_t* count;
+    uint32_t capacity;
+    int32_t ptype;
+} psl_particles;
+
+enum {
+    PSL_SAMPLE_DENSE = 1    /* write history h0+i at slot i with its status
+                               (every history, also rejected ones) instead of
+                               compacting accepted particles                */
+};
+
+/* Samples histories [h0, h0+n) of replica `replica` (global id
+ * g = replica * N + h) from one sub-source (the range must not cross a
+ * sub-source change; batches from psl_plan_get_batch never do):
+ *   - PSL by binary search of h in the count prefix; position and energy
+ *     uniform in the PSL and its bin;
+ *   - direction from Eq. (5) (primary: Gaussian focal spot, Eq. 4), Eq. (6)
+ *     (scatter: K-component Gaussian mixture in alpha, beta) or Eq. (7)
+ *     (electron), rotated by theta = atan2(y, x);
+ *   - jaw rejection at the upper jaw surfaces; beam -> patient transform;
+ *     start at the entry of the particle's line into the phantom box.
+ * Random numbers: Philox4x32-10 keyed by `seed`, counter (block, 1<<16,
+ * g_lo, g_hi).  Without PSL_SAMPLE_DENSE accepted particles are appended at
+ * *out->count (which the caller zeroes) and rejected ones only enter the
+ * tally's energy ledger.  Needs out->capacity >= n (dense) or room for n more.
+ * The tally receives the source-side energy ledger. */
+int sample_batch(const psl_plan* plan, const psl_phantom* phantom, uint32_t replica,
+                 uint64_t h0, uint32_t n, uint64_t seed, psl_particles* out,
+                 uint32_t flags, psl_tally* tally, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Transport and tally
+ * ------------------------------------------------------------------------ */
+
+/* Physics switches.  Photons: free-electron Klein-Nishina Compton scattering
+ * with Woodcock tracking; absorbed locally below e_cut_photon.  Electrons:
+ * continuous slowing down with the Bethe collision stopping power of water
+ * scaled by density, steps ending at voxel faces or after losing step_frac of
+ * their energy, Highland Gaussian multiple scattering (ms_enable); absorbed
+ * locally below e_cut_electron (Sec. 2.3 names the cut-offs). */
+typedef struct {
+    float e_cut_electron;   /* MeV, e.g. 0.2   */
+    float e_cut_photon;     /* MeV, e.g. 0.01  */
+    float step_frac;        /* e.g. 0.1        */
+    int32_t ms_enable;      /* 1 = on          */
+} psl_transport_params;
+
+/* A dose tally on `phantom`.  index_map_dev == NULL: one cell per voxel.
+ * Otherwise (Sec. 2.2.2) index_map_dev is a device int32 [nz][ny][nx] map,
+ * 0 = voxel not tallied, k > 0 = row k-1, and the tally is a 2D array
+ * [n_rows][n_cols] addressed by (row, particle tag).  Holds an FP32 replica
+ * array, FP64 sum and sum-of-squares arrays, the energy ledger and event
+ * counters.  Synchronous. */
+int psl_tally_create(const psl_phantom* phantom, const int32_t* index_map_dev, int32_t n_rows,
+                     int32_t n_cols, psl_tally** out);
+void psl_tally_free(psl_tally* tally);
+
+/* Transports every particle of `in` (photons or electrons, per in->ptype) to
+ * completion and adds the deposits of this replica to the tally's FP32 array.
+ * Electrons set in motion by photons go through `electrons`, a caller stack
+ * whose capacity must cover in->capacity * floor(e_max / e_cut_electron)
+ * (each push costs the photon at least e_cut_electron); it is grouped into
+ * energy bands before electron transport.  Random numbers: Philox4x32-10 keyed
+ * by `seed`, counter (block, 2<<16 | sub, g_lo, g_hi), sub 0 for the source
+ * particle and 1+n for the electron of its n-th push. */
+int transport_batch(const psl_phantom* phantom, const psl_particles* in,
+                    psl_particles* electrons, psl_tally* tally,
+                    const psl_transport_params* params, uint64_t seed, void* stream);
+
+enum {
+    PSL_TALLY_RESET = 1,     /* zero every array, ledger and counter          */
+    PSL_TALLY_FOLD = 2,      /* sum += E_r, sum2 += E_r^2, E_r = 0 (FP64)     */
+    PSL_TALLY_FINALIZE = 4   /* dose and its standard error from the folds    */
+};
+
+/* Tally operations, applied in the order RESET, FOLD, FINALIZE when several
+ * bits are set.  FINALIZE writes dose_dev and sigma_dev (device FP64, one per
+ * cell) in Gy per model particle: mean over folded replicas of
+ * 1.602176634e-10 * E / (rho V) * (column weight of `plan`), and the standard
+ * error of that mean.  plan, dose_dev and sigma_dev may be NULL without
+ * FINALIZE. */
+int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose_dev,
+               double* sigma_dev, void* stream);
+
+/* Synchronises with the device and reads the energy ledger (MeV, host double
+ * [8]: source, jaw-rejected, missed phantom, invalid, escaped photons, escaped
+ * electrons, deposited, electron path length in cm), the event counters (host
+ * uint64 [16]: histories, entered, Woodcock steps, real interactions, electrons
+ * pushed, local electron deposits, electron steps, atomic deposits, uncollided
+ * escapes, Kahn trials, electron face crossings, step-guard hits,
+ * electron-stack overflows, replicas folded) and the device status word.
+ * Returns PSL_EOVERFLOW if a stack overflowed since the last RESET.  Either
+ * output may be NULL. */
+int psl_tally_stats(psl_tally* tally, double* ledger, uint64_t* counters);
+
+/* ------------------------------------------------------------------------
+ * Commissioning (Sec. 2.2.3, Eq. 8; Sec. 2.2.4)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double delta;           /* stop when the relative decrease of F < delta ... */
+    double pg_tol;          /* ... and |projected gradient| <= pg_tol |grad F(x0)| */
+    double armijo_sigma;    /* sufficient-decrease constant, e.g. 1e-4         */
+    double armijo_beta;     /* step reduction factor, e.g. 0.5                 */
+    int64_t max_iter;
+} psl_nnls_opts;
+
+typedef struct {
+    int64_t iters;
+    double f;               /* ||A x - b||^2 at the returned x */
+    double pg_norm;
+} psl_nnls_report;
+
+/* Solves min_{x >= 0} ||A x - b||^2 by gradient projection
+ * x+ = max(0, x - s grad F(x)) with Armijo's rule; the trial step is the
+ * Barzilai-Borwein step of the previous iteration.  A: host FP64 m x n,
+ * column-major; b: host m; x: host n, in = start (e.g. all ones, the original
+ * PSR weights), out = solution.  The products with A and A^T run as FP64
+ * kernels on the current device.  Synchronous.  Returns PSL_ENOTCONV (with x
+ * and report filled) when max_iter is reached. */
+int commission_nnls(const double* A, int64_t m, int64_t n, const double* b, double* x,
+                    const psl_nnls_opts* opts, psl_nnls_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSL_H */

@@ -524,6 +524,7 @@ typedef struct {
     double alpha, beta;       /* local direction angles (scatter, electron) */
     double jaw_margin;        /* distance of the back-traced point to the nearest jaw edge */
     double box_margin;        /* chord length of the line through the phantom box */
+    double ring_margin;       /* distance of r to the nearest ring edge (scatter) */
     double x, y, z, u, v, w;  /* patient frame, at the phantom entry */
 } or_sample_rec;
 
@@ -597,6 +598,7 @@ static void sample_history(const or_sampler* S, uint64_t seed, uint64_t g, or_sa
             /* Eq. (6): PSR index from the sampled radius, component from the
              * cumulative table (decision taken in FP32), then one Gaussian */
             int ring = (int)floor(r / m->ring_dr);
+            rec->ring_margin = fmin(r - ring * m->ring_dr, (ring + 1) * m->ring_dr - r);
             if (ring > m->n_ring - 1) ring = m->n_ring - 1;
             size_t base = ((size_t)rec->ebin * m->n_ring + ring) * m->n_comp;
             int k = 0;

@@ -86,7 +86,7 @@ SAMPLE_REC = np.dtype([("j", "i4"), ("k", "i4"), ("status", "i4"), ("stype", "i4
                        ("tag", "i4"), ("pad", "i4"), ("xb", "f8"), ("yb", "f8"),
                        ("ub", "f8"), ("vb", "f8"), ("wb", "f8"), ("e", "f8"),
                        ("xs", "f8"), ("ys", "f8"), ("alpha", "f8"), ("beta", "f8"),
-                       ("jaw_margin", "f8"), ("box_margin", "f8"), ("x", "f8"), ("y", "f8"),
+                       ("jaw_margin", "f8"), ("box_margin", "f8"), ("ring_margin", "f8"), ("x", "f8"), ("y", "f8"),
                        ("z", "f8"), ("u", "f8"), ("v", "f8"), ("w", "f8")])
 
 LEDGER = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")

@@ -1,0 +1,755 @@
+// Transport and tally kernels.
+//
+// Photons: Woodcock (delta) tracking with the majorant mu_max(E) = rho_max n_e
+// sigma_KN(E); a tentative collision is real with probability rho_v / rho_max;
+// Compton scattering angle by Kahn's rejection method for the Klein-Nishina
+// distribution; Compton electrons at or above the electron cut-off are pushed
+// onto an electron stack, below it deposited on the spot.
+// Electrons: continuous slowing down along straight steps that end at the
+// exit face of the current voxel or after losing a fraction of the energy
+// (T' = R^-1(R(T) - rho s)); Highland Gaussian multiple-scattering deflection
+// after each step.  Deposits accumulate per lane while the electron stays in
+// one voxel and are flushed with one FP32 atomic when it leaves.
+// Between the two, electrons are grouped by energy band (counting sort) so
+// that the waves of the electron kernel hold particles of similar range.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "device.hpp"
+
+namespace psl {
+namespace {
+
+constexpr float kMe = 0.51099895f;
+constexpr float kX0Water = 36.08f;      // g/cm^2
+constexpr int kMaxElectronSteps = 100000;
+constexpr int kMaxPhotonSteps = 1000000;   // safety bounds: never reached by valid input
+constexpr int kMaxKahnTrials = 1000;
+constexpr int kBands = 32;              // electron energy bands for the counting sort
+constexpr int kBlock = 256;
+
+struct Stack {
+    float *x, *y, *z, *u, *v, *w, *e;
+    uint64_t* hid;
+    uint32_t* tag;
+    uint32_t* count;
+    uint32_t capacity;
+};
+
+Stack to_stack(const psl_particles* p) {
+    return Stack{p->x, p->y, p->z, p->u, p->v, p->w, p->e, p->hid, p->tag, p->count, p->capacity};
+}
+
+struct TransportArgs {
+    Stack in;
+    Stack el;                  // electron stack (photon kernel output / electron kernel input)
+    const uint32_t* perm;      // electron order (nullable: identity)
+    PhantomDev ph;
+    PhysicsDev phys;
+    TallyDev tally;
+    float e_cut_e, e_cut_g, step_frac;
+    int ms;
+    uint32_t seed_lo, seed_hi;
+};
+
+// ---- table lookups (linear interpolation) ---------------------------------
+__device__ __forceinline__ float lerp_tab(const float* tab, int n, float x) {
+    x = fminf(fmaxf(x, 0.f), float(n - 1) - 1e-3f);
+    const int i = int(x);
+    const float f = x - float(i);
+    return fmaf(f, tab[i + 1] - tab[i], tab[i]);
+}
+
+__device__ __forceinline__ float kn_mu(const PhysicsDev& P, const float* tab, float e) {
+    return lerp_tab(tab, KN_TAB_N, (__logf(e) - P.kn_lne0) * P.kn_inv_dlne);
+}
+
+__device__ __forceinline__ float csda_range(const PhysicsDev& P, const float* tab, float t) {
+    if (!(t > P.t_cut)) return 0.f;
+    return lerp_tab(tab, RNG_TAB_N, (__logf(t) - P.rng_lnt0) * P.rng_inv_dlnt);
+}
+
+__device__ __forceinline__ float csda_energy(const PhysicsDev& P, const float* tab, float r) {
+    if (!(r > 0.f)) return P.t_cut;
+    return lerp_tab(tab, INV_TAB_N, (__logf(r + P.r_off) - P.inv_u0) * P.inv_inv_du);
+}
+
+// ---- geometry -------------------------------------------------------------
+__device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t, float cphi,
+                                       float sphi) {
+    const float sin_t = sqrtf(fmaxf(0.f, 1.f - cos_t * cos_t));
+    float nu, nv, nw;
+    if (fabsf(w) < 0.99999f) {
+        const float t = sqrtf(1.f - w * w);
+        const float it = 1.f / t;
+        nu = u * cos_t + sin_t * (u * w * cphi - v * sphi) * it;
+        nv = v * cos_t + sin_t * (v * w * cphi + u * sphi) * it;
+        nw = w * cos_t - sin_t * cphi * t;
+    } else {
+        nu = sin_t * cphi;
+        nv = sin_t * sphi;
+        nw = (w > 0.f ? 1.f : -1.f) * cos_t;
+    }
+    const float inv = rsqrtf(nu * nu + nv * nv + nw * nw);
+    u = nu * inv;
+    v = nv * inv;
+    w = nw * inv;
+}
+
+__device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, float e,
+                                        unsigned long long& n_atomic) {
+    if (e == 0.f) return;
+    int c = v;
+    if (T.imap) {
+        const int row = T.imap[v];
+        if (row <= 0) return;
+        const int col = int(tag & 0xFFFFu);
+        if (col >= T.n_cols) {
+            // particle tag from a plan with more columns than this tally
+            atomicAdd(T.counters + C_OVERFLOW, 1ull);
+            return;
+        }
+        c = (row - 1) * T.n_cols + col;
+    }
+    atomicAdd(T.grid + c, e);
+    ++n_atomic;
+}
+
+// ---- photon kernel --------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
+    __shared__ float s_kn[KN_TAB_N];
+    for (int i = threadIdx.x; i < KN_TAB_N; i += blockDim.x) s_kn[i] = a.phys.kn[i];
+    __syncthreads();
+
+    const PhantomDev& G = a.ph;
+    const uint32_t n = min(*a.in.count, a.in.capacity);
+    double esc_g = 0.0, dep = 0.0;
+    unsigned long long c_wc = 0, c_real = 0, c_push = 0, c_local = 0, c_atom = 0, c_unc = 0,
+                       c_kahn = 0, c_over = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float px = a.in.x[i], py = a.in.y[i], pz = a.in.z[i];
+        float du = a.in.u[i], dv = a.in.v[i], dw = a.in.w[i];
+        float e = a.in.e[i];
+        const uint64_t g = a.in.hid[i];
+        const uint32_t tag = a.in.tag[i] & 0xFFFFu;
+        dev::Stream st;
+        st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, 0);
+        uint32_t n_push = 0;
+        bool collided = false;
+        for (int step = 0;; ++step) {
+            if (!(e >= a.e_cut_g) || step >= kMaxPhotonSteps) {
+                // below the cut-off on entry, or the safety bound: absorb here
+                const int vx = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
+                const int vy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
+                const int vz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
+                const float ee = isfinite(e) ? e : 0.f;
+                deposit(a.tally, (vz * G.ny + vy) * G.nx + vx, tag, ee, c_atom);
+                dep += ee;
+                c_over += step >= kMaxPhotonSteps ? 1ull : 0ull;
+                break;
+            }
+            const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
+            const float s = -logf(1.f - st.next()) / mu;
+            px = fmaf(s, du, px);
+            py = fmaf(s, dv, py);
+            pz = fmaf(s, dw, pz);
+            const float fx = floorf((px - G.origin[0]) * G.inv_vox[0]);
+            const float fy = floorf((py - G.origin[1]) * G.inv_vox[1]);
+            const float fz = floorf((pz - G.origin[2]) * G.inv_vox[2]);
+            if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) && fz >= 0.f &&
+                  fz < float(G.nz))) {
+                esc_g += e;
+                c_unc += collided ? 0ull : 1ull;
+                break;
+            }
+            const int v = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
+            ++c_wc;
+            const float ur = st.next();
+            if (!(ur < G.dens[v] * G.inv_rho_max)) continue;   // virtual collision
+            collided = true;
+            ++c_real;
+            // Kahn's method for x = E/E' in [1, 1 + 2k]
+            const float k = e * (1.f / kMe);
+            const float k2 = 2.f * k;
+            float x = 1.f;
+            for (int trial = 0; trial < kMaxKahnTrials; ++trial) {
+                const float r1 = st.next(), r2 = st.next(), r3 = st.next();
+                ++c_kahn;
+                if (r1 <= (1.f + k2) / (9.f + k2)) {
+                    x = fmaf(k2, r2, 1.f);
+                    if (r3 <= 4.f * (1.f / x - 1.f / (x * x))) break;
+                } else {
+                    x = (1.f + k2) / fmaf(k2, r2, 1.f);
+                    const float c = 1.f - (x - 1.f) / k;
+                    if (r3 <= 0.5f * (c * c + 1.f / x)) break;
+                }
+            }
+            const float cos_t = 1.f - (x - 1.f) / k;
+            float sphi, cphi;
+            sincospif(2.f * st.next(), &sphi, &cphi);
+            const float e1 = e / x;
+            const float te = e - e1;
+            float nu = du, nv = dv, nw = dw;
+            rotate(nu, nv, nw, cos_t, cphi, sphi);
+            if (te >= a.e_cut_e) {
+                // electron direction from momentum conservation: p_e = E d - E' d'
+                float qx = e * du - e1 * nu, qy = e * dv - e1 * nv, qz = e * dw - e1 * nw;
+                const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
+                ++n_push;
+                ++c_push;
+                const uint32_t slot = dev::wave_reserve(true, a.el.count);
+                if (slot < a.el.capacity) {
+                    a.el.x[slot] = px; a.el.y[slot] = py; a.el.z[slot] = pz;
+                    a.el.u[slot] = qx * inv; a.el.v[slot] = qy * inv; a.el.w[slot] = qz * inv;
+                    a.el.e[slot] = te;
+                    a.el.hid[slot] = g;
+                    a.el.tag[slot] = tag | (n_push << 16);
+                } else {
+                    ++c_over;
+                }
+            } else {
+                deposit(a.tally, v, tag, te, c_atom);
+                dep += te;
+                ++c_local;
+            }
+            e = e1;
+            du = nu; dv = nv; dw = nw;
+            if (e < a.e_cut_g) {
+                deposit(a.tally, v, tag, e, c_atom);
+                dep += e;
+                break;
+            }
+        }
+    }
+    const double led[2] = {esc_g, dep};
+    dev::block_add_u64(a.tally.counters + C_WC_STEPS, c_wc);
+    dev::block_add_u64(a.tally.counters + C_REAL, c_real);
+    dev::block_add_u64(a.tally.counters + C_E_PUSHED, c_push);
+    dev::block_add_u64(a.tally.counters + C_E_LOCAL, c_local);
+    dev::block_add_u64(a.tally.counters + C_DEPOSITS, c_atom);
+    dev::block_add_u64(a.tally.counters + C_ESC_UNCOLLIDED, c_unc);
+    dev::block_add_u64(a.tally.counters + C_KAHN_TRIALS, c_kahn);
+    dev::block_add_u64(a.tally.counters + C_OVERFLOW, c_over);
+    double ls[1] = {led[0]};
+    dev::block_add(a.tally.ledger + L_ESC_G, ls);
+    ls[0] = led[1];
+    dev::block_add(a.tally.ledger + L_DEP, ls);
+}
+
+// ---- electron energy bands (counting sort) --------------------------------
+// log-spaced bands between the electron cut-off and the table top
+__device__ __forceinline__ int band_of(float t, float lt0, float inv_w) {
+    const int b = int((__logf(t) - lt0) * inv_w);
+    return min(max(b, 0), kBands - 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_band_count(const float* e, const uint32_t* count,
+                                                      uint32_t cap, uint32_t* hist, float lt0,
+                                                      float inv_w) {
+    __shared__ uint32_t s[kBands];
+    if (threadIdx.x < kBands) s[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&s[band_of(e[i], lt0, inv_w)], 1u);
+    __syncthreads();
+    if (threadIdx.x < kBands && s[threadIdx.x]) atomicAdd(hist + threadIdx.x, s[threadIdx.x]);
+}
+
+// hist[kBands] -> exclusive offsets in hist[kBands..2 kBands), highest band first
+__global__ void k_band_scan(uint32_t* hist) {
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = kBands - 1; b >= 0; --b) {
+            hist[kBands + b] = run;
+            run += hist[b];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_band_scatter(const float* e, const uint32_t* count,
+                                                        uint32_t cap, uint32_t* offsets,
+                                                        uint32_t* perm, float lt0, float inv_w) {
+    const uint32_t n = min(*count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t slot = atomicAdd(offsets + band_of(e[i], lt0, inv_w), 1u);
+        perm[slot] = i;
+    }
+}
+
+// ---- electron kernel ------------------------------------------------------
+// Distance along (dx, dy, dz) from p to the exit face of voxel i on one axis.
+__device__ __forceinline__ void face_distance(float p, float d, int i, float o, float vx, int ax,
+                                              float& sb, int& axis) {
+    if (d != 0.f) {
+        const float face = o + float(i + (d > 0.f ? 1 : 0)) * vx;
+        const float t = (face - p) / d;
+        if (t < sb) {
+            sb = t;
+            axis = ax;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
+    __shared__ float s_rng[RNG_TAB_N];
+    __shared__ float s_inv[INV_TAB_N];
+    for (int i = threadIdx.x; i < RNG_TAB_N; i += blockDim.x) s_rng[i] = a.phys.rng[i];
+    for (int i = threadIdx.x; i < INV_TAB_N; i += blockDim.x) s_inv[i] = a.phys.inv[i];
+    __syncthreads();
+
+    const PhantomDev& G = a.ph;
+    const PhysicsDev& P = a.phys;
+    const float tcut = a.e_cut_e;
+    const uint32_t n = min(*s.count, s.capacity);
+    double esc_e = 0.0, dep = 0.0, path = 0.0;
+    unsigned long long c_steps = 0, c_atom = 0, c_bnd = 0, c_guard = 0, c_local = 0;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const uint32_t i = a.perm ? a.perm[q] : q;
+        float px = s.x[i], py = s.y[i], pz = s.z[i];
+        float dx = s.u[i], dy = s.v[i], dz = s.w[i];
+        float t = s.e[i];
+        const uint64_t g = s.hid[i];
+        const uint32_t tg = s.tag[i];
+        const uint32_t tag = tg & 0xFFFFu, sub = (tg >> 16) & 0xFFu;
+        int ix = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
+        int iy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
+        int iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
+        int cur_v = (iz * G.ny + iy) * G.nx + ix;
+        if (t < tcut) {
+            deposit(a.tally, cur_v, tag, t, c_atom);
+            dep += t;
+            ++c_local;
+            continue;
+        }
+        dev::Stream st;
+        st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, sub);
+        int pend_v = cur_v;
+        float pend_e = 0.f;
+        for (int step = 0;; ++step) {
+            if (step >= kMaxElectronSteps) {
+                pend_e += t;
+                dep += t;
+                ++c_guard;
+                break;
+            }
+            const float rho = G.dens[cur_v];
+            float sb = INFINITY;
+            int axis = 0;
+            face_distance(px, dx, ix, G.origin[0], G.vox[0], 0, sb, axis);
+            face_distance(py, dy, iy, G.origin[1], G.vox[1], 1, sb, axis);
+            face_distance(pz, dz, iz, G.origin[2], G.vox[2], 2, sb, axis);
+            sb = fmaxf(sb, 0.f);
+            // energy-loss limited step
+            const float r0 = csda_range(P, s_rng, t);
+            const float ef = t * (1.f - a.step_frac);
+            const bool fin = !(ef > tcut);
+            float sf = INFINITY;
+            if (rho > 0.f) sf = (fin ? r0 : r0 - csda_range(P, s_rng, ef)) / rho;
+            ++c_steps;
+            const bool boundary = !(sf <= sb);
+            const float sl = boundary ? sb : sf;
+            if (!boundary && fin) {
+                // the residual range ends inside this voxel
+                path += sl;
+                pend_e += t;
+                dep += t;
+                break;
+            }
+            const float tn = csda_energy(P, s_inv, r0 - rho * sl);
+            const float de = fmaxf(t - tn, 0.f);
+            pend_e += de;
+            dep += de;
+            px = fmaf(sl, dx, px);
+            py = fmaf(sl, dy, py);
+            pz = fmaf(sl, dz, pz);
+            path += sl;
+            const float t_old = t;
+            t -= de;
+            if (boundary) {
+                ++c_bnd;
+                bool out;
+                if (axis == 0) {
+                    ix += dx > 0.f ? 1 : -1;
+                    out = ix < 0 || ix >= G.nx;
+                } else if (axis == 1) {
+                    iy += dy > 0.f ? 1 : -1;
+                    out = iy < 0 || iy >= G.ny;
+                } else {
+                    iz += dz > 0.f ? 1 : -1;
+                    out = iz < 0 || iz >= G.nz;
+                }
+                if (out) {
+                    esc_e += t;
+                    break;
+                }
+                cur_v = (iz * G.ny + iy) * G.nx + ix;
+                deposit(a.tally, pend_v, tag, pend_e, c_atom);
+                pend_v = cur_v;
+                pend_e = 0.f;
+            }
+            if (t < tcut) {
+                pend_e += t;
+                dep += t;
+                break;
+            }
+            if (a.ms) {
+                // Highland width (PDG) for the step, beta*c*p at the mid-step energy
+                const float tx = rho * sl * (1.f / kX0Water);
+                const float tm = 0.5f * (t_old + t);
+                const float bcp = tm * (tm + 2.f * kMe) / (tm + kMe);
+                float th0 = 0.f;
+                if (tx > 0.f) th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, logf(tx), 1.f), 0.f);
+                const float u1 = st.next(), u2 = st.next();
+                const float th = fminf(th0 * sqrtf(-2.f * logf(1.f - u1)), 3.14159265358979f);
+                float sphi, cphi;
+                sincospif(2.f * u2, &sphi, &cphi);
+                rotate(dx, dy, dz, cosf(th), cphi, sphi);
+            }
+        }
+        deposit(a.tally, pend_v, tag, pend_e, c_atom);
+    }
+    double l1[1] = {esc_e};
+    dev::block_add(a.tally.ledger + L_ESC_E, l1);
+    l1[0] = dep;
+    dev::block_add(a.tally.ledger + L_DEP, l1);
+    l1[0] = path;
+    dev::block_add(a.tally.ledger + L_EPATH, l1);
+    dev::block_add_u64(a.tally.counters + C_E_STEPS, c_steps);
+    dev::block_add_u64(a.tally.counters + C_DEPOSITS, c_atom);
+    dev::block_add_u64(a.tally.counters + C_E_BOUNDARY, c_bnd);
+    dev::block_add_u64(a.tally.counters + C_GUARD, c_guard);
+    dev::block_add_u64(a.tally.counters + C_E_LOCAL, c_local);
+}
+
+// ---- small utility kernels (no hipMemsetAsync, so graphs replay cleanly) --
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+template <class T>
+__global__ void k_zero(T* p, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = T(0);
+}
+
+__global__ void k_fold(float* grid, double* sum, double* sum2, int64_t n,
+                       unsigned long long* counters) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const double e = grid[i];
+        sum[i] += e;
+        sum2[i] += e * e;
+        grid[i] = 0.f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(counters + C_FOLDS, 1ull);
+}
+
+// dose = k * mean, sigma = k * sqrt(var / R), with k per cell
+__global__ void k_finalize(const double* sum, const double* sum2, int64_t n, int n_cols,
+                           const float* rho_cell, int rho_per_row, const double* col_w,
+                           double scale, const unsigned long long* counters, double* dose,
+                           double* sigma) {
+    const double R = double(counters[C_FOLDS]);
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t row = rho_per_row ? i / n_cols : i;
+        const int col = rho_per_row ? int(i % n_cols) : 0;
+        const double rho = rho_cell[row];
+        const double k = rho > 0.0 ? scale * col_w[col] / rho : 0.0;
+        double mean = 0.0, var = 0.0;
+        if (R > 0) {
+            mean = sum[i] / R;
+            if (R > 1) var = fmax((sum2[i] / R - mean * mean) * R / (R - 1.0), 0.0);
+        }
+        dose[i] = k * mean;
+        sigma[i] = R > 0 ? k * sqrt(var / R) : 0.0;
+    }
+}
+
+__global__ void k_density_scan(const float* dens, int64_t n, unsigned int* max_bits,
+                               unsigned int* bad) {
+    unsigned int m = 0, b = 0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const float r = dens[i];
+        if (!(r >= 0.f) || !isfinite(r)) b = 1;
+        else m = max(m, __float_as_uint(r));
+    }
+    // non-negative floats order like their bit patterns
+    for (int off = 32; off >= 1; off >>= 1) {
+        m = max(m, (unsigned int)__shfl_xor(int(m), off, 64));
+        b |= (unsigned int)__shfl_xor(int(b), off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(max_bits, m);
+        if (b) atomicOr(bad, 1u);
+    }
+}
+
+__global__ void k_row_density(const int32_t* imap, const float* dens, int64_t n, float* row_rho,
+                              int n_rows, unsigned int* bad) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int r = imap[i];
+        if (r > 0) {
+            if (r > n_rows) atomicOr(bad, 1u);
+            else row_rho[r - 1] = dens[i];
+        } else if (r < 0) {
+            atomicOr(bad, 1u);
+        }
+    }
+}
+
+int grid_for(int64_t n, int cap = 4096) {
+    return int(std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, cap)));
+}
+
+}  // namespace
+
+// Launch helpers used by the runtime as well.
+void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
+}
+
+void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
+                      psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
+                      hipStream_t stream, bool sort_electrons) {
+    psl_phantom* ph = const_cast<psl_phantom*>(phc);
+    TransportArgs a{};
+    a.in = to_stack(in);
+    a.el = to_stack(el);
+    a.perm = nullptr;
+    a.ph = ph->g;
+    a.phys = ph->phys;
+    a.tally = tally->dev();
+    a.e_cut_e = prm->e_cut_electron;
+    a.e_cut_g = prm->e_cut_photon;
+    a.step_frac = prm->step_frac;
+    a.ms = prm->ms_enable;
+    a.seed_lo = uint32_t(seed);
+    a.seed_hi = uint32_t(seed >> 32);
+    Stack estack = a.el;
+    if (in->ptype == 0) {
+        launch_zero_u32(el->count, 1, stream);
+        hipLaunchKernelGGL(k_photon, dim3(grid_for(in->capacity, 2048)), dim3(kBlock), 0, stream, a);
+        PSL_HIP(hipGetLastError());
+    } else {
+        estack = a.in;
+    }
+    const int eg = grid_for(estack.capacity, 2048);
+    if (sort_electrons) {
+        uint32_t* hist = tally->bands.as<uint32_t>();
+        uint32_t* perm = tally->perm.as<uint32_t>();
+        PSL_CHECK(tally->perm.bytes >= size_t(estack.capacity) * 4, "electron order buffer too small");
+        launch_zero_u32(hist, 2 * kBands, stream);
+        const float lt0 = std::log(ph->phys.t_cut);
+        const float inv_w = float(kBands) / (std::log(ph->phys.t_max) - lt0);
+        hipLaunchKernelGGL(k_band_count, dim3(eg), dim3(kBlock), 0, stream, estack.e, estack.count,
+                           estack.capacity, hist, lt0, inv_w);
+        hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(64), 0, stream, hist);
+        hipLaunchKernelGGL(k_band_scatter, dim3(eg), dim3(kBlock), 0, stream, estack.e,
+                           estack.count, estack.capacity, hist + kBands, perm, lt0, inv_w);
+        a.perm = perm;
+    }
+    hipLaunchKernelGGL(k_electron, dim3(eg), dim3(kBlock), 0, stream, a, estack);
+    PSL_HIP(hipGetLastError());
+}
+
+void launch_fold(psl_tally* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold, dim3(grid_for(t->cells)), dim3(kBlock), 0, s, t->grid.as<float>(),
+                       t->sum.as<double>(), t->sum2.as<double>(), t->cells, t->dev().counters);
+    PSL_HIP(hipGetLastError());
+}
+
+void ensure_perm(psl_tally* t, uint32_t capacity) {
+    if (t->perm.bytes < size_t(capacity) * 4) t->perm.alloc(size_t(capacity) * 4);
+}
+
+}  // namespace psl
+
+using namespace psl;
+
+extern "C" int psl_phantom_create(const float* density_dev, int32_t nx, int32_t ny, int32_t nz,
+                                  const double vox[3], const double origin[3], psl_phantom** out) {
+    return guarded([&] {
+        PSL_CHECK(density_dev && vox && origin && out, "psl_phantom_create: null argument");
+        PSL_CHECK(nx >= 1 && ny >= 1 && nz >= 1, "phantom dimensions must be >= 1");
+        PSL_CHECK(int64_t(nx) * ny * nz < (int64_t(1) << 31), "phantom has too many voxels");
+        for (int k = 0; k < 3; ++k) PSL_CHECK(vox[k] > 0 && std::isfinite(origin[k]), "bad voxel size / origin");
+        auto ph = std::make_unique<psl_phantom>();
+        PSL_HIP(hipGetDevice(&ph->device));
+        PhantomDev& g = ph->g;
+        g.dens = density_dev;
+        g.nx = nx;
+        g.ny = ny;
+        g.nz = nz;
+        const int n[3] = {nx, ny, nz};
+        for (int k = 0; k < 3; ++k) {
+            g.vox[k] = float(vox[k]);
+            g.inv_vox[k] = float(1.0 / vox[k]);
+            g.origin[k] = float(origin[k]);
+            g.hi[k] = float(origin[k] + n[k] * vox[k]);
+        }
+        DevBuf scratch;
+        scratch.alloc(8);
+        unsigned int* w = scratch.as<unsigned int>();
+        const int64_t nv = int64_t(nx) * ny * nz;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, w, 2);
+        hipLaunchKernelGGL(k_density_scan, dim3(grid_for(nv, 1024)), dim3(kBlock), 0, nullptr,
+                           density_dev, nv, w, w + 1);
+        PSL_HIP(hipGetLastError());
+        unsigned int hw[2];
+        PSL_HIP(hipMemcpy(hw, w, 8, hipMemcpyDeviceToHost));
+        PSL_CHECK(hw[1] == 0, "densities must be finite and >= 0");
+        float rmax;
+        std::memcpy(&rmax, &hw[0], 4);
+        PSL_CHECK(rmax > 0.f, "phantom has no matter (max density 0)");
+        g.rho_max = rmax;
+        g.inv_rho_max = 1.f / rmax;
+        *out = ph.release();
+    });
+}
+
+extern "C" void psl_phantom_free(psl_phantom* p) { delete p; }
+
+extern "C" int psl_tally_create(const psl_phantom* ph, const int32_t* imap, int32_t n_rows,
+                                int32_t n_cols, psl_tally** out) {
+    return guarded([&] {
+        PSL_CHECK(ph && out, "psl_tally_create: null argument");
+        auto t = std::make_unique<psl_tally>();
+        t->phantom = ph;
+        const int64_t nv = int64_t(ph->g.nx) * ph->g.ny * ph->g.nz;
+        if (imap) {
+            PSL_CHECK(n_rows >= 1 && n_cols >= 1 && n_cols <= 65536, "bad n_rows / n_cols");
+            t->imap = imap;
+            t->n_rows = n_rows;
+            t->n_cols = n_cols;
+            t->cells = int64_t(n_rows) * n_cols;
+        } else {
+            t->n_rows = 0;
+            t->n_cols = 1;
+            t->cells = nv;
+        }
+        t->grid.alloc(size_t(t->cells) * 4);
+        t->sum.alloc(size_t(t->cells) * 8);
+        t->sum2.alloc(size_t(t->cells) * 8);
+        t->stats.alloc(size_t(L_N) * 8 + size_t(C_N) * 8);
+        t->bands.alloc(2 * kBands * 4);
+        t->col_w.alloc(size_t(t->n_cols) * 8);
+        if (imap) {
+            t->row_rho.alloc(size_t(n_rows) * 4);
+            DevBuf flag;
+            flag.alloc(4);
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, flag.as<uint32_t>(), 1);
+            hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(n_rows)), dim3(kBlock), 0, nullptr,
+                               t->row_rho.as<float>(), int64_t(n_rows));
+            hipLaunchKernelGGL(k_row_density, dim3(grid_for(nv, 1024)), dim3(kBlock), 0, nullptr,
+                               imap, ph->g.dens, nv, t->row_rho.as<float>(), n_rows,
+                               flag.as<unsigned int>());
+            unsigned int bad = 0;
+            PSL_HIP(hipMemcpy(&bad, flag.p, 4, hipMemcpyDeviceToHost));
+            PSL_CHECK(bad == 0, "index map entries must be in [0, n_rows]");
+        }
+        psl_tally* raw = t.release();
+        const int rc = tally_dose(raw, PSL_TALLY_RESET, nullptr, nullptr, nullptr, nullptr);
+        PSL_HIP(hipDeviceSynchronize());
+        if (rc != PSL_OK) {
+            delete raw;
+            fail(rc, "tally reset failed");
+        }
+        *out = raw;
+    });
+}
+
+extern "C" void psl_tally_free(psl_tally* t) { delete t; }
+
+extern "C" int transport_batch(const psl_phantom* phantom, const psl_particles* in,
+                               psl_particles* electrons, psl_tally* tally,
+                               const psl_transport_params* params, uint64_t seed, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(phantom && in && tally && params, "transport_batch: null argument");
+        PSL_CHECK(tally->phantom == phantom, "tally belongs to another phantom");
+        PSL_CHECK(in->ptype == 0 || in->ptype == 1, "in->ptype must be 0 (photon) or 1 (electron)");
+        PSL_CHECK(in->count && in->x && in->e && in->hid && in->tag, "particle stack has null arrays");
+        PSL_CHECK(params->e_cut_photon > 0.f && params->e_cut_electron > 0.f &&
+                      params->step_frac > 0.f && params->step_frac < 1.f,
+                  "bad transport parameters");
+        if (in->ptype == 0) {
+            PSL_CHECK(electrons && electrons->count && electrons->x && electrons->e,
+                      "photon transport needs an electron stack");
+        }
+        const psl_particles* es = in->ptype == 0 ? electrons : in;
+        ensure_physics(const_cast<psl_phantom*>(phantom), params);
+        ensure_perm(tally, es->capacity);
+        psl_particles dummy = *in;
+        launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, params, seed,
+                         static_cast<hipStream_t>(stream), true);
+    });
+}
+
+extern "C" int tally_dose(psl_tally* t, int32_t ops, const psl_plan* plan, double* dose,
+                          double* sigma, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(t, "tally_dose: null tally");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (ops & PSL_TALLY_RESET) {
+            hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(t->cells)), dim3(kBlock), 0, s,
+                               t->grid.as<float>(), t->cells);
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(t->cells)), dim3(kBlock), 0, s,
+                               t->sum.as<double>(), t->cells);
+            hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(t->cells)), dim3(kBlock), 0, s,
+                               t->sum2.as<double>(), t->cells);
+            hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, s, t->stats.as<double>(),
+                               int64_t(L_N + C_N));
+            PSL_HIP(hipGetLastError());
+        }
+        if (ops & PSL_TALLY_FOLD) launch_fold(t, s);
+        if (ops & PSL_TALLY_FINALIZE) {
+            PSL_CHECK(plan && dose && sigma, "FINALIZE needs a plan and output arrays");
+            PSL_CHECK(plan->n_cols == t->n_cols || (!t->imap && t->n_cols == 1),
+                      "plan has %d tally columns, tally %d", plan->n_cols, t->n_cols);
+            std::vector<double> cw(size_t(t->n_cols));
+            if (t->imap) {
+                cw = plan->col_weight;
+            } else {
+                // a voxel tally holds all columns together: one weight per history
+                cw[0] = plan->col_weight[0];
+                for (double c : plan->col_weight)
+                    PSL_CHECK(c == cw[0], "a voxel tally needs an Eq. (3) plan (equal column weights)");
+            }
+            PSL_HIP(hipMemcpyAsync(t->col_w.p, cw.data(), cw.size() * 8, hipMemcpyHostToDevice, s));
+            const PhantomDev& g = t->phantom->g;
+            const double vol = double(g.vox[0]) * g.vox[1] * g.vox[2];
+            const double scale = 1.602176634e-10 / vol;
+            const float* rho = t->imap ? t->row_rho.as<float>() : g.dens;
+            hipLaunchKernelGGL(k_finalize, dim3(grid_for(t->cells)), dim3(kBlock), 0, s,
+                               t->sum.as<double>(), t->sum2.as<double>(), t->cells, t->n_cols, rho,
+                               t->imap ? 1 : 0, t->col_w.as<double>(), scale, t->dev().counters,
+                               dose, sigma);
+            PSL_HIP(hipGetLastError());
+            PSL_HIP(hipStreamSynchronize(s));   // cw lives on this stack frame
+        }
+    });
+}
+
+extern "C" int psl_tally_stats(psl_tally* t, double* ledger, uint64_t* counters) {
+    int status = PSL_OK;
+    int rc = guarded([&] {
+        PSL_CHECK(t, "psl_tally_stats: null tally");
+        PSL_HIP(hipDeviceSynchronize());
+        std::vector<double> buf(L_N + C_N);
+        PSL_HIP(hipMemcpy(buf.data(), t->stats.p, buf.size() * 8, hipMemcpyDeviceToHost));
+        if (ledger) std::memcpy(ledger, buf.data(), L_N * 8);
+        const uint64_t* c = reinterpret_cast<const uint64_t*>(buf.data() + L_N);
+        if (counters) std::memcpy(counters, c, C_N * 8);
+        if (c[C_OVERFLOW]) {
+            status = PSL_EOVERFLOW;
+            set_last_error("a particle stack overflowed; results are invalid");
+        }
+    });
+    return rc != PSL_OK ? rc : status;
+}

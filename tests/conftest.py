@@ -23,3 +23,18 @@ def orc():
 def wl():
     from paper_1503_01725_amd import workloads
     return workloads
+
+
+@pytest.fixture(scope="session")
+def N():
+    from paper_1503_01725_amd import _native
+    _native.lib()
+    return _native
+
+
+@pytest.fixture(scope="session")
+def eng():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1503_01725_amd import engine
+    return engine

@@ -1,0 +1,129 @@
+"""GPU parity of sample_batch (steps S3-S5) against the oracle, per history.
+
+Tolerance: |gpu - oracle| <= 1e-6 * max(|oracle|, s) with s = 1 cm for
+positions, 1 for direction cosines, 1 MeV for energy.  The phantom entry point
+is the plane point moved a distance t along the direction, so its tolerance
+adds the direction tolerance times |t|.  Integer results (tally
+tag, history id) must be equal.  A status flip is accepted only where the
+oracle puts the particle within 1e-5 cm of a jaw edge, within 1e-4 cm of a
+phantom edge, or (scatter) within 1e-5 cm of a ring edge (where the PSR and so
+the direction parameters change)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _close(a, b, s, rel=1e-6):
+    return np.abs(a - b) <= rel * np.maximum(np.abs(b), s)
+
+
+def _dense_sample(eng, N, plan, phantom, tally, rep, seed, h0, n):
+    import torch
+    st = eng.Particles(n)
+    N.sample_batch(plan.h, phantom.h, rep, h0, n, seed, st.c, N.PSL_SAMPLE_DENSE, tally.h,
+                   eng._stream_ptr())
+    torch.cuda.synchronize()
+    return st.host(n)
+
+
+def _plane_to_entry(ref, beams):
+    """Distance from the plane point (patient frame) to the phantom entry."""
+    t = np.zeros(len(ref))
+    for bi, b in enumerate(beams):
+        sel = ref["beam"] == bi
+        g, c = np.radians(b.gantry_deg), np.radians(b.couch_deg)
+        ry = np.array([[np.cos(g), 0, np.sin(g)], [0, 1, 0], [-np.sin(g), 0, np.cos(g)]])
+        rz = np.array([[np.cos(c), -np.sin(c), 0], [np.sin(c), np.cos(c), 0], [0, 0, 1]])
+        R = rz @ ry
+        pb = np.stack([ref["xb"][sel], ref["yb"][sel], np.zeros(sel.sum())])
+        pp = (R @ pb).T + np.asarray(b.iso)
+        pe = np.stack([ref["x"][sel], ref["y"][sel], ref["z"][sel]], axis=1)
+        t[sel] = np.linalg.norm(pe - pp, axis=1)
+    return t
+
+
+def _check_segment(gpu, ref, stype, beams):
+    ok_flip = (ref["jaw_margin"] < 1e-5) | (np.abs(ref["box_margin"]) < 1e-4)
+    if stype == 1:
+        ok_flip |= ref["ring_margin"] < 1e-5
+    same = gpu["status"] == ref["status"]
+    assert np.all(same | ok_flip), np.flatnonzero(~(same | ok_flip))[:10]
+    assert np.mean(same) > 0.999
+    m = same & ~ok_flip if stype == 1 else same
+    assert np.array_equal(gpu["tag"], ref["tag"].astype(np.uint32))
+    assert _close(gpu["e"], ref["e"], 1.0)[m].all()
+    acc = m & (ref["status"] == 0)
+    rej = m & (ref["status"] != 0)
+    slant = _plane_to_entry(ref, beams)
+    for f in ("x", "y", "z"):
+        good = np.abs(gpu[f] - ref[f]) <= 1e-6 * (np.maximum(np.abs(ref[f]), 1.0) + slant)
+        assert good[acc].all(), (f, np.flatnonzero(acc & ~good)[:5])
+    for f in ("u", "v", "w"):
+        good = _close(gpu[f], ref[f], 1.0)
+        assert good[acc].all(), (f, np.flatnonzero(acc & ~good)[:5])
+    for f, rf, s in (("x", "xb", 1.0), ("y", "yb", 1.0), ("u", "ub", 1.0), ("v", "vb", 1.0),
+                     ("w", "wb", 1.0)):
+        good = _close(gpu[f], ref[rf], s)
+        assert good[rej].all(), (f, np.flatnonzero(rej & ~good)[:5])
+    return acc.sum(), rej.sum()
+
+
+@pytest.mark.parametrize("name,n_hist", [("water60_10x10", 100000), ("hetero256_5beam", 150000)])
+def test_sample_batch_matches_oracle(eng, N, orc, wl, name, n_hist):
+    W = wl.workload(name)
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, n_hist, n_replica=3)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    ref_w, _ = orc.psl_build(W.model)
+    oplan = orc.plan_build(W.model, ref_w, W.beams, n_hist)
+    seed = 0x5EED_1234_ABCD
+    rep = 2
+    nb = plan.set_batching(1 << 30, 24)     # one batch per (beam, sub-source)
+    totals = np.zeros(2)
+    for i in range(nb):
+        b = plan.batch(i)
+        print(f"[sample parity] {name} batch {i} stype {b.stype} h0 {b.h0} n {b.n}", flush=True)
+        gpu = _dense_sample(eng, N, plan, ph, tally, rep, seed, b.h0, b.n)
+        ref = orc.sample(W.model, oplan, W.beams, W.phantom, seed, rep * n_hist + b.h0, b.n)
+        assert np.array_equal(gpu["hid"], rep * n_hist + b.h0 + np.arange(b.n, dtype=np.uint64))
+        totals += _check_segment(gpu, ref, b.stype, W.beams)
+    assert totals[0] > 1000 and totals[1] > 1000
+
+
+def test_sample_compacted_equals_dense(eng, N, wl):
+    import torch
+    W = wl.workload("water60_10x10")
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, 50000)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    b = plan.batch(0)
+    dense = _dense_sample(eng, N, plan, ph, tally, 0, 9, b.h0, b.n)
+    st = eng.Particles(b.n)
+    st.zero_count()
+    N.sample_batch(plan.h, ph.h, 0, b.h0, b.n, 9, st.c, 0, tally.h, eng._stream_ptr())
+    torch.cuda.synchronize()
+    comp = st.host()
+    ok = dense["status"] == 0
+    assert comp["hid"].size == ok.sum()
+    order = np.argsort(comp["hid"])
+    for f in ("x", "y", "z", "u", "v", "w", "e"):
+        assert np.array_equal(comp[f][order], dense[f][ok])
+
+
+def test_sample_rejects_bad_ranges(eng, N, wl):
+    W = wl.workload("water60_10x10")
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, 1000)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    st = eng.Particles(2000)
+    with pytest.raises(N.PslError) as e:
+        N.sample_batch(plan.h, ph.h, 0, 0, 1000, 1, st.c, 0, tally.h, eng._stream_ptr())
+    assert e.value.code == N.PSL_EINVAL      # spans several sub-sources
+    with pytest.raises(N.PslError):
+        N.sample_batch(plan.h, ph.h, 0, 990, 20, 1, st.c, 0, tally.h, eng._stream_ptr())
