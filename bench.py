@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the dose path: histories/s for the synthetic 6 MV-like PSR
+source, one 10x10 cm field, 128^3 water at 0.25 cm, 1e8 histories
+(10 replicas x 1e7), FP32 transport with FP64 dose and variance accumulation.
+
+One step = reset the tally, run every batch of every replica through the
+native runtime (sampling -> photon transport -> electron energy sort ->
+electron transport, one FP64 fold per replica; all launches replayed from one
+captured hipGraph), and finalise dose and standard error.  Inputs (model
+tables, plan, phantom) are resident in device memory before timing starts.
+
+Prints one JSON line (see the design doc for the roofline and CPU-baseline
+definitions).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "histories/s (6MV-like 10×10 field, 128³ water)"
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work per unit ("Roofline"): FP32 operations the
+# method performs per electron step / per Woodcock step / per real Compton
+# interaction (an FMA counts 2, a transcendental 1), and HBM bytes per unit.
+FLOP_PER_E_STEP = 104.0
+FLOP_PER_WC_STEP = 24.0
+FLOP_PER_COMPTON = 96.0
+BYTES_PER_E_STEP = 4.0 + 8.0          # density gather + share of the deposit RMW
+BYTES_PER_ELECTRON = 36.0 + 4.0       # SoA record + sort order
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(W, n_hist_rep, seconds):
+    """The oracle on a bounded, evenly strided sample of replica 0's histories."""
+    import numpy as np
+    from oracle import oracle as orc
+    ref_w, _ = orc.psl_build(W.model)
+    op = orc.plan_build(W.model, ref_w, W.beams, n_hist_rep)
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                  64)
+    # calibrate on a small strided sample, then size the main one to ~seconds
+    n_cal = 20000
+    t0 = time.perf_counter()
+    orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep, stride=n_hist_rep // n_cal,
+            n_threads=threads)
+    rate0 = n_cal / (time.perf_counter() - t0)
+    n = int(max(n_cal, min(rate0 * seconds, n_hist_rep)))
+    stride = max(1, n_hist_rep // n)
+    n = (n_hist_rep + stride - 1) // stride
+    t0 = time.perf_counter()
+    _, _, led, cnt = orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep, stride=stride,
+                             n_threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": cnt["hist"] / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{cnt['hist']} histories (every {stride}th of replica 0 of the same plan), "
+                      f"{dt:.1f} s on {threads} threads, FP64 C oracle -O2"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water128_10")
+    ap.add_argument("--max-batch", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--band-width", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--sort", default="auto", choices=("auto", "0", "1"),
+                    help="group electrons by energy band before transport")
+    ap.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1503_01725_amd import _native as N
+    from paper_1503_01725_amd import engine as eng
+    from paper_1503_01725_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    W = wl.workload(args.workload)
+    n_rep = W.n_replica
+    n_hist_rep = W.n_hist // n_rep
+    seed = W.seed
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, n_hist_rep, n_replica=n_rep)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    prm = eng.transport_params(W.e_cut_electron, W.e_cut_photon)
+
+    tune = None
+    srt = 1
+    if args.max_batch and args.band_width:
+        mb, bw = args.max_batch, args.band_width
+    else:
+        log("[bench] autotuning batch size and energy-band width on one replica")
+        cands_m = [args.max_batch] if args.max_batch else [131072, 262144, 524288, 1048576]
+        cands_w = [args.band_width] if args.band_width else [1, 3, 24]
+        best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w)
+        mb, bw, srt = int(best.max_batch), int(best.band_width), int(best.sort_electrons)
+        tune = {"max_batch": cands_m, "band_width": cands_w, "sort_electrons": [0, 1],
+                "ms_per_replica": ms.tolist()}
+        log(f"[bench] autotune -> max_batch {mb} band_width {bw} sort {srt}")
+    if args.sort in ("0", "1"):
+        srt = int(args.sort)
+    # the timed region launches eagerly with a HIP event pair around every
+    # kernel (events inside a captured graph carry no timestamps); the same
+    # steps replayed from a captured hipGraph are timed separately below
+    opts = eng.run_opts(mb, bw, use_graph=args.no_timing and not args.no_graph,
+                        sort_electrons=bool(srt), timing=not args.no_timing, seed=seed)
+    dose = torch.zeros(tally.cells, dtype=torch.float64, device="cuda")
+    sig = torch.zeros_like(dose)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tally.op(N.PSL_TALLY_RESET)
+        eng.run_plan(plan, ph, tally, prm, opts)
+        N.tally_dose(tally.h, N.PSL_TALLY_FINALIZE, plan.h, dose.data_ptr(), sig.data_ptr(),
+                     int(stream.cuda_stream))
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] {args.steps} timed steps in {elapsed:.3f} s")
+    timing = N.psl_run_get_timing(tally.h) if not args.no_timing else None
+    led, cnt = tally.stats()
+    graph_replay = None
+    if not args.no_timing and not args.no_graph:
+        opts = eng.run_opts(mb, bw, use_graph=True, sort_electrons=bool(srt), timing=False,
+                            seed=seed)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        g_el = time.perf_counter() - t0
+        graph_replay = {"value": n_hist_rep * n_rep * args.steps / g_el,
+                        "ms_per_step": 1000.0 * g_el / args.steps}
+        log(f"[bench] graph replay: {args.steps} steps in {g_el:.3f} s")
+    hist_per_step = n_hist_rep * n_rep
+    value = hist_per_step * args.steps / elapsed
+
+    out = {"metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "histories": hist_per_step,
+                      "replicas": n_rep, "phantom": "128^3 water, 0.25 cm voxels",
+                      "field": "10x10 cm, SSD 100", "max_batch": mb, "band_width": bw,
+                      "sort_electrons": srt,
+                      "launch": "eager+events" if not args.no_timing else
+                      ("graph" if not args.no_graph else "eager"), "autotune": tune}}
+    if graph_replay:
+        out["graph_replay"] = graph_replay
+    if timing:
+        # roofline of the dominant kernel over the last timed step (counters
+        # cover the same step: the tally is reset at the start of each step)
+        phase = max(("photon", "electron", "sample"), key=lambda p: timing[p][0])
+        ms, launches = timing[phase]
+        avg_s = ms / launches / 1e3
+        if phase == "electron":
+            flop = FLOP_PER_E_STEP * cnt["e_steps"] / launches
+            bytes_ = (BYTES_PER_E_STEP * cnt["e_steps"]
+                      + BYTES_PER_ELECTRON * (cnt["e_pushed"] + cnt["entered"] * 0.01)) / launches
+        elif phase == "photon":
+            flop = (FLOP_PER_WC_STEP * cnt["wc_steps"] + FLOP_PER_COMPTON * cnt["real"]) / launches
+            bytes_ = (40.0 * cnt["entered"] + 4.0 * cnt["wc_steps"] + 40.0 * cnt["e_pushed"]) / launches
+        else:
+            flop = 150.0 * cnt["hist"] / launches
+            bytes_ = 40.0 * cnt["entered"] / launches
+        achieved = flop / avg_s / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": f"k_{phase}", "achieved": achieved,
+                           "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                           "avg_launch_ms": ms / launches, "launches_per_step": launches,
+                           "hbm_algorithmic_GBs": bytes_ / avg_s / 1e9,
+                           "hbm_frac": bytes_ / avg_s / 1e9 / PEAK_HBM_GBS}
+        out["phase_ms_per_step"] = {p: round(v[0], 3) for p, v in timing.items()}
+    out["counters_per_step"] = {k: int(v) for k, v in cnt.items()}
+    out["ledger_closure"] = (led["src"] - sum(led[k] for k in ("jaw", "missed", "invalid", "esc_g",
+                                                                "esc_e", "dep"))) / led["src"]
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(W, n_hist_rep, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -190,7 +190,9 @@ typedef struct {
 
 enum {
     PSL_SAMPLE_DENSE = 1    /* write history h0+i at slot i with its status
-                               (every history, also rejected ones) instead of
+                               (every history, also rejected ones, whose slot
+                               holds the beam-frame plane position and
+                               direction) and set *count = n, instead of
                                compacting accepted particles                */
 };
 
@@ -242,10 +244,13 @@ void psl_tally_free(psl_tally* tally);
 
 /* Transports every particle of `in` (photons or electrons, per in->ptype) to
  * completion and adds the deposits of this replica to the tally's FP32 array.
- * Electrons set in motion by photons go through `electrons`, a caller stack
- * whose capacity must cover in->capacity * floor(e_max / e_cut_electron)
- * (each push costs the photon at least e_cut_electron); it is grouped into
- * energy bands before electron transport.  Random numbers: Philox4x32-10 keyed
+ * Entries whose status bits are non-zero (dense sampling output of rejected
+ * histories) are skipped.  Electrons set in motion by photons go through
+ * `electrons`, a caller stack whose capacity must cover
+ * in->capacity * (floor(e_max / e_cut_electron) + 1): each push costs the
+ * photon at least e_cut_electron, and the stack is filled in chunks of 64 per
+ * wavefront whose unused ends stay in it as empty (skipped) entries.  The
+ * electron stack is grouped into energy bands before electron transport.  Random numbers: Philox4x32-10 keyed
  * by `seed`, counter (block, 2<<16 | sub, g_lo, g_hi), sub 0 for the source
  * particle and 1+n for the electron of its n-th push. */
 int transport_batch(const psl_phantom* phantom, const psl_particles* in,
@@ -277,6 +282,51 @@ int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose
  * Returns PSL_EOVERFLOW if a stack overflowed since the last RESET.  Either
  * output may be NULL. */
 int psl_tally_stats(psl_tally* tally, double* ledger, uint64_t* counters);
+
+/* ------------------------------------------------------------------------
+ * Batched runtime (Sec. 2.1.3: the sampling and transport kernels are iterated
+ * over batches of one particle type; Sec. 2.2.2: all fields and basis doses in
+ * one run)
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t max_batch;      /* histories per batch (M), >= 64, e.g. 131072        */
+    int32_t band_width;      /* energy bins per band, >= 1                          */
+    int32_t use_graph;       /* 1: capture every launch of every replica once in a
+                                hipGraph and replay it (cached while the plan,
+                                phantom, options and parameters stay the same)     */
+    int32_t sort_electrons;  /* 1: group electrons by energy band before transport */
+    int32_t timing;          /* 1: launch eagerly (no graph) with a HIP event pair
+                                around every kernel, read by psl_run_get_timing     */
+    uint64_t seed;           /* Philox key                                          */
+} psl_run_opts;
+
+/* Runs every batch of every replica of `plan` -- sample_batch, transport_batch
+ * and one tally FOLD per replica, with replica r using history ids
+ * g = r * N + h -- on `stream`.  Particle stacks live in the tally's workspace
+ * (allocated on first use; the electron stack holds max_batch *
+ * floor(e_max / e_cut_electron) entries, so it cannot overflow).  The tally is
+ * not reset.  Asynchronous. */
+int psl_run(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
+            const psl_transport_params* params, const psl_run_opts* opts, void* stream);
+
+/* Kernel time of the last psl_run with timing = 1, summed per phase
+ * (0 sampling, 1 photon transport, 2 electron energy sort, 3 electron
+ * transport, 4 fold), and the number of launches of each.  Synchronises. */
+typedef struct {
+    double ms[5];
+    uint64_t launches[5];
+} psl_run_timing;
+int psl_run_get_timing(psl_tally* tally, psl_run_timing* out);
+
+/* Autotuner: times one replica (`replica`) of the plan for every candidate
+ * (max_batch[i], band_width[j], sort_electrons s in {0, 1}) with graph replay,
+ * writes the measured milliseconds to ms_out[(i * n_w + j) * 2 + s]
+ * (nullable) and the fastest options to *best (use_graph = 1, seed as given).
+ * Resets the tally afterwards.  Synchronous. */
+int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
+                 const psl_transport_params* params, uint64_t seed, const uint32_t* max_batch,
+                 int32_t n_m, const int32_t* band_width, int32_t n_w, uint32_t replica,
+                 psl_run_opts* best, double* ms_out);
 
 /* ------------------------------------------------------------------------
  * Commissioning (Sec. 2.2.3, Eq. 8; Sec. 2.2.4)

@@ -1054,17 +1054,19 @@ static int n_threads_of(int req)
 #endif
 }
 
-/* Samples histories g = r*N + h for r in [rep0, rep0+n_rep), h in [h0, h1) and
- * transports them.  Energy per replica is accumulated in FP64; sum/sum2 receive
+/* Samples histories g = r*N + h for r in [rep0, rep0+n_rep), h = h0, h0 + stride,
+ * ... < h1, and transports them.  Energy per replica is accumulated in FP64; sum/sum2 receive
  * the sum over replicas of E_r and E_r^2 per tally cell (V voxels, or
  * n_rows * n_cols cells in index-map mode).  ledger[8], counters[16]. */
 int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_beams,
            const or_phantom* ph, const or_params* tp, uint64_t seed, uint32_t rep0,
-           uint32_t n_rep, uint64_t h0, uint64_t h1, const int32_t* imap, int64_t n_rows,
+           uint32_t n_rep, uint64_t h0, uint64_t h1, uint64_t stride, const int32_t* imap,
+           int64_t n_rows,
            int64_t n_cols, double* sum, double* sum2, double* ledger, uint64_t* counters,
            int n_threads)
 {
-    if (!plan->n_list || h1 > plan->n_hist || h0 > h1) return -1;
+    if (!plan->n_list || h1 > plan->n_hist || h0 > h1 || stride == 0) return -1;
+    const int64_t n_sel = (int64_t)((h1 - h0 + stride - 1) / stride);
     gl_init();
     double* cdf = (double*)malloc(sizeof(double) * (size_t)m->n_ebin * m->n_ring * m->n_comp);
     or_scatter_cdf(m, cdf);
@@ -1094,8 +1096,9 @@ int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_b
             or_tracker* T = &trk[tid];
             tracker_init(T, ph, tp, rt, rho_max, imap, n_cols, grids + (size_t)cells * tid);
 #pragma omp for schedule(static)
-            for (int64_t h = (int64_t)h0; h < (int64_t)h1; ++h) {
-                uint64_t g = (uint64_t)r * plan->n_hist + (uint64_t)h;
+            for (int64_t k = 0; k < n_sel; ++k) {
+                uint64_t h = h0 + (uint64_t)k * stride;
+                uint64_t g = (uint64_t)r * plan->n_hist + h;
                 or_sample_rec rec;
                 sample_history(&S, seed, g, &rec);
                 T->cnt[C_HIST]++;

@@ -119,8 +119,8 @@ def _declare(L):
     L.or_highland.restype = C.c_double
     L.or_ms_sample.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
     L.or_run.argtypes = [P(OrModel), P(OrPlan), P(OrBeam), C.c_int, P(OrPhantom), P(OrParams),
-                         C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, i32p,
-                         C.c_int64, C.c_int64, dp, dp, dp, u64p, C.c_int]
+                         C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64,
+                         i32p, C.c_int64, C.c_int64, dp, dp, dp, u64p, C.c_int]
     L.or_sample.argtypes = [P(OrModel), P(OrPlan), P(OrBeam), C.c_int, P(OrPhantom), C.c_uint64,
                             C.c_uint64, C.c_int64, C.c_void_p]
     L.or_transport.argtypes = [P(OrPhantom), P(OrParams), C.c_uint64, C.c_int64, i32p, dp, dp, dp,
@@ -271,7 +271,7 @@ def sample(model, plan, beams, phantom, seed, g0, n):
 
 
 def run(model, plan, beams, phantom, seed, n_rep, h0=0, h1=None, rep0=0, tparams=None,
-        index_map=None, n_rows=0, n_cols=0, n_threads=0):
+        index_map=None, n_rows=0, n_cols=0, n_threads=0, stride=1):
     """Samples and transports histories; returns (sum, sum2, ledger, counters)."""
     M = Model(model)
     b = beams_array(beams)
@@ -290,7 +290,7 @@ def run(model, plan, beams, phantom, seed, n_rep, h0=0, h1=None, rep0=0, tparams
     led = np.zeros(8)
     cnt = np.zeros(16, dtype=np.uint64)
     rc = lib().or_run(C.byref(M.c), C.byref(pc), b, len(beams), C.byref(ph.c), C.byref(tp),
-                      seed, rep0, n_rep, h0, h1, None if imap is None else _ptr(imap, i32p),
+                      seed, rep0, n_rep, h0, h1, stride, None if imap is None else _ptr(imap, i32p),
                       n_rows, n_cols, _ptr(s, dp), _ptr(s2, dp), _ptr(led, dp),
                       _ptr(cnt, u64p), n_threads)
     if rc != 0:

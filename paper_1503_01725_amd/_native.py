@@ -65,6 +65,18 @@ class psl_transport_params(C.Structure):
                 ("step_frac", C.c_float), ("ms_enable", C.c_int32)]
 
 
+class psl_run_opts(C.Structure):
+    _fields_ = [("max_batch", C.c_uint32), ("band_width", C.c_int32), ("use_graph", C.c_int32),
+                ("sort_electrons", C.c_int32), ("timing", C.c_int32), ("seed", C.c_uint64)]
+
+
+class psl_run_timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_uint64 * 5)]
+
+
+PHASES = ("sample", "photon", "sort", "electron", "fold")
+
+
 class psl_nnls_opts(C.Structure):
     _fields_ = [("delta", C.c_double), ("pg_tol", C.c_double), ("armijo_sigma", C.c_double),
                 ("armijo_beta", C.c_double), ("max_iter", C.c_int64)]
@@ -102,9 +114,14 @@ _SIGS = {
 }
 _RESTYPE = {"psl_last_error": C.c_char_p, "psl_model_free": None, "psl_plan_free": None,
             "psl_phantom_free": None, "psl_tally_free": None}
-_OPTIONAL = {"commission_nnls": [dp, C.c_int64, C.c_int64, dp, dp, P(psl_nnls_opts),
-                                 P(psl_nnls_report)],
-             "psl_run": None, "psl_autotune": None}
+_SIGS.update({
+    "commission_nnls": [dp, C.c_int64, C.c_int64, dp, dp, P(psl_nnls_opts), P(psl_nnls_report)],
+    "psl_run": [vp, vp, vp, P(psl_transport_params), P(psl_run_opts), vp],
+    "psl_run_get_timing": [vp, P(psl_run_timing)],
+    "psl_autotune": [vp, vp, vp, P(psl_transport_params), C.c_uint64, u32p, C.c_int32, i32p,
+                     C.c_int32, C.c_uint32, P(psl_run_opts), dp],
+})
+_OPTIONAL = {}
 
 _lib = None
 
@@ -189,6 +206,28 @@ def transport_batch(phantom, particles, electrons, tally, params, seed, stream):
 def tally_dose(tally, ops, plan, dose_ptr, sigma_ptr, stream):
     return _call("tally_dose", tally, ops, plan, vp(dose_ptr) if dose_ptr else None,
                  vp(sigma_ptr) if sigma_ptr else None, vp(stream))
+
+
+def psl_run(plan, phantom, tally, params, opts, stream):
+    return _call("psl_run", plan, phantom, tally, C.byref(params), C.byref(opts), vp(stream))
+
+
+def psl_run_get_timing(tally):
+    t = psl_run_timing()
+    _call("psl_run_get_timing", tally, C.byref(t))
+    return {p: (t.ms[i], int(t.launches[i])) for i, p in enumerate(PHASES)}
+
+
+def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, replica=0):
+    import numpy as np
+    mb = np.ascontiguousarray(max_batches, dtype=np.uint32)
+    bw = np.ascontiguousarray(band_widths, dtype=np.int32)
+    ms = np.zeros(len(mb) * len(bw) * 2)
+    best = psl_run_opts()
+    _call("psl_autotune", plan, phantom, tally, C.byref(params), seed, mb.ctypes.data_as(u32p),
+          len(mb), bw.ctypes.data_as(i32p), len(bw), replica, C.byref(best),
+          ms.ctypes.data_as(dp))
+    return best, ms.reshape(len(mb), len(bw), 2)
 
 
 def commission_nnls(a_ptr, m, n, b_ptr, x_ptr, opts, report):

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
-SOURCES = ["host_model.cpp", "physics.cpp", "k_sample.hip", "k_transport.hip"]
+SOURCES = ["host_model.cpp", "physics.cpp", "k_sample.hip", "k_transport.hip", "runtime.hip",
+           "k_nnls.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}",

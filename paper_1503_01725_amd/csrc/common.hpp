@@ -136,11 +136,12 @@ enum {
     C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW, C_FOLDS, C_N = 16
 };
 
-// Device-side tally state.
+// Device-side tally state.  `stats` holds kStripes copies of the ledger
+// (L_N doubles) followed by the counters (C_N uint64), summed by the host.
 struct TallyDev {
     float* grid;            // FP32 replica cells
-    double* ledger;         // [L_N]
-    unsigned long long* counters;   // [C_N]
+    double* stats;          // [kStripes][L_N + C_N]
+    unsigned long long* counters;   // counters of copy 0
     const int32_t* imap;    // nullable voxel -> row+1
     int32_t n_cols;
 };
@@ -152,6 +153,8 @@ struct PhantomDev {
     float vox[3], inv_vox[3], origin[3], hi[3];
     float rho_max, inv_rho_max;
 };
+
+struct Runner;   // batched-runtime workspace (runtime.hip)
 
 }  // namespace psl
 
@@ -182,6 +185,8 @@ struct psl_plan {
     double s_area = 0.0;
     std::vector<psl_batch> batches;
     std::vector<int64_t> batch_jlo, batch_jhi;   // list range of each batch
+    uint32_t cur_max_batch = 0;        // batching the lists above were built for
+    int32_t cur_band_width = 0;
     std::vector<psl::PslEntry> list_host;
     std::vector<psl::BeamDev> beams_host;
     // device copies, uploaded on first use (set-up itself needs no GPU)
@@ -212,11 +217,14 @@ struct psl_tally {
     psl::DevBuf col_w;     // double [n_cols] column weights (finalize scratch)
     psl::DevBuf perm;      // uint32 electron order after the energy-band sort
     psl::DevBuf bands;     // uint32 band counters / offsets
+    psl::DevBuf queues;    // uint32 work-queue heads of the transport kernels
     uint32_t folds = 0;
+    psl::Runner* runner = nullptr;     // batched-runtime workspace (runtime.hip)
+    ~psl_tally();
     psl::TallyDev dev() const {
         psl::TallyDev t;
         t.grid = grid.as<float>();
-        t.ledger = stats.as<double>();
+        t.stats = stats.as<double>();
         t.counters = reinterpret_cast<unsigned long long*>(stats.as<double>() + psl::L_N);
         t.imap = imap;
         t.n_cols = n_cols;
@@ -230,4 +238,21 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p);
 // Device copies of a model's / plan's sampling tables; defined in host_model.cpp.
 void ensure_device(const psl_model* m);
 void ensure_device(const psl_plan* p);
+
+// Optional HIP events recorded around the transport launches (may be null).
+struct PhaseEvents {
+    hipEvent_t photon0, photon1, sort0, sort1, electron0, electron1;
+};
+
+// Kernel launchers shared by the public calls and the batched runtime.
+void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica,
+                   const uint32_t* rep_dev, uint64_t h0, uint32_t n, int64_t jlo, int64_t jhi,
+                   int stype, uint64_t seed, const psl_particles* out, int dense, psl_tally* tally,
+                   hipStream_t stream);
+void launch_transport(const psl_phantom* ph, const psl_particles* in, psl_particles* el,
+                      psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
+                      hipStream_t stream, bool sort_electrons, const PhaseEvents* ev = nullptr);
+void launch_zero_u32(uint32_t* p, int n, hipStream_t s);
+void launch_fold(psl_tally* t, hipStream_t s);
+void ensure_perm(psl_tally* t, uint32_t capacity);
 }  // namespace psl

@@ -84,21 +84,53 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
-// Adds per-thread values of a whole block into global accumulators: one wave
-// reduction, then lane 0 of every wave adds its partial (few waves per block).
-template <int N>
-__device__ __forceinline__ void block_add(double* dst, const double (&v)[N]) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const double s = wave_sum(v[i]);
-        if (lane == 0 && s != 0.0) atomicAdd(dst + i, s);
-    }
-}
+// Per-thread ledger and event counters, flushed once per block at the end of
+// a kernel.  The tally keeps kStripes copies of the accumulators and block b
+// adds into copy b % kStripes, so that no address sees more than a handful of
+// atomics per launch (same-address atomics serialise in the L2).
+constexpr int kStripes = 64;
+constexpr int kStatWords = L_N + C_N;
 
-__device__ __forceinline__ void block_add_u64(unsigned long long* dst, unsigned long long v) {
-    const unsigned long long s = wave_sum(v);
-    if ((threadIdx.x & 63) == 0 && s != 0ull) atomicAdd(dst, s);
+struct LocalStats {
+    double l[L_N];
+    unsigned long long c[C_N];
+    __device__ LocalStats() {
+#pragma unroll
+        for (int i = 0; i < L_N; ++i) l[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < C_N; ++i) c[i] = 0ull;
+    }
+};
+
+// Every thread of the block must call this (it synchronises the block).
+__device__ __forceinline__ void flush_stats(double* stats, const LocalStats& s) {
+    __shared__ double red_l[L_N][16];
+    __shared__ unsigned long long red_c[C_N][16];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < L_N; ++i) {
+        const double v = wave_sum(s.l[i]);
+        if (lane == 0) red_l[i][w] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < C_N; ++i) {
+        const unsigned long long v = wave_sum(s.c[i]);
+        if (lane == 0) red_c[i][w] = v;
+    }
+    __syncthreads();
+    double* mine = stats + (blockIdx.x % kStripes) * kStatWords;
+    const int t = threadIdx.x;
+    if (t < L_N) {
+        double v = 0.0;
+        for (int k = 0; k < nw; ++k) v += red_l[t][k];
+        if (v != 0.0) atomicAdd(mine + t, v);
+    } else if (t < L_N + C_N) {
+        unsigned long long v = 0ull;
+        for (int k = 0; k < nw; ++k) v += red_c[t - L_N][k];
+        if (v != 0ull) atomicAdd(reinterpret_cast<unsigned long long*>(mine + L_N) + (t - L_N), v);
+    }
+    __syncthreads();
 }
 
 // Reserves `want ? 1 : 0` slots per lane in a global stack with a single

@@ -457,6 +457,8 @@ extern "C" int psl_plan_set_batching(psl_plan* p, uint32_t max_batch, int32_t ba
             p->batch_jlo[i] = b0 - p->cum.begin();
             p->batch_jhi[i] = (b1 - p->cum.begin()) + 1;
         }
+        p->cur_max_batch = max_batch;
+        p->cur_band_width = band_width;
         if (n_batches) *n_batches = int64_t(p->batches.size());
     });
 }

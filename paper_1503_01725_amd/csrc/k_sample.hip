@@ -27,8 +27,8 @@ struct SampleArgs {
     uint32_t* tag;
     uint32_t* count;
     uint32_t capacity;
-    int dense;
-    double* ledger;
+    int dense;                   // 0 compact, 1 dense (full records), 2 dense (tags only if rejected)
+    double* stats;
     unsigned long long* counters;
 };
 
@@ -48,7 +48,20 @@ template <int STYPE>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = i < a.n;
-    double led[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // src, jaw, missed, invalid, entered count
+    // The block's histories are consecutive, so their PSLs lie between the
+    // PSLs of its first and last history: two threads locate those, then every
+    // thread searches only that short range (cached) instead of the whole list.
+    __shared__ int64_t s_range[2];
+    {
+        const uint32_t first = blockIdx.x * blockDim.x;
+        const uint32_t last = min(first + blockDim.x, a.n) - 1u;
+        if (threadIdx.x == 0) s_range[0] = upper_bound(a.cum, a.jlo, a.jhi, a.h0 + first);
+        if (threadIdx.x == 64 || (blockDim.x <= 64 && threadIdx.x == 0))
+            s_range[1] = upper_bound(a.cum, a.jlo, a.jhi, a.h0 + last) + 1;
+    }
+    __syncthreads();
+    const int64_t jb0 = s_range[0], jb1 = s_range[1];
+    dev::LocalStats ls;
     bool accept = false;
     float px = 0.f, py = 0.f, pz = 0.f, du = 0.f, dv = 0.f, dw = 0.f, en = 0.f;
     uint64_t g = 0;
@@ -57,7 +70,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
         const uint64_t h = a.h0 + i;
         const uint32_t rep = a.rep_dev ? *a.rep_dev : a.rep;
         g = uint64_t(rep) * a.n_hist + h;
-        const int64_t j = upper_bound(a.cum, a.jlo, a.jhi, h);
+        const int64_t j = upper_bound(a.cum, jb0, jb1, h);
         const PslEntry ent = a.list[j];
         tag = ent.tag;
 
@@ -122,10 +135,11 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
         const float vb = sn * ul + ct * vl;
         const float wb = wl;
 
-        led[0] = en;
+        ls.l[L_SRC] = en;
+        ls.c[C_HIST] = 1;
         if (invalid) {
             status = kInvalid;
-            led[3] = en;
+            ls.l[L_INVALID] = en;
         } else {
             const BeamDev& B = a.beams[ent.beam];
             // jaw rejection at the upper jaw surfaces (closed intervals)
@@ -133,7 +147,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
             const float xj = fmaf(ub / wb, a.zjx, x);
             if (!(yj >= B.jy1 && yj <= B.jy2 && xj >= B.jx1 && xj <= B.jx2)) {
                 status = kJaw;
-                led[1] = en;
+                ls.l[L_JAW] = en;
             } else {
                 // beam frame -> patient frame (the plane is the isocentre plane)
                 const float p0 = B.iso[0] + B.R[0] * x + B.R[1] * y;
@@ -159,13 +173,13 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
                 }
                 if (!(tmax > tmin)) {
                     status = kMissed;
-                    led[2] = en;
+                    ls.l[L_MISSED] = en;
                 } else {
                     px = fmaf(tmin, du, p0);
                     py = fmaf(tmin, dv, p1);
                     pz = fmaf(tmin, dw, p2);
                     accept = true;
-                    led[4] = 1.0;
+                    ls.c[C_ENTERED] = 1;
                 }
             }
         }
@@ -181,11 +195,14 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     }
 
     if (a.dense) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.count = a.n;
         if (live) {
-            a.x[i] = px; a.y[i] = py; a.z[i] = pz;
-            a.u[i] = du; a.v[i] = dv; a.w[i] = dw;
-            a.e[i] = en;
-            a.hid[i] = g;
+            if (accept || a.dense == 1) {
+                a.x[i] = px; a.y[i] = py; a.z[i] = pz;
+                a.u[i] = du; a.v[i] = dv; a.w[i] = dw;
+                a.e[i] = en;
+                a.hid[i] = g;
+            }
             a.tag[i] = tag | (status << 24);
         }
     } else {
@@ -198,14 +215,11 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
                 a.hid[slot] = g;
                 a.tag[slot] = tag;
             } else {
-                atomicAdd(a.counters + C_OVERFLOW, 1ull);
+                ls.c[C_OVERFLOW] += 1;
             }
         }
     }
-    const double sums[4] = {led[0], led[1], led[2], led[3]};
-    dev::block_add(a.ledger + L_SRC, sums);
-    dev::block_add_u64(a.counters + C_HIST, live ? 1ull : 0ull);
-    dev::block_add_u64(a.counters + C_ENTERED, accept ? 1ull : 0ull);
+    dev::flush_stats(a.stats, ls);
 }
 
 }  // namespace
@@ -257,7 +271,7 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
     a.capacity = out->capacity;
     a.dense = dense;
     TallyDev t = tally->dev();
-    a.ledger = t.ledger;
+    a.stats = t.stats;
     a.counters = t.counters;
     const dim3 block(256), grid((n + 255) / 256);
     if (stype == 0) hipLaunchKernelGGL(k_sample<0>, grid, block, 0, stream, a);

@@ -46,6 +46,7 @@ struct TransportArgs {
     Stack in;
     Stack el;                  // electron stack (photon kernel output / electron kernel input)
     const uint32_t* perm;      // electron order (nullable: identity)
+    uint32_t* queue;           // [0] photon, [1] electron work-queue heads (zeroed per launch)
     PhantomDev ph;
     PhysicsDev phys;
     TallyDev tally;
@@ -117,6 +118,41 @@ __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, 
     ++n_atomic;
 }
 
+// ---- work queue -------------------------------------------------------------
+// A wave reserves kChunk consecutive stack entries with one atomic and hands
+// them to its idle lanes over the following iterations; lanes whose particle
+// has finished take the next entry of the wave's chunk.
+constexpr uint32_t kChunk = 64;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+struct WaveQueue {
+    uint32_t base = 0, left = 0;
+    bool drained = false;
+};
+
+__device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t* head, uint32_t n) {
+    const unsigned long long m = __ballot(need);
+    if (m == 0ull) return kNone;
+    const int lane = threadIdx.x & 63;
+    if (q.left == 0 && !q.drained) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(head, kChunk);
+        b = __shfl(b, 0, 64);
+        if (b >= n) {
+            q.drained = true;
+        } else {
+            q.base = b;
+            q.left = min(kChunk, n - b);
+        }
+    }
+    const uint32_t give = min(uint32_t(__popcll(m)), q.left);
+    const uint32_t rank = uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+    const uint32_t idx = (need && rank < give) ? q.base + rank : kNone;
+    q.base += give;
+    q.left -= give;
+    return idx;
+}
+
 // ---- photon kernel --------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     __shared__ float s_kn[KN_TAB_N];
@@ -125,21 +161,47 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
 
     const PhantomDev& G = a.ph;
     const uint32_t n = min(*a.in.count, a.in.capacity);
-    double esc_g = 0.0, dep = 0.0;
-    unsigned long long c_wc = 0, c_real = 0, c_push = 0, c_local = 0, c_atom = 0, c_unc = 0,
-                       c_kahn = 0, c_over = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float px = a.in.x[i], py = a.in.y[i], pz = a.in.z[i];
-        float du = a.in.u[i], dv = a.in.v[i], dw = a.in.w[i];
-        float e = a.in.e[i];
-        const uint64_t g = a.in.hid[i];
-        const uint32_t tag = a.in.tag[i] & 0xFFFFu;
-        dev::Stream st;
-        st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, 0);
-        uint32_t n_push = 0;
-        bool collided = false;
-        for (int step = 0;; ++step) {
-            if (!(e >= a.e_cut_g) || step >= kMaxPhotonSteps) {
+    dev::LocalStats ls;
+    double& esc_g = ls.l[L_ESC_G];
+    double& dep = ls.l[L_DEP];
+    unsigned long long &c_wc = ls.c[C_WC_STEPS], &c_real = ls.c[C_REAL], &c_push = ls.c[C_E_PUSHED],
+                       &c_local = ls.c[C_E_LOCAL], &c_atom = ls.c[C_DEPOSITS],
+                       &c_unc = ls.c[C_ESC_UNCOLLIDED], &c_kahn = ls.c[C_KAHN_TRIALS],
+                       &c_over = ls.c[C_OVERFLOW];
+    // electron-stack slots reserved by this wave and not used yet
+    uint32_t el_base = 0, el_left = 0;
+    // per-lane photon state
+    float px = 0.f, py = 0.f, pz = 0.f, du = 0.f, dv = 0.f, dw = 0.f, e = 0.f;
+    uint64_t g = 0;
+    uint32_t tag = 0, n_push = 0;
+    int steps = 0;
+    bool collided = false, alive = false;
+    WaveQueue wq;
+    dev::Stream st;
+    for (;;) {
+        {
+            const uint32_t i = take_work(!alive, wq, a.queue, n);
+            const uint32_t tg = i != kNone ? a.in.tag[i] : 0u;
+            if (i != kNone && (tg >> 24) == 0u) {   // skip entries marked rejected / empty
+                px = a.in.x[i]; py = a.in.y[i]; pz = a.in.z[i];
+                du = a.in.u[i]; dv = a.in.v[i]; dw = a.in.w[i];
+                e = a.in.e[i];
+                g = a.in.hid[i];
+                tag = tg & 0xFFFFu;
+                st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, 0);
+                n_push = 0;
+                steps = 0;
+                collided = false;
+                alive = true;
+            }
+        }
+        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        // electron set in motion by this lane's step (pushed below, where the
+        // whole wave has reconverged)
+        bool push = false;
+        float qx = 0.f, qy = 0.f, qz = 0.f, te = 0.f;
+        if (alive) {
+            if (!(e >= a.e_cut_g) || steps >= kMaxPhotonSteps) {
                 // below the cut-off on entry, or the safety bound: absorb here
                 const int vx = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
                 const int vy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
@@ -147,135 +209,233 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 const float ee = isfinite(e) ? e : 0.f;
                 deposit(a.tally, (vz * G.ny + vy) * G.nx + vx, tag, ee, c_atom);
                 dep += ee;
-                c_over += step >= kMaxPhotonSteps ? 1ull : 0ull;
-                break;
-            }
-            const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
-            const float s = -logf(1.f - st.next()) / mu;
-            px = fmaf(s, du, px);
-            py = fmaf(s, dv, py);
-            pz = fmaf(s, dw, pz);
-            const float fx = floorf((px - G.origin[0]) * G.inv_vox[0]);
-            const float fy = floorf((py - G.origin[1]) * G.inv_vox[1]);
-            const float fz = floorf((pz - G.origin[2]) * G.inv_vox[2]);
-            if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) && fz >= 0.f &&
-                  fz < float(G.nz))) {
-                esc_g += e;
-                c_unc += collided ? 0ull : 1ull;
-                break;
-            }
-            const int v = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
-            ++c_wc;
-            const float ur = st.next();
-            if (!(ur < G.dens[v] * G.inv_rho_max)) continue;   // virtual collision
-            collided = true;
-            ++c_real;
-            // Kahn's method for x = E/E' in [1, 1 + 2k]
-            const float k = e * (1.f / kMe);
-            const float k2 = 2.f * k;
-            float x = 1.f;
-            for (int trial = 0; trial < kMaxKahnTrials; ++trial) {
-                const float r1 = st.next(), r2 = st.next(), r3 = st.next();
-                ++c_kahn;
-                if (r1 <= (1.f + k2) / (9.f + k2)) {
-                    x = fmaf(k2, r2, 1.f);
-                    if (r3 <= 4.f * (1.f / x - 1.f / (x * x))) break;
+                c_over += steps >= kMaxPhotonSteps ? 1ull : 0ull;
+                alive = false;
+            } else {
+                ++steps;
+                // one Woodcock flight
+                const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
+                const float s = -logf(1.f - st.next()) / mu;
+                px = fmaf(s, du, px);
+                py = fmaf(s, dv, py);
+                pz = fmaf(s, dw, pz);
+                const float fx = floorf((px - G.origin[0]) * G.inv_vox[0]);
+                const float fy = floorf((py - G.origin[1]) * G.inv_vox[1]);
+                const float fz = floorf((pz - G.origin[2]) * G.inv_vox[2]);
+                if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) &&
+                      fz >= 0.f && fz < float(G.nz))) {
+                    esc_g += e;
+                    c_unc += collided ? 0ull : 1ull;
+                    alive = false;
                 } else {
-                    x = (1.f + k2) / fmaf(k2, r2, 1.f);
-                    const float c = 1.f - (x - 1.f) / k;
-                    if (r3 <= 0.5f * (c * c + 1.f / x)) break;
+                    const int v = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
+                    ++c_wc;
+                    const float ur = st.next();
+                    if (ur < G.dens[v] * G.inv_rho_max) {   // real collision
+                        collided = true;
+                        ++c_real;
+                        // Kahn's method for x = E/E' in [1, 1 + 2k]
+                        const float k = e * (1.f / kMe);
+                        const float k2 = 2.f * k;
+                        float x = 1.f;
+                        for (int trial = 0; trial < kMaxKahnTrials; ++trial) {
+                            const float r1 = st.next(), r2 = st.next(), r3 = st.next();
+                            ++c_kahn;
+                            if (r1 <= (1.f + k2) / (9.f + k2)) {
+                                x = fmaf(k2, r2, 1.f);
+                                if (r3 <= 4.f * (1.f / x - 1.f / (x * x))) break;
+                            } else {
+                                x = (1.f + k2) / fmaf(k2, r2, 1.f);
+                                const float c = 1.f - (x - 1.f) / k;
+                                if (r3 <= 0.5f * (c * c + 1.f / x)) break;
+                            }
+                        }
+                        const float cos_t = 1.f - (x - 1.f) / k;
+                        float sphi, cphi;
+                        sincospif(2.f * st.next(), &sphi, &cphi);
+                        const float e1 = e / x;
+                        te = e - e1;
+                        float nu = du, nv = dv, nw = dw;
+                        rotate(nu, nv, nw, cos_t, cphi, sphi);
+                        if (te >= a.e_cut_e) {
+                            // electron direction from momentum conservation: p_e = E d - E' d'
+                            qx = e * du - e1 * nu;
+                            qy = e * dv - e1 * nv;
+                            qz = e * dw - e1 * nw;
+                            const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
+                            qx *= inv;
+                            qy *= inv;
+                            qz *= inv;
+                            ++n_push;
+                            ++c_push;
+                            push = true;
+                        } else {
+                            deposit(a.tally, v, tag, te, c_atom);
+                            dep += te;
+                            ++c_local;
+                        }
+                        e = e1;
+                        du = nu; dv = nv; dw = nw;
+                        if (e < a.e_cut_g) {
+                            deposit(a.tally, v, tag, e, c_atom);
+                            dep += e;
+                            alive = false;
+                        }
+                    }
                 }
             }
-            const float cos_t = 1.f - (x - 1.f) / k;
-            float sphi, cphi;
-            sincospif(2.f * st.next(), &sphi, &cphi);
-            const float e1 = e / x;
-            const float te = e - e1;
-            float nu = du, nv = dv, nw = dw;
-            rotate(nu, nv, nw, cos_t, cphi, sphi);
-            if (te >= a.e_cut_e) {
-                // electron direction from momentum conservation: p_e = E d - E' d'
-                float qx = e * du - e1 * nu, qy = e * dv - e1 * nv, qz = e * dw - e1 * nw;
-                const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
-                ++n_push;
-                ++c_push;
-                const uint32_t slot = dev::wave_reserve(true, a.el.count);
+        }
+        // wave-convergent push: slots from the wave's reserved chunk of the
+        // electron stack, a new chunk of kChunk when it runs out
+        const unsigned long long m = __ballot(push);
+        if (m != 0ull) {
+            const int lane = threadIdx.x & 63;
+            const uint32_t k_push = uint32_t(__popcll(m));
+            const uint32_t rank = uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
+            uint32_t fresh = 0;
+            if (k_push > el_left) {
+                if (lane == 0) fresh = atomicAdd(a.el.count, kChunk);
+                fresh = __shfl(fresh, 0, 64);
+            }
+            const uint32_t slot = rank < el_left ? el_base + rank : fresh + (rank - el_left);
+            if (k_push > el_left) {
+                el_base = fresh + (k_push - el_left);
+                el_left = kChunk - (k_push - el_left);
+            } else {
+                el_base += k_push;
+                el_left -= k_push;
+            }
+            if (push) {
                 if (slot < a.el.capacity) {
                     a.el.x[slot] = px; a.el.y[slot] = py; a.el.z[slot] = pz;
-                    a.el.u[slot] = qx * inv; a.el.v[slot] = qy * inv; a.el.w[slot] = qz * inv;
+                    a.el.u[slot] = qx; a.el.v[slot] = qy; a.el.w[slot] = qz;
                     a.el.e[slot] = te;
                     a.el.hid[slot] = g;
                     a.el.tag[slot] = tag | (n_push << 16);
                 } else {
                     ++c_over;
                 }
-            } else {
-                deposit(a.tally, v, tag, te, c_atom);
-                dep += te;
-                ++c_local;
-            }
-            e = e1;
-            du = nu; dv = nv; dw = nw;
-            if (e < a.e_cut_g) {
-                deposit(a.tally, v, tag, e, c_atom);
-                dep += e;
-                break;
             }
         }
     }
-    const double led[2] = {esc_g, dep};
-    dev::block_add_u64(a.tally.counters + C_WC_STEPS, c_wc);
-    dev::block_add_u64(a.tally.counters + C_REAL, c_real);
-    dev::block_add_u64(a.tally.counters + C_E_PUSHED, c_push);
-    dev::block_add_u64(a.tally.counters + C_E_LOCAL, c_local);
-    dev::block_add_u64(a.tally.counters + C_DEPOSITS, c_atom);
-    dev::block_add_u64(a.tally.counters + C_ESC_UNCOLLIDED, c_unc);
-    dev::block_add_u64(a.tally.counters + C_KAHN_TRIALS, c_kahn);
-    dev::block_add_u64(a.tally.counters + C_OVERFLOW, c_over);
-    double ls[1] = {led[0]};
-    dev::block_add(a.tally.ledger + L_ESC_G, ls);
-    ls[0] = led[1];
-    dev::block_add(a.tally.ledger + L_DEP, ls);
+    // the unused rest of the wave's last chunk stays in the stack as empty entries
+    if (el_left > 0) {
+        const int lane = threadIdx.x & 63;
+        for (uint32_t j = uint32_t(lane); j < el_left; j += 64) {
+            const uint32_t slot = el_base + j;
+            if (slot < a.el.capacity) a.el.tag[slot] = 1u << 24;
+        }
+    }
+    dev::flush_stats(a.tally.stats, ls);
 }
 
 // ---- electron energy bands (counting sort) --------------------------------
+// Block b of a fixed grid of kSortBlocks owns the chunk [b c, (b+1) c) of the
+// stack.  Pass 1 writes per-block band counts, pass 2 turns them into offsets
+// (band-major, highest band first, so long-range electrons start first),
+// pass 3 scatters the indices; only LDS atomics are used.
+constexpr int kSortBlocks = 1024;
+
 // log-spaced bands between the electron cut-off and the table top
 __device__ __forceinline__ int band_of(float t, float lt0, float inv_w) {
     const int b = int((__logf(t) - lt0) * inv_w);
     return min(max(b, 0), kBands - 1);
 }
 
-__global__ void __launch_bounds__(kBlock) k_band_count(const float* e, const uint32_t* count,
-                                                      uint32_t cap, uint32_t* hist, float lt0,
-                                                      float inv_w) {
-    __shared__ uint32_t s[kBands];
-    if (threadIdx.x < kBands) s[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t n = min(*count, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        atomicAdd(&s[band_of(e[i], lt0, inv_w)], 1u);
-    __syncthreads();
-    if (threadIdx.x < kBands && s[threadIdx.x]) atomicAdd(hist + threadIdx.x, s[threadIdx.x]);
+// Lanes of a wave with the same band share one LDS atomic; returns the lane's
+// slot relative to the LDS counter of its band.
+__device__ __forceinline__ uint32_t wave_band_rank(bool valid, int b, uint32_t* s_cnt) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    bool pending = valid;
+    uint32_t slot = 0;
+    for (;;) {
+        const unsigned long long act = __ballot(pending);
+        if (act == 0ull) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int lb = __shfl(b, leader, 64);
+        const unsigned long long mine = __ballot(pending && b == lb);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(s_cnt + lb, uint32_t(__popcll(mine)));
+        base = __shfl(base, leader, 64);
+        if (pending && b == lb) {
+            slot = base + uint32_t(__popcll(mine & below));
+            pending = false;
+        }
+    }
+    return slot;
 }
 
-// hist[kBands] -> exclusive offsets in hist[kBands..2 kBands), highest band first
-__global__ void k_band_scan(uint32_t* hist) {
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int b = kBands - 1; b >= 0; --b) {
-            hist[kBands + b] = run;
-            run += hist[b];
-        }
+__global__ void __launch_bounds__(kBlock) k_band_count(const float* e, const uint32_t* tag,
+                                                      const uint32_t* count, uint32_t cap,
+                                                      uint32_t* hist, float lt0, float inv_w) {
+    __shared__ uint32_t s_cnt[kBands];
+    if (threadIdx.x < kBands) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = min(*count, cap);
+    const uint32_t chunk = (n + kSortBlocks - 1) / kSortBlocks;
+    const uint32_t i0 = blockIdx.x * chunk, i1 = min(i0 + chunk, n);
+    for (uint32_t base = i0; base < i1; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < i1;
+        // entries marked rejected / empty go to band 0, where the kernel skips them
+        const int b = valid && (tag[i] >> 24) == 0u ? band_of(e[i], lt0, inv_w) : 0;
+        wave_band_rank(valid, b, s_cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBands) hist[threadIdx.x * kSortBlocks + blockIdx.x] = s_cnt[threadIdx.x];
+}
+
+// exclusive scan over (band descending, block ascending)
+__global__ void __launch_bounds__(1024) k_band_scan(const uint32_t* hist, uint32_t* offs) {
+    constexpr int kPer = kBands * kSortBlocks / 1024;
+    __shared__ uint32_t s_sum[1024];
+    uint32_t vals[kPer];
+    uint32_t tot = 0;
+    for (int k = 0; k < kPer; ++k) {
+        const int pos = threadIdx.x * kPer + k;               // position in scan order
+        const int band = kBands - 1 - pos / kSortBlocks, blk = pos % kSortBlocks;
+        vals[k] = hist[band * kSortBlocks + blk];
+        tot += vals[k];
+    }
+    s_sum[threadIdx.x] = tot;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = s_sum[threadIdx.x] - tot;
+    for (int k = 0; k < kPer; ++k) {
+        const int pos = threadIdx.x * kPer + k;
+        const int band = kBands - 1 - pos / kSortBlocks, blk = pos % kSortBlocks;
+        offs[band * kSortBlocks + blk] = run;
+        run += vals[k];
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_band_scatter(const float* e, const uint32_t* count,
-                                                        uint32_t cap, uint32_t* offsets,
-                                                        uint32_t* perm, float lt0, float inv_w) {
+__global__ void __launch_bounds__(kBlock) k_band_scatter(const float* e, const uint32_t* tag,
+                                                        const uint32_t* count, uint32_t cap,
+                                                        const uint32_t* offs, uint32_t* perm,
+                                                        float lt0, float inv_w) {
+    __shared__ uint32_t s_cnt[kBands];
+    __shared__ uint32_t s_off[kBands];
+    if (threadIdx.x < kBands) {
+        s_cnt[threadIdx.x] = 0;
+        s_off[threadIdx.x] = offs[threadIdx.x * kSortBlocks + blockIdx.x];
+    }
+    __syncthreads();
     const uint32_t n = min(*count, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t slot = atomicAdd(offsets + band_of(e[i], lt0, inv_w), 1u);
-        perm[slot] = i;
+    const uint32_t chunk = (n + kSortBlocks - 1) / kSortBlocks;
+    const uint32_t i0 = blockIdx.x * chunk, i1 = min(i0 + chunk, n);
+    for (uint32_t base = i0; base < i1; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        const bool valid = i < i1;
+        // entries marked rejected / empty go to band 0, where the kernel skips them
+        const int b = valid && (tag[i] >> 24) == 0u ? band_of(e[i], lt0, inv_w) : 0;
+        const uint32_t r = wave_band_rank(valid, b, s_cnt);
+        if (valid) perm[s_off[b] + r] = i;
     }
 }
 
@@ -304,37 +464,56 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     const PhysicsDev& P = a.phys;
     const float tcut = a.e_cut_e;
     const uint32_t n = min(*s.count, s.capacity);
-    double esc_e = 0.0, dep = 0.0, path = 0.0;
-    unsigned long long c_steps = 0, c_atom = 0, c_bnd = 0, c_guard = 0, c_local = 0;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const uint32_t i = a.perm ? a.perm[q] : q;
-        float px = s.x[i], py = s.y[i], pz = s.z[i];
-        float dx = s.u[i], dy = s.v[i], dz = s.w[i];
-        float t = s.e[i];
-        const uint64_t g = s.hid[i];
-        const uint32_t tg = s.tag[i];
-        const uint32_t tag = tg & 0xFFFFu, sub = (tg >> 16) & 0xFFu;
-        int ix = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
-        int iy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
-        int iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
-        int cur_v = (iz * G.ny + iy) * G.nx + ix;
-        if (t < tcut) {
-            deposit(a.tally, cur_v, tag, t, c_atom);
-            dep += t;
-            ++c_local;
-            continue;
-        }
-        dev::Stream st;
-        st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, sub);
-        int pend_v = cur_v;
-        float pend_e = 0.f;
-        for (int step = 0;; ++step) {
-            if (step >= kMaxElectronSteps) {
-                pend_e += t;
-                dep += t;
-                ++c_guard;
-                break;
+    dev::LocalStats ls;
+    double &esc_e = ls.l[L_ESC_E], &dep = ls.l[L_DEP], &path = ls.l[L_EPATH];
+    unsigned long long &c_steps = ls.c[C_E_STEPS], &c_atom = ls.c[C_DEPOSITS],
+                       &c_bnd = ls.c[C_E_BOUNDARY], &c_guard = ls.c[C_GUARD],
+                       &c_local = ls.c[C_E_LOCAL];
+    // per-lane electron state
+    float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, pend_e = 0.f;
+    int ix = 0, iy = 0, iz = 0, cur_v = 0, pend_v = 0, steps = 0;
+    uint32_t tag = 0;
+    bool alive = false;
+    WaveQueue wq;
+    dev::Stream st;
+    for (;;) {
+        {
+            const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
+            const uint32_t i = q != kNone ? (a.perm ? a.perm[q] : q) : 0u;
+            const uint32_t tg = q != kNone ? s.tag[i] : 0u;
+            if (q != kNone && (tg >> 24) == 0u) {   // skip entries marked rejected / empty
+                px = s.x[i]; py = s.y[i]; pz = s.z[i];
+                dx = s.u[i]; dy = s.v[i]; dz = s.w[i];
+                t = s.e[i];
+                const uint64_t g = s.hid[i];
+                tag = tg & 0xFFFFu;
+                ix = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
+                iy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
+                iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
+                cur_v = (iz * G.ny + iy) * G.nx + ix;
+                if (t < tcut) {
+                    deposit(a.tally, cur_v, tag, t, c_atom);
+                    dep += t;
+                    ++c_local;
+                } else {
+                    st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, (tg >> 16) & 0xFFu);
+                    pend_v = cur_v;
+                    pend_e = 0.f;
+                    steps = 0;
+                    alive = true;
+                }
             }
+        }
+        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        if (!alive) continue;
+        bool done = false;
+        if (steps >= kMaxElectronSteps) {
+            pend_e += t;
+            dep += t;
+            ++c_guard;
+            done = true;
+        } else {
+            ++steps;
             const float rho = G.dens[cur_v];
             float sb = INFINITY;
             int axis = 0;
@@ -356,75 +535,80 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                 path += sl;
                 pend_e += t;
                 dep += t;
-                break;
-            }
-            const float tn = csda_energy(P, s_inv, r0 - rho * sl);
-            const float de = fmaxf(t - tn, 0.f);
-            pend_e += de;
-            dep += de;
-            px = fmaf(sl, dx, px);
-            py = fmaf(sl, dy, py);
-            pz = fmaf(sl, dz, pz);
-            path += sl;
-            const float t_old = t;
-            t -= de;
-            if (boundary) {
-                ++c_bnd;
-                bool out;
-                if (axis == 0) {
-                    ix += dx > 0.f ? 1 : -1;
-                    out = ix < 0 || ix >= G.nx;
-                } else if (axis == 1) {
-                    iy += dy > 0.f ? 1 : -1;
-                    out = iy < 0 || iy >= G.ny;
-                } else {
-                    iz += dz > 0.f ? 1 : -1;
-                    out = iz < 0 || iz >= G.nz;
+                done = true;
+            } else {
+                const float tn = csda_energy(P, s_inv, r0 - rho * sl);
+                const float de = fmaxf(t - tn, 0.f);
+                pend_e += de;
+                dep += de;
+                px = fmaf(sl, dx, px);
+                py = fmaf(sl, dy, py);
+                pz = fmaf(sl, dz, pz);
+                path += sl;
+                const float t_old = t;
+                t -= de;
+                bool out = false;
+                if (boundary) {
+                    ++c_bnd;
+                    if (axis == 0) {
+                        ix += dx > 0.f ? 1 : -1;
+                        out = ix < 0 || ix >= G.nx;
+                    } else if (axis == 1) {
+                        iy += dy > 0.f ? 1 : -1;
+                        out = iy < 0 || iy >= G.ny;
+                    } else {
+                        iz += dz > 0.f ? 1 : -1;
+                        out = iz < 0 || iz >= G.nz;
+                    }
+                    if (out) {
+                        esc_e += t;
+                        done = true;
+                    } else {
+                        cur_v = (iz * G.ny + iy) * G.nx + ix;
+                        deposit(a.tally, pend_v, tag, pend_e, c_atom);
+                        pend_v = cur_v;
+                        pend_e = 0.f;
+                    }
                 }
-                if (out) {
-                    esc_e += t;
-                    break;
+                if (!out) {
+                    if (t < tcut) {
+                        pend_e += t;
+                        dep += t;
+                        done = true;
+                    } else if (a.ms) {
+                        // Highland width (PDG) for the step, beta*c*p at the mid-step energy
+                        const float tx = rho * sl * (1.f / kX0Water);
+                        const float tm = 0.5f * (t_old + t);
+                        const float bcp = tm * (tm + 2.f * kMe) / (tm + kMe);
+                        float th0 = 0.f;
+                        if (tx > 0.f)
+                            th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, logf(tx), 1.f), 0.f);
+                        const float u1 = st.next(), u2 = st.next();
+                        const float th = fminf(th0 * sqrtf(-2.f * logf(1.f - u1)), 3.14159265358979f);
+                        float sphi, cphi;
+                        sincospif(2.f * u2, &sphi, &cphi);
+                        rotate(dx, dy, dz, cosf(th), cphi, sphi);
+                    }
                 }
-                cur_v = (iz * G.ny + iy) * G.nx + ix;
-                deposit(a.tally, pend_v, tag, pend_e, c_atom);
-                pend_v = cur_v;
-                pend_e = 0.f;
-            }
-            if (t < tcut) {
-                pend_e += t;
-                dep += t;
-                break;
-            }
-            if (a.ms) {
-                // Highland width (PDG) for the step, beta*c*p at the mid-step energy
-                const float tx = rho * sl * (1.f / kX0Water);
-                const float tm = 0.5f * (t_old + t);
-                const float bcp = tm * (tm + 2.f * kMe) / (tm + kMe);
-                float th0 = 0.f;
-                if (tx > 0.f) th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, logf(tx), 1.f), 0.f);
-                const float u1 = st.next(), u2 = st.next();
-                const float th = fminf(th0 * sqrtf(-2.f * logf(1.f - u1)), 3.14159265358979f);
-                float sphi, cphi;
-                sincospif(2.f * u2, &sphi, &cphi);
-                rotate(dx, dy, dz, cosf(th), cphi, sphi);
             }
         }
-        deposit(a.tally, pend_v, tag, pend_e, c_atom);
+        if (done) {
+            deposit(a.tally, pend_v, tag, pend_e, c_atom);
+            alive = false;
+        }
     }
-    double l1[1] = {esc_e};
-    dev::block_add(a.tally.ledger + L_ESC_E, l1);
-    l1[0] = dep;
-    dev::block_add(a.tally.ledger + L_DEP, l1);
-    l1[0] = path;
-    dev::block_add(a.tally.ledger + L_EPATH, l1);
-    dev::block_add_u64(a.tally.counters + C_E_STEPS, c_steps);
-    dev::block_add_u64(a.tally.counters + C_DEPOSITS, c_atom);
-    dev::block_add_u64(a.tally.counters + C_E_BOUNDARY, c_bnd);
-    dev::block_add_u64(a.tally.counters + C_GUARD, c_guard);
-    dev::block_add_u64(a.tally.counters + C_E_LOCAL, c_local);
+    dev::flush_stats(a.tally.stats, ls);
 }
 
 // ---- small utility kernels (no hipMemsetAsync, so graphs replay cleanly) --
+__global__ void k_reset_queues(uint32_t* el_count, uint32_t* queue) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (el_count) *el_count = 0u;
+        queue[0] = 0u;
+        queue[1] = 0u;
+    }
+}
+
 __global__ void k_zero_u32(uint32_t* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -517,7 +701,7 @@ void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
 
 void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
-                      hipStream_t stream, bool sort_electrons) {
+                      hipStream_t stream, bool sort_electrons, const PhaseEvents* ev) {
     psl_phantom* ph = const_cast<psl_phantom*>(phc);
     TransportArgs a{};
     a.in = to_stack(in);
@@ -532,31 +716,39 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.ms = prm->ms_enable;
     a.seed_lo = uint32_t(seed);
     a.seed_hi = uint32_t(seed >> 32);
+    a.queue = tally->queues.as<uint32_t>();
     Stack estack = a.el;
+    hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream,
+                       in->ptype == 0 ? el->count : nullptr, a.queue);
     if (in->ptype == 0) {
-        launch_zero_u32(el->count, 1, stream);
+        if (ev) PSL_HIP(hipEventRecord(ev->photon0, stream));
         hipLaunchKernelGGL(k_photon, dim3(grid_for(in->capacity, 2048)), dim3(kBlock), 0, stream, a);
         PSL_HIP(hipGetLastError());
+        if (ev) PSL_HIP(hipEventRecord(ev->photon1, stream));
     } else {
         estack = a.in;
     }
     const int eg = grid_for(estack.capacity, 2048);
+    if (ev) PSL_HIP(hipEventRecord(ev->sort0, stream));
     if (sort_electrons) {
         uint32_t* hist = tally->bands.as<uint32_t>();
+        uint32_t* offs = hist + kBands * kSortBlocks;
         uint32_t* perm = tally->perm.as<uint32_t>();
         PSL_CHECK(tally->perm.bytes >= size_t(estack.capacity) * 4, "electron order buffer too small");
-        launch_zero_u32(hist, 2 * kBands, stream);
         const float lt0 = std::log(ph->phys.t_cut);
         const float inv_w = float(kBands) / (std::log(ph->phys.t_max) - lt0);
-        hipLaunchKernelGGL(k_band_count, dim3(eg), dim3(kBlock), 0, stream, estack.e, estack.count,
-                           estack.capacity, hist, lt0, inv_w);
-        hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(64), 0, stream, hist);
-        hipLaunchKernelGGL(k_band_scatter, dim3(eg), dim3(kBlock), 0, stream, estack.e,
-                           estack.count, estack.capacity, hist + kBands, perm, lt0, inv_w);
+        hipLaunchKernelGGL(k_band_count, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
+                           estack.tag, estack.count, estack.capacity, hist, lt0, inv_w);
+        hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(1024), 0, stream, hist, offs);
+        hipLaunchKernelGGL(k_band_scatter, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
+                           estack.tag, estack.count, estack.capacity, offs, perm, lt0, inv_w);
         a.perm = perm;
     }
+    if (ev) PSL_HIP(hipEventRecord(ev->sort1, stream));
+    if (ev) PSL_HIP(hipEventRecord(ev->electron0, stream));
     hipLaunchKernelGGL(k_electron, dim3(eg), dim3(kBlock), 0, stream, a, estack);
     PSL_HIP(hipGetLastError());
+    if (ev) PSL_HIP(hipEventRecord(ev->electron1, stream));
 }
 
 void launch_fold(psl_tally* t, hipStream_t s) {
@@ -637,8 +829,9 @@ extern "C" int psl_tally_create(const psl_phantom* ph, const int32_t* imap, int3
         t->grid.alloc(size_t(t->cells) * 4);
         t->sum.alloc(size_t(t->cells) * 8);
         t->sum2.alloc(size_t(t->cells) * 8);
-        t->stats.alloc(size_t(L_N) * 8 + size_t(C_N) * 8);
-        t->bands.alloc(2 * kBands * 4);
+        t->stats.alloc(size_t(dev::kStripes) * dev::kStatWords * 8);
+        t->bands.alloc(size_t(2) * kBands * kSortBlocks * 4);
+        t->queues.alloc(256);
         t->col_w.alloc(size_t(t->n_cols) * 8);
         if (imap) {
             t->row_rho.alloc(size_t(n_rows) * 4);
@@ -703,8 +896,8 @@ extern "C" int tally_dose(psl_tally* t, int32_t ops, const psl_plan* plan, doubl
                                t->sum.as<double>(), t->cells);
             hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(t->cells)), dim3(kBlock), 0, s,
                                t->sum2.as<double>(), t->cells);
-            hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, s, t->stats.as<double>(),
-                               int64_t(L_N + C_N));
+            hipLaunchKernelGGL(k_zero<double>, dim3(4), dim3(kBlock), 0, s, t->stats.as<double>(),
+                               int64_t(dev::kStripes) * dev::kStatWords);
             PSL_HIP(hipGetLastError());
         }
         if (ops & PSL_TALLY_FOLD) launch_fold(t, s);
@@ -741,10 +934,17 @@ extern "C" int psl_tally_stats(psl_tally* t, double* ledger, uint64_t* counters)
     int rc = guarded([&] {
         PSL_CHECK(t, "psl_tally_stats: null tally");
         PSL_HIP(hipDeviceSynchronize());
-        std::vector<double> buf(L_N + C_N);
+        std::vector<double> buf(size_t(dev::kStripes) * dev::kStatWords);
         PSL_HIP(hipMemcpy(buf.data(), t->stats.p, buf.size() * 8, hipMemcpyDeviceToHost));
-        if (ledger) std::memcpy(ledger, buf.data(), L_N * 8);
-        const uint64_t* c = reinterpret_cast<const uint64_t*>(buf.data() + L_N);
+        double led[L_N] = {0};
+        uint64_t c[C_N] = {0};
+        for (int k = 0; k < dev::kStripes; ++k) {
+            const double* row = buf.data() + size_t(k) * dev::kStatWords;
+            for (int i = 0; i < L_N; ++i) led[i] += row[i];
+            const uint64_t* cr = reinterpret_cast<const uint64_t*>(row + L_N);
+            for (int i = 0; i < C_N; ++i) c[i] += cr[i];
+        }
+        if (ledger) std::memcpy(ledger, led, L_N * 8);
         if (counters) std::memcpy(counters, c, C_N * 8);
         if (c[C_OVERFLOW]) {
             status = PSL_EOVERFLOW;

@@ -1,0 +1,337 @@
+// Batched runtime: runs every batch of every replica of a plan (Sec. 2.1.3:
+// sampling and transport kernels iterated, one particle type per batch) as one
+// stream of launches, optionally captured once into a hipGraph and replayed,
+// with the particle stacks owned by the tally's workspace.  Also the autotuner
+// that picks the batch size and the energy-band width from measured times.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "common.hpp"
+
+namespace psl {
+namespace {
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void k_inc_u32(uint32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1u;
+}
+
+enum Phase { kSample = 0, kPhoton, kSort, kElectron, kFold, kPhases };
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// One structure-of-arrays stack carved out of a single allocation.
+void carve(DevBuf& mem, uint32_t cap, psl_particles& p) {
+    const size_t f = align256(size_t(cap) * 4), h = align256(size_t(cap) * 8);
+    mem.alloc(7 * f + h + f + 256);
+    char* b = mem.as<char>();
+    float** fl[7] = {&p.x, &p.y, &p.z, &p.u, &p.v, &p.w, &p.e};
+    for (int i = 0; i < 7; ++i) *fl[i] = reinterpret_cast<float*>(b + i * f);
+    p.hid = reinterpret_cast<uint64_t*>(b + 7 * f);
+    p.tag = reinterpret_cast<uint32_t*>(b + 7 * f + h);
+    p.count = reinterpret_cast<uint32_t*>(b + 7 * f + h + f);
+    p.capacity = cap;
+    p.ptype = 0;
+}
+
+struct GraphKey {
+    const psl_plan* plan = nullptr;
+    const psl_phantom* phantom = nullptr;
+    uint32_t max_batch = 0;
+    int32_t band_width = 0, sort = 0, timing = 0;
+    uint32_t rep0 = 0, n_rep = 0;
+    uint64_t seed = 0, n_hist = 0;
+    float cut_e = 0, cut_g = 0, frac = 0;
+    int32_t ms = 0;
+    uint32_t ph_cap = 0, el_cap = 0;
+    uint64_t n_batches = 0;
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
+};
+
+}  // namespace
+
+struct Runner {
+    uint32_t ph_cap = 0, el_cap = 0;
+    DevBuf ph_mem, el_mem, rep;
+    psl_particles phs{}, els{};
+    hipStream_t cs = nullptr;
+    hipEvent_t start = nullptr, done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphKey key{};
+    bool have_graph = false;
+    // timing: (phase, start, end) for every timed launch of the last run
+    std::vector<hipEvent_t> pool;
+    std::vector<std::array<int, 3>> timed;
+    size_t pool_used = 0;
+
+    ~Runner() {
+        drop_graph();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        if (start) (void)hipEventDestroy(start);
+        if (done) (void)hipEventDestroy(done);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        have_graph = false;
+    }
+    void init() {
+        if (!cs) {
+            PSL_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            PSL_HIP(hipEventCreate(&start));
+            PSL_HIP(hipEventCreate(&done));
+            rep.alloc(256);
+        }
+    }
+    void ensure_stacks(uint32_t ph, uint32_t el) {
+        if (ph > ph_cap) {
+            drop_graph();
+            carve(ph_mem, ph, phs);
+            ph_cap = ph;
+        }
+        if (el > el_cap) {
+            drop_graph();
+            carve(el_mem, el, els);
+            el_cap = el;
+        }
+    }
+    hipEvent_t event() {
+        if (pool_used == pool.size()) {
+            hipEvent_t e;
+            PSL_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[pool_used++];
+    }
+    int timed_pair(int phase) {
+        const int a = int(pool_used);
+        event();
+        event();
+        timed.push_back({phase, a, a + 1});
+        return int(timed.size()) - 1;
+    }
+};
+
+namespace {
+
+// Enqueues all launches of replicas [rep0, rep0 + n_rep) on stream s.
+void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
+             const psl_transport_params* prm, const psl_run_opts& o, uint32_t rep0, uint32_t n_rep,
+             hipStream_t s) {
+    uint32_t* rep = R.rep.as<uint32_t>();
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, rep, rep0);
+    const size_t nb = plan->batches.size();
+    for (uint32_t r = 0; r < n_rep; ++r) {
+        for (size_t i = 0; i < nb; ++i) {
+            const psl_batch& b = plan->batches[i];
+            R.phs.ptype = b.stype == 2 ? 1 : 0;
+            int ts = -1;
+            if (o.timing) {
+                ts = R.timed_pair(kSample);
+                PSL_HIP(hipEventRecord(R.pool[R.timed[ts][1]], s));
+            }
+            // dense output, tags only for rejected histories: no stack atomics
+            launch_sample(plan, ph, 0, rep, b.h0, b.n, plan->batch_jlo[i], plan->batch_jhi[i],
+                          b.stype, o.seed, &R.phs, 2, tally, s);
+            if (o.timing) PSL_HIP(hipEventRecord(R.pool[R.timed[ts][2]], s));
+            PhaseEvents ev{};
+            if (o.timing) {
+                const int tp = b.stype == 2 ? -1 : R.timed_pair(kPhoton);
+                const int tso = R.timed_pair(kSort);
+                const int tel = R.timed_pair(kElectron);
+                if (tp >= 0) {
+                    ev.photon0 = R.pool[R.timed[tp][1]];
+                    ev.photon1 = R.pool[R.timed[tp][2]];
+                }
+                ev.sort0 = R.pool[R.timed[tso][1]];
+                ev.sort1 = R.pool[R.timed[tso][2]];
+                ev.electron0 = R.pool[R.timed[tel][1]];
+                ev.electron1 = R.pool[R.timed[tel][2]];
+            }
+            launch_transport(ph, &R.phs, &R.els, tally, prm, o.seed, s, o.sort_electrons != 0,
+                             o.timing ? &ev : nullptr);
+        }
+        int tf = -1;
+        if (o.timing) {
+            tf = R.timed_pair(kFold);
+            PSL_HIP(hipEventRecord(R.pool[R.timed[tf][1]], s));
+        }
+        launch_fold(tally, s);
+        if (o.timing) PSL_HIP(hipEventRecord(R.pool[R.timed[tf][2]], s));
+        hipLaunchKernelGGL(k_inc_u32, dim3(1), dim3(64), 0, s, rep);
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
+              const psl_transport_params* prm, const psl_run_opts& o, uint32_t rep0,
+              uint32_t n_rep, hipStream_t user) {
+    PSL_CHECK(o.max_batch >= 64, "max_batch must be >= 64");
+    PSL_CHECK(o.band_width >= 1, "band_width must be >= 1");
+    PSL_CHECK(tally->phantom == ph, "tally belongs to another phantom");
+    PSL_CHECK(prm->e_cut_photon > 0.f && prm->e_cut_electron > 0.f && prm->step_frac > 0.f &&
+                  prm->step_frac < 1.f,
+              "bad transport parameters");
+    PSL_CHECK(tally->imap || plan->n_cols == 1 ||
+                  std::all_of(plan->col_weight.begin(), plan->col_weight.end(),
+                              [&](double c) { return c == plan->col_weight[0]; }),
+              "a voxel tally needs an Eq. (3) plan");
+    PSL_CHECK(!tally->imap || plan->n_cols <= tally->n_cols, "plan has more columns than the tally");
+    if (!tally->runner) tally->runner = new Runner();
+    Runner& R = *tally->runner;
+    R.init();
+    if (plan->cur_max_batch != o.max_batch || plan->cur_band_width != o.band_width) {
+        int64_t nb = 0;
+        const int rc = psl_plan_set_batching(plan, o.max_batch, o.band_width, &nb);
+        if (rc != PSL_OK) fail(rc, "%s", psl_last_error());
+    }
+    // every push costs the photon at least the electron cut-off; one more
+    // entry per photon covers the unused ends of the waves' reserved chunks
+    const double emax = plan->model->e_max;
+    const uint32_t per = uint32_t(std::max(1.0, std::floor(emax / prm->e_cut_electron))) + 1;
+    const uint64_t el_need = uint64_t(o.max_batch) * per;
+    PSL_CHECK(el_need < (uint64_t(1) << 32), "electron stack would exceed 2^32 entries");
+    R.ensure_stacks(o.max_batch, uint32_t(el_need));
+    ensure_physics(const_cast<psl_phantom*>(ph), prm);
+    ensure_device(plan);
+    ensure_perm(tally, std::max(R.ph_cap, R.el_cap));
+
+    R.timed.clear();
+    R.pool_used = 0;
+    // HIP events recorded inside a captured graph carry no timestamps, so a
+    // timed run always launches eagerly, with an event pair around each kernel
+    if (!o.use_graph || o.timing) {
+        enqueue(R, plan, ph, tally, prm, o, rep0, n_rep, user);
+        PSL_HIP(hipEventRecord(R.done, user));
+        return;
+    }
+    GraphKey k;
+    std::memset(&k, 0, sizeof k);   // padding takes part in the comparison
+    k.plan = plan;
+    k.phantom = ph;
+    k.max_batch = o.max_batch;
+    k.band_width = o.band_width;
+    k.sort = o.sort_electrons;
+    k.timing = o.timing;
+    k.rep0 = rep0;
+    k.n_rep = n_rep;
+    k.seed = o.seed;
+    k.n_hist = plan->n_hist;
+    k.cut_e = prm->e_cut_electron;
+    k.cut_g = prm->e_cut_photon;
+    k.frac = prm->step_frac;
+    k.ms = prm->ms_enable;
+    k.ph_cap = R.ph_cap;
+    k.el_cap = R.el_cap;
+    k.n_batches = plan->batches.size();
+    if (!(R.have_graph && R.key == k)) {
+        R.drop_graph();
+        PSL_HIP(hipStreamBeginCapture(R.cs, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue(R, plan, ph, tally, prm, o, rep0, n_rep, R.cs);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(R.cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        PSL_HIP(hipStreamEndCapture(R.cs, &R.graph));
+        PSL_HIP(hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0));
+        std::memcpy(&R.key, &k, sizeof k);
+        R.have_graph = true;
+    }
+    PSL_HIP(hipEventRecord(R.start, user));
+    PSL_HIP(hipStreamWaitEvent(R.cs, R.start, 0));
+    PSL_HIP(hipGraphLaunch(R.exec, R.cs));
+    PSL_HIP(hipEventRecord(R.done, R.cs));
+    PSL_HIP(hipStreamWaitEvent(user, R.done, 0));
+}
+
+}  // namespace
+}  // namespace psl
+
+using namespace psl;
+
+psl_tally::~psl_tally() { delete runner; }
+
+extern "C" int psl_run(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
+                       const psl_transport_params* params, const psl_run_opts* opts, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(plan && phantom && tally && params && opts, "psl_run: null argument");
+        run_impl(plan, phantom, tally, params, *opts, 0, plan->n_replica,
+                 static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" int psl_run_get_timing(psl_tally* tally, psl_run_timing* out) {
+    return guarded([&] {
+        PSL_CHECK(tally && out, "null argument");
+        std::memset(out, 0, sizeof *out);
+        if (!tally->runner) return;
+        Runner& R = *tally->runner;
+        PSL_HIP(hipEventSynchronize(R.done));
+        PSL_HIP(hipDeviceSynchronize());
+        for (const auto& t : R.timed) {
+            float ms = 0.f;
+            PSL_HIP(hipEventElapsedTime(&ms, R.pool[t[1]], R.pool[t[2]]));
+            out->ms[t[0]] += ms;
+            out->launches[t[0]] += 1;
+        }
+    });
+}
+
+extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
+                            const psl_transport_params* params, uint64_t seed,
+                            const uint32_t* max_batch, int32_t n_m, const int32_t* band_width,
+                            int32_t n_w, uint32_t replica, psl_run_opts* best, double* ms_out) {
+    return guarded([&] {
+        PSL_CHECK(plan && phantom && tally && params && max_batch && band_width && best,
+                  "psl_autotune: null argument");
+        PSL_CHECK(n_m >= 1 && n_w >= 1, "empty candidate set");
+        PSL_CHECK(replica < plan->n_replica, "replica out of range");
+        hipEvent_t e0, e1;
+        PSL_HIP(hipEventCreate(&e0));
+        PSL_HIP(hipEventCreate(&e1));
+        double best_ms = 1e300;
+        for (int i = 0; i < n_m; ++i)
+            for (int j = 0; j < n_w; ++j)
+                for (int srt = 0; srt < 2; ++srt) {
+                    psl_run_opts o{};
+                    o.max_batch = max_batch[i];
+                    o.band_width = band_width[j];
+                    o.use_graph = 1;
+                    o.sort_electrons = srt;
+                    o.timing = 0;
+                    o.seed = seed;
+                    // first launch captures and warms up, the second is timed
+                    run_impl(plan, phantom, tally, params, o, replica, 1, nullptr);
+                    PSL_HIP(hipEventRecord(e0, nullptr));
+                    run_impl(plan, phantom, tally, params, o, replica, 1, nullptr);
+                    PSL_HIP(hipEventRecord(e1, nullptr));
+                    PSL_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms_out) ms_out[(i * n_w + j) * 2 + srt] = ms;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        *best = o;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        const int rc = tally_dose(tally, PSL_TALLY_RESET, nullptr, nullptr, nullptr, nullptr);
+        if (rc != PSL_OK) fail(rc, "%s", psl_last_error());
+        PSL_HIP(hipDeviceSynchronize());
+        if (tally->runner) tally->runner->drop_graph();
+    });
+}

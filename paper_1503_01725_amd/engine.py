@@ -230,8 +230,9 @@ def transport_params(e_cut_electron=0.2, e_cut_photon=0.01, step_frac=0.1, ms=Tr
 
 def electron_capacity(photon_capacity, e_max, e_cut_electron):
     """Electron stack size that can never overflow: a photon pays at least the
-    electron cut-off for every electron it sets in motion."""
-    return int(photon_capacity * max(1, int(np.floor(e_max / e_cut_electron))))
+    electron cut-off for every electron it sets in motion, and one more entry
+    per photon covers the unused ends of the per-wave chunks."""
+    return int(photon_capacity * (max(1, int(np.floor(e_max / e_cut_electron))) + 1))
 
 
 def run_plan_eager(plan: Plan, phantom: Phantom, tally: Tally, params, seed, max_batch=131072,
@@ -253,3 +254,34 @@ def run_plan_eager(plan: Plan, phantom: Phantom, tally: Tally, params, seed, max
             N.sample_batch(plan.h, phantom.h, r, b.h0, b.n, seed, ph_stack.c, 0, tally.h, s)
             N.transport_batch(phantom.h, ph_stack.c, el_stack.c, tally.h, params, seed, s)
         tally.op(N.PSL_TALLY_FOLD, stream=stream)
+
+
+def run_opts(max_batch=131072, band_width=1, use_graph=True, sort_electrons=True, timing=False,
+             seed=0):
+    return N.psl_run_opts(int(max_batch), int(band_width), 1 if use_graph else 0,
+                          1 if sort_electrons else 0, 1 if timing else 0, int(seed))
+
+
+def run_plan(plan: Plan, phantom: Phantom, tally: Tally, params, opts, stream=None):
+    """All batches of all replicas through the native runtime (psl_run)."""
+    N.psl_run(plan.h, phantom.h, tally.h, params, opts, _stream_ptr(stream))
+
+
+def autotune(plan: Plan, phantom: Phantom, tally: Tally, params, seed,
+             max_batches=(65536, 131072, 262144, 524288), band_widths=(1, 2, 4)):
+    return N.psl_autotune(plan.h, phantom.h, tally.h, params, seed, max_batches, band_widths)
+
+
+def commission_nnls(A, b, x0=None, delta=1e-10, pg_tol=1e-8, sigma=1e-4, beta=0.5,
+                    max_iter=100000):
+    """Eq. (8) by gradient projection + Armijo on the GPU (FP64)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    m, n = A.shape
+    a_flat = np.ascontiguousarray(A.T).ravel()        # column-major storage
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.ones(n) if x0 is None else np.array(x0, dtype=np.float64)
+    opts = N.psl_nnls_opts(delta, pg_tol, sigma, beta, max_iter)
+    rep = N.psl_nnls_report()
+    rc = N.commission_nnls(a_flat.ctypes.data_as(N.dp), m, n, b.ctypes.data_as(N.dp),
+                           x.ctypes.data_as(N.dp), opts, rep)
+    return x, dict(iters=int(rep.iters), f=rep.f, pg=rep.pg_norm, converged=rc == N.PSL_OK)

@@ -1,0 +1,88 @@
+"""GPU tests of the batched runtime (psl_run with and without hipGraph replay,
+timing, autotuner) and of the FP64 commissioning solve."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(eng, wl, name="water60_10x10", n_hist=10000, n_rep=3):
+    W = wl.workload(name)
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, n_hist, n_replica=n_rep)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    return W, model, plan, ph, tally
+
+
+def _dose(eng, N, tally, plan):
+    import torch
+    d, s = tally.finalize(plan)
+    torch.cuda.synchronize()
+    return d.cpu().numpy().ravel(), s.cpu().numpy().ravel(), tally.stats()
+
+
+def test_graph_run_equals_eager_loop(eng, N, wl):
+    W, model, plan, ph, tally = _setup(eng, wl)
+    prm = eng.transport_params()
+    eng.run_plan_eager(plan, ph, tally, prm, 77, max_batch=20000, band_width=2)
+    d0, s0, (led0, cnt0) = _dose(eng, N, tally, plan)
+    for graph in (False, True, True):          # eager, captured, cached replay
+        tally.op(N.PSL_TALLY_RESET)
+        eng.run_plan(plan, ph, tally, prm, eng.run_opts(20000, 2, use_graph=graph, seed=77))
+        d, s, (led, cnt) = _dose(eng, N, tally, plan)
+        assert cnt["hist"] == cnt0["hist"] and cnt["folds"] == 3
+        assert cnt["real"] == cnt0["real"] and cnt["e_steps"] == cnt0["e_steps"]
+        assert led["dep"] == pytest.approx(led0["dep"], rel=1e-6)
+        hi = d0 > 0.01 * d0.max()
+        assert np.allclose(d[hi], d0[hi], rtol=1e-4)
+
+
+def test_run_timing_counts_launches(eng, N, wl):
+    W, model, plan, ph, tally = _setup(eng, wl, n_rep=2)
+    prm = eng.transport_params()
+    opts = eng.run_opts(8192, 1, use_graph=True, timing=True, seed=5)
+    for _ in range(2):
+        tally.op(N.PSL_TALLY_RESET)
+        eng.run_plan(plan, ph, tally, prm, opts)
+        t = N.psl_run_get_timing(tally.h)
+    nb = plan.set_batching(8192, 1)
+    n_photon = sum(1 for i in range(nb) if plan.batch(i).stype != 2)
+    assert t["sample"][1] == 2 * nb and t["electron"][1] == 2 * nb
+    assert t["photon"][1] == 2 * n_photon and t["fold"][1] == 2
+    assert all(v[0] > 0 for k, v in t.items() if k != "sort")
+
+
+def test_autotuner_picks_a_candidate(eng, N, wl):
+    W, model, plan, ph, tally = _setup(eng, wl, n_rep=2)
+    prm = eng.transport_params()
+    best, ms = eng.autotune(plan, ph, tally, prm, 3, (4096, 32768), (1, 4))
+    assert (best.max_batch, best.band_width) in {(4096, 1), (4096, 4), (32768, 1), (32768, 4)}
+    assert ms.shape == (2, 2, 2) and np.all(ms > 0)
+    assert ms.min() == pytest.approx(ms[[4096, 32768].index(best.max_batch),
+                                         [1, 4].index(best.band_width), best.sort_electrons])
+    led, cnt = tally.stats()
+    assert cnt["hist"] == 0                       # the tally was reset
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_commission_nnls_matches_oracle(eng, orc, seed):
+    rng = np.random.default_rng(seed)
+    m, n = 300, 80
+    A = rng.uniform(0, 1, (m, n)) + 0.1 * np.eye(m, n)
+    x_true = rng.uniform(-0.5, 1.5, n)
+    b = A @ x_true + 0.01 * rng.standard_normal(m)
+    x, rep = eng.commission_nnls(A, b)
+    xo, repo = orc.nnls_gp(A, b)
+    assert rep["converged"] and repo["converged"]
+    assert rep["f"] == pytest.approx(repo["f"], rel=1e-9)
+    assert np.allclose(x, xo, atol=2e-5 * np.abs(xo).max())
+    assert np.array_equal(x == 0, xo == 0)
+
+
+def test_commission_nnls_reports_iteration_limit(eng, N):
+    rng = np.random.default_rng(4)
+    A = rng.uniform(0, 1, (40, 30))
+    b = rng.uniform(0, 1, 40)
+    x, rep = eng.commission_nnls(A, b, max_iter=2)
+    assert not rep["converged"] and rep["iters"] == 2
