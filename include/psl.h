@@ -355,6 +355,47 @@ typedef struct {
 int commission_nnls(const double* A, int64_t m, int64_t n, const double* b, double* x,
                     const psl_nnls_opts* opts, psl_nnls_report* report);
 
+/* ------------------------------------------------------------------------
+ * Learned 3D dose denoiser (not part of the paper's method): a 4-level U-Net
+ * with c, 2c, 4c, 8c channels (two 3x3x3 conv + ReLU per level, 2x2x2 max
+ * pooling down, 2x2x2 stride-2 transposed conv up, skip concatenation, 1x1x1
+ * head plus the input dose), BF16 activations and weights on MFMA with FP32
+ * accumulation, FP32 master weights, Adam on the mean squared error.
+ * ------------------------------------------------------------------------ */
+typedef struct psl_unet psl_unet;
+
+/* Network for volumes of d x h x w voxels (multiples of 8) and base width
+ * c in {8, 16, 32}; allocates all activation buffers.  Synchronous. */
+int psl_unet_create(int32_t base_width, int32_t d, int32_t h, int32_t w, psl_unet** out);
+void psl_unet_free(psl_unet* net);
+
+/* Number of FP32 parameters.  Flat layout (host arrays), in this order: per
+ * encoder level k = 0..3 conv a, conv b; per decoder level k = 2, 1, 0 the
+ * transposed conv, conv a, conv b; the head.  Each conv: weights
+ * [c_out][c_in][3][3][3] then bias [c_out]; each transposed conv: weights
+ * [c_in][c_out][2][2][2] then bias [c_out]; head: weights [c] then bias [1].
+ * The decoder's conv a reads [skip channels | upsampled channels]. */
+int psl_unet_param_count(const psl_unet* net, int64_t* n);
+/* Copies FP32 parameters in (resets the Adam state) / out. Synchronous. */
+int psl_unet_set_params(psl_unet* net, const float* host);
+int psl_unet_get_params(const psl_unet* net, float* host);
+
+/* input_dev: device FP32 [2][d][h][w] (dose scaled by its maximum, density);
+ * pred_dev: device FP32 [d][h][w] (scaled dose).  Asynchronous. */
+int psl_unet_forward(psl_unet* net, const float* input_dev, float* pred_dev, void* stream);
+
+/* Forward + backward + one Adam step (beta 0.9 / 0.999, eps 1e-8) at learning
+ * rate lr.  target_dev: device FP32 [d][h][w].  If loss_dev (device FP64
+ * [64]) is given it receives partial sums whose total is the MSE before the
+ * step.  Asynchronous. */
+int psl_unet_train_step(psl_unet* net, const float* input_dev, const float* target_dev, float lr,
+                        double* loss_dev, void* stream);
+
+/* Loss and FP32 gradients (host, flat layout above) without an update; for
+ * checking the backward kernels.  Synchronous. */
+int psl_unet_gradients(psl_unet* net, const float* input_dev, const float* target_dev,
+                       float* grads_host, double* loss);
+
 #ifdef __cplusplus
 }
 #endif

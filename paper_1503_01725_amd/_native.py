@@ -121,6 +121,17 @@ _SIGS.update({
     "psl_autotune": [vp, vp, vp, P(psl_transport_params), C.c_uint64, u32p, C.c_int32, i32p,
                      C.c_int32, C.c_uint32, P(psl_run_opts), dp],
 })
+_SIGS.update({
+    "psl_unet_create": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(vp)],
+    "psl_unet_free": [vp],
+    "psl_unet_param_count": [vp, P(C.c_int64)],
+    "psl_unet_set_params": [vp, fp],
+    "psl_unet_get_params": [vp, fp],
+    "psl_unet_forward": [vp, vp, vp, vp],
+    "psl_unet_train_step": [vp, vp, vp, C.c_float, vp, vp],
+    "psl_unet_gradients": [vp, vp, vp, fp, dp],
+})
+_RESTYPE["psl_unet_free"] = None
 _OPTIONAL = {}
 
 _lib = None

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
 SOURCES = ["host_model.cpp", "physics.cpp", "k_sample.hip", "k_transport.hip", "runtime.hip",
-           "k_nnls.hip"]
+           "k_nnls.hip", "k_denoise.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}",

@@ -155,6 +155,7 @@ struct PhantomDev {
 };
 
 struct Runner;   // batched-runtime workspace (runtime.hip)
+struct UNet;     // denoiser (k_denoise.hip)
 
 }  // namespace psl
 

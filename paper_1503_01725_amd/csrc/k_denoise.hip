@@ -1,0 +1,867 @@
+// Learned 3D dose denoiser: a 4-level U-Net (two 3x3x3 conv + ReLU per level,
+// 2x2x2 max pooling down, 2x2x2 stride-2 transposed conv up, skip
+// concatenation, 1x1x1 head plus the scaled input dose) trained with Adam on
+// MSE.  Activations and weights are BF16 in channels-last layout
+// ([position][channel]); every convolution is an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation; weight gradients and the
+// master weights are FP32.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+
+namespace psl {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLevels = 4;
+constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return uint16_t(u >> 16);   // inf / nan
+    u += 0x7FFFu + ((u >> 16) & 1u);                                  // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+// A channels-last BF16 view: element (pos, c) at p[pos * stride + off + c].
+struct View {
+    uint16_t* p;
+    int D, H, W, C, stride, off;
+};
+
+enum Mode { kConvFwd = 0, kConvBwdData, kConvWgrad, kTconvFwd, kTconvBwdData, kTconvWgrad };
+
+struct GemmArgs {
+    View a;              // conv/tconv input (fwd, wgrad) or output gradient (bwd-data)
+    View b;              // output (fwd, bwd-data) or output gradient (wgrad)
+    const uint16_t* wt;  // packed weights B^T [N][K] (fwd / bwd-data)
+    const float* bias;   // fwd: [C_out]
+    View mask;           // bwd-data: multiply by (mask > 0) if mask.p
+    float* wgrad;        // wgrad: FP32 gradient in the reference layout
+    int M, N, K;
+    int cin, cout;       // channels of the layer (real, not padded)
+    int relu;
+    int k_per_split;     // wgrad: positions per blockIdx.z
+};
+
+__device__ __forceinline__ void pos3(int m, int D, int H, int W, int& z, int& y, int& x) {
+    x = m % W;
+    const int t = m / W;
+    y = t % H;
+    z = t / H;
+}
+
+__device__ __forceinline__ uint4 load8(const View& v, int pos, int c) {
+    return *reinterpret_cast<const uint4*>(v.p + size_t(pos) * v.stride + v.off + c);
+}
+
+// 8 consecutive K values of row `row` (direct loads) ------------------------
+template <int MODE>
+__device__ __forceinline__ uint4 load_a_row(const GemmArgs& g, int m, int k) {
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    if (m >= g.M || k >= g.K) return zero;
+    const View& v = g.a;
+    if (MODE == kConvFwd || MODE == kConvBwdData) {
+        const int tap = k / v.C, c = k - tap * v.C;
+        int z, y, x;
+        pos3(m, v.D, v.H, v.W, z, y, x);
+        z += tap / 9 - 1;
+        y += (tap / 3) % 3 - 1;
+        x += tap % 3 - 1;
+        if (z < 0 || z >= v.D || y < 0 || y >= v.H || x < 0 || x >= v.W) return zero;
+        return load8(v, (z * v.H + y) * v.W + x, c);
+    } else if (MODE == kTconvFwd) {
+        return load8(v, m, k);
+    } else {   // kTconvBwdData: m is a coarse voxel, v the fine-grid gradient;
+               // k = abc * cout + o picks child abc, channel o
+        const int abc = k / g.cout, o = k - abc * g.cout;
+        int z, y, x;
+        pos3(m, v.D >> 1, v.H >> 1, v.W >> 1, z, y, x);
+        const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1), cx = 2 * x + (abc & 1);
+        return load8(v, (cz * v.H + cy) * v.W + cx, o);
+    }
+}
+
+// 8 consecutive rows at one K value (transposed loads, weight gradients) ----
+// A rows: output channels (conv) / input channels (tconv) at position k.
+template <int MODE>
+__device__ __forceinline__ uint4 load_a_col(const GemmArgs& g, int row, int k) {
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    if (row >= g.M || k >= g.K) return zero;
+    if (MODE == kConvWgrad) return load8(g.b, k, row);     // dY[pos][o..o+7]
+    return load8(g.a, k, row);                             // tconv: X[pos][c..c+7]
+}
+
+// B^T rows n..n+7 at position k.
+template <int MODE>
+__device__ __forceinline__ uint4 load_b_col(const GemmArgs& g, int n, int k) {
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    if (n >= g.N || k >= g.K) return zero;
+    int z, y, x;
+    if (MODE == kConvWgrad) {
+        const View& v = g.a;
+        const int tap = n / v.C, c = n - tap * v.C;
+        pos3(k, v.D, v.H, v.W, z, y, x);
+        z += tap / 9 - 1;
+        y += (tap / 3) % 3 - 1;
+        x += tap % 3 - 1;
+        if (z < 0 || z >= v.D || y < 0 || y >= v.H || x < 0 || x >= v.W) return zero;
+        return load8(v, (z * v.H + y) * v.W + x, c);
+    } else {   // kTconvWgrad: n = abc * cout + o, dY at the child voxel of position k
+        const View& v = g.a;   // coarse grid
+        const int abc = n / g.cout, o = n - abc * g.cout;
+        pos3(k, v.D, v.H, v.W, z, y, x);
+        const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1), cx = 2 * x + (abc & 1);
+        return load8(g.b, (cz * (2 * v.H) + cy) * (2 * v.W) + cx, o);
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    __shared__ uint16_t As[kBM][kBK + kLdsPad];
+    __shared__ uint16_t Bs[kBN][kBK + kLdsPad];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
+    constexpr bool kWgrad = MODE == kConvWgrad || MODE == kTconvWgrad;
+    int k_lo = 0, k_hi = g.K;
+    if (kWgrad) {
+        k_lo = blockIdx.z * g.k_per_split;
+        k_hi = min(g.K, k_lo + g.k_per_split);
+    }
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+
+    for (int k0 = k_lo; k0 < k_hi; k0 += kBK) {
+        if (!kWgrad) {
+            // direct: row = t/4, 8 K values at (t%4)*8
+            const int r = t >> 2, kc = (t & 3) << 3;
+            const uint4 av = load_a_row<MODE>(g, m0 + r, k0 + kc);
+            *reinterpret_cast<uint4*>(&As[r][kc]) = av;
+            uint4 bv = {0u, 0u, 0u, 0u};
+            if (n0 + r < g.N && k0 + kc < g.K)
+                bv = *reinterpret_cast<const uint4*>(g.wt + size_t(n0 + r) * g.K + k0 + kc);
+            *reinterpret_cast<uint4*>(&Bs[r][kc]) = bv;
+        } else {
+            // transposed: 8 rows at (t%8)*8, one K value t/8 (positions beyond k_hi are zero)
+            const int rc = (t & 7) << 3, kk = t >> 3;
+            const int kpos = k0 + kk;
+            const bool in = kpos < k_hi;
+            uint4 av = {0u, 0u, 0u, 0u}, bv = {0u, 0u, 0u, 0u};
+            if (in) {
+                av = load_a_col<MODE>(g, m0 + rc, kpos);
+                bv = load_b_col<MODE>(g, n0 + rc, kpos);
+            }
+            const uint16_t* ae = reinterpret_cast<const uint16_t*>(&av);
+            const uint16_t* be = reinterpret_cast<const uint16_t*>(&bv);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                As[rc + j][kk] = ae[j];
+                Bs[rc + j][kk] = be[j];
+            }
+        }
+        __syncthreads();
+        const int lr = lane & 15, kq = (lane >> 4) << 3;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const uint4 araw = *reinterpret_cast<const uint4*>(&As[wr + 16 * i + lr][kq]);
+            const bf16x8 a = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint4 braw = *reinterpret_cast<const uint4*>(&Bs[wc + 16 * j + lr][kq]);
+                const bf16x8 b = __builtin_bit_cast(bf16x8, braw);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + wr + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + wc + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][e];
+                if (MODE == kConvFwd) {
+                    v += g.bias[n];
+                    if (g.relu) v = fmaxf(v, 0.f);
+                    g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(v);
+                } else if (MODE == kConvBwdData || MODE == kTconvBwdData) {
+                    if (g.mask.p && !(bf2f(g.mask.p[size_t(m) * g.mask.stride + g.mask.off + n]) > 0.f))
+                        v = 0.f;
+                    g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(v);
+                } else if (MODE == kTconvFwd) {
+                    const int abc = n / g.cout, o = n - abc * g.cout;
+                    int z, y, x;
+                    pos3(m, g.a.D, g.a.H, g.a.W, z, y, x);
+                    const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1),
+                              cx = 2 * x + (abc & 1);
+                    const size_t child = (size_t(cz) * (2 * g.a.H) + cy) * (2 * g.a.W) + cx;
+                    g.b.p[child * g.b.stride + g.b.off + o] = f2bf(v + g.bias[o]);
+                } else if (MODE == kConvWgrad) {
+                    // row m = output channel, column n = tap * C_in_padded + c
+                    const int tap = n / g.a.C, c = n - tap * g.a.C;
+                    if (c < g.cin && v != 0.f)
+                        atomicAdd(g.wgrad + (size_t(m) * g.cin + c) * 27 + tap, v);
+                } else {   // kTconvWgrad: row m = input channel, column n = abc * cout + o
+                    const int abc = n / g.cout, o = n - abc * g.cout;
+                    if (v != 0.f) atomicAdd(g.wgrad + (size_t(m) * g.cout + o) * 8 + abc, v);
+                }
+            }
+}
+
+// ---- element-wise / reduction kernels ---------------------------------------
+// input [2][P] FP32 (scaled dose, density) -> x0 [P][8] BF16 (channels 2..7 zero)
+__global__ void k_pack_input(const float* in, int P, uint16_t* x0) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        uint16_t v[8] = {f2bf(in[p]), f2bf(in[P + p]), 0, 0, 0, 0, 0, 0};
+        *reinterpret_cast<uint4*>(x0 + size_t(p) * 8) = *reinterpret_cast<uint4*>(v);
+    }
+}
+
+// 2x2x2 max pooling of view `in` (fine) into `out` (coarse); argmax = first
+// maximum in (z, y, x) order of the block
+__global__ void k_pool_fwd(View in, View out, uint8_t* arg) {
+    const int C = in.C;
+    const int total = out.D * out.H * out.W * C;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int c = i % C, q = i / C;
+        int z, y, x;
+        pos3(q, out.D, out.H, out.W, z, y, x);
+        float best = -INFINITY;
+        int bi = 0;
+        for (int a = 0; a < 8; ++a) {
+            const int fz = 2 * z + (a >> 2), fy = 2 * y + ((a >> 1) & 1), fx = 2 * x + (a & 1);
+            const float v = bf2f(in.p[size_t((fz * in.H + fy) * in.W + fx) * in.stride + in.off + c]);
+            if (v > best) {
+                best = v;
+                bi = a;
+            }
+        }
+        out.p[size_t(q) * out.stride + out.off + c] = f2bf(best);
+        arg[i] = uint8_t(bi);
+    }
+}
+
+// gradient of the fine level: routed pool gradient + skip gradient, masked by
+// the ReLU output `h` of that level
+__global__ void k_pool_bwd(View gcoarse, const uint8_t* arg, View gskip, View h, View gfine) {
+    const int C = gfine.C;
+    const int total = gfine.D * gfine.H * gfine.W * C;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int c = i % C, p = i / C;
+        int z, y, x;
+        pos3(p, gfine.D, gfine.H, gfine.W, z, y, x);
+        const int q = ((z >> 1) * gcoarse.H + (y >> 1)) * gcoarse.W + (x >> 1);
+        const int a = ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
+        float v = bf2f(gskip.p[size_t(p) * gskip.stride + gskip.off + c]);
+        if (arg[size_t(q) * C + c] == a) v += bf2f(gcoarse.p[size_t(q) * gcoarse.stride + gcoarse.off + c]);
+        if (!(bf2f(h.p[size_t(p) * h.stride + h.off + c]) > 0.f)) v = 0.f;
+        gfine.p[size_t(p) * gfine.stride + gfine.off + c] = f2bf(v);
+    }
+}
+
+// head: pred = sum_c w[c] h[p][c] + b + dose[p]
+__global__ void k_head_fwd(View h, const float* hw, const float* hb, const float* dose, int P,
+                           float* pred) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        float s = hb[0] + dose[p];
+        for (int c = 0; c < h.C; ++c) s += hw[c] * bf2f(h.p[size_t(p) * h.stride + h.off + c]);
+        pred[p] = s;
+    }
+}
+
+// loss = mean (pred - t)^2 (partial sums per block into striped slots),
+// gy = 2 (pred - t) / P
+__global__ void k_loss(const float* pred, const float* tgt, int P, float* gy, double* loss_parts) {
+    double s = 0.0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const float d = pred[p] - tgt[p];
+        gy[p] = 2.f * d / float(P);
+        s += double(d) * d;
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(loss_parts + (blockIdx.x & 63), s / double(P));
+}
+
+// head backward: d head.w[c] += sum_p gy h, d head.b += sum_p gy,
+// g[p][c] = w[c] gy[p] masked by h > 0
+__global__ void k_head_bwd(View h, const float* hw, const float* gy, int P, float* ghw, float* ghb,
+                           View g) {
+    __shared__ float s_w[256];
+    __shared__ float s_b;
+    const int C = h.C;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) s_w[c] = 0.f;
+    if (threadIdx.x == 0) s_b = 0.f;
+    __syncthreads();
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const float gp = gy[p];
+        atomicAdd(&s_b, gp);
+        for (int c = 0; c < C; ++c) {
+            const float hv = bf2f(h.p[size_t(p) * h.stride + h.off + c]);
+            atomicAdd(&s_w[c], gp * hv);
+            g.p[size_t(p) * g.stride + g.off + c] = f2bf(hv > 0.f ? hw[c] * gp : 0.f);
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(ghw + c, s_w[c]);
+    if (threadIdx.x == 0) atomicAdd(ghb, s_b);
+}
+
+// bias gradient: column sums of a gradient view over all positions
+__global__ void k_bias_grad(View g, int P, float* gb) {
+    __shared__ float s[256];
+    const int C = g.C;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) s[c] = 0.f;
+    __syncthreads();
+    const int per = (P + gridDim.x - 1) / gridDim.x;
+    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
+    for (int c = threadIdx.x % C; c < C; c += C) {
+        // threads sharing a column stride over positions
+        float acc = 0.f;
+        for (int p = p0 + threadIdx.x / C; p < p1; p += blockDim.x / C)
+            acc += bf2f(g.p[size_t(p) * g.stride + g.off + c]);
+        atomicAdd(&s[c], acc);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(gb + c, s[c]);
+}
+
+__global__ void k_zero_f(float* p, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0.f;
+}
+
+__global__ void k_zero_d(double* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+// Adam (Kingma & Ba) on the FP32 master parameters
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// conv weights [o][c][27] -> forward B^T [o][tap*cin_pad + c] and backward
+// B^T [c][tap'*cout + o] with tap' = 26 - tap (flipped kernel)
+__global__ void k_pack_conv(const float* w, int cout, int cin, int cin_pad, uint16_t* wf,
+                            uint16_t* wb) {
+    const int total = cout * cin_pad * 27;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int tap = i % 27, c = (i / 27) % cin_pad, o = i / (27 * cin_pad);
+        const float v = c < cin ? w[(size_t(o) * cin + c) * 27 + tap] : 0.f;
+        wf[size_t(o) * (27 * cin_pad) + tap * cin_pad + c] = f2bf(v);
+        if (wb && c < cin) wb[size_t(c) * (27 * cout) + (26 - tap) * cout + o] = f2bf(v);
+    }
+}
+
+// tconv weights [c][o][8] -> forward B^T [abc*cout + o][c], backward B^T [c][abc*cout + o]
+__global__ void k_pack_tconv(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb) {
+    const int total = cin * cout * 8;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int abc = i % 8, o = (i / 8) % cout, c = i / (8 * cout);
+        const uint16_t v = f2bf(w[i]);
+        wf[size_t(abc * cout + o) * cin + c] = v;
+        wb[size_t(c) * (8 * cout) + abc * cout + o] = v;
+    }
+}
+
+int grid1(int64_t n, int cap = 4096) {
+    return int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap)));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Network object
+// ---------------------------------------------------------------------------
+struct UNet {
+    int c = 32, D = 0, H = 0, W = 0;
+    int64_t n_params = 0;
+    // parameter offsets in the flat FP32 arrays (reference order)
+    struct Conv { int64_t w, b; int cin, cout, cin_pad; uint16_t* wf; uint16_t* wb; };
+    struct Tconv { int64_t w, b; int cin, cout; uint16_t* wf; uint16_t* wb; };
+    Conv enc_a[kLevels], enc_b[kLevels], dec_a[kLevels], dec_b[kLevels];
+    Tconv up[kLevels];
+    int64_t head_w = 0, head_b = 0;
+    DevBuf params, grads, adam_m, adam_v, packed;
+    // activations (BF16 channels-last) and gradients per level
+    DevBuf x0, cat[kLevels], enc_a_out[kLevels], dec_a_out[kLevels], dec_b_out[kLevels],
+        bottom_b, pooled[kLevels], arg[kLevels], g1[kLevels], g2[kLevels], gcat[kLevels], pred,
+        gy, loss;
+    int64_t step = 0;
+    int dims[kLevels][3];
+    int64_t P(int k) const { return int64_t(dims[k][0]) * dims[k][1] * dims[k][2]; }
+    int ch(int k) const { return c << k; }
+};
+
+namespace {
+
+View view(const DevBuf& b, const UNet& u, int level, int C, int stride, int off) {
+    return View{b.as<uint16_t>(), u.dims[level][0], u.dims[level][1], u.dims[level][2], C, stride, off};
+}
+
+void gemm_launch(int mode, const GemmArgs& g, hipStream_t s, int splits = 1) {
+    dim3 grid((g.M + kBM - 1) / kBM, (g.N + kBN - 1) / kBN, splits), block(256);
+    switch (mode) {
+        case kConvFwd: hipLaunchKernelGGL(k_gemm<kConvFwd>, grid, block, 0, s, g); break;
+        case kConvBwdData: hipLaunchKernelGGL(k_gemm<kConvBwdData>, grid, block, 0, s, g); break;
+        case kConvWgrad: hipLaunchKernelGGL(k_gemm<kConvWgrad>, grid, block, 0, s, g); break;
+        case kTconvFwd: hipLaunchKernelGGL(k_gemm<kTconvFwd>, grid, block, 0, s, g); break;
+        case kTconvBwdData: hipLaunchKernelGGL(k_gemm<kTconvBwdData>, grid, block, 0, s, g); break;
+        default: hipLaunchKernelGGL(k_gemm<kTconvWgrad>, grid, block, 0, s, g); break;
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+// forward conv: in (cin_pad channels view) -> out view, bias, ReLU
+void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t s) {
+    GemmArgs g{};
+    g.a = in;
+    g.b = out;
+    g.wt = L.wf;
+    g.bias = u.params.as<float>() + L.b;
+    g.M = int(int64_t(in.D) * in.H * in.W);
+    g.N = L.cout;
+    g.K = 27 * L.cin_pad;
+    g.cin = L.cin;
+    g.cout = L.cout;
+    g.relu = 1;
+    gemm_launch(kConvFwd, g, s);
+}
+
+int wgrad_splits(int64_t positions) {
+    return int(std::max<int64_t>(1, std::min<int64_t>(positions / 2048, 512)));
+}
+
+// conv backward: gz (gradient at the conv output, ReLU already applied) ->
+// weight and bias gradients, and (optional) gradient at the input masked by
+// the input activation
+void conv_bwd(const UNet& u, const UNet::Conv& L, View in, View gz, View* gin, hipStream_t s) {
+    const int64_t P = int64_t(in.D) * in.H * in.W;
+    GemmArgs g{};
+    g.a = in;
+    g.b = gz;
+    g.wgrad = u.grads.as<float>() + L.w;
+    g.M = L.cout;
+    g.N = 27 * L.cin_pad;
+    g.K = int(P);
+    g.cin = L.cin;
+    g.cout = L.cout;
+    const int splits = wgrad_splits(P);
+    g.k_per_split = int(((P + splits - 1) / splits + kBK - 1) / kBK * kBK);
+    gemm_launch(kConvWgrad, g, s, int((P + g.k_per_split - 1) / g.k_per_split));
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gz, int(P), u.grads.as<float>() + L.b);
+    if (gin) {
+        GemmArgs d{};
+        d.a = gz;
+        d.b = *gin;
+        d.wt = L.wb;
+        d.mask = in;
+        d.M = int(P);
+        d.N = L.cin;
+        d.K = 27 * L.cout;
+        d.cin = L.cin;
+        d.cout = L.cout;
+        gemm_launch(kConvBwdData, d, s);
+    }
+}
+
+void build_layout(UNet& u) {
+    int64_t off = 0;
+    auto conv = [&](UNet::Conv& L, int cin, int cout) {
+        L.cin = cin;
+        L.cout = cout;
+        L.cin_pad = (cin + 7) / 8 * 8;
+        L.w = off;
+        off += int64_t(cout) * cin * 27;
+        L.b = off;
+        off += cout;
+    };
+    auto tconv = [&](UNet::Tconv& L, int cin, int cout) {
+        L.cin = cin;
+        L.cout = cout;
+        L.w = off;
+        off += int64_t(cin) * cout * 8;
+        L.b = off;
+        off += cout;
+    };
+    int prev = 2;
+    for (int k = 0; k < kLevels; ++k) {
+        conv(u.enc_a[k], prev, u.ch(k));
+        conv(u.enc_b[k], u.ch(k), u.ch(k));
+        prev = u.ch(k);
+    }
+    for (int k = kLevels - 2; k >= 0; --k) {
+        tconv(u.up[k], u.ch(k + 1), u.ch(k));
+        conv(u.dec_a[k], 2 * u.ch(k), u.ch(k));
+        conv(u.dec_b[k], u.ch(k), u.ch(k));
+    }
+    u.head_w = off;
+    off += u.c;
+    u.head_b = off;
+    off += 1;
+    u.n_params = off;
+}
+
+void pack_all(UNet& u, hipStream_t s) {
+    const float* p = u.params.as<float>();
+    auto pc = [&](UNet::Conv& L) {
+        hipLaunchKernelGGL(k_pack_conv, dim3(grid1(int64_t(L.cout) * L.cin_pad * 27)), dim3(256), 0,
+                           s, p + L.w, L.cout, L.cin, L.cin_pad, L.wf, L.wb);
+    };
+    for (int k = 0; k < kLevels; ++k) {
+        pc(u.enc_a[k]);
+        pc(u.enc_b[k]);
+    }
+    for (int k = 0; k < kLevels - 1; ++k) {
+        pc(u.dec_a[k]);
+        pc(u.dec_b[k]);
+        hipLaunchKernelGGL(k_pack_tconv, dim3(grid1(int64_t(u.up[k].cin) * u.up[k].cout * 8)),
+                           dim3(256), 0, s, p + u.up[k].w, u.up[k].cin, u.up[k].cout, u.up[k].wf,
+                           u.up[k].wb);
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+// input [2][P0] FP32 -> pred [P0] FP32 (activations kept for the backward pass)
+void forward(UNet& u, const float* input, hipStream_t s) {
+    const int64_t P0 = u.P(0);
+    hipLaunchKernelGGL(k_pack_input, dim3(grid1(P0)), dim3(256), 0, s, input, int(P0),
+                       u.x0.as<uint16_t>());
+    View h = view(u.x0, u, 0, 8, 8, 0);
+    for (int k = 0; k < kLevels; ++k) {
+        const int C = u.ch(k);
+        if (k > 0) {
+            View pooled = view(u.pooled[k], u, k, u.ch(k - 1), u.ch(k - 1), 0);
+            hipLaunchKernelGGL(k_pool_fwd, dim3(grid1(u.P(k) * u.ch(k - 1))), dim3(256), 0, s, h,
+                               pooled, u.arg[k].as<uint8_t>());
+            h = pooled;
+        }
+        View a = view(u.enc_a_out[k], u, k, C, C, 0);
+        conv_fwd(u, u.enc_a[k], h, a, s);
+        // encoder output of levels < 3 goes straight into the first half of the
+        // decoder's concatenation buffer
+        View b = k < kLevels - 1 ? view(u.cat[k], u, k, C, 2 * C, 0) : view(u.bottom_b, u, k, C, C, 0);
+        conv_fwd(u, u.enc_b[k], a, b, s);
+        h = b;
+    }
+    for (int k = kLevels - 2; k >= 0; --k) {
+        const int C = u.ch(k);
+        View upv = view(u.cat[k], u, k, C, 2 * C, C);
+        GemmArgs g{};
+        g.a = h;
+        g.b = upv;
+        g.wt = u.up[k].wf;
+        g.bias = u.params.as<float>() + u.up[k].b;
+        g.M = int(u.P(k + 1));
+        g.N = 8 * C;
+        g.K = u.ch(k + 1);
+        g.cin = u.ch(k + 1);
+        g.cout = C;
+        gemm_launch(kTconvFwd, g, s);
+        View catv = view(u.cat[k], u, k, 2 * C, 2 * C, 0);
+        View a = view(u.dec_a_out[k], u, k, C, C, 0);
+        conv_fwd(u, u.dec_a[k], catv, a, s);
+        View b = view(u.dec_b_out[k], u, k, C, C, 0);
+        conv_fwd(u, u.dec_b[k], a, b, s);
+        h = b;
+    }
+    hipLaunchKernelGGL(k_head_fwd, dim3(grid1(P0)), dim3(256), 0, s, h,
+                       u.params.as<float>() + u.head_w, u.params.as<float>() + u.head_b, input,
+                       int(P0), u.pred.as<float>());
+    PSL_HIP(hipGetLastError());
+}
+
+// loss + gradients of every parameter into u.grads (zeroed here)
+void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
+    const int64_t P0 = u.P(0);
+    hipLaunchKernelGGL(k_zero_f, dim3(grid1(u.n_params)), dim3(256), 0, s, u.grads.as<float>(),
+                       u.n_params);
+    hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, s, u.loss.as<double>(), 64);
+    hipLaunchKernelGGL(k_loss, dim3(grid1(P0, 1024)), dim3(256), 0, s, u.pred.as<float>(), target,
+                       int(P0), u.gy.as<float>(), u.loss.as<double>());
+    // head
+    const int C0 = u.ch(0);
+    View h0 = view(u.dec_b_out[0], u, 0, C0, C0, 0);
+    View g = view(u.g1[0], u, 0, C0, C0, 0);
+    hipLaunchKernelGGL(k_head_bwd, dim3(grid1(P0, 512)), dim3(256), 0, s, h0,
+                       u.params.as<float>() + u.head_w, u.gy.as<float>(), int(P0),
+                       u.grads.as<float>() + u.head_w, u.grads.as<float>() + u.head_b, g);
+    // decoder, top level first; g holds the gradient at the ReLU output of
+    // dec_b (already masked)
+    View gz = g;
+    for (int k = 0; k < kLevels - 1; ++k) {
+        const int C = u.ch(k);
+        View a = view(u.dec_a_out[k], u, k, C, C, 0);
+        View ga = view(u.g2[k], u, k, C, C, 0);
+        conv_bwd(u, u.dec_b[k], a, gz, &ga, s);            // ga masked by a > 0
+        View catv = view(u.cat[k], u, k, 2 * C, 2 * C, 0);
+        View gcat = view(u.gcat[k], u, k, 2 * C, 2 * C, 0);
+        conv_bwd(u, u.dec_a[k], catv, ga, &gcat, s);       // masked by cat > 0
+        // the up half of gcat was masked by the tconv output > 0, which is not a
+        // ReLU output; recompute it unmasked below from the same product
+        View gup = view(u.gcat[k], u, k, C, 2 * C, C);
+        {
+            GemmArgs d{};
+            d.a = ga;
+            d.b = gup;
+            d.wt = u.dec_a[k].wb + size_t(C) * 27 * C;   // rows C..2C-1 of the backward pack
+            d.M = int(u.P(k));
+            d.N = C;
+            d.K = 27 * C;
+            d.cin = 2 * C;
+            d.cout = C;
+            gemm_launch(kConvBwdData, d, s);
+        }
+        // tconv backward: weights, bias, gradient at its input (masked by the
+        // lower level's ReLU output)
+        View hin = k + 1 < kLevels - 1 ? view(u.dec_b_out[k + 1], u, k + 1, u.ch(k + 1), u.ch(k + 1), 0)
+                                       : view(u.bottom_b, u, k + 1, u.ch(k + 1), u.ch(k + 1), 0);
+        GemmArgs w{};
+        w.a = hin;
+        w.b = gup;
+        w.wgrad = u.grads.as<float>() + u.up[k].w;
+        w.M = u.ch(k + 1);
+        w.N = 8 * C;
+        w.K = int(u.P(k + 1));
+        w.cin = u.ch(k + 1);
+        w.cout = C;
+        const int splits = wgrad_splits(u.P(k + 1));
+        w.k_per_split = int(((u.P(k + 1) + splits - 1) / splits + kBK - 1) / kBK * kBK);
+        gemm_launch(kTconvWgrad, w, s, int((u.P(k + 1) + w.k_per_split - 1) / w.k_per_split));
+        hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gup, int(u.P(k)),
+                           u.grads.as<float>() + u.up[k].b);
+        View gh = view(u.g1[k + 1], u, k + 1, u.ch(k + 1), u.ch(k + 1), 0);
+        GemmArgs d{};
+        d.a = gup;
+        d.b = gh;
+        d.wt = u.up[k].wb;
+        d.mask = hin;
+        d.M = int(u.P(k + 1));
+        d.N = u.ch(k + 1);
+        d.K = 8 * C;
+        d.cin = u.ch(k + 1);
+        d.cout = C;
+        gemm_launch(kTconvBwdData, d, s);
+        gz = gh;
+    }
+    // encoder, bottom level first; gz = gradient at the ReLU output of enc_b[k]
+    for (int k = kLevels - 1; k >= 0; --k) {
+        const int C = u.ch(k);
+        View a = view(u.enc_a_out[k], u, k, C, C, 0);
+        View ga = view(u.g2[k], u, k, C, C, 0);
+        conv_bwd(u, u.enc_b[k], a, gz, &ga, s);
+        View hin = k == 0 ? view(u.x0, u, 0, 8, 8, 0) : view(u.pooled[k], u, k, u.ch(k - 1), u.ch(k - 1), 0);
+        if (k == 0) {
+            conv_bwd(u, u.enc_a[k], hin, ga, nullptr, s);
+        } else {
+            View gp = view(u.g1[k], u, k, u.ch(k - 1), u.ch(k - 1), 0);
+            // pooled values are maxima of ReLU outputs: the mask hin > 0 is the
+            // same as the mask of the selected fine value
+            conv_bwd(u, u.enc_a[k], hin, ga, &gp, s);
+            const int Cf = u.ch(k - 1);
+            View gskip = view(u.gcat[k - 1], u, k - 1, Cf, 2 * Cf, 0);
+            View hfine = view(u.cat[k - 1], u, k - 1, Cf, 2 * Cf, 0);
+            View gfine = view(u.g1[k - 1], u, k - 1, Cf, Cf, 0);
+            hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(u.P(k - 1) * Cf)), dim3(256), 0, s, gp,
+                               u.arg[k].as<uint8_t>(), gskip, hfine, gfine);
+            gz = gfine;
+        }
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+UNet* unet_cast(psl_unet* p) { return reinterpret_cast<UNet*>(p); }
+
+}  // namespace
+}  // namespace psl
+
+using namespace psl;
+
+extern "C" int psl_unet_create(int32_t base_width, int32_t d, int32_t h, int32_t w, psl_unet** out) {
+    return guarded([&] {
+        PSL_CHECK(out, "null argument");
+        PSL_CHECK(base_width == 8 || base_width == 16 || base_width == 32,
+                  "base width must be 8, 16 or 32");
+        PSL_CHECK(d >= 8 && h >= 8 && w >= 8 && d % 8 == 0 && h % 8 == 0 && w % 8 == 0,
+                  "volume dimensions must be multiples of 8");
+        PSL_CHECK(int64_t(d) * h * w < (int64_t(1) << 31) / 64, "volume too large");
+        auto u = std::make_unique<UNet>();
+        u->c = base_width;
+        u->D = d;
+        u->H = h;
+        u->W = w;
+        for (int k = 0; k < kLevels; ++k) {
+            u->dims[k][0] = d >> k;
+            u->dims[k][1] = h >> k;
+            u->dims[k][2] = w >> k;
+        }
+        build_layout(*u);
+        const size_t np = size_t(u->n_params);
+        u->params.alloc(np * 4);
+        u->grads.alloc(np * 4);
+        u->adam_m.alloc(np * 4);
+        u->adam_v.alloc(np * 4);
+        // packed BF16 weights: forward + backward layouts of every layer
+        size_t pk = 0;
+        auto cnt_conv = [&](UNet::Conv& L) { pk += size_t(L.cout) * L.cin_pad * 27 + size_t(L.cin) * 27 * L.cout; };
+        for (int k = 0; k < kLevels; ++k) {
+            cnt_conv(u->enc_a[k]);
+            cnt_conv(u->enc_b[k]);
+        }
+        for (int k = 0; k < kLevels - 1; ++k) {
+            cnt_conv(u->dec_a[k]);
+            cnt_conv(u->dec_b[k]);
+            pk += 2 * size_t(u->up[k].cin) * u->up[k].cout * 8;
+        }
+        u->packed.alloc(pk * 2 + 4096);
+        uint16_t* q = u->packed.as<uint16_t>();
+        auto take = [&](size_t n) { uint16_t* r = q; q += (n + 7) / 8 * 8; return r; };
+        auto place_conv = [&](UNet::Conv& L) {
+            L.wf = take(size_t(L.cout) * L.cin_pad * 27);
+            L.wb = take(size_t(L.cin) * 27 * L.cout);
+        };
+        for (int k = 0; k < kLevels; ++k) {
+            place_conv(u->enc_a[k]);
+            place_conv(u->enc_b[k]);
+        }
+        for (int k = 0; k < kLevels - 1; ++k) {
+            place_conv(u->dec_a[k]);
+            place_conv(u->dec_b[k]);
+            u->up[k].wf = take(size_t(u->up[k].cin) * u->up[k].cout * 8);
+            u->up[k].wb = take(size_t(u->up[k].cin) * u->up[k].cout * 8);
+        }
+        u->x0.alloc(size_t(u->P(0)) * 8 * 2);
+        for (int k = 0; k < kLevels; ++k) {
+            const size_t P = size_t(u->P(k)), C = size_t(u->ch(k));
+            u->cat[k].alloc(P * 2 * C * 2);
+            u->enc_a_out[k].alloc(P * C * 2);
+            u->dec_a_out[k].alloc(P * C * 2);
+            u->dec_b_out[k].alloc(P * C * 2);
+            u->g1[k].alloc(P * 2 * C * 2);
+            u->g2[k].alloc(P * 2 * C * 2);
+            u->gcat[k].alloc(P * 2 * C * 2);
+            if (k > 0) {
+                u->pooled[k].alloc(P * size_t(u->ch(k - 1)) * 2);
+                u->arg[k].alloc(P * size_t(u->ch(k - 1)));
+            }
+        }
+        u->bottom_b.alloc(size_t(u->P(kLevels - 1)) * u->ch(kLevels - 1) * 2);
+        u->pred.alloc(size_t(u->P(0)) * 4);
+        u->gy.alloc(size_t(u->P(0)) * 4);
+        u->loss.alloc(64 * 8);
+        hipLaunchKernelGGL(k_zero_f, dim3(grid1(int64_t(np))), dim3(256), 0, nullptr,
+                           u->adam_m.as<float>(), int64_t(np));
+        hipLaunchKernelGGL(k_zero_f, dim3(grid1(int64_t(np))), dim3(256), 0, nullptr,
+                           u->adam_v.as<float>(), int64_t(np));
+        PSL_HIP(hipDeviceSynchronize());
+        *out = reinterpret_cast<psl_unet*>(u.release());
+    });
+}
+
+extern "C" void psl_unet_free(psl_unet* net) { delete unet_cast(net); }
+
+extern "C" int psl_unet_param_count(const psl_unet* net, int64_t* n) {
+    return guarded([&] {
+        PSL_CHECK(net && n, "null argument");
+        *n = reinterpret_cast<const UNet*>(net)->n_params;
+    });
+}
+
+extern "C" int psl_unet_set_params(psl_unet* net, const float* host) {
+    return guarded([&] {
+        PSL_CHECK(net && host, "null argument");
+        UNet& u = *unet_cast(net);
+        PSL_HIP(hipMemcpy(u.params.p, host, size_t(u.n_params) * 4, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_zero_f, dim3(grid1(u.n_params)), dim3(256), 0, nullptr,
+                           u.adam_m.as<float>(), u.n_params);
+        hipLaunchKernelGGL(k_zero_f, dim3(grid1(u.n_params)), dim3(256), 0, nullptr,
+                           u.adam_v.as<float>(), u.n_params);
+        u.step = 0;
+        pack_all(u, nullptr);
+        PSL_HIP(hipDeviceSynchronize());
+    });
+}
+
+extern "C" int psl_unet_get_params(const psl_unet* net, float* host) {
+    return guarded([&] {
+        PSL_CHECK(net && host, "null argument");
+        const UNet& u = *reinterpret_cast<const UNet*>(net);
+        PSL_HIP(hipMemcpy(host, u.params.p, size_t(u.n_params) * 4, hipMemcpyDeviceToHost));
+    });
+}
+
+extern "C" int psl_unet_forward(psl_unet* net, const float* input, float* pred, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(net && input && pred, "null argument");
+        UNet& u = *unet_cast(net);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        forward(u, input, s);
+        PSL_HIP(hipMemcpyAsync(pred, u.pred.p, size_t(u.P(0)) * 4, hipMemcpyDeviceToDevice, s));
+    });
+}
+
+extern "C" int psl_unet_gradients(psl_unet* net, const float* input, const float* target,
+                                  float* grads_host, double* loss) {
+    return guarded([&] {
+        PSL_CHECK(net && input && target, "null argument");
+        UNet& u = *unet_cast(net);
+        forward(u, input, nullptr);
+        backward(u, input, target, nullptr);
+        PSL_HIP(hipDeviceSynchronize());
+        if (grads_host)
+            PSL_HIP(hipMemcpy(grads_host, u.grads.p, size_t(u.n_params) * 4, hipMemcpyDeviceToHost));
+        if (loss) {
+            double parts[64];
+            PSL_HIP(hipMemcpy(parts, u.loss.p, sizeof parts, hipMemcpyDeviceToHost));
+            double l = 0.0;
+            for (double v : parts) l += v;
+            *loss = l;
+        }
+    });
+}
+
+extern "C" int psl_unet_train_step(psl_unet* net, const float* input, const float* target, float lr,
+                                   double* loss_dev, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(net && input && target, "null argument");
+        PSL_CHECK(lr > 0.f, "learning rate must be > 0");
+        UNet& u = *unet_cast(net);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        forward(u, input, s);
+        backward(u, input, target, s);
+        u.step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - std::pow(b1, float(u.step)), c2 = 1.f - std::pow(b2, float(u.step));
+        hipLaunchKernelGGL(k_adam, dim3(grid1(u.n_params)), dim3(256), 0, s, u.params.as<float>(),
+                           u.grads.as<float>(), u.adam_m.as<float>(), u.adam_v.as<float>(),
+                           u.n_params, lr, b1, b2, 1e-8f, c1, c2);
+        pack_all(u, s);
+        if (loss_dev)
+            PSL_HIP(hipMemcpyAsync(loss_dev, u.loss.p, 64 * 8, hipMemcpyDeviceToDevice, s));
+    });
+}

@@ -285,3 +285,50 @@ def commission_nnls(A, b, x0=None, delta=1e-10, pg_tol=1e-8, sigma=1e-4, beta=0.
     rc = N.commission_nnls(a_flat.ctypes.data_as(N.dp), m, n, b.ctypes.data_as(N.dp),
                            x.ctypes.data_as(N.dp), opts, rep)
     return x, dict(iters=int(rep.iters), f=rep.f, pg=rep.pg_norm, converged=rc == N.PSL_OK)
+
+
+class UNet:
+    """The 3D U-Net denoiser (psl_unet_*): c base channels, d x h x w volumes."""
+
+    def __init__(self, c, d, h, w):
+        self.c, self.shape = c, (d, h, w)
+        out = C.c_void_p()
+        N.check(N.lib().psl_unet_create(c, d, h, w, C.byref(out)))
+        self.h = out
+        n = C.c_int64()
+        N.check(N.lib().psl_unet_param_count(self.h, C.byref(n)))
+        self.n_params = n.value
+        self.loss_parts = torch.zeros(64, dtype=torch.float64, device="cuda")
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.n_params
+        N.check(N.lib().psl_unet_set_params(self.h, flat.ctypes.data_as(N.fp)))
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        N.check(N.lib().psl_unet_get_params(self.h, out.ctypes.data_as(N.fp)))
+        return out
+
+    def forward(self, inp, stream=None):
+        pred = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        N.check(N.lib().psl_unet_forward(self.h, inp.data_ptr(), pred.data_ptr(),
+                                         _stream_ptr(stream)))
+        return pred
+
+    def train_step(self, inp, tgt, lr, stream=None):
+        N.check(N.lib().psl_unet_train_step(self.h, inp.data_ptr(), tgt.data_ptr(), lr,
+                                            self.loss_parts.data_ptr(), _stream_ptr(stream)))
+        return self.loss_parts
+
+    def gradients(self, inp, tgt):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        loss = C.c_double()
+        N.check(N.lib().psl_unet_gradients(self.h, inp.data_ptr(), tgt.data_ptr(),
+                                           g.ctypes.data_as(N.fp), C.byref(loss)))
+        return g, loss.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            N.lib().psl_unet_free(self.h)
+            self.h = None
