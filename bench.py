@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 512 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -133,6 +135,12 @@ def main():
         N.tally_dose(tally.h, N.PSL_TALLY_FINALIZE, plan.h, dose.data_ptr(), sig.data_ptr(),
                      int(stream.cuda_stream))
 
+    if args.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()

@@ -1,0 +1,35 @@
+"""Host-side checks of the denoiser pipeline: the flat parameter layout of
+psl.h matches the oracle's parameter list, and the time-to-1% summary
+follows its definition on a hand-made result."""
+import math
+
+import numpy as np
+import pytest
+
+
+def test_flat_layout_matches_oracle_parameter_list():
+    from oracle import denoiser as D
+    from paper_1503_01725_amd import unet_init
+    for c in (8, 16, 32):
+        a = [(n, int(np.prod(s))) for n, s in D.param_shapes(c, 2)]
+        b = [(n, int(np.prod(s))) for n, s in unet_init.layer_shapes(c)]
+        assert a == b
+    flat = unet_init.init_params(7, 8)
+    total = sum(int(np.prod(s)) for _, s in D.param_shapes(8, 2))
+    assert flat.dtype == np.float32 and flat.size == total
+
+
+def test_time_to_one_percent_summary():
+    from paper_1503_01725_amd.denoise import summarize
+    row = {"plain_rms": 2.0, "denoised_rms": 0.3, "plain_gamma": 0.8, "denoised_gamma": 0.99,
+           "sigma_rel": 0.05, "t_infer_s": 0.01}
+    res = {"cases": [{"hist_per_s": 1e8, "1e+06": dict(row), "3e+06": dict(row),
+                      "1e+07": dict(row)}]}
+    out = summarize(res)
+    n1 = 1e6 * (0.05 / 0.01) ** 2
+    assert out["time_to_1pct"]["plain_histories"] == pytest.approx(n1)
+    assert out["time_to_1pct"]["plain_s"] == pytest.approx(n1 / 1e8)
+    rms1 = 2.0 * math.sqrt(1e6 / n1)
+    assert out["time_to_1pct"]["rms_error_percent_of_dmax"] == pytest.approx(rms1)
+    assert out["time_to_1pct"]["denoised_histories"] == 1e6
+    assert out["time_to_1pct"]["denoised_s"] == pytest.approx(1e6 / 1e8 + 0.01)
