@@ -34,6 +34,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
 // Uniform in [0, 1) from the top 24 bits; exact in FP32.
 __device__ __forceinline__ float top24(uint32_t x) { return float(x >> 8) * kTwoPow24Inv; }
 
+// One Philox block turned into four uniforms.  Kept out of line so that the
+// many draw sites of the transport loops share one copy of the 10 rounds.
+__device__ __noinline__ float4 philox_uniforms(uint32_t blk, uint32_t tagsub, uint32_t g0,
+                                               uint32_t g1, uint32_t k0, uint32_t k1) {
+    uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
+    philox4x32_10(x0, x1, x2, x3, k0, k1);
+    return make_float4(top24(x0), top24(x1), top24(x2), top24(x3));
+}
+
 // The uniforms of one particle: key = seed, counter = (block, tag<<16 | sub,
 // g_lo, g_hi); consumed four per block, in order.
 struct Stream {
@@ -52,12 +61,11 @@ struct Stream {
         left = 0;
     }
     __device__ __forceinline__ void refill() {
-        uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
-        philox4x32_10(x0, x1, x2, x3, k0, k1);
-        u0 = top24(x0);
-        u1 = top24(x1);
-        u2 = top24(x2);
-        u3 = top24(x3);
+        const float4 u = philox_uniforms(blk, tagsub, g0, g1, k0, k1);
+        u0 = u.x;
+        u1 = u.y;
+        u2 = u.z;
+        u3 = u.w;
         ++blk;
         left = 4;
     }

@@ -55,38 +55,53 @@ def test_commission_tally_matches_oracle(commission):
     assert np.median(rel) < 1e-3
 
 
-def test_columns_sum_to_open_field_dose(eng, wl, commission):
-    """Sum over basis columns of one field (x = 1) equals the Eq. (3) open-field
-    dose on the same voxels within the statistical error."""
+def test_columns_sum_to_open_field_dose(eng, wl):
+    """Sum over the basis columns of one field (x = 1) equals the Eq. (3)
+    open-field dose on the same voxels within the statistical error (GPU
+    only, 2e4 histories per basis so that the per-PSL allocation of the
+    stratified counts is fine enough)."""
     import torch
-    c = commission
-    W = c["W"]
-    model = eng.Model(W.model)
+    W = wl.workload("commission60")
+    imap, n_rows = W.extra["index_map"], W.extra["n_rows"]
+    bmap = W.extra["basis_map"]
     beam = W.beams[2]                                   # 10 x 10 field
-    plan = eng.Plan(model, [beam], 400000, n_replica=4)
+    model = eng.Model(W.model)
     ph = eng.Phantom(W.phantom)
+    prm = eng.transport_params()
+    plan_c = eng.Plan(model, [beam], 0, n_replica=4, basis_map=bmap, hist_per_basis=20000)
+    tally_c = eng.Tally(ph, index_map=imap, n_rows=n_rows, n_cols=720)
+    eng.run_plan(plan_c, ph, tally_c, prm, eng.run_opts(1 << 20, 24, seed=41))
+    A, sA = tally_c.finalize(plan_c)
+    plan = eng.Plan(model, [beam], 4000000, n_replica=4)
     tally = eng.Tally(ph)
-    eng.run_plan(plan, ph, tally, eng.transport_params(), eng.run_opts(262144, 24, seed=5))
+    eng.run_plan(plan, ph, tally, prm, eng.run_opts(1 << 20, 24, seed=5))
     d, s = tally.finalize(plan)
     torch.cuda.synchronize()
+    A, sA = A.cpu().numpy(), sA.cpu().numpy()
     d = d.cpu().numpy().ravel()
     s = s.cpu().numpy().ravel()
-    sel = np.flatnonzero(c["imap"].ravel())
-    rows = c["imap"].ravel()[sel] - 1
-    a_field = c["A"][:, 2 * 720:3 * 720].sum(axis=1)
-    sa_field = np.sqrt((c["sA"][:, 2 * 720:3 * 720] ** 2).sum(axis=1))
-    open_d = np.zeros(c["n_rows"])
-    open_s = np.zeros(c["n_rows"])
+    sel = np.flatnonzero(imap.ravel())
+    rows = imap.ravel()[sel] - 1
+    a_field = A.sum(axis=1)
+    sa_field = np.sqrt((sA ** 2).sum(axis=1))
+    open_d = np.zeros(n_rows)
+    open_s = np.zeros(n_rows)
     open_d[rows] = d[sel]
     open_s[rows] = s[sel]
     hi = open_d > 0.2 * open_d.max()
     z = (a_field[hi] - open_d[hi]) / np.sqrt(sa_field[hi] ** 2 + open_s[hi] ** 2)
     assert hi.sum() > 50
-    assert np.mean(np.abs(z) < 3) > 0.9
+    assert np.mean(np.abs(z) < 3) > 0.95
     assert abs(np.mean(z)) < 0.5
+    # integral over the selected voxels within 0.5 %
+    assert a_field[hi].sum() == pytest.approx(open_d[hi].sum(), rel=5e-3)
 
 
 def test_nnls_fit_of_gpu_matrix(eng, orc, wl, commission):
+    """Noise-free target b = A x_true from the GPU-built basis matrix: both
+    gradient-projection solvers (GPU and oracle) reduce the residual to
+    1e-3 of |b| within the same iteration budget (the matrix is too
+    ill-conditioned for full convergence, so the iterates are not compared)."""
     c = commission
     A = c["A"]
     used = A.max(axis=0) > 0
@@ -95,6 +110,7 @@ def test_nnls_fit_of_gpu_matrix(eng, orc, wl, commission):
     scale = b.max()
     x, rep = eng.commission_nnls(A / scale, b / scale, max_iter=20000)
     xo, repo = orc.nnls_gp(A / scale, b / scale, max_iter=20000)
-    # the noise-free target is reproduced (F -> 0) and both solvers agree on F
+    for xx in (x, xo):
+        assert np.all(xx >= 0)
+        assert np.linalg.norm(A @ xx - b) < 1e-3 * np.linalg.norm(b)
     assert rep["f"] < 1e-6 * np.sum((b / scale) ** 2)
-    assert rep["f"] == pytest.approx(repo["f"], rel=1e-3, abs=1e-12)
