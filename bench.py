@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--workload", default="water128_10")
     ap.add_argument("--max-batch", type=int, default=0, help="0 = autotune")
     ap.add_argument("--band-width", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--lane-load", type=int, default=0,
+                    help="histories per lane of the persistent transport grids (0 = autotune)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--sort", default="auto", choices=("auto", "0", "1"),
                     help="group electrons by energy band before transport")
@@ -107,24 +109,27 @@ def main():
 
     tune = None
     srt = 1
-    if args.max_batch and args.band_width:
-        mb, bw = args.max_batch, args.band_width
+    if args.max_batch and args.band_width and args.lane_load:
+        mb, bw, ll = args.max_batch, args.band_width, args.lane_load
     else:
-        log("[bench] autotuning batch size and energy-band width on one replica")
-        cands_m = [args.max_batch] if args.max_batch else [131072, 262144, 524288, 1048576]
-        cands_w = [args.band_width] if args.band_width else [1, 3, 24]
-        best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w)
-        mb, bw, srt = int(best.max_batch), int(best.band_width), int(best.sort_electrons)
-        tune = {"max_batch": cands_m, "band_width": cands_w, "sort_electrons": [0, 1],
-                "ms_per_replica": ms.tolist()}
-        log(f"[bench] autotune -> max_batch {mb} band_width {bw} sort {srt}")
+        log("[bench] autotuning batch size, energy-band width and grid size on one replica")
+        cands_m = [args.max_batch] if args.max_batch else [262144, 524288, 1048576, 2097152]
+        cands_w = [args.band_width] if args.band_width else [3, 24]
+        cands_l = [args.lane_load] if args.lane_load else [1, 2, 4, 8]
+        best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w, cands_l)
+        mb, bw, ll = int(best.max_batch), int(best.band_width), int(best.lane_load)
+        srt = int(best.sort_electrons)
+        tune = {"max_batch": cands_m, "band_width": cands_w, "lane_load": cands_l,
+                "sort_electrons": [0, 1], "ms_per_replica": ms.tolist()}
+        log(f"[bench] autotune -> max_batch {mb} band_width {bw} lane_load {ll} sort {srt}")
     if args.sort in ("0", "1"):
         srt = int(args.sort)
     # the timed region launches eagerly with a HIP event pair around every
     # kernel (events inside a captured graph carry no timestamps); the same
     # steps replayed from a captured hipGraph are timed separately below
     opts = eng.run_opts(mb, bw, use_graph=args.no_timing and not args.no_graph,
-                        sort_electrons=bool(srt), timing=not args.no_timing, seed=seed)
+                        sort_electrons=bool(srt), timing=not args.no_timing, seed=seed,
+                        lane_load=ll)
     dose = torch.zeros(tally.cells, dtype=torch.float64, device="cuda")
     sig = torch.zeros_like(dose)
     stream = torch.cuda.current_stream()
@@ -157,7 +162,7 @@ def main():
     graph_replay = None
     if not args.no_timing and not args.no_graph:
         opts = eng.run_opts(mb, bw, use_graph=True, sort_electrons=bool(srt), timing=False,
-                            seed=seed)
+                            seed=seed, lane_load=ll)
         step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -178,6 +183,7 @@ def main():
            "config": {"workload": args.workload, "histories": hist_per_step,
                       "replicas": n_rep, "phantom": "128^3 water, 0.25 cm voxels",
                       "field": "10x10 cm, SSD 100", "max_batch": mb, "band_width": bw,
+                      "lane_load": ll,
                       "sort_electrons": srt,
                       "launch": "eager+events" if not args.no_timing else
                       ("graph" if not args.no_graph else "eager"), "autotune": tune}}

@@ -250,7 +250,9 @@ void psl_tally_free(psl_tally* tally);
  * in->capacity * (floor(e_max / e_cut_electron) + 1): each push costs the
  * photon at least e_cut_electron, and the stack is filled in chunks of 64 per
  * wavefront whose unused ends stay in it as empty (skipped) entries.  The
- * electron stack is grouped into energy bands before electron transport.  Random numbers: Philox4x32-10 keyed
+ * electron stack is grouped into energy bands before electron transport.  The
+ * persistent transport grids hold ceil(in->capacity / 1024) workgroups of 256
+ * (at most 2048), about four histories per lane.  Random numbers: Philox4x32-10 keyed
  * by `seed`, counter (block, 2<<16 | sub, g_lo, g_hi), sub 0 for the source
  * particle and 1+n for the electron of its n-th push. */
 int transport_batch(const psl_phantom* phantom, const psl_particles* in,
@@ -298,6 +300,10 @@ typedef struct {
     int32_t timing;          /* 1: launch eagerly (no graph) with a HIP event pair
                                 around every kernel, read by psl_run_get_timing     */
     uint64_t seed;           /* Philox key                                          */
+    int32_t lane_load;       /* histories per lane of the persistent transport
+                                grids: they launch ceil(max_batch / (256 *
+                                lane_load)) workgroups of 256, at most 2048
+                                (0 = 4)                                            */
 } psl_run_opts;
 
 /* Runs every batch of every replica of `plan` -- sample_batch, transport_batch
@@ -319,14 +325,15 @@ typedef struct {
 int psl_run_get_timing(psl_tally* tally, psl_run_timing* out);
 
 /* Autotuner: times one replica (`replica`) of the plan for every candidate
- * (max_batch[i], band_width[j], sort_electrons s in {0, 1}) with graph replay,
- * writes the measured milliseconds to ms_out[(i * n_w + j) * 2 + s]
- * (nullable) and the fastest options to *best (use_graph = 1, seed as given).
- * Resets the tally afterwards.  Synchronous. */
+ * (max_batch[i], band_width[j], lane_load[l], sort_electrons s in {0, 1})
+ * with graph replay, writes the measured milliseconds to
+ * ms_out[((i * n_w + j) * n_l + l) * 2 + s] (nullable) and the fastest options
+ * to *best (use_graph = 1, seed as given).  Resets the tally afterwards.
+ * Synchronous. */
 int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
                  const psl_transport_params* params, uint64_t seed, const uint32_t* max_batch,
-                 int32_t n_m, const int32_t* band_width, int32_t n_w, uint32_t replica,
-                 psl_run_opts* best, double* ms_out);
+                 int32_t n_m, const int32_t* band_width, int32_t n_w, const int32_t* lane_load,
+                 int32_t n_l, uint32_t replica, psl_run_opts* best, double* ms_out);
 
 /* ------------------------------------------------------------------------
  * Commissioning (Sec. 2.2.3, Eq. 8; Sec. 2.2.4)

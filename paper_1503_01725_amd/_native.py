@@ -67,7 +67,8 @@ class psl_transport_params(C.Structure):
 
 class psl_run_opts(C.Structure):
     _fields_ = [("max_batch", C.c_uint32), ("band_width", C.c_int32), ("use_graph", C.c_int32),
-                ("sort_electrons", C.c_int32), ("timing", C.c_int32), ("seed", C.c_uint64)]
+                ("sort_electrons", C.c_int32), ("timing", C.c_int32), ("seed", C.c_uint64),
+                ("lane_load", C.c_int32)]
 
 
 class psl_run_timing(C.Structure):
@@ -119,7 +120,7 @@ _SIGS.update({
     "psl_run": [vp, vp, vp, P(psl_transport_params), P(psl_run_opts), vp],
     "psl_run_get_timing": [vp, P(psl_run_timing)],
     "psl_autotune": [vp, vp, vp, P(psl_transport_params), C.c_uint64, u32p, C.c_int32, i32p,
-                     C.c_int32, C.c_uint32, P(psl_run_opts), dp],
+                     C.c_int32, i32p, C.c_int32, C.c_uint32, P(psl_run_opts), dp],
 })
 _SIGS.update({
     "psl_unet_create": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(vp)],
@@ -229,16 +230,18 @@ def psl_run_get_timing(tally):
     return {p: (t.ms[i], int(t.launches[i])) for i, p in enumerate(PHASES)}
 
 
-def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, replica=0):
+def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, lane_loads=(4,),
+                 replica=0):
     import numpy as np
     mb = np.ascontiguousarray(max_batches, dtype=np.uint32)
     bw = np.ascontiguousarray(band_widths, dtype=np.int32)
-    ms = np.zeros(len(mb) * len(bw) * 2)
+    ll = np.ascontiguousarray(lane_loads, dtype=np.int32)
+    ms = np.zeros(len(mb) * len(bw) * len(ll) * 2)
     best = psl_run_opts()
     _call("psl_autotune", plan, phantom, tally, C.byref(params), seed, mb.ctypes.data_as(u32p),
-          len(mb), bw.ctypes.data_as(i32p), len(bw), replica, C.byref(best),
-          ms.ctypes.data_as(dp))
-    return best, ms.reshape(len(mb), len(bw), 2)
+          len(mb), bw.ctypes.data_as(i32p), len(bw), ll.ctypes.data_as(i32p), len(ll), replica,
+          C.byref(best), ms.ctypes.data_as(dp))
+    return best, ms.reshape(len(mb), len(bw), len(ll), 2)
 
 
 def commission_nnls(a_ptr, m, n, b_ptr, x_ptr, opts, report):

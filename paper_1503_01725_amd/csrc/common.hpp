@@ -252,7 +252,8 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
                    hipStream_t stream);
 void launch_transport(const psl_phantom* ph, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
-                      hipStream_t stream, bool sort_electrons, const PhaseEvents* ev = nullptr);
+                      hipStream_t stream, bool sort_electrons, int lane_load,
+                      const PhaseEvents* ev = nullptr);
 void launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 void launch_fold(psl_tally* t, hipStream_t s);
 void ensure_perm(psl_tally* t, uint32_t capacity);

@@ -80,6 +80,67 @@ struct Stream {
     }
 };
 
+// The same per-particle stream with its uniforms buffered in LDS, so that the
+// Philox blocks of a wavefront are generated together.  A lane that runs dry
+// at its own draw site calls the generator with only itself active, and in a
+// wavefront of 64 lanes some lane runs dry at almost every site; instead the
+// whole wavefront tops its buffers up at one point of the loop (topup), where
+// every lane with room generates at once, and next() only falls back to its
+// own generation when a history draws more than the top-up left.  The
+// sequence of values each history consumes is unchanged.
+//
+// Lane t of a workgroup of kLanes threads owns the column pool[j * kLanes + t]
+// for ring slots j < R (bank-conflict free for any per-lane slot).
+template <int R, int kLanes>
+struct PoolStream {
+    static_assert((R & (R - 1)) == 0 && R >= 8, "ring size must be a power of two >= 8");
+    uint32_t k0, k1, blk, tagsub, g0, g1;
+    uint32_t head, cnt;
+    float* col;
+
+    __device__ __forceinline__ explicit PoolStream(float* pool)
+        : k0(0), k1(0), blk(0), tagsub(0), g0(0), g1(0), head(0), cnt(0),
+          col(pool + threadIdx.x) {}
+
+    __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, uint64_t g,
+                                         uint32_t tag, uint32_t sub) {
+        k0 = seed_lo;
+        k1 = seed_hi;
+        blk = 0;
+        tagsub = (tag << 16) | (sub & 0xFFFFu);
+        g0 = uint32_t(g);
+        g1 = uint32_t(g >> 32);
+        head = 0;
+        cnt = 0;
+    }
+    // Appends the next block of four (needs cnt <= R - 4).
+    __device__ __forceinline__ void gen() {
+        const float4 u = philox_uniforms(blk, tagsub, g0, g1, k0, k1);
+        ++blk;
+        const uint32_t t = head + cnt;
+        col[((t + 0u) & (R - 1)) * kLanes] = u.x;
+        col[((t + 1u) & (R - 1)) * kLanes] = u.y;
+        col[((t + 2u) & (R - 1)) * kLanes] = u.z;
+        col[((t + 3u) & (R - 1)) * kLanes] = u.w;
+        cnt += 4;
+    }
+    // Wave-uniform call: until no active lane holds fewer than `need`
+    // uniforms, every active lane holding fewer than `fill` generates a block
+    // (need <= fill <= R - 3).
+    __device__ __forceinline__ void topup(bool active, uint32_t need, uint32_t fill) {
+        while (__ballot(active && cnt < need) != 0ull) {
+            if (active && cnt < fill) gen();
+        }
+    }
+    __device__ __forceinline__ float next() {
+        if (cnt == 0) gen();
+        const float r = col[head * kLanes];
+        head = (head + 1u) & (R - 1);
+        --cnt;
+        return r;
+    }
+};
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -99,14 +160,16 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 constexpr int kStripes = 64;
 constexpr int kStatWords = L_N + C_N;
 
+// Event counts are 32-bit per lane (a lane sees far fewer than 2^32 events in
+// one launch) and widened to 64 bits in the flush.
 struct LocalStats {
     double l[L_N];
-    unsigned long long c[C_N];
+    uint32_t c[C_N];
     __device__ LocalStats() {
 #pragma unroll
         for (int i = 0; i < L_N; ++i) l[i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < C_N; ++i) c[i] = 0ull;
+        for (int i = 0; i < C_N; ++i) c[i] = 0u;
     }
 };
 
@@ -123,7 +186,7 @@ __device__ __forceinline__ void flush_stats(double* stats, const LocalStats& s) 
     }
 #pragma unroll
     for (int i = 0; i < C_N; ++i) {
-        const unsigned long long v = wave_sum(s.c[i]);
+        const unsigned long long v = wave_sum(static_cast<unsigned long long>(s.c[i]));
         if (lane == 0) red_c[i][w] = v;
     }
     __syncthreads();

@@ -29,6 +29,9 @@ constexpr int kMaxPhotonSteps = 1000000;   // safety bounds: never reached by va
 constexpr int kMaxKahnTrials = 1000;
 constexpr int kBands = 32;              // electron energy bands for the counting sort
 constexpr int kBlock = 256;
+// LDS uniform buffers per lane (ring slots) of the photon and electron kernels
+constexpr int kPhotonPool = 16;
+constexpr int kElectronPool = 8;
 
 struct Stack {
     float *x, *y, *z, *u, *v, *w, *e;
@@ -100,7 +103,7 @@ __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t
 }
 
 __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, float e,
-                                        unsigned long long& n_atomic) {
+                                        uint32_t& n_atomic) {
     if (e == 0.f) return;
     int c = v;
     if (T.imap) {
@@ -156,6 +159,7 @@ __device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t*
 // ---- photon kernel --------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     __shared__ float s_kn[KN_TAB_N];
+    __shared__ float s_pool[kPhotonPool * kBlock];
     for (int i = threadIdx.x; i < KN_TAB_N; i += blockDim.x) s_kn[i] = a.phys.kn[i];
     __syncthreads();
 
@@ -164,10 +168,10 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     dev::LocalStats ls;
     double& esc_g = ls.l[L_ESC_G];
     double& dep = ls.l[L_DEP];
-    unsigned long long &c_wc = ls.c[C_WC_STEPS], &c_real = ls.c[C_REAL], &c_push = ls.c[C_E_PUSHED],
-                       &c_local = ls.c[C_E_LOCAL], &c_atom = ls.c[C_DEPOSITS],
-                       &c_unc = ls.c[C_ESC_UNCOLLIDED], &c_kahn = ls.c[C_KAHN_TRIALS],
-                       &c_over = ls.c[C_OVERFLOW];
+    uint32_t &c_wc = ls.c[C_WC_STEPS], &c_real = ls.c[C_REAL], &c_push = ls.c[C_E_PUSHED],
+             &c_local = ls.c[C_E_LOCAL], &c_atom = ls.c[C_DEPOSITS],
+             &c_unc = ls.c[C_ESC_UNCOLLIDED], &c_kahn = ls.c[C_KAHN_TRIALS],
+             &c_over = ls.c[C_OVERFLOW];
     // electron-stack slots reserved by this wave and not used yet
     uint32_t el_base = 0, el_left = 0;
     // per-lane photon state
@@ -177,7 +181,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     int steps = 0;
     bool collided = false, alive = false;
     WaveQueue wq;
-    dev::Stream st;
+    dev::PoolStream<kPhotonPool, kBlock> st(s_pool);
     for (;;) {
         {
             const uint32_t i = take_work(!alive, wq, a.queue, n);
@@ -196,6 +200,8 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             }
         }
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        // a flight, the collision test, two Kahn trials and the azimuth
+        st.topup(alive, 9, 9);
         // electron set in motion by this lane's step (pushed below, where the
         // whole wave has reconverged)
         bool push = false;
@@ -209,7 +215,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 const float ee = isfinite(e) ? e : 0.f;
                 deposit(a.tally, (vz * G.ny + vy) * G.nx + vx, tag, ee, c_atom);
                 dep += ee;
-                c_over += steps >= kMaxPhotonSteps ? 1ull : 0ull;
+                c_over += steps >= kMaxPhotonSteps ? 1u : 0u;
                 alive = false;
             } else {
                 ++steps;
@@ -225,7 +231,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) &&
                       fz >= 0.f && fz < float(G.nz))) {
                     esc_g += e;
-                    c_unc += collided ? 0ull : 1ull;
+                    c_unc += collided ? 0u : 1u;
                     alive = false;
                 } else {
                     const int v = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
@@ -456,6 +462,7 @@ __device__ __forceinline__ void face_distance(float p, float d, int i, float o, 
 __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     __shared__ float s_rng[RNG_TAB_N];
     __shared__ float s_inv[INV_TAB_N];
+    __shared__ float s_pool[kElectronPool * kBlock];
     for (int i = threadIdx.x; i < RNG_TAB_N; i += blockDim.x) s_rng[i] = a.phys.rng[i];
     for (int i = threadIdx.x; i < INV_TAB_N; i += blockDim.x) s_inv[i] = a.phys.inv[i];
     __syncthreads();
@@ -466,16 +473,15 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     const uint32_t n = min(*s.count, s.capacity);
     dev::LocalStats ls;
     double &esc_e = ls.l[L_ESC_E], &dep = ls.l[L_DEP], &path = ls.l[L_EPATH];
-    unsigned long long &c_steps = ls.c[C_E_STEPS], &c_atom = ls.c[C_DEPOSITS],
-                       &c_bnd = ls.c[C_E_BOUNDARY], &c_guard = ls.c[C_GUARD],
-                       &c_local = ls.c[C_E_LOCAL];
+    uint32_t &c_steps = ls.c[C_E_STEPS], &c_atom = ls.c[C_DEPOSITS], &c_bnd = ls.c[C_E_BOUNDARY],
+             &c_guard = ls.c[C_GUARD], &c_local = ls.c[C_E_LOCAL];
     // per-lane electron state
     float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, pend_e = 0.f;
     int ix = 0, iy = 0, iz = 0, cur_v = 0, pend_v = 0, steps = 0;
     uint32_t tag = 0;
     bool alive = false;
     WaveQueue wq;
-    dev::Stream st;
+    dev::PoolStream<kElectronPool, kBlock> st(s_pool);
     for (;;) {
         {
             const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
@@ -505,6 +511,8 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
             }
         }
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        // one multiple-scattering deflection (two uniforms) per step
+        st.topup(alive && a.ms, 2, 5);
         if (!alive) continue;
         bool done = false;
         if (steps >= kMaxElectronSteps) {
@@ -701,7 +709,8 @@ void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
 
 void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
-                      hipStream_t stream, bool sort_electrons, const PhaseEvents* ev) {
+                      hipStream_t stream, bool sort_electrons, int lane_load,
+                      const PhaseEvents* ev) {
     psl_phantom* ph = const_cast<psl_phantom*>(phc);
     TransportArgs a{};
     a.in = to_stack(in);
@@ -718,17 +727,23 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.seed_hi = uint32_t(seed >> 32);
     a.queue = tally->queues.as<uint32_t>();
     Stack estack = a.el;
+    // The transport kernels are persistent: every lane takes histories from a
+    // queue until it is drained.  The grid is sized to the batch (about
+    // lane_load histories per lane), not to the stacks, so that a lane works
+    // through several histories and a wave is not held up by the one long
+    // history among 64 short ones.
+    const int64_t per_block = int64_t(kBlock) * std::max(1, lane_load);
+    const int tg = int(std::max<int64_t>(1, std::min<int64_t>((int64_t(in->capacity) + per_block - 1) / per_block, 2048)));
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream,
                        in->ptype == 0 ? el->count : nullptr, a.queue);
     if (in->ptype == 0) {
         if (ev) PSL_HIP(hipEventRecord(ev->photon0, stream));
-        hipLaunchKernelGGL(k_photon, dim3(grid_for(in->capacity, 2048)), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL(k_photon, dim3(tg), dim3(kBlock), 0, stream, a);
         PSL_HIP(hipGetLastError());
         if (ev) PSL_HIP(hipEventRecord(ev->photon1, stream));
     } else {
         estack = a.in;
     }
-    const int eg = grid_for(estack.capacity, 2048);
     if (ev) PSL_HIP(hipEventRecord(ev->sort0, stream));
     if (sort_electrons) {
         uint32_t* hist = tally->bands.as<uint32_t>();
@@ -746,7 +761,7 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     }
     if (ev) PSL_HIP(hipEventRecord(ev->sort1, stream));
     if (ev) PSL_HIP(hipEventRecord(ev->electron0, stream));
-    hipLaunchKernelGGL(k_electron, dim3(eg), dim3(kBlock), 0, stream, a, estack);
+    hipLaunchKernelGGL(k_electron, dim3(tg), dim3(kBlock), 0, stream, a, estack);
     PSL_HIP(hipGetLastError());
     if (ev) PSL_HIP(hipEventRecord(ev->electron1, stream));
 }
@@ -880,7 +895,7 @@ extern "C" int transport_batch(const psl_phantom* phantom, const psl_particles* 
         ensure_perm(tally, es->capacity);
         psl_particles dummy = *in;
         launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, params, seed,
-                         static_cast<hipStream_t>(stream), true);
+                         static_cast<hipStream_t>(stream), true, 4);
     });
 }
 

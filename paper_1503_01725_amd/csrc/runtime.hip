@@ -44,7 +44,7 @@ struct GraphKey {
     const psl_plan* plan = nullptr;
     const psl_phantom* phantom = nullptr;
     uint32_t max_batch = 0;
-    int32_t band_width = 0, sort = 0, timing = 0;
+    int32_t band_width = 0, sort = 0, timing = 0, lane_load = 0;
     uint32_t rep0 = 0, n_rep = 0;
     uint64_t seed = 0, n_hist = 0;
     float cut_e = 0, cut_g = 0, frac = 0;
@@ -159,7 +159,7 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
                 ev.electron1 = R.pool[R.timed[tel][2]];
             }
             launch_transport(ph, &R.phs, &R.els, tally, prm, o.seed, s, o.sort_electrons != 0,
-                             o.timing ? &ev : nullptr);
+                             o.lane_load > 0 ? o.lane_load : 4, o.timing ? &ev : nullptr);
         }
         int tf = -1;
         if (o.timing) {
@@ -178,6 +178,7 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
               uint32_t n_rep, hipStream_t user) {
     PSL_CHECK(o.max_batch >= 64, "max_batch must be >= 64");
     PSL_CHECK(o.band_width >= 1, "band_width must be >= 1");
+    PSL_CHECK(o.lane_load >= 0 && o.lane_load <= 4096, "lane_load must be in [0, 4096]");
     PSL_CHECK(tally->phantom == ph, "tally belongs to another phantom");
     PSL_CHECK(prm->e_cut_photon > 0.f && prm->e_cut_electron > 0.f && prm->step_frac > 0.f &&
                   prm->step_frac < 1.f,
@@ -222,6 +223,7 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     k.max_batch = o.max_batch;
     k.band_width = o.band_width;
     k.sort = o.sort_electrons;
+    k.lane_load = o.lane_load;
     k.timing = o.timing;
     k.rep0 = rep0;
     k.n_rep = n_rep;
@@ -293,11 +295,13 @@ extern "C" int psl_run_get_timing(psl_tally* tally, psl_run_timing* out) {
 extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
                             const psl_transport_params* params, uint64_t seed,
                             const uint32_t* max_batch, int32_t n_m, const int32_t* band_width,
-                            int32_t n_w, uint32_t replica, psl_run_opts* best, double* ms_out) {
+                            int32_t n_w, const int32_t* lane_load, int32_t n_l, uint32_t replica,
+                            psl_run_opts* best, double* ms_out) {
     return guarded([&] {
-        PSL_CHECK(plan && phantom && tally && params && max_batch && band_width && best,
+        PSL_CHECK(plan && phantom && tally && params && max_batch && band_width && lane_load &&
+                      best,
                   "psl_autotune: null argument");
-        PSL_CHECK(n_m >= 1 && n_w >= 1, "empty candidate set");
+        PSL_CHECK(n_m >= 1 && n_w >= 1 && n_l >= 1, "empty candidate set");
         PSL_CHECK(replica < plan->n_replica, "replica out of range");
         hipEvent_t e0, e1;
         PSL_HIP(hipEventCreate(&e0));
@@ -305,10 +309,12 @@ extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tall
         double best_ms = 1e300;
         for (int i = 0; i < n_m; ++i)
             for (int j = 0; j < n_w; ++j)
+              for (int l = 0; l < n_l; ++l)
                 for (int srt = 0; srt < 2; ++srt) {
                     psl_run_opts o{};
                     o.max_batch = max_batch[i];
                     o.band_width = band_width[j];
+                    o.lane_load = lane_load[l];
                     o.use_graph = 1;
                     o.sort_electrons = srt;
                     o.timing = 0;
@@ -321,7 +327,7 @@ extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tall
                     PSL_HIP(hipEventSynchronize(e1));
                     float ms = 0.f;
                     PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms_out) ms_out[(i * n_w + j) * 2 + srt] = ms;
+                    if (ms_out) ms_out[((i * n_w + j) * n_l + l) * 2 + srt] = ms;
                     if (ms < best_ms) {
                         best_ms = ms;
                         *best = o;
