@@ -5,9 +5,12 @@ source, one 10x10 cm field, 128^3 water at 0.25 cm, 1e8 histories
 
 One step = reset the tally, run every batch of every replica through the
 native runtime (sampling -> photon transport -> electron energy sort ->
-electron transport, one FP64 fold per replica; all launches replayed from one
-captured hipGraph), and finalise dose and standard error.  Inputs (model
-tables, plan, phantom) are resident in device memory before timing starts.
+electron transport, one FP64 fold per replica), and finalise dose and
+standard error.  The timed steps launch eagerly with a HIP event pair around
+every kernel (the per-kernel times feed the roofline); the same steps
+replayed from one captured hipGraph are timed afterwards (graph_replay).
+Inputs (model tables, plan, phantom) are resident in device memory before
+timing starts.
 
 Prints one JSON line (see the design doc for the roofline and CPU-baseline
 definitions).
@@ -22,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "histories/s (6MV-like 10×10 field, 128³ water)"
+METRICS = {"water128_10": METRIC}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -37,6 +41,41 @@ BYTES_PER_ELECTRON = 36.0 + 4.0       # SoA record + sort order
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# HBM bytes per launch measured with the FETCH_SIZE / WRITE_SIZE counters
+# (scaled by a plain copy of known size); valid only for the kernel sources
+# and options they were taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "water128_10x10_hbm_traffic.md")
+TRAFFIC_SOURCES = ["paper_1503_01725_amd/csrc/k_transport.hip",
+                   "paper_1503_01725_amd/csrc/device.hpp",
+                   "paper_1503_01725_amd/csrc/common.hpp", "paper_1503_01725_amd/build.py"]
+
+
+def measured_traffic(kernel, options):
+    """Bytes per launch of `kernel` from the committed counter summary, or None
+    if the sources changed since or the options differ."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    sha, opts, rows = None, None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            w = line.split()
+            if len(w) >= 2 and w[0] == "source_sha256":
+                sha = w[1]
+            elif w and w[0] == "options":
+                opts = {k: int(v) for k, v in (x.split("=") for x in w[1:])}
+            elif len(w) >= 3 and w[0] == "traffic":
+                rows[w[1]] = {k: float(v) for k, v in (x.split("=") for x in w[2:])}
+    if sha != h.hexdigest() or opts != options or kernel not in rows:
+        return None
+    r = rows[kernel]
+    return r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]
 
 
 def cpu_baseline(W, n_hist_rep, seconds):
@@ -65,6 +104,60 @@ def cpu_baseline(W, n_hist_rep, seconds):
                       f"{dt:.1f} s on {threads} threads, FP64 C oracle -O2"}
 
 
+def describe_phantom(ph):
+    import numpy as np
+    nx, ny, nz = ph.shape_xyz
+    d = ph.density
+    kind = "water" if float(d.min()) == float(d.max()) == 1.0 else \
+        f"heterogeneous, density {float(d.min()):.2f}-{float(d.max()):.2f}"
+    return f"{nx}x{ny}x{nz} {kind}, {ph.vox[0]:g} cm voxels"
+
+
+def describe_beams(beams):
+    return [f"{b.x2 - b.x1:.1f}x{b.y2 - b.y1:.1f} cm at gantry {b.gantry_deg:.0f} deg"
+            for b in beams]
+
+
+def ceilings(N, torch, dose, cnt, value, hist_per_step):
+    """The three ceilings of the dose path, each as a histories/s bound:
+    HBM (streaming copy probe / algorithmic bytes per history), FP32 atomics
+    (atomic-add probe along an address stream drawn from this step's dose
+    distribution / deposits per history) and FP32 VALU (157.3 TFLOP/s /
+    algorithmic FP32 operations per history)."""
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    ms = N.psl_probe_copy(b.data_ptr(), a.data_ptr(), nbytes, 10)
+    copy_gbs = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    del a, b
+    # deposit addresses: i.i.d. voxels drawn with probability proportional to
+    # the step's dose (a stand-in for the recorded deposit stream)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12345)
+    cdf = torch.cumsum(dose.clamp_min(0), 0)
+    cdf = cdf / cdf[-1]
+    n_atom = 1 << 24
+    u = torch.rand(n_atom, generator=g, device="cuda", dtype=torch.float64)
+    addr = torch.searchsorted(cdf, u).clamp_(max=dose.numel() - 1).to(torch.int32)
+    grid = torch.zeros(dose.numel(), dtype=torch.float32, device="cuda")
+    ms_a = N.psl_probe_atomics(grid.data_ptr(), grid.numel(), addr.data_ptr(), n_atom, 10)
+    atomic_rate = n_atom / (ms_a * 1e-3)
+    del addr, grid, u, cdf
+    h = float(hist_per_step)
+    bytes_h = (2 * 40.0 * cnt["entered"] + 80.0 * cnt["e_pushed"] + 4.0 * cnt["wc_steps"]
+               + BYTES_PER_E_STEP * cnt["e_steps"]) / h
+    atoms_h = cnt["deposits"] / h
+    flop_h = (150.0 * cnt["hist"] + FLOP_PER_WC_STEP * cnt["wc_steps"]
+              + FLOP_PER_COMPTON * cnt["real"] + FLOP_PER_E_STEP * cnt["e_steps"]) / h
+    bounds = {"hbm": copy_gbs * 1e9 / bytes_h, "atomic": atomic_rate / atoms_h,
+              "valu": PEAK_FP32_TFLOPS * 1e12 / flop_h}
+    binding = min(bounds, key=bounds.get)
+    return {"hbm_copy_GBs": copy_gbs, "atomic_adds_per_s": atomic_rate,
+            "bytes_per_history": bytes_h, "atomics_per_history": atoms_h,
+            "flop_per_history": flop_h, "bound_histories_per_s": bounds, "binding": binding,
+            "frac_of_binding": value / bounds[binding]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +174,8 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip the HBM-copy and atomic-rate probes")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -113,9 +208,9 @@ def main():
         mb, bw, ll = args.max_batch, args.band_width, args.lane_load
     else:
         log("[bench] autotuning batch size, energy-band width and grid size on one replica")
-        cands_m = [args.max_batch] if args.max_batch else [262144, 524288, 1048576, 2097152]
+        cands_m = [args.max_batch] if args.max_batch else [1048576, 2097152, 4194304]
         cands_w = [args.band_width] if args.band_width else [3, 24]
-        cands_l = [args.lane_load] if args.lane_load else [1, 2, 4, 8]
+        cands_l = [args.lane_load] if args.lane_load else [4, 8, 16, 32]
         best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w, cands_l)
         mb, bw, ll = int(best.max_batch), int(best.band_width), int(best.lane_load)
         srt = int(best.sort_electrons)
@@ -176,13 +271,13 @@ def main():
     hist_per_step = n_hist_rep * n_rep
     value = hist_per_step * args.steps / elapsed
 
-    out = {"metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1,
+    out = {"metric": METRICS.get(args.workload, f"histories/s ({args.workload})"), "value": value, "unit": "histories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": args.workload, "histories": hist_per_step,
-                      "replicas": n_rep, "phantom": "128^3 water, 0.25 cm voxels",
-                      "field": "10x10 cm, SSD 100", "max_batch": mb, "band_width": bw,
+                      "replicas": n_rep, "phantom": describe_phantom(W.phantom),
+                      "fields": describe_beams(W.beams), "max_batch": mb, "band_width": bw,
                       "lane_load": ll,
                       "sort_electrons": srt,
                       "launch": "eager+events" if not args.no_timing else
@@ -206,13 +301,17 @@ def main():
             flop = 150.0 * cnt["hist"] / launches
             bytes_ = 40.0 * cnt["entered"] / launches
         achieved = flop / avg_s / 1e12
+        traffic = measured_traffic(f"k_{phase}", {"max_batch": mb, "band_width": bw,
+                                                  "lane_load": ll, "sort_electrons": srt})
         out["roofline"] = {"bound": "alu", "kernel": f"k_{phase}", "achieved": achieved,
                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                            "avg_launch_ms": ms / launches, "launches_per_step": launches,
                            "hbm_algorithmic_GBs": bytes_ / avg_s / 1e9,
                            "hbm_frac": bytes_ / avg_s / 1e9 / PEAK_HBM_GBS}
         out["phase_ms_per_step"] = {p: round(v[0], 3) for p, v in timing.items()}
+    if not args.no_ceilings:
+        out["ceilings"] = ceilings(N, torch, dose, cnt, value, hist_per_step)
     out["counters_per_step"] = {k: int(v) for k, v in cnt.items()}
     out["ledger_closure"] = (led["src"] - sum(led[k] for k in ("jaw", "missed", "invalid", "esc_g",
                                                                 "esc_e", "dep"))) / led["src"]

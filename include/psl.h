@@ -336,6 +336,26 @@ int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
                  int32_t n_l, uint32_t replica, psl_run_opts* best, double* ms_out);
 
 /* ------------------------------------------------------------------------
+ * Ceiling probes (measurement helpers for the dose path's roofline)
+ * ------------------------------------------------------------------------ */
+
+/* FP32 atomic adds of 1.0 (result unused) into grid_dev[addr_dev[i]] for
+ * i < n, the instruction the dose tally uses (Sec. 2.1.3: every deposit goes
+ * into the shared grid); addresses outside [0, cells) are skipped.  Runs one
+ * warm-up and `repeats` timed launches on a private stream and writes the
+ * average milliseconds per launch to *ms_out.  grid_dev (device FP32
+ * [cells]) accumulates every launch.  Synchronous. */
+int psl_probe_atomics(float* grid_dev, int64_t cells, const int32_t* addr_dev, int64_t n,
+                      int32_t repeats, double* ms_out);
+
+/* Streaming device-to-device copy of `bytes` (a multiple of 16, both
+ * buffers 16-byte aligned) with 16-byte loads and stores; average
+ * milliseconds per launch over `repeats` timed launches after one warm-up.
+ * Synchronous. */
+int psl_probe_copy(void* dst_dev, const void* src_dev, int64_t bytes, int32_t repeats,
+                   double* ms_out);
+
+/* ------------------------------------------------------------------------
  * Commissioning (Sec. 2.2.3, Eq. 8; Sec. 2.2.4)
  * ------------------------------------------------------------------------ */
 typedef struct {

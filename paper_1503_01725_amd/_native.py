@@ -123,6 +123,10 @@ _SIGS.update({
                      C.c_int32, i32p, C.c_int32, C.c_uint32, P(psl_run_opts), dp],
 })
 _SIGS.update({
+    "psl_probe_atomics": [vp, C.c_int64, vp, C.c_int64, C.c_int32, dp],
+    "psl_probe_copy": [vp, vp, C.c_int64, C.c_int32, dp],
+})
+_SIGS.update({
     "psl_unet_create": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(vp)],
     "psl_unet_free": [vp],
     "psl_unet_param_count": [vp, P(C.c_int64)],
@@ -242,6 +246,18 @@ def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, l
           len(mb), bw.ctypes.data_as(i32p), len(bw), ll.ctypes.data_as(i32p), len(ll), replica,
           C.byref(best), ms.ctypes.data_as(dp))
     return best, ms.reshape(len(mb), len(bw), len(ll), 2)
+
+
+def psl_probe_atomics(grid_ptr, cells, addr_ptr, n, repeats=5):
+    ms = C.c_double()
+    _call("psl_probe_atomics", grid_ptr, cells, addr_ptr, n, repeats, C.byref(ms))
+    return ms.value
+
+
+def psl_probe_copy(dst_ptr, src_ptr, nbytes, repeats=5):
+    ms = C.c_double()
+    _call("psl_probe_copy", dst_ptr, src_ptr, nbytes, repeats, C.byref(ms))
+    return ms.value
 
 
 def commission_nnls(a_ptr, m, n, b_ptr, x_ptr, opts, report):

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
 SOURCES = ["host_model.cpp", "physics.cpp", "k_sample.hip", "k_transport.hip", "runtime.hip",
-           "k_nnls.hip", "k_denoise.hip"]
+           "k_nnls.hip", "k_denoise.hip", "k_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}",
@@ -24,8 +24,14 @@ DEVICE = ["-x", "hip", "--offload-arch=gfx950", "-munsafe-fp-atomics",
 HOST = ["-x", "hip", "--offload-arch=gfx950", "-ffp-contract=off", "-fno-fast-math"]
 
 
+# Transport kernels: FP32 division and square root from the hardware
+# reciprocal / square-root instructions (about 1 ulp) instead of the
+# correctly rounded sequences.
+PER_FILE = {"k_transport.hip": ["-fno-hip-fp32-correctly-rounded-divide-sqrt"]}
+
+
 def _compile(src: str, obj: str) -> None:
-    flags = HOST if src.endswith(".cpp") else DEVICE
+    flags = (HOST if src.endswith(".cpp") else DEVICE) + PER_FILE.get(src, [])
     cmd = [HIPCC, *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -34,15 +34,6 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
 // Uniform in [0, 1) from the top 24 bits; exact in FP32.
 __device__ __forceinline__ float top24(uint32_t x) { return float(x >> 8) * kTwoPow24Inv; }
 
-// One Philox block turned into four uniforms.  Kept out of line so that the
-// many draw sites of the transport loops share one copy of the 10 rounds.
-__device__ __noinline__ float4 philox_uniforms(uint32_t blk, uint32_t tagsub, uint32_t g0,
-                                               uint32_t g1, uint32_t k0, uint32_t k1) {
-    uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
-    philox4x32_10(x0, x1, x2, x3, k0, k1);
-    return make_float4(top24(x0), top24(x1), top24(x2), top24(x3));
-}
-
 // The uniforms of one particle: key = seed, counter = (block, tag<<16 | sub,
 // g_lo, g_hi); consumed four per block, in order.
 struct Stream {
@@ -61,11 +52,12 @@ struct Stream {
         left = 0;
     }
     __device__ __forceinline__ void refill() {
-        const float4 u = philox_uniforms(blk, tagsub, g0, g1, k0, k1);
-        u0 = u.x;
-        u1 = u.y;
-        u2 = u.z;
-        u3 = u.w;
+        uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
+        philox4x32_10(x0, x1, x2, x3, k0, k1);
+        u0 = top24(x0);
+        u1 = top24(x1);
+        u2 = top24(x2);
+        u3 = top24(x3);
         ++blk;
         left = 4;
     }
@@ -82,30 +74,30 @@ struct Stream {
 
 // The same per-particle stream with its uniforms buffered in LDS, so that the
 // Philox blocks of a wavefront are generated together.  A lane that runs dry
-// at its own draw site calls the generator with only itself active, and in a
-// wavefront of 64 lanes some lane runs dry at almost every site; instead the
-// whole wavefront tops its buffers up at one point of the loop (topup), where
-// every lane with room generates at once, and next() only falls back to its
-// own generation when a history draws more than the top-up left.  The
-// sequence of values each history consumes is unchanged.
+// at its own draw site would call the generator with only itself active, and
+// in a wavefront of 64 lanes some lane runs dry at almost every site; instead
+// the whole wavefront tops its buffers up at one point of the loop (topup),
+// where every lane with room generates at once, and the loop consumes at
+// most what the top-up guarantees (pop), carrying unfinished work over to the
+// next iteration.  The sequence of values each history consumes is unchanged.
 //
 // Lane t of a workgroup of kLanes threads owns the column pool[j * kLanes + t]
-// for ring slots j < R (bank-conflict free for any per-lane slot).
+// for ring slots j < R (bank-conflict free for any per-lane slot).  The key is
+// fixed for the launch, so it stays in scalar registers.
 template <int R, int kLanes>
 struct PoolStream {
     static_assert((R & (R - 1)) == 0 && R >= 8, "ring size must be a power of two >= 8");
-    uint32_t k0, k1, blk, tagsub, g0, g1;
+    const uint32_t k0, k1;
+    uint32_t blk, tagsub, g0, g1;
     uint32_t head, cnt;
     float* col;
 
-    __device__ __forceinline__ explicit PoolStream(float* pool)
-        : k0(0), k1(0), blk(0), tagsub(0), g0(0), g1(0), head(0), cnt(0),
+    __device__ __forceinline__ PoolStream(float* pool, uint32_t seed_lo, uint32_t seed_hi)
+        : k0(seed_lo), k1(seed_hi), blk(0), tagsub(0), g0(0), g1(0), head(0), cnt(0),
           col(pool + threadIdx.x) {}
 
-    __device__ __forceinline__ void init(uint32_t seed_lo, uint32_t seed_hi, uint64_t g,
-                                         uint32_t tag, uint32_t sub) {
-        k0 = seed_lo;
-        k1 = seed_hi;
+    // Counter of the particle's stream: (block, tag<<16 | sub, g_lo, g_hi).
+    __device__ __forceinline__ void init(uint64_t g, uint32_t tag, uint32_t sub) {
         blk = 0;
         tagsub = (tag << 16) | (sub & 0xFFFFu);
         g0 = uint32_t(g);
@@ -113,27 +105,26 @@ struct PoolStream {
         head = 0;
         cnt = 0;
     }
-    // Appends the next block of four (needs cnt <= R - 4).
-    __device__ __forceinline__ void gen() {
-        const float4 u = philox_uniforms(blk, tagsub, g0, g1, k0, k1);
-        ++blk;
-        const uint32_t t = head + cnt;
-        col[((t + 0u) & (R - 1)) * kLanes] = u.x;
-        col[((t + 1u) & (R - 1)) * kLanes] = u.y;
-        col[((t + 2u) & (R - 1)) * kLanes] = u.z;
-        col[((t + 3u) & (R - 1)) * kLanes] = u.w;
-        cnt += 4;
-    }
     // Wave-uniform call: until no active lane holds fewer than `need`
-    // uniforms, every active lane holding fewer than `fill` generates a block
-    // (need <= fill <= R - 3).
+    // uniforms, every active lane holding fewer than `fill` appends the next
+    // block of four (need <= fill <= R - 3).
     __device__ __forceinline__ void topup(bool active, uint32_t need, uint32_t fill) {
         while (__ballot(active && cnt < need) != 0ull) {
-            if (active && cnt < fill) gen();
+            if (active && cnt < fill) {
+                uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
+                philox4x32_10(x0, x1, x2, x3, k0, k1);
+                ++blk;
+                const uint32_t t = head + cnt;
+                col[((t + 0u) & (R - 1)) * kLanes] = top24(x0);
+                col[((t + 1u) & (R - 1)) * kLanes] = top24(x1);
+                col[((t + 2u) & (R - 1)) * kLanes] = top24(x2);
+                col[((t + 3u) & (R - 1)) * kLanes] = top24(x3);
+                cnt += 4;
+            }
         }
     }
-    __device__ __forceinline__ float next() {
-        if (cnt == 0) gen();
+    // Next uniform; the caller guarantees cnt > 0.
+    __device__ __forceinline__ float pop() {
         const float r = col[head * kLanes];
         head = (head + 1u) & (R - 1);
         --cnt;

@@ -80,6 +80,15 @@ __device__ __forceinline__ float csda_energy(const PhysicsDev& P, const float* t
     return lerp_tab(tab, INV_TAB_N, (__logf(r + P.r_off) - P.inv_u0) * P.inv_inv_du);
 }
 
+// ---- hardware transcendentals ---------------------------------------------
+// Sine and cosine of a whole turn times r (v_sin_f32 / v_cos_f32 take their
+// argument in revolutions, |r| <= 256), and the natural logarithm from
+// v_log_f32.  A few ulp, far below the statistical noise of the transport.
+__device__ __forceinline__ void sincos_turn(float r, float& s, float& c) {
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+
 // ---- geometry -------------------------------------------------------------
 __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t, float cphi,
                                        float sphi) {
@@ -157,6 +166,13 @@ __device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t*
 }
 
 // ---- photon kernel --------------------------------------------------------
+// One lane follows one photon at a time through Woodcock flights and Compton
+// collisions.  A lane's photon is a small state machine (flight, Kahn trials,
+// scattering) that advances as far as the uniforms topped up at the start of
+// the iteration allow and resumes in the next iteration, so every Philox block
+// of the wavefront is generated at the one top-up point.
+enum PhotonPhase : uint32_t { kFlight = 0, kKahn = 1, kScatter = 2 };
+
 __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     __shared__ float s_kn[KN_TAB_N];
     __shared__ float s_pool[kPhotonPool * kBlock];
@@ -176,12 +192,13 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     uint32_t el_base = 0, el_left = 0;
     // per-lane photon state
     float px = 0.f, py = 0.f, pz = 0.f, du = 0.f, dv = 0.f, dw = 0.f, e = 0.f;
+    float kx = 1.f;          // Kahn variable E/E' of the current collision
     uint64_t g = 0;
-    uint32_t tag = 0, n_push = 0;
-    int steps = 0;
+    uint32_t tag = 0, n_push = 0, phase = kFlight, trials = 0;
+    int steps = 0, cv = 0;   // cv: voxel of the current collision
     bool collided = false, alive = false;
     WaveQueue wq;
-    dev::PoolStream<kPhotonPool, kBlock> st(s_pool);
+    dev::PoolStream<kPhotonPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
     for (;;) {
         {
             const uint32_t i = take_work(!alive, wq, a.queue, n);
@@ -192,21 +209,23 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 e = a.in.e[i];
                 g = a.in.hid[i];
                 tag = tg & 0xFFFFu;
-                st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, 0);
+                st.init(g, dev::kTagTransport, 0);
                 n_push = 0;
                 steps = 0;
+                phase = kFlight;
                 collided = false;
                 alive = true;
             }
         }
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
-        // a flight, the collision test, two Kahn trials and the azimuth
-        st.topup(alive, 9, 9);
-        // electron set in motion by this lane's step (pushed below, where the
-        // whole wave has reconverged)
+        // a flight and its collision test (2), two Kahn trials (6) and the
+        // azimuth (1) fit in one iteration
+        st.topup(alive, 9, 12);
+        // electron set in motion by this lane (pushed below, where the whole
+        // wave has reconverged)
         bool push = false;
         float qx = 0.f, qy = 0.f, qz = 0.f, te = 0.f;
-        if (alive) {
+        if (alive && phase == kFlight) {
             if (!(e >= a.e_cut_g) || steps >= kMaxPhotonSteps) {
                 // below the cut-off on entry, or the safety bound: absorb here
                 const int vx = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
@@ -221,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 ++steps;
                 // one Woodcock flight
                 const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
-                const float s = -logf(1.f - st.next()) / mu;
+                const float s = -__logf(1.f - st.pop()) / mu;
                 px = fmaf(s, du, px);
                 py = fmaf(s, dv, py);
                 pz = fmaf(s, dw, pz);
@@ -234,61 +253,73 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                     c_unc += collided ? 0u : 1u;
                     alive = false;
                 } else {
-                    const int v = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
+                    cv = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
                     ++c_wc;
-                    const float ur = st.next();
-                    if (ur < G.dens[v] * G.inv_rho_max) {   // real collision
+                    if (st.pop() < G.dens[cv] * G.inv_rho_max) {   // real collision
                         collided = true;
                         ++c_real;
-                        // Kahn's method for x = E/E' in [1, 1 + 2k]
-                        const float k = e * (1.f / kMe);
-                        const float k2 = 2.f * k;
-                        float x = 1.f;
-                        for (int trial = 0; trial < kMaxKahnTrials; ++trial) {
-                            const float r1 = st.next(), r2 = st.next(), r3 = st.next();
-                            ++c_kahn;
-                            if (r1 <= (1.f + k2) / (9.f + k2)) {
-                                x = fmaf(k2, r2, 1.f);
-                                if (r3 <= 4.f * (1.f / x - 1.f / (x * x))) break;
-                            } else {
-                                x = (1.f + k2) / fmaf(k2, r2, 1.f);
-                                const float c = 1.f - (x - 1.f) / k;
-                                if (r3 <= 0.5f * (c * c + 1.f / x)) break;
-                            }
-                        }
-                        const float cos_t = 1.f - (x - 1.f) / k;
-                        float sphi, cphi;
-                        sincospif(2.f * st.next(), &sphi, &cphi);
-                        const float e1 = e / x;
-                        te = e - e1;
-                        float nu = du, nv = dv, nw = dw;
-                        rotate(nu, nv, nw, cos_t, cphi, sphi);
-                        if (te >= a.e_cut_e) {
-                            // electron direction from momentum conservation: p_e = E d - E' d'
-                            qx = e * du - e1 * nu;
-                            qy = e * dv - e1 * nv;
-                            qz = e * dw - e1 * nw;
-                            const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
-                            qx *= inv;
-                            qy *= inv;
-                            qz *= inv;
-                            ++n_push;
-                            ++c_push;
-                            push = true;
-                        } else {
-                            deposit(a.tally, v, tag, te, c_atom);
-                            dep += te;
-                            ++c_local;
-                        }
-                        e = e1;
-                        du = nu; dv = nv; dw = nw;
-                        if (e < a.e_cut_g) {
-                            deposit(a.tally, v, tag, e, c_atom);
-                            dep += e;
-                            alive = false;
-                        }
+                        phase = kKahn;
+                        trials = 0;
                     }
                 }
+            }
+        }
+        if (alive && phase == kKahn) {
+            // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a trial
+            const float k = e * (1.f / kMe);
+            const float k2 = 2.f * k;
+            while (st.cnt >= 3u) {
+                const float r1 = st.pop(), r2 = st.pop(), r3 = st.pop();
+                ++c_kahn;
+                ++trials;
+                bool acc;
+                if (r1 <= (1.f + k2) / (9.f + k2)) {
+                    kx = fmaf(k2, r2, 1.f);
+                    acc = r3 <= 4.f * (1.f / kx - 1.f / (kx * kx));
+                } else {
+                    kx = (1.f + k2) / fmaf(k2, r2, 1.f);
+                    const float c = 1.f - (kx - 1.f) / k;
+                    acc = r3 <= 0.5f * (c * c + 1.f / kx);
+                }
+                if (acc || trials >= uint32_t(kMaxKahnTrials)) {
+                    phase = kScatter;
+                    break;
+                }
+            }
+        }
+        if (alive && phase == kScatter && st.cnt >= 1u) {
+            const float k = e * (1.f / kMe);
+            const float cos_t = 1.f - (kx - 1.f) / k;
+            float sphi, cphi;
+            sincos_turn(st.pop(), sphi, cphi);
+            const float e1 = e / kx;
+            te = e - e1;
+            float nu = du, nv = dv, nw = dw;
+            rotate(nu, nv, nw, cos_t, cphi, sphi);
+            if (te >= a.e_cut_e) {
+                // electron direction from momentum conservation: p_e = E d - E' d'
+                qx = e * du - e1 * nu;
+                qy = e * dv - e1 * nv;
+                qz = e * dw - e1 * nw;
+                const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
+                qx *= inv;
+                qy *= inv;
+                qz *= inv;
+                ++n_push;
+                ++c_push;
+                push = true;
+            } else {
+                deposit(a.tally, cv, tag, te, c_atom);
+                dep += te;
+                ++c_local;
+            }
+            e = e1;
+            du = nu; dv = nv; dw = nw;
+            phase = kFlight;
+            if (e < a.e_cut_g) {
+                deposit(a.tally, cv, tag, e, c_atom);
+                dep += e;
+                alive = false;
             }
         }
         // wave-convergent push: slots from the wave's reserved chunk of the
@@ -481,7 +512,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     uint32_t tag = 0;
     bool alive = false;
     WaveQueue wq;
-    dev::PoolStream<kElectronPool, kBlock> st(s_pool);
+    dev::PoolStream<kElectronPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
     for (;;) {
         {
             const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
@@ -502,7 +533,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                     dep += t;
                     ++c_local;
                 } else {
-                    st.init(a.seed_lo, a.seed_hi, g, dev::kTagTransport, (tg >> 16) & 0xFFu);
+                    st.init(g, dev::kTagTransport, (tg >> 16) & 0xFFu);
                     pend_v = cur_v;
                     pend_e = 0.f;
                     steps = 0;
@@ -511,7 +542,8 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
             }
         }
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
-        // one multiple-scattering deflection (two uniforms) per step
+        // one multiple-scattering deflection (two uniforms) per step, at most
+        // one step per iteration
         st.topup(alive && a.ms, 2, 5);
         if (!alive) continue;
         bool done = false;
@@ -590,12 +622,13 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                         const float bcp = tm * (tm + 2.f * kMe) / (tm + kMe);
                         float th0 = 0.f;
                         if (tx > 0.f)
-                            th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, logf(tx), 1.f), 0.f);
-                        const float u1 = st.next(), u2 = st.next();
-                        const float th = fminf(th0 * sqrtf(-2.f * logf(1.f - u1)), 3.14159265358979f);
+                            th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, __logf(tx), 1.f), 0.f);
+                        const float u1 = st.pop(), u2 = st.pop();
+                        const float th = fminf(th0 * sqrtf(-2.f * __logf(1.f - u1)), 3.14159265358979f);
                         float sphi, cphi;
-                        sincospif(2.f * u2, &sphi, &cphi);
-                        rotate(dx, dy, dz, cosf(th), cphi, sphi);
+                        sincos_turn(u2, sphi, cphi);
+                        rotate(dx, dy, dz, __builtin_amdgcn_cosf(th * 0.15915494309189535f), cphi,
+                               sphi);
                     }
                 }
             }
