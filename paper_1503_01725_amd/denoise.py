@@ -143,6 +143,68 @@ def train(net, pairs, epochs, lr, log=print, lr_decay=0.5):
     return hist
 
 
+def unet_flops(c, n, levels=4):
+    """Dense FP operations of one forward pass (a multiply-add counts 2) of the
+    U-Net at base width c on an n^3 volume: 3x3x3 convolutions, 2x2x2
+    transposed convolutions and the 1x1x1 head."""
+    from .unet_init import layer_shapes
+    f = 0.0
+    for name, shape in layer_shapes(c, levels=levels):
+        if not name.endswith(".w"):
+            continue
+        if name == "head.w":
+            f += 2.0 * c * n ** 3
+            continue
+        lvl = int(name[3]) if name.startswith(("enc", "dec")) else int(name[2])
+        p = (n >> lvl) ** 3                       # output voxels of the layer
+        if name.startswith("up"):
+            f += 2.0 * shape[0] * shape[1] * 8 * (n >> (lvl + 1)) ** 3
+        else:
+            f += 2.0 * shape[0] * shape[1] * 27 * p
+    return f
+
+
+def bench_unet(width=32, n=128, iters=10, log=print):
+    """Forward and training-step time of the U-Net on an n^3 volume and the
+    MFMA rate they reach (BF16 dense peak 2.5 PFLOP/s).  A training step is
+    forward + backward (input-gradient and weight-gradient GEMMs, 2x the
+    forward) + Adam."""
+    import torch
+    from . import engine as eng
+    from .unet_init import init_params
+    net = eng.UNet(width, n, n, n)
+    net.set_params(init_params(7, width, net.n_params))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    inp = torch.rand((2, n, n, n), generator=g, device="cuda")
+    tgt = torch.rand((n, n, n), generator=g, device="cuda")
+    for _ in range(2):
+        net.forward(inp)
+        net.train_step(inp, tgt, 1e-4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        net.forward(inp)
+    e1.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / iters
+    e0.record()
+    for _ in range(iters):
+        net.train_step(inp, tgt, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / iters
+    f = unet_flops(width, n)
+    out = {"width": width, "n": n, "params": int(net.n_params), "forward_ms": t_fwd,
+           "train_step_ms": t_train, "forward_tflops": f / t_fwd / 1e9,
+           "train_tflops": 3 * f / t_train / 1e9, "forward_gflop": f / 1e9,
+           "mfma_peak_tflops": 2500.0, "forward_frac": f / t_fwd / 1e9 / 2500.0,
+           "train_frac": 3 * f / t_train / 1e9 / 2500.0}
+    log(f"[denoise] {json.dumps(out)}")
+    return out
+
+
 def main():
     import argparse
     import torch
@@ -158,7 +220,12 @@ def main():
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--out", default="gpurun_out/denoise.json")
     ap.add_argument("--save", default="")
+    ap.add_argument("--bench", action="store_true",
+                    help="only time forward / training step at --width, --n")
     args = ap.parse_args()
+    if args.bench:
+        print(json.dumps(bench_unet(args.width, args.n)))
+        return
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
