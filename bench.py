@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--band-width", type=int, default=0, help="0 = autotune")
     ap.add_argument("--lane-load", type=int, default=0,
                     help="histories per lane of the persistent transport grids (0 = autotune)")
+    ap.add_argument("--pipelines", type=int, default=0,
+                    help="concurrent batch pipelines, 1 or 2 (0 = autotune)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--sort", default="auto", choices=("auto", "0", "1"),
                     help="group electrons by energy band before transport")
@@ -204,19 +206,22 @@ def main():
 
     tune = None
     srt = 1
-    if args.max_batch and args.band_width and args.lane_load:
-        mb, bw, ll = args.max_batch, args.band_width, args.lane_load
+    if args.max_batch and args.band_width and args.lane_load and args.pipelines:
+        mb, bw, ll, npipe = args.max_batch, args.band_width, args.lane_load, args.pipelines
     else:
-        log("[bench] autotuning batch size, energy-band width and grid size on one replica")
+        log("[bench] autotuning batch size, band width, grid size and pipelines on one replica")
         cands_m = [args.max_batch] if args.max_batch else [2097152, 4194304, 8388608]
         cands_w = [args.band_width] if args.band_width else [3, 24]
         cands_l = [args.lane_load] if args.lane_load else [8, 16, 32, 64]
         best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w, cands_l)
         mb, bw, ll = int(best.max_batch), int(best.band_width), int(best.lane_load)
-        srt = int(best.sort_electrons)
+        srt, npipe = int(best.sort_electrons), int(best.pipelines)
+        if args.pipelines:
+            npipe = args.pipelines
         tune = {"max_batch": cands_m, "band_width": cands_w, "lane_load": cands_l,
-                "sort_electrons": [0, 1], "ms_per_replica": ms.tolist()}
-        log(f"[bench] autotune -> max_batch {mb} band_width {bw} lane_load {ll} sort {srt}")
+                "sort_electrons": [0, 1], "pipelines": [1, 2], "ms_per_replica": ms.tolist()}
+        log(f"[bench] autotune -> max_batch {mb} band_width {bw} lane_load {ll} sort {srt} "
+            f"pipelines {npipe}")
     if args.sort in ("0", "1"):
         srt = int(args.sort)
     # the timed region launches eagerly with a HIP event pair around every
@@ -224,7 +229,7 @@ def main():
     # steps replayed from a captured hipGraph are timed separately below
     opts = eng.run_opts(mb, bw, use_graph=args.no_timing and not args.no_graph,
                         sort_electrons=bool(srt), timing=not args.no_timing, seed=seed,
-                        lane_load=ll)
+                        lane_load=ll, pipelines=npipe)
     dose = torch.zeros(tally.cells, dtype=torch.float64, device="cuda")
     sig = torch.zeros_like(dose)
     stream = torch.cuda.current_stream()
@@ -257,7 +262,7 @@ def main():
     graph_replay = None
     if not args.no_timing and not args.no_graph:
         opts = eng.run_opts(mb, bw, use_graph=True, sort_electrons=bool(srt), timing=False,
-                            seed=seed, lane_load=ll)
+                            seed=seed, lane_load=ll, pipelines=npipe)
         step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -278,7 +283,7 @@ def main():
            "config": {"workload": args.workload, "histories": hist_per_step,
                       "replicas": n_rep, "phantom": describe_phantom(W.phantom),
                       "fields": describe_beams(W.beams), "max_batch": mb, "band_width": bw,
-                      "lane_load": ll,
+                      "lane_load": ll, "pipelines": npipe,
                       "sort_electrons": srt,
                       "launch": "eager+events" if not args.no_timing else
                       ("graph" if not args.no_graph else "eager"), "autotune": tune}}
@@ -302,7 +307,7 @@ def main():
             bytes_ = 40.0 * cnt["entered"] / launches
         achieved = flop / avg_s / 1e12
         traffic = measured_traffic(f"k_{phase}", {"max_batch": mb, "band_width": bw,
-                                                  "lane_load": ll, "sort_electrons": srt})
+                                                  "lane_load": ll, "pipelines": npipe, "sort_electrons": srt})
         out["roofline"] = {"bound": "alu", "kernel": f"k_{phase}", "achieved": achieved,
                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,

@@ -304,11 +304,16 @@ typedef struct {
                                 grids: they launch ceil(max_batch / (256 *
                                 lane_load)) workgroups of 256, at most 2048
                                 (0 = 4)                                            */
+    int32_t pipelines;       /* 1 or 2 batch pipelines (own stacks and stream each);
+                                with 2 the batches of a replica alternate between
+                                them and run concurrently, joined before the
+                                replica's fold (0 = 1)                              */
 } psl_run_opts;
 
 /* Runs every batch of every replica of `plan` -- sample_batch, transport_batch
  * and one tally FOLD per replica, with replica r using history ids
- * g = r * N + h -- on `stream`.  Particle stacks live in the tally's workspace
+ * g = r * N + h -- on `stream` (and, with two pipelines, on two streams of
+ * the runtime forked from and joined back to `stream`).  Particle stacks live in the tally's workspace
  * (allocated on first use; the electron stack holds max_batch *
  * floor(e_max / e_cut_electron) entries, so it cannot overflow).  The tally is
  * not reset.  Asynchronous. */
@@ -325,11 +330,12 @@ typedef struct {
 int psl_run_get_timing(psl_tally* tally, psl_run_timing* out);
 
 /* Autotuner: times one replica (`replica`) of the plan for every candidate
- * (max_batch[i], band_width[j], lane_load[l], sort_electrons s in {0, 1})
- * with graph replay, writes the measured milliseconds to
- * ms_out[((i * n_w + j) * n_l + l) * 2 + s] (nullable) and the fastest options
- * to *best (use_graph = 1, seed as given).  Resets the tally afterwards.
- * Synchronous. */
+ * (max_batch[i], band_width[j], lane_load[l], sort_electrons s in {0, 1},
+ * pipelines p in {1, 2}) with graph replay, writes the measured milliseconds
+ * to ms_out[(((i * n_w + j) * n_l + l) * 2 + s) * 2 + p - 1] (nullable) and
+ * to *best the first candidate in that order within 3 % of the fastest
+ * (use_graph = 1, seed as given), so that near-ties resolve alike from run to
+ * run.  Resets the tally afterwards.  Synchronous. */
 int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
                  const psl_transport_params* params, uint64_t seed, const uint32_t* max_batch,
                  int32_t n_m, const int32_t* band_width, int32_t n_w, const int32_t* lane_load,

@@ -68,7 +68,7 @@ class psl_transport_params(C.Structure):
 class psl_run_opts(C.Structure):
     _fields_ = [("max_batch", C.c_uint32), ("band_width", C.c_int32), ("use_graph", C.c_int32),
                 ("sort_electrons", C.c_int32), ("timing", C.c_int32), ("seed", C.c_uint64),
-                ("lane_load", C.c_int32)]
+                ("lane_load", C.c_int32), ("pipelines", C.c_int32)]
 
 
 class psl_run_timing(C.Structure):
@@ -240,12 +240,12 @@ def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, l
     mb = np.ascontiguousarray(max_batches, dtype=np.uint32)
     bw = np.ascontiguousarray(band_widths, dtype=np.int32)
     ll = np.ascontiguousarray(lane_loads, dtype=np.int32)
-    ms = np.zeros(len(mb) * len(bw) * len(ll) * 2)
+    ms = np.zeros(len(mb) * len(bw) * len(ll) * 4)
     best = psl_run_opts()
     _call("psl_autotune", plan, phantom, tally, C.byref(params), seed, mb.ctypes.data_as(u32p),
           len(mb), bw.ctypes.data_as(i32p), len(bw), ll.ctypes.data_as(i32p), len(ll), replica,
           C.byref(best), ms.ctypes.data_as(dp))
-    return best, ms.reshape(len(mb), len(bw), len(ll), 2)
+    return best, ms.reshape(len(mb), len(bw), len(ll), 2, 2)
 
 
 def psl_probe_atomics(grid_ptr, cells, addr_ptr, n, repeats=5):

@@ -87,6 +87,17 @@ struct DevBuf {
     }
 };
 
+// Scratch of one transport pipeline: the two work-queue heads, the band
+// counters / offsets of the electron energy sort and the electron order.
+constexpr int kSortBands = 32;      // electron energy bands of the counting sort
+constexpr int kSortBlocks = 1024;   // fixed grid of the counting sort
+struct TransportWs {
+    uint32_t* queues = nullptr;     // [64]
+    uint32_t* bands = nullptr;      // [2 * kSortBands * kSortBlocks]
+    uint32_t* perm = nullptr;       // [perm_cap]
+    uint32_t perm_cap = 0;
+};
+
 // ---------------------------------------------------------------------------
 // Device layouts
 // ---------------------------------------------------------------------------
@@ -216,9 +227,8 @@ struct psl_tally {
     psl::DevBuf stats;     // double ledger [L_N] + u64 counters [C_N]
     psl::DevBuf row_rho;   // float [n_rows] density of each row's voxel (index-map mode)
     psl::DevBuf col_w;     // double [n_cols] column weights (finalize scratch)
-    psl::DevBuf perm;      // uint32 electron order after the energy-band sort
-    psl::DevBuf bands;     // uint32 band counters / offsets
-    psl::DevBuf queues;    // uint32 work-queue heads of the transport kernels
+    psl::DevBuf ws_mem;    // transport scratch of transport_batch (queues, bands, order)
+    psl::TransportWs ws{};
     uint32_t folds = 0;
     psl::Runner* runner = nullptr;     // batched-runtime workspace (runtime.hip)
     ~psl_tally();
@@ -240,6 +250,10 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p);
 void ensure_device(const psl_model* m);
 void ensure_device(const psl_plan* p);
 
+// Allocates the scratch for an electron stack of up to perm_cap entries in buf.
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap);
+
+
 // Optional HIP events recorded around the transport launches (may be null).
 struct PhaseEvents {
     hipEvent_t photon0, photon1, sort0, sort1, electron0, electron1;
@@ -251,10 +265,9 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
                    int stype, uint64_t seed, const psl_particles* out, int dense, psl_tally* tally,
                    hipStream_t stream);
 void launch_transport(const psl_phantom* ph, const psl_particles* in, psl_particles* el,
-                      psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
-                      hipStream_t stream, bool sort_electrons, int lane_load,
+                      psl_tally* tally, const TransportWs& ws, const psl_transport_params* prm,
+                      uint64_t seed, hipStream_t stream, bool sort_electrons, int lane_load,
                       const PhaseEvents* ev = nullptr);
 void launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 void launch_fold(psl_tally* t, hipStream_t s);
-void ensure_perm(psl_tally* t, uint32_t capacity);
 }  // namespace psl

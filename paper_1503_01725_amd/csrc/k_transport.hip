@@ -27,7 +27,7 @@ constexpr float kX0Water = 36.08f;      // g/cm^2
 constexpr int kMaxElectronSteps = 100000;
 constexpr int kMaxPhotonSteps = 1000000;   // safety bounds: never reached by valid input
 constexpr int kMaxKahnTrials = 1000;
-constexpr int kBands = 32;              // electron energy bands for the counting sort
+constexpr int kBands = kSortBands;
 constexpr int kBlock = 256;
 // LDS uniform buffers per lane (ring slots) of the photon and electron kernels
 constexpr int kPhotonPool = 16;
@@ -371,7 +371,6 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
 // stack.  Pass 1 writes per-block band counts, pass 2 turns them into offsets
 // (band-major, highest band first, so long-range electrons start first),
 // pass 3 scatters the indices; only LDS atomics are used.
-constexpr int kSortBlocks = 1024;
 
 // log-spaced bands between the electron cut-off and the table top
 __device__ __forceinline__ int band_of(float t, float lt0, float inv_w) {
@@ -740,9 +739,21 @@ void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
 }
 
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap) {
+    const size_t q = 256, b = size_t(2) * kBands * kSortBlocks * 4, pm = size_t(perm_cap) * 4;
+    buf.alloc(q + b + pm);
+    TransportWs ws;
+    char* base = buf.as<char>();
+    ws.queues = reinterpret_cast<uint32_t*>(base);
+    ws.bands = reinterpret_cast<uint32_t*>(base + q);
+    ws.perm = reinterpret_cast<uint32_t*>(base + q + b);
+    ws.perm_cap = perm_cap;
+    return ws;
+}
+
 void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
-                      psl_tally* tally, const psl_transport_params* prm, uint64_t seed,
-                      hipStream_t stream, bool sort_electrons, int lane_load,
+                      psl_tally* tally, const TransportWs& ws, const psl_transport_params* prm,
+                      uint64_t seed, hipStream_t stream, bool sort_electrons, int lane_load,
                       const PhaseEvents* ev) {
     psl_phantom* ph = const_cast<psl_phantom*>(phc);
     TransportArgs a{};
@@ -758,7 +769,7 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.ms = prm->ms_enable;
     a.seed_lo = uint32_t(seed);
     a.seed_hi = uint32_t(seed >> 32);
-    a.queue = tally->queues.as<uint32_t>();
+    a.queue = ws.queues;
     Stack estack = a.el;
     // The transport kernels are persistent: every lane takes histories from a
     // queue until it is drained.  The grid is sized to the batch (about
@@ -779,10 +790,10 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     }
     if (ev) PSL_HIP(hipEventRecord(ev->sort0, stream));
     if (sort_electrons) {
-        uint32_t* hist = tally->bands.as<uint32_t>();
+        uint32_t* hist = ws.bands;
         uint32_t* offs = hist + kBands * kSortBlocks;
-        uint32_t* perm = tally->perm.as<uint32_t>();
-        PSL_CHECK(tally->perm.bytes >= size_t(estack.capacity) * 4, "electron order buffer too small");
+        uint32_t* perm = ws.perm;
+        PSL_CHECK(ws.perm_cap >= estack.capacity, "electron order buffer too small");
         const float lt0 = std::log(ph->phys.t_cut);
         const float inv_w = float(kBands) / (std::log(ph->phys.t_max) - lt0);
         hipLaunchKernelGGL(k_band_count, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
@@ -805,9 +816,6 @@ void launch_fold(psl_tally* t, hipStream_t s) {
     PSL_HIP(hipGetLastError());
 }
 
-void ensure_perm(psl_tally* t, uint32_t capacity) {
-    if (t->perm.bytes < size_t(capacity) * 4) t->perm.alloc(size_t(capacity) * 4);
-}
 
 }  // namespace psl
 
@@ -878,8 +886,7 @@ extern "C" int psl_tally_create(const psl_phantom* ph, const int32_t* imap, int3
         t->sum.alloc(size_t(t->cells) * 8);
         t->sum2.alloc(size_t(t->cells) * 8);
         t->stats.alloc(size_t(dev::kStripes) * dev::kStatWords * 8);
-        t->bands.alloc(size_t(2) * kBands * kSortBlocks * 4);
-        t->queues.alloc(256);
+        t->ws = alloc_transport_ws(t->ws_mem, 0);
         t->col_w.alloc(size_t(t->n_cols) * 8);
         if (imap) {
             t->row_rho.alloc(size_t(n_rows) * 4);
@@ -925,10 +932,11 @@ extern "C" int transport_batch(const psl_phantom* phantom, const psl_particles* 
         }
         const psl_particles* es = in->ptype == 0 ? electrons : in;
         ensure_physics(const_cast<psl_phantom*>(phantom), params);
-        ensure_perm(tally, es->capacity);
+        if (tally->ws.perm_cap < es->capacity)
+            tally->ws = alloc_transport_ws(tally->ws_mem, es->capacity);
         psl_particles dummy = *in;
-        launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, params, seed,
-                         static_cast<hipStream_t>(stream), true, 4);
+        launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, tally->ws,
+                         params, seed, static_cast<hipStream_t>(stream), true, 4);
     });
 }
 

@@ -257,12 +257,12 @@ def run_plan_eager(plan: Plan, phantom: Phantom, tally: Tally, params, seed, max
 
 
 def run_opts(max_batch=131072, band_width=1, use_graph=True, sort_electrons=True, timing=False,
-             seed=0, lane_load=0):
+             seed=0, lane_load=0, pipelines=0):
     """Options of psl_run; lane_load 0 = four histories per lane of the
-    persistent transport grids."""
+    persistent transport grids; pipelines 0 = one batch pipeline."""
     return N.psl_run_opts(int(max_batch), int(band_width), 1 if use_graph else 0,
                           1 if sort_electrons else 0, 1 if timing else 0, int(seed),
-                          int(lane_load))
+                          int(lane_load), int(pipelines))
 
 
 def run_plan(plan: Plan, phantom: Phantom, tally: Tally, params, opts, stream=None):
@@ -272,8 +272,8 @@ def run_plan(plan: Plan, phantom: Phantom, tally: Tally, params, opts, stream=No
 
 def autotune(plan: Plan, phantom: Phantom, tally: Tally, params, seed,
              max_batches=(65536, 131072, 262144, 524288), band_widths=(1, 2, 4), lane_loads=(4,)):
-    """Fastest (max_batch, band_width, lane_load, sort) by timing one replica;
-    returns the options and the times [n_m, n_w, n_l, 2] in ms."""
+    """Fastest (max_batch, band_width, lane_load, sort, pipelines) by timing one
+    replica; returns the options and the times [n_m, n_w, n_l, 2, 2] in ms."""
     return N.psl_autotune(plan.h, phantom.h, tally.h, params, seed, max_batches, band_widths,
                           lane_loads)
 
