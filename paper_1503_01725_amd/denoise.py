@@ -19,6 +19,10 @@ import numpy as np
 from . import workloads as wl
 
 
+# history counts of the evaluated plain / denoised doses
+EVAL_COUNTS = (1e6, 3e6, 1e7, 3e7, 1e8)
+
+
 def case_geometry(seed, n=128, vox=0.25):
     rng = np.random.Generator(np.random.PCG64([int(seed), 4242]))
     ph = wl.hetero_phantom(seed, nx=n, ny=n, nz=n, vox=vox)
@@ -260,7 +264,7 @@ def main():
         rate = args.n_high / t_ref
         refn = ref.cpu().numpy()
         row = {"seed": s, "hist_per_s": rate}
-        for nl in (1e6, 3e6, 1e7):
+        for nl in EVAL_COUNTS:
             d, sd = E.dose(int(nl), n_rep=4, seed_offset=int(nl) % 97 + 3)
             scale = float(d.max())
             inp = torch.stack([d / scale, torch.as_tensor(ph.density, device="cuda")]).contiguous()
@@ -285,7 +289,7 @@ def main():
 
 def summarize(res):
     """Aggregate RMS / gamma and the time-to-1% comparison."""
-    keys = ("1e+06", "3e+06", "1e+07")
+    keys = tuple(f"{nl:.0e}" for nl in EVAL_COUNTS)
     out = {}
     for k in keys:
         rows = [c[k] for c in res["cases"]]
@@ -302,15 +306,24 @@ def summarize(res):
     # denoised: fewest histories whose denoised RMS reaches that error
     t_den = None
     n_den = None
-    for k, nl in zip(keys, (1e6, 3e6, 1e7)):
+    for k, nl in zip(keys, EVAL_COUNTS):
         if out[k]["denoised_rms"] <= rms_at_1pct:
             n_den = nl
             t_den = nl / rate + out[k]["t_infer_s"]
             break
+    # equal error: the plain histories (RMS ~ 1/sqrt(N), fitted at 1e6) whose
+    # RMS error equals each denoised dose's, and the time ratio
+    equal = {}
+    for k, nl in zip(keys, EVAL_COUNTS):
+        n_eq = 1e6 * (out["1e+06"]["plain_rms"] / out[k]["denoised_rms"]) ** 2
+        t_d = nl / rate + out[k]["t_infer_s"]
+        equal[k] = {"denoised_rms": out[k]["denoised_rms"], "plain_histories_same_rms": n_eq,
+                    "speedup": (n_eq / rate) / t_d}
     return {"per_history_count": out, "hist_per_s": rate,
             "time_to_1pct": {"rms_error_percent_of_dmax": rms_at_1pct,
                              "plain_histories": n1, "plain_s": t_plain,
-                             "denoised_histories": n_den, "denoised_s": t_den}}
+                             "denoised_histories": n_den, "denoised_s": t_den},
+            "equal_rms": equal}
 
 
 if __name__ == "__main__":
