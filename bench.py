@@ -78,30 +78,48 @@ def measured_traffic(kernel, options):
     return r["fetch_bytes_per_launch"] + r["write_bytes_per_launch"]
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W, n_hist_rep, seconds):
-    """The oracle on a bounded, evenly strided sample of replica 0's histories."""
-    import numpy as np
+    """The oracle on a bounded, evenly strided sample of replica 0's histories:
+    the sample grows until one run takes about `seconds` on all threads; a
+    single-thread rate is measured on a sample a quarter as long."""
     from oracle import oracle as orc
     ref_w, _ = orc.psl_build(W.model)
     op = orc.plan_build(W.model, ref_w, W.beams, n_hist_rep)
     threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
                   64)
-    # calibrate on a small strided sample, then size the main one to ~seconds
-    n_cal = 20000
-    t0 = time.perf_counter()
-    orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep, stride=n_hist_rep // n_cal,
-            n_threads=threads)
-    rate0 = n_cal / (time.perf_counter() - t0)
-    n = int(max(n_cal, min(rate0 * seconds, n_hist_rep)))
-    stride = max(1, n_hist_rep // n)
-    n = (n_hist_rep + stride - 1) // stride
-    t0 = time.perf_counter()
-    _, _, led, cnt = orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep, stride=stride,
-                             n_threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": cnt["hist"] / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
-            "sample": f"{cnt['hist']} histories (every {stride}th of replica 0 of the same plan), "
-                      f"{dt:.1f} s on {threads} threads, FP64 C oracle -O2"}
+
+    def timed(stride, nt):
+        t0 = time.perf_counter()
+        _, _, led, cnt = orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep,
+                                 stride=stride, n_threads=nt)
+        return cnt["hist"], time.perf_counter() - t0
+
+    def sized(nt, target):
+        stride = max(1, n_hist_rep // 20000)
+        while True:
+            n, dt = timed(stride, nt)
+            if dt >= 0.6 * target or stride == 1:
+                return n, dt, stride
+            stride = max(1, int(stride * dt / target))
+
+    n, dt, stride = sized(threads, seconds)
+    n1, dt1, stride1 = sized(1, seconds / 4)
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} histories (every {stride}th of replica 0 of the same plan), "
+                      f"{dt:.1f} s on {threads} threads of {_cpu_model()}, FP64 C oracle -O2",
+            "value_1_thread": n1 / dt1,
+            "sample_1_thread": f"{n1} histories (every {stride1}th), {dt1:.1f} s"}
 
 
 def describe_phantom(ph):
@@ -252,10 +270,16 @@ def main():
         log(f"[bench] warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         step()
+        e1.record(stream)
+        step_ms.append((e0, e1))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    step_ms = [a.elapsed_time(b) for a, b in step_ms]
     log(f"[bench] {args.steps} timed steps in {elapsed:.3f} s")
     timing = N.psl_run_get_timing(tally.h) if not args.no_timing else None
     led, cnt = tally.stats()
@@ -278,7 +302,8 @@ def main():
 
     out = {"metric": METRICS.get(args.workload, f"histories/s ({args.workload})"), "value": value, "unit": "histories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True,
+           "ms_per_step": 1000.0 * elapsed / args.steps,
+           "ms_per_step_median": float(np.median(step_ms)), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": args.workload, "histories": hist_per_step,
                       "replicas": n_rep, "phantom": describe_phantom(W.phantom),

@@ -11,6 +11,15 @@ import torch
 from . import _native as N
 
 
+def _release(obj, free_fn):
+    """Frees a library handle once; a no-op during interpreter shutdown, when
+    the binding module may already be gone."""
+    h = getattr(obj, "h", None)
+    if h and N is not None and getattr(N, "lib", None) is not None:
+        getattr(N.lib(), free_fn)(h)
+    obj.h = None
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -40,9 +49,10 @@ class Model:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
-            N.lib().psl_model_free(self.h)
-            self.h = None
+        try:
+            _release(self, "psl_model_free")
+        except TypeError:      # interpreter shutdown: module globals already cleared
+            pass
 
 
 def _beams(beams):
@@ -126,9 +136,10 @@ class Plan:
         return b
 
     def __del__(self):
-        if getattr(self, "h", None):
-            N.lib().psl_plan_free(self.h)
-            self.h = None
+        try:
+            _release(self, "psl_plan_free")
+        except TypeError:      # interpreter shutdown: module globals already cleared
+            pass
 
 
 class Phantom:
@@ -141,9 +152,10 @@ class Phantom:
         self.h = N.psl_phantom_create(self.density.data_ptr(), nx, ny, nz, ph.vox, ph.origin)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            N.lib().psl_phantom_free(self.h)
-            self.h = None
+        try:
+            _release(self, "psl_phantom_free")
+        except TypeError:      # interpreter shutdown: module globals already cleared
+            pass
 
 
 class Tally:
@@ -186,9 +198,10 @@ class Tally:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
-            N.lib().psl_tally_free(self.h)
-            self.h = None
+        try:
+            _release(self, "psl_tally_free")
+        except TypeError:      # interpreter shutdown: module globals already cleared
+            pass
 
 
 class Particles:
@@ -335,6 +348,7 @@ class UNet:
         return g, loss.value
 
     def __del__(self):
-        if getattr(self, "h", None):
-            N.lib().psl_unet_free(self.h)
-            self.h = None
+        try:
+            _release(self, "psl_unet_free")
+        except TypeError:      # interpreter shutdown: module globals already cleared
+            pass

@@ -1,0 +1,106 @@
+"""The dose path at the full benchmark size: 128^3 water, 10x10 cm field,
+10 replicas x 1e7 histories, in the launch configuration the benchmark
+times (M = 2^22 histories per batch, 32 histories per lane, two batch
+pipelines, graph replay).  The oracle cannot follow 1e8 histories in
+seconds, so the full run is checked through properties that hold at any
+size (energy ledger, event counts, mirror symmetry of the field), and
+sampled ranges of the same plan's histories of every sub-source are
+compared with the oracle (shared random streams, so the same histories)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(max_batch=1 << 22, band_width=24, sort_electrons=False, lane_load=32, pipelines=2)
+LEDGER_OUT = ("jaw", "missed", "invalid", "esc_g", "esc_e", "dep")
+
+
+@pytest.fixture(scope="module")
+def full(eng, wl):
+    import torch
+    W = wl.workload("water128_10")
+    model = eng.Model(W.model)
+    per = W.n_hist // W.n_replica
+    plan = eng.Plan(model, W.beams, per, n_replica=W.n_replica)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    prm = eng.transport_params()
+    print("[fullsize] water128_10, 1e8 histories, graph replay, two pipelines", flush=True)
+    eng.run_plan(plan, ph, tally, prm, eng.run_opts(use_graph=True, seed=W.seed, **OPTS))
+    d, s = tally.finalize(plan)
+    torch.cuda.synchronize()
+    led, cnt = tally.stats()
+    nx, ny, nz = W.phantom.shape_xyz
+    return dict(W=W, model=model, plan=plan, ph=ph, prm=prm, per=per,
+                d=d.cpu().numpy().reshape(nz, ny, nx), s=s.cpu().numpy().reshape(nz, ny, nx),
+                led=led, cnt=cnt)
+
+
+def test_full_size_ledger_and_counts(full):
+    led, cnt = full["led"], full["cnt"]
+    assert cnt["hist"] == 10 ** 8 and cnt["folds"] == 10
+    assert cnt["overflow"] == 0 and cnt["guard"] == 0
+    assert abs(led["src"] - sum(led[k] for k in LEDGER_OUT)) / led["src"] < 1e-9
+    assert 0 < cnt["entered"] < cnt["hist"]
+    # every real interaction is a Compton event in water (rho = rho_max)
+    assert cnt["real"] == cnt["wc_steps"]
+
+
+def test_full_size_mirror_symmetry(full):
+    """The source, the symmetric jaws and the centred water cube are
+    symmetric under x -> -x and y -> -y; over one half of the field region
+    the standardised differences of mirrored voxels are N(0, 1)-like and
+    centred."""
+    d, s = full["d"], full["s"]
+    nz, ny, nx = d.shape
+    hi = d > 0.2 * d.max()
+    for axis, n in ((2, nx), (1, ny)):
+        dm, sm = np.flip(d, axis=axis), np.flip(s, axis=axis)
+        sel = hi & np.flip(hi, axis=axis)
+        half = np.zeros_like(sel)
+        idx = [slice(None)] * 3
+        idx[axis] = slice(0, n // 2)
+        half[tuple(idx)] = True
+        sel &= half
+        z = (d - dm)[sel] / np.sqrt(s ** 2 + sm ** 2)[sel]
+        assert sel.sum() > 10000
+        assert np.mean(np.abs(z) < 3) > 0.99
+        assert abs(np.mean(z)) < 0.1, (axis, np.mean(z))
+
+
+def test_full_size_sampled_histories_match_oracle(full, eng, orc, N):
+    """For a range of 2e4 consecutive histories of replica 7 inside a batch of
+    each sub-source, the GPU (sample_batch + transport_batch) and the oracle
+    follow the same histories: the source ledger agrees to FP32 rounding and
+    the deposited energy and event counts to within 0.3 %."""
+    import torch
+    W, plan, ph, prm = full["W"], full["plan"], full["ph"], full["prm"]
+    ref_w, _ = orc.psl_build(W.model)
+    op = orc.plan_build(W.model, ref_w, W.beams, full["per"])
+    nb = plan.set_batching(OPTS["max_batch"], OPTS["band_width"])
+    seen = set()
+    for i in range(nb):
+        b = plan.batch(i)
+        if b.stype in seen or b.n < 80000:
+            continue
+        seen.add(b.stype)
+        n = 20000
+        h0 = b.h0 + b.n // 2
+        print(f"[fullsize] sampled range stype {b.stype} h [{h0}, {h0 + n}) replica 7", flush=True)
+        tally = eng.Tally(ph)
+        stack = eng.Particles(n)
+        el = eng.Particles(eng.electron_capacity(n, plan.info.e_max, prm.e_cut_electron))
+        stack.zero_count()
+        N.sample_batch(plan.h, ph.h, 7, h0, n, W.seed, stack.c, 0, tally.h, 0)
+        N.transport_batch(ph.h, stack.c, el.c, tally.h, prm, W.seed, 0)
+        torch.cuda.synchronize()
+        led, cnt = tally.stats()
+        _, _, led_ref, cnt_ref = orc.run(W.model, op, W.beams, W.phantom, W.seed, 1, h0, h0 + n,
+                                         rep0=7)
+        assert cnt["hist"] == cnt_ref["hist"] == n
+        assert led["src"] == pytest.approx(led_ref["src"], rel=1e-6)
+        assert cnt["entered"] == pytest.approx(cnt_ref["entered"], rel=1e-3, abs=2)
+        assert led["dep"] == pytest.approx(led_ref["dep"], rel=3e-3)
+        assert cnt["e_pushed"] == pytest.approx(cnt_ref["e_pushed"], rel=3e-3, abs=5)
+        assert cnt["e_steps"] == pytest.approx(cnt_ref["e_steps"], rel=3e-3)
+    assert seen == {0, 1, 2}
