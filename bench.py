@@ -230,7 +230,7 @@ def main():
         log("[bench] autotuning batch size, band width, grid size and pipelines on one replica")
         cands_m = [args.max_batch] if args.max_batch else [2097152, 4194304, 8388608]
         cands_w = [args.band_width] if args.band_width else [3, 24]
-        cands_l = [args.lane_load] if args.lane_load else [8, 16, 32, 64]
+        cands_l = [args.lane_load] if args.lane_load else [16, 32, 64]
         best, ms = eng.autotune(plan, ph, tally, prm, seed, cands_m, cands_w, cands_l)
         mb, bw, ll = int(best.max_batch), int(best.band_width), int(best.lane_load)
         srt, npipe = int(best.sort_electrons), int(best.pipelines)

@@ -307,7 +307,8 @@ typedef struct {
     int32_t pipelines;       /* 1 or 2 batch pipelines (own stacks and stream each);
                                 with 2 the batches of a replica alternate between
                                 them and run concurrently, joined before the
-                                replica's fold (0 = 1)                              */
+                                replica's fold; a replica of one batch uses one
+                                (0 = 1)                                             */
 } psl_run_opts;
 
 /* Runs every batch of every replica of `plan` -- sample_batch, transport_batch

@@ -240,7 +240,7 @@ def psl_autotune(plan, phantom, tally, params, seed, max_batches, band_widths, l
     mb = np.ascontiguousarray(max_batches, dtype=np.uint32)
     bw = np.ascontiguousarray(band_widths, dtype=np.int32)
     ll = np.ascontiguousarray(lane_loads, dtype=np.int32)
-    ms = np.zeros(len(mb) * len(bw) * len(ll) * 4)
+    ms = np.zeros(len(mb) * len(bw) * len(ll) * 2 * 2)
     best = psl_run_opts()
     _call("psl_autotune", plan, phantom, tally, C.byref(params), seed, mb.ctypes.data_as(u32p),
           len(mb), bw.ctypes.data_as(i32p), len(bw), ll.ctypes.data_as(i32p), len(ll), replica,

@@ -163,6 +163,7 @@ struct PhantomDev {
     int nx, ny, nz;
     float vox[3], inv_vox[3], origin[3], hi[3];
     float rho_max, inv_rho_max;
+    float real_min;    // smallest rho / rho_max over the voxels (FP32 product)
 };
 
 struct Runner;   // batched-runtime workspace (runtime.hip)

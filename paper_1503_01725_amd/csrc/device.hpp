@@ -18,8 +18,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a0 = 0xD2511F53u * x0, b0 = __umulhi(0xD2511F53u, x0);
-        const uint32_t a1 = 0xCD9E8D57u * x2, b1 = __umulhi(0xCD9E8D57u, x2);
+        // full 64-bit products: one v_mad_u64_u32 gives both halves
+        const uint64_t p0 = uint64_t(0xD2511F53u) * x0, p1 = uint64_t(0xCD9E8D57u) * x2;
+        const uint32_t a0 = uint32_t(p0), b0 = uint32_t(p0 >> 32);
+        const uint32_t a1 = uint32_t(p1), b1 = uint32_t(p1 >> 32);
         const uint32_t y0 = b1 ^ x1 ^ k0;
         const uint32_t y2 = b0 ^ x3 ^ k1;
         x0 = y0;

@@ -58,6 +58,23 @@ struct TransportArgs {
     uint32_t seed_lo, seed_hi;
 };
 
+// ---- hardware transcendentals ---------------------------------------------
+// Sine and cosine of a whole turn times r (v_sin_f32 / v_cos_f32 take their
+// argument in revolutions, |r| <= 256); reciprocal, natural logarithm and
+// square root from v_rcp_f32, v_log_f32 and v_sqrt_f32 without the range
+// scaling the library wraps around them for denormal arguments, which the
+// transport never produces (energies >= the cut-offs, lengths and 1 - u >=
+// 2^-24, or guarded zeros).  About 1 ulp, far below the statistical noise.
+__device__ __forceinline__ void sincos_turn(float r, float& s, float& c) {
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_log(float x) {
+    return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+}
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---- table lookups (linear interpolation) ---------------------------------
 __device__ __forceinline__ float lerp_tab(const float* tab, int n, float x) {
     x = fminf(fmaxf(x, 0.f), float(n - 1) - 1e-3f);
@@ -67,36 +84,27 @@ __device__ __forceinline__ float lerp_tab(const float* tab, int n, float x) {
 }
 
 __device__ __forceinline__ float kn_mu(const PhysicsDev& P, const float* tab, float e) {
-    return lerp_tab(tab, KN_TAB_N, (__logf(e) - P.kn_lne0) * P.kn_inv_dlne);
+    return lerp_tab(tab, KN_TAB_N, (hw_log(e) - P.kn_lne0) * P.kn_inv_dlne);
 }
 
 __device__ __forceinline__ float csda_range(const PhysicsDev& P, const float* tab, float t) {
     if (!(t > P.t_cut)) return 0.f;
-    return lerp_tab(tab, RNG_TAB_N, (__logf(t) - P.rng_lnt0) * P.rng_inv_dlnt);
+    return lerp_tab(tab, RNG_TAB_N, (hw_log(t) - P.rng_lnt0) * P.rng_inv_dlnt);
 }
 
 __device__ __forceinline__ float csda_energy(const PhysicsDev& P, const float* tab, float r) {
     if (!(r > 0.f)) return P.t_cut;
-    return lerp_tab(tab, INV_TAB_N, (__logf(r + P.r_off) - P.inv_u0) * P.inv_inv_du);
-}
-
-// ---- hardware transcendentals ---------------------------------------------
-// Sine and cosine of a whole turn times r (v_sin_f32 / v_cos_f32 take their
-// argument in revolutions, |r| <= 256), and the natural logarithm from
-// v_log_f32.  A few ulp, far below the statistical noise of the transport.
-__device__ __forceinline__ void sincos_turn(float r, float& s, float& c) {
-    s = __builtin_amdgcn_sinf(r);
-    c = __builtin_amdgcn_cosf(r);
+    return lerp_tab(tab, INV_TAB_N, (hw_log(r + P.r_off) - P.inv_u0) * P.inv_inv_du);
 }
 
 // ---- geometry -------------------------------------------------------------
 __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t, float cphi,
                                        float sphi) {
-    const float sin_t = sqrtf(fmaxf(0.f, 1.f - cos_t * cos_t));
+    const float sin_t = hw_sqrt(fmaxf(0.f, 1.f - cos_t * cos_t));
     float nu, nv, nw;
     if (fabsf(w) < 0.99999f) {
-        const float t = sqrtf(1.f - w * w);
-        const float it = 1.f / t;
+        const float t = hw_sqrt(1.f - w * w);
+        const float it = hw_rcp(t);
         nu = u * cos_t + sin_t * (u * w * cphi - v * sphi) * it;
         nv = v * cos_t + sin_t * (v * w * cphi + u * sphi) * it;
         nw = w * cos_t - sin_t * cphi * t;
@@ -111,23 +119,45 @@ __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t
     w = nw * inv;
 }
 
+// Tally cell of voxel v for a particle of column `tag` (index-map mode: the
+// voxel's row and the column), or -1 when the voxel is not tallied or the
+// column is beyond the tally (counted as an overflow).
+__device__ __forceinline__ int tally_cell(const TallyDev& T, int v, uint32_t tag) {
+    if (!T.imap) return v;
+    const int row = T.imap[v];
+    if (row <= 0) return -1;
+    const int col = int(tag & 0xFFFFu);
+    if (col >= T.n_cols) {
+        // particle tag from a plan with more columns than this tally
+        atomicAdd(T.counters + C_OVERFLOW, 1ull);
+        return -1;
+    }
+    return (row - 1) * T.n_cols + col;
+}
+
 __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, float e,
                                         uint32_t& n_atomic) {
     if (e == 0.f) return;
-    int c = v;
-    if (T.imap) {
-        const int row = T.imap[v];
-        if (row <= 0) return;
-        const int col = int(tag & 0xFFFFu);
-        if (col >= T.n_cols) {
-            // particle tag from a plan with more columns than this tally
-            atomicAdd(T.counters + C_OVERFLOW, 1ull);
-            return;
-        }
-        c = (row - 1) * T.n_cols + col;
-    }
+    const int c = tally_cell(T, v, tag);
+    if (c < 0) return;
     atomicAdd(T.grid + c, e);
     ++n_atomic;
+}
+
+// Two deposits (v < 0: none) whose index-map lookups are both issued before
+// either atomic, so that no lookup waits behind an atomic.
+__device__ __forceinline__ void deposit2(const TallyDev& T, int v0, float e0, int v1, float e1,
+                                         uint32_t tag, uint32_t& n_atomic) {
+    const int c0 = v0 >= 0 && e0 != 0.f ? tally_cell(T, v0, tag) : -1;
+    const int c1 = v1 >= 0 && e1 != 0.f ? tally_cell(T, v1, tag) : -1;
+    if (c0 >= 0) {
+        atomicAdd(T.grid + c0, e0);
+        ++n_atomic;
+    }
+    if (c1 >= 0) {
+        atomicAdd(T.grid + c1, e1);
+        ++n_atomic;
+    }
 }
 
 // ---- work queue -------------------------------------------------------------
@@ -199,7 +229,134 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     bool collided = false, alive = false;
     WaveQueue wq;
     dev::PoolStream<kPhotonPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
+    // Order of an iteration: the physics step (no global writes), then the
+    // refill of idle lanes (their loads are waited on), then this step's
+    // global writes.  A load issued after a store or atomic can only be
+    // waited on together with it (one in-order counter), so the refill's
+    // wait covers the writes of the previous iteration, issued a whole step
+    // earlier, rather than those just made.
     for (;;) {
+        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        // a flight and its collision test (2), two Kahn trials (6) and the
+        // azimuth (1) fit in one iteration
+        st.topup(alive, 9, 12);
+        // this step's writes, deferred: one deposit, one electron
+        int w_v = -1;
+        float w_e = 0.f;
+        uint32_t w_tag = tag;
+        bool push = false;
+        float qx = 0.f, qy = 0.f, qz = 0.f, te = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+        uint64_t w_g = g;
+        uint32_t w_ptag = 0;
+        if (alive && phase == kFlight) {
+            if (!(e >= a.e_cut_g) || steps >= kMaxPhotonSteps) {
+                // below the cut-off on entry, or the safety bound: absorb here
+                const int vx = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
+                const int vy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
+                const int vz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
+                const float ee = isfinite(e) ? e : 0.f;
+                w_v = (vz * G.ny + vy) * G.nx + vx;
+                w_e = ee;
+                dep += ee;
+                c_over += steps >= kMaxPhotonSteps ? 1u : 0u;
+                alive = false;
+            } else {
+                ++steps;
+                // one Woodcock flight
+                const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
+                const float s = -hw_log(1.f - st.pop()) * hw_rcp(mu);
+                px = fmaf(s, du, px);
+                py = fmaf(s, dv, py);
+                pz = fmaf(s, dw, pz);
+                const float fx = floorf((px - G.origin[0]) * G.inv_vox[0]);
+                const float fy = floorf((py - G.origin[1]) * G.inv_vox[1]);
+                const float fz = floorf((pz - G.origin[2]) * G.inv_vox[2]);
+                if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) &&
+                      fz >= 0.f && fz < float(G.nz))) {
+                    esc_g += e;
+                    c_unc += collided ? 0u : 1u;
+                    alive = false;
+                } else {
+                    cv = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
+                    ++c_wc;
+                    // real collision if u < rho_v / rho_max; below the
+                    // phantom's smallest ratio that holds in every voxel and
+                    // the density is not read
+                    const float u = st.pop();
+                    if (u < G.real_min || u < G.dens[cv] * G.inv_rho_max) {
+                        collided = true;
+                        ++c_real;
+                        phase = kKahn;
+                        trials = 0;
+                    }
+                }
+            }
+        }
+        if (alive && phase == kKahn) {
+            // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a trial
+            const float k = e * (1.f / kMe);
+            const float k2 = 2.f * k;
+            const float ik = kMe * hw_rcp(e);
+            while (st.cnt >= 3u) {
+                const float r1 = st.pop(), r2 = st.pop(), r3 = st.pop();
+                ++c_kahn;
+                ++trials;
+                bool acc;
+                if (r1 <= (1.f + k2) * hw_rcp(9.f + k2)) {
+                    kx = fmaf(k2, r2, 1.f);
+                    const float ix = hw_rcp(kx);
+                    acc = r3 <= 4.f * (ix - ix * ix);
+                } else {
+                    kx = (1.f + k2) * hw_rcp(fmaf(k2, r2, 1.f));
+                    const float c = 1.f - (kx - 1.f) * ik;
+                    acc = r3 <= 0.5f * (c * c + hw_rcp(kx));
+                }
+                if (acc || trials >= uint32_t(kMaxKahnTrials)) {
+                    phase = kScatter;
+                    break;
+                }
+            }
+        }
+        if (alive && phase == kScatter && st.cnt >= 1u) {
+            const float cos_t = 1.f - (kx - 1.f) * kMe * hw_rcp(e);
+            float sphi, cphi;
+            sincos_turn(st.pop(), sphi, cphi);
+            const float e1 = e * hw_rcp(kx);
+            te = e - e1;
+            float nu = du, nv = dv, nw = dw;
+            rotate(nu, nv, nw, cos_t, cphi, sphi);
+            if (te >= a.e_cut_e) {
+                // electron direction from momentum conservation: p_e = E d - E' d'
+                qx = e * du - e1 * nu;
+                qy = e * dv - e1 * nv;
+                qz = e * dw - e1 * nw;
+                const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
+                qx *= inv;
+                qy *= inv;
+                qz *= inv;
+                ++n_push;
+                ++c_push;
+                push = true;
+                ex = px; ey = py; ez = pz;
+                w_ptag = tag | (n_push << 16);
+            } else {
+                w_v = cv;
+                w_e = te;
+                dep += te;
+                ++c_local;
+            }
+            e = e1;
+            du = nu; dv = nv; dw = nw;
+            phase = kFlight;
+            if (e < a.e_cut_g) {
+                // absorbed where it scattered (same voxel as a local electron)
+                w_v = cv;
+                w_e += e;
+                dep += e;
+                alive = false;
+            }
+        }
+        // refill idle lanes from the wave's chunk of the photon stack
         {
             const uint32_t i = take_work(!alive, wq, a.queue, n);
             const uint32_t tg = i != kNone ? a.in.tag[i] : 0u;
@@ -217,111 +374,8 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 alive = true;
             }
         }
-        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
-        // a flight and its collision test (2), two Kahn trials (6) and the
-        // azimuth (1) fit in one iteration
-        st.topup(alive, 9, 12);
-        // electron set in motion by this lane (pushed below, where the whole
-        // wave has reconverged)
-        bool push = false;
-        float qx = 0.f, qy = 0.f, qz = 0.f, te = 0.f;
-        if (alive && phase == kFlight) {
-            if (!(e >= a.e_cut_g) || steps >= kMaxPhotonSteps) {
-                // below the cut-off on entry, or the safety bound: absorb here
-                const int vx = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
-                const int vy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
-                const int vz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
-                const float ee = isfinite(e) ? e : 0.f;
-                deposit(a.tally, (vz * G.ny + vy) * G.nx + vx, tag, ee, c_atom);
-                dep += ee;
-                c_over += steps >= kMaxPhotonSteps ? 1u : 0u;
-                alive = false;
-            } else {
-                ++steps;
-                // one Woodcock flight
-                const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
-                const float s = -__logf(1.f - st.pop()) / mu;
-                px = fmaf(s, du, px);
-                py = fmaf(s, dv, py);
-                pz = fmaf(s, dw, pz);
-                const float fx = floorf((px - G.origin[0]) * G.inv_vox[0]);
-                const float fy = floorf((py - G.origin[1]) * G.inv_vox[1]);
-                const float fz = floorf((pz - G.origin[2]) * G.inv_vox[2]);
-                if (!(fx >= 0.f && fx < float(G.nx) && fy >= 0.f && fy < float(G.ny) &&
-                      fz >= 0.f && fz < float(G.nz))) {
-                    esc_g += e;
-                    c_unc += collided ? 0u : 1u;
-                    alive = false;
-                } else {
-                    cv = (int(fz) * G.ny + int(fy)) * G.nx + int(fx);
-                    ++c_wc;
-                    if (st.pop() < G.dens[cv] * G.inv_rho_max) {   // real collision
-                        collided = true;
-                        ++c_real;
-                        phase = kKahn;
-                        trials = 0;
-                    }
-                }
-            }
-        }
-        if (alive && phase == kKahn) {
-            // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a trial
-            const float k = e * (1.f / kMe);
-            const float k2 = 2.f * k;
-            while (st.cnt >= 3u) {
-                const float r1 = st.pop(), r2 = st.pop(), r3 = st.pop();
-                ++c_kahn;
-                ++trials;
-                bool acc;
-                if (r1 <= (1.f + k2) / (9.f + k2)) {
-                    kx = fmaf(k2, r2, 1.f);
-                    acc = r3 <= 4.f * (1.f / kx - 1.f / (kx * kx));
-                } else {
-                    kx = (1.f + k2) / fmaf(k2, r2, 1.f);
-                    const float c = 1.f - (kx - 1.f) / k;
-                    acc = r3 <= 0.5f * (c * c + 1.f / kx);
-                }
-                if (acc || trials >= uint32_t(kMaxKahnTrials)) {
-                    phase = kScatter;
-                    break;
-                }
-            }
-        }
-        if (alive && phase == kScatter && st.cnt >= 1u) {
-            const float k = e * (1.f / kMe);
-            const float cos_t = 1.f - (kx - 1.f) / k;
-            float sphi, cphi;
-            sincos_turn(st.pop(), sphi, cphi);
-            const float e1 = e / kx;
-            te = e - e1;
-            float nu = du, nv = dv, nw = dw;
-            rotate(nu, nv, nw, cos_t, cphi, sphi);
-            if (te >= a.e_cut_e) {
-                // electron direction from momentum conservation: p_e = E d - E' d'
-                qx = e * du - e1 * nu;
-                qy = e * dv - e1 * nv;
-                qz = e * dw - e1 * nw;
-                const float inv = rsqrtf(qx * qx + qy * qy + qz * qz);
-                qx *= inv;
-                qy *= inv;
-                qz *= inv;
-                ++n_push;
-                ++c_push;
-                push = true;
-            } else {
-                deposit(a.tally, cv, tag, te, c_atom);
-                dep += te;
-                ++c_local;
-            }
-            e = e1;
-            du = nu; dv = nv; dw = nw;
-            phase = kFlight;
-            if (e < a.e_cut_g) {
-                deposit(a.tally, cv, tag, e, c_atom);
-                dep += e;
-                alive = false;
-            }
-        }
+        // this step's writes: the electron first (its chunk reservation
+        // returns a value, which must not wait behind the deposit's atomic)
         // wave-convergent push: slots from the wave's reserved chunk of the
         // electron stack, a new chunk of kChunk when it runs out
         const unsigned long long m = __ballot(push);
@@ -344,16 +398,17 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             }
             if (push) {
                 if (slot < a.el.capacity) {
-                    a.el.x[slot] = px; a.el.y[slot] = py; a.el.z[slot] = pz;
+                    a.el.x[slot] = ex; a.el.y[slot] = ey; a.el.z[slot] = ez;
                     a.el.u[slot] = qx; a.el.v[slot] = qy; a.el.w[slot] = qz;
                     a.el.e[slot] = te;
-                    a.el.hid[slot] = g;
-                    a.el.tag[slot] = tag | (n_push << 16);
+                    a.el.hid[slot] = w_g;
+                    a.el.tag[slot] = w_ptag;
                 } else {
                     ++c_over;
                 }
             }
         }
+        if (w_v >= 0) deposit(a.tally, w_v, w_tag, w_e, c_atom);
     }
     // the unused rest of the wave's last chunk stays in the stack as empty entries
     if (el_left > 0) {
@@ -481,7 +536,7 @@ __device__ __forceinline__ void face_distance(float p, float d, int i, float o, 
                                               float& sb, int& axis) {
     if (d != 0.f) {
         const float face = o + float(i + (d > 0.f ? 1 : 0)) * vx;
-        const float t = (face - p) / d;
+        const float t = (face - p) * hw_rcp(d);
         if (t < sb) {
             sb = t;
             axis = ax;
@@ -507,12 +562,125 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
              &c_guard = ls.c[C_GUARD], &c_local = ls.c[C_E_LOCAL];
     // per-lane electron state
     float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, pend_e = 0.f;
+    float rho = 0.f;   // density of the current voxel
     int ix = 0, iy = 0, iz = 0, cur_v = 0, pend_v = 0, steps = 0;
     uint32_t tag = 0;
     bool alive = false;
     WaveQueue wq;
     dev::PoolStream<kElectronPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
+    // Order of an iteration as in k_photon: the CSDA step (deposits
+    // deferred), the refill of idle lanes, then this step's deposits.
     for (;;) {
+        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
+        // one multiple-scattering deflection (two uniforms) per step, at most
+        // one step per iteration
+        st.topup(alive && a.ms, 2, 5);
+        // this step's deposits, deferred: the voxel left and the last voxel
+        int w_v0 = -1, w_v1 = -1;
+        float w_e0 = 0.f, w_e1 = 0.f;
+        const uint32_t w_tag = tag;
+        if (alive) {
+            bool done = false;
+            if (steps >= kMaxElectronSteps) {
+                pend_e += t;
+                dep += t;
+                ++c_guard;
+                done = true;
+            } else {
+                ++steps;
+                const float rho_s = rho;   // medium of this step
+                float sb = INFINITY;
+                int axis = 0;
+                face_distance(px, dx, ix, G.origin[0], G.vox[0], 0, sb, axis);
+                face_distance(py, dy, iy, G.origin[1], G.vox[1], 1, sb, axis);
+                face_distance(pz, dz, iz, G.origin[2], G.vox[2], 2, sb, axis);
+                sb = fmaxf(sb, 0.f);
+                // energy-loss limited step
+                const float r0 = csda_range(P, s_rng, t);
+                const float ef = t * (1.f - a.step_frac);
+                const bool fin = !(ef > tcut);
+                float sf = INFINITY;
+                if (rho_s > 0.f) sf = (fin ? r0 : r0 - csda_range(P, s_rng, ef)) * hw_rcp(rho_s);
+                ++c_steps;
+                const bool boundary = !(sf <= sb);
+                const float sl = boundary ? sb : sf;
+                if (!boundary && fin) {
+                    // the residual range ends inside this voxel
+                    path += sl;
+                    pend_e += t;
+                    dep += t;
+                    done = true;
+                } else {
+                    const float tn = csda_energy(P, s_inv, r0 - rho_s * sl);
+                    const float de = fmaxf(t - tn, 0.f);
+                    pend_e += de;
+                    dep += de;
+                    px = fmaf(sl, dx, px);
+                    py = fmaf(sl, dy, py);
+                    pz = fmaf(sl, dz, pz);
+                    path += sl;
+                    const float t_old = t;
+                    t -= de;
+                    bool out = false;
+                    if (boundary) {
+                        ++c_bnd;
+                        if (axis == 0) {
+                            ix += dx > 0.f ? 1 : -1;
+                            out = ix < 0 || ix >= G.nx;
+                        } else if (axis == 1) {
+                            iy += dy > 0.f ? 1 : -1;
+                            out = iy < 0 || iy >= G.ny;
+                        } else {
+                            iz += dz > 0.f ? 1 : -1;
+                            out = iz < 0 || iz >= G.nz;
+                        }
+                        if (out) {
+                            esc_e += t;
+                            done = true;
+                        } else {
+                            cur_v = (iz * G.ny + iy) * G.nx + ix;
+                            // the next step's density, loaded while the rest
+                            // of this iteration runs
+                            rho = G.dens[cur_v];
+                            w_v0 = pend_v;
+                            w_e0 = pend_e;
+                            pend_v = cur_v;
+                            pend_e = 0.f;
+                        }
+                    }
+                    if (!out) {
+                        if (t < tcut) {
+                            pend_e += t;
+                            dep += t;
+                            done = true;
+                        } else if (a.ms) {
+                            // Highland width (PDG) for the step, beta*c*p at the mid-step energy
+                            const float tx = rho_s * sl * (1.f / kX0Water);
+                            const float tm = 0.5f * (t_old + t);
+                            const float bcp = tm * (tm + 2.f * kMe) * hw_rcp(tm + kMe);
+                            float th0 = 0.f;
+                            if (tx > 0.f)
+                                th0 = fmaxf(13.6f * hw_rcp(bcp) * hw_sqrt(tx) *
+                                                fmaf(0.038f, hw_log(tx), 1.f),
+                                            0.f);
+                            const float u1 = st.pop(), u2 = st.pop();
+                            const float th =
+                                fminf(th0 * hw_sqrt(-2.f * hw_log(1.f - u1)), 3.14159265358979f);
+                            float sphi, cphi;
+                            sincos_turn(u2, sphi, cphi);
+                            rotate(dx, dy, dz, __builtin_amdgcn_cosf(th * 0.15915494309189535f),
+                                   cphi, sphi);
+                        }
+                    }
+                }
+            }
+            if (done) {
+                w_v1 = pend_v;
+                w_e1 = pend_e;
+                alive = false;
+            }
+        }
+        // refill idle lanes from the wave's chunk of the (band-ordered) stack
         {
             const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
             const uint32_t i = q != kNone ? (a.perm ? a.perm[q] : q) : 0u;
@@ -528,6 +696,8 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                 iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
                 cur_v = (iz * G.ny + iy) * G.nx + ix;
                 if (t < tcut) {
+                    // below the cut-off on entry: local deposit (after the
+                    // refill's loads, so not deferred)
                     deposit(a.tally, cur_v, tag, t, c_atom);
                     dep += t;
                     ++c_local;
@@ -535,107 +705,14 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                     st.init(g, dev::kTagTransport, (tg >> 16) & 0xFFu);
                     pend_v = cur_v;
                     pend_e = 0.f;
+                    rho = G.dens[cur_v];
                     steps = 0;
                     alive = true;
                 }
             }
         }
-        if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
-        // one multiple-scattering deflection (two uniforms) per step, at most
-        // one step per iteration
-        st.topup(alive && a.ms, 2, 5);
-        if (!alive) continue;
-        bool done = false;
-        if (steps >= kMaxElectronSteps) {
-            pend_e += t;
-            dep += t;
-            ++c_guard;
-            done = true;
-        } else {
-            ++steps;
-            const float rho = G.dens[cur_v];
-            float sb = INFINITY;
-            int axis = 0;
-            face_distance(px, dx, ix, G.origin[0], G.vox[0], 0, sb, axis);
-            face_distance(py, dy, iy, G.origin[1], G.vox[1], 1, sb, axis);
-            face_distance(pz, dz, iz, G.origin[2], G.vox[2], 2, sb, axis);
-            sb = fmaxf(sb, 0.f);
-            // energy-loss limited step
-            const float r0 = csda_range(P, s_rng, t);
-            const float ef = t * (1.f - a.step_frac);
-            const bool fin = !(ef > tcut);
-            float sf = INFINITY;
-            if (rho > 0.f) sf = (fin ? r0 : r0 - csda_range(P, s_rng, ef)) / rho;
-            ++c_steps;
-            const bool boundary = !(sf <= sb);
-            const float sl = boundary ? sb : sf;
-            if (!boundary && fin) {
-                // the residual range ends inside this voxel
-                path += sl;
-                pend_e += t;
-                dep += t;
-                done = true;
-            } else {
-                const float tn = csda_energy(P, s_inv, r0 - rho * sl);
-                const float de = fmaxf(t - tn, 0.f);
-                pend_e += de;
-                dep += de;
-                px = fmaf(sl, dx, px);
-                py = fmaf(sl, dy, py);
-                pz = fmaf(sl, dz, pz);
-                path += sl;
-                const float t_old = t;
-                t -= de;
-                bool out = false;
-                if (boundary) {
-                    ++c_bnd;
-                    if (axis == 0) {
-                        ix += dx > 0.f ? 1 : -1;
-                        out = ix < 0 || ix >= G.nx;
-                    } else if (axis == 1) {
-                        iy += dy > 0.f ? 1 : -1;
-                        out = iy < 0 || iy >= G.ny;
-                    } else {
-                        iz += dz > 0.f ? 1 : -1;
-                        out = iz < 0 || iz >= G.nz;
-                    }
-                    if (out) {
-                        esc_e += t;
-                        done = true;
-                    } else {
-                        cur_v = (iz * G.ny + iy) * G.nx + ix;
-                        deposit(a.tally, pend_v, tag, pend_e, c_atom);
-                        pend_v = cur_v;
-                        pend_e = 0.f;
-                    }
-                }
-                if (!out) {
-                    if (t < tcut) {
-                        pend_e += t;
-                        dep += t;
-                        done = true;
-                    } else if (a.ms) {
-                        // Highland width (PDG) for the step, beta*c*p at the mid-step energy
-                        const float tx = rho * sl * (1.f / kX0Water);
-                        const float tm = 0.5f * (t_old + t);
-                        const float bcp = tm * (tm + 2.f * kMe) / (tm + kMe);
-                        float th0 = 0.f;
-                        if (tx > 0.f)
-                            th0 = fmaxf(13.6f / bcp * sqrtf(tx) * fmaf(0.038f, __logf(tx), 1.f), 0.f);
-                        const float u1 = st.pop(), u2 = st.pop();
-                        const float th = fminf(th0 * sqrtf(-2.f * __logf(1.f - u1)), 3.14159265358979f);
-                        float sphi, cphi;
-                        sincos_turn(u2, sphi, cphi);
-                        rotate(dx, dy, dz, __builtin_amdgcn_cosf(th * 0.15915494309189535f), cphi,
-                               sphi);
-                    }
-                }
-            }
-        }
-        if (done) {
-            deposit(a.tally, pend_v, tag, pend_e, c_atom);
-            alive = false;
-        }
+        // this step's deposits
+        deposit2(a.tally, w_v0, w_e0, w_v1, w_e1, w_tag, c_atom);
     }
     dev::flush_stats(a.tally.stats, ls);
 }
@@ -694,22 +771,31 @@ __global__ void k_finalize(const double* sum, const double* sum2, int64_t n, int
     }
 }
 
+// Largest and smallest density (the smallest as the complement of its bit
+// pattern, so that both reduce with atomicMax from zero) and a flag for
+// negative or non-finite values.
 __global__ void k_density_scan(const float* dens, int64_t n, unsigned int* max_bits,
-                               unsigned int* bad) {
-    unsigned int m = 0, b = 0;
+                               unsigned int* bad, unsigned int* min_bits_c) {
+    unsigned int m = 0, mc = 0, b = 0;
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x) {
         const float r = dens[i];
-        if (!(r >= 0.f) || !isfinite(r)) b = 1;
-        else m = max(m, __float_as_uint(r));
+        if (!(r >= 0.f) || !isfinite(r)) {
+            b = 1;
+        } else {
+            m = max(m, __float_as_uint(r));
+            mc = max(mc, ~__float_as_uint(r));
+        }
     }
     // non-negative floats order like their bit patterns
     for (int off = 32; off >= 1; off >>= 1) {
         m = max(m, (unsigned int)__shfl_xor(int(m), off, 64));
+        mc = max(mc, (unsigned int)__shfl_xor(int(mc), off, 64));
         b |= (unsigned int)__shfl_xor(int(b), off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         atomicMax(max_bits, m);
+        atomicMax(min_bits_c, mc);
         if (b) atomicOr(bad, 1u);
     }
 }
@@ -843,21 +929,26 @@ extern "C" int psl_phantom_create(const float* density_dev, int32_t nx, int32_t 
             g.hi[k] = float(origin[k] + n[k] * vox[k]);
         }
         DevBuf scratch;
-        scratch.alloc(8);
+        scratch.alloc(12);
         unsigned int* w = scratch.as<unsigned int>();
         const int64_t nv = int64_t(nx) * ny * nz;
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, w, 2);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, nullptr, w, 3);
         hipLaunchKernelGGL(k_density_scan, dim3(grid_for(nv, 1024)), dim3(kBlock), 0, nullptr,
-                           density_dev, nv, w, w + 1);
+                           density_dev, nv, w, w + 1, w + 2);
         PSL_HIP(hipGetLastError());
-        unsigned int hw[2];
-        PSL_HIP(hipMemcpy(hw, w, 8, hipMemcpyDeviceToHost));
+        unsigned int hw[3];
+        PSL_HIP(hipMemcpy(hw, w, 12, hipMemcpyDeviceToHost));
         PSL_CHECK(hw[1] == 0, "densities must be finite and >= 0");
-        float rmax;
+        float rmax, rmin;
         std::memcpy(&rmax, &hw[0], 4);
+        const unsigned int min_bits = ~hw[2];
+        std::memcpy(&rmin, &min_bits, 4);
         PSL_CHECK(rmax > 0.f, "phantom has no matter (max density 0)");
         g.rho_max = rmax;
         g.inv_rho_max = 1.f / rmax;
+        // the same FP32 product as the kernel's collision test, so that
+        // rho * inv_rho_max >= real_min holds in floating point for every voxel
+        g.real_min = rmin * g.inv_rho_max;
         *out = ph.release();
     });
 }

@@ -160,16 +160,21 @@ struct Runner {
 
 namespace {
 
-int n_pipes_of(const psl_run_opts& o) { return o.pipelines == 2 ? 2 : 1; }
+// Pipelines in use: as many as asked, but never more than the batches of a
+// replica, so that no pipeline's stream joins a capture without work.
+int n_pipes_of(const psl_run_opts& o, const psl_plan* plan) {
+    const int want = o.pipelines >= 2 ? o.pipelines : 1;
+    return int(std::max<size_t>(1, std::min<size_t>(size_t(want), plan->batches.size())));
+}
 
 // Enqueues all launches of replicas [rep0, rep0 + n_rep) on stream s; with
-// two pipelines the batches of each replica fork onto the pipelines' streams
-// and join back on s before the replica's fold.
+// several pipelines the batches of each replica fork onto the pipelines' streams
+// and join back on s before the replica's fold (batch i on pipeline i mod n).
 void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
              const psl_transport_params* prm, const psl_run_opts& o, uint32_t rep0, uint32_t n_rep,
              hipStream_t s) {
     uint32_t* rep = R.rep.as<uint32_t>();
-    const int np = n_pipes_of(o);
+    const int np = n_pipes_of(o, plan);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, rep, rep0);
     const size_t nb = plan->batches.size();
     for (uint32_t r = 0; r < n_rep; ++r) {
@@ -257,7 +262,7 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     const uint32_t per = uint32_t(std::max(1.0, std::floor(emax / prm->e_cut_electron))) + 1;
     const uint64_t el_need = uint64_t(o.max_batch) * per;
     PSL_CHECK(el_need < (uint64_t(1) << 32), "electron stack would exceed 2^32 entries");
-    R.ensure_stacks(n_pipes_of(o), o.max_batch, uint32_t(el_need));
+    R.ensure_stacks(n_pipes_of(o, plan), o.max_batch, uint32_t(el_need));
     ensure_physics(const_cast<psl_phantom*>(ph), prm);
     ensure_device(plan);
 
@@ -287,7 +292,7 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     k.cut_g = prm->e_cut_photon;
     k.frac = prm->step_frac;
     k.ms = prm->ms_enable;
-    k.pipes = n_pipes_of(o);
+    k.pipes = n_pipes_of(o, plan);
     k.ph_cap = R.pipes[0].ph_cap;
     k.el_cap = R.pipes[0].el_cap;
     k.n_batches = plan->batches.size();
@@ -385,7 +390,7 @@ extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tall
                     PSL_HIP(hipEventSynchronize(e1));
                     float ms = 0.f;
                     PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms_out) ms_out[(((i * n_w + j) * n_l + l) * 2 + srt) * 2 + (pp - 1)] = ms;
+                    if (ms_out) ms_out[(((i * n_w + j) * n_l + l) * 2 + srt) * kMaxPipes + (pp - 1)] = ms;
                     cand.push_back(o);
                     times.push_back(ms);
                 }
