@@ -23,8 +23,10 @@ def test_time_to_one_percent_summary():
     from paper_1503_01725_amd.denoise import summarize
     row = {"plain_rms": 2.0, "denoised_rms": 0.3, "plain_gamma": 0.8, "denoised_gamma": 0.99,
            "sigma_rel": 0.05, "t_infer_s": 0.01}
-    res = {"cases": [{"hist_per_s": 1e8, "1e+06": dict(row), "3e+06": dict(row),
-                      "1e+07": dict(row)}]}
+    from paper_1503_01725_amd.denoise import EVAL_COUNTS
+    case = {"hist_per_s": 1e8}
+    case.update({f"{nl:.0e}": dict(row) for nl in EVAL_COUNTS})
+    res = {"cases": [case]}
     out = summarize(res)
     n1 = 1e6 * (0.05 / 0.01) ** 2
     assert out["time_to_1pct"]["plain_histories"] == pytest.approx(n1)
@@ -33,3 +35,7 @@ def test_time_to_one_percent_summary():
     assert out["time_to_1pct"]["rms_error_percent_of_dmax"] == pytest.approx(rms1)
     assert out["time_to_1pct"]["denoised_histories"] == 1e6
     assert out["time_to_1pct"]["denoised_s"] == pytest.approx(1e6 / 1e8 + 0.01)
+    # equal-RMS speed-up at 1e6: plain histories (2.0 / 0.3)^2 * 1e6 against 1e6 + inference
+    eq = out["equal_rms"]["1e+06"]
+    assert eq["plain_histories_same_rms"] == pytest.approx(1e6 * (2.0 / 0.3) ** 2)
+    assert eq["speedup"] == pytest.approx((1e6 * (2.0 / 0.3) ** 2 / 1e8) / (1e6 / 1e8 + 0.01))
