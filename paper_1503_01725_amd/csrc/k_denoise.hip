@@ -44,6 +44,7 @@ struct GemmArgs {
     const float* bias;   // fwd: [C_out]
     View mask;           // bwd-data: multiply by (mask > 0) if mask.p
     float* wgrad;        // wgrad: FP32 gradient in the reference layout
+    float* partial;      // wgrad: [splits][M][N] FP32 per-split sums (reduced afterwards)
     int M, N, K;
     int cin, cout;       // channels of the layer (real, not padded)
     int relu;
@@ -152,21 +153,29 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                 bv = *reinterpret_cast<const uint4*>(g.wt + size_t(n0 + r) * g.K + k0 + kc);
             *reinterpret_cast<uint4*>(&Bs[r][kc]) = bv;
         } else {
-            // transposed: 8 rows at (t%8)*8, one K value t/8 (positions beyond k_hi are zero)
-            const int rc = (t & 7) << 3, kk = t >> 3;
+            // transposed: threads 0-127 stage A, 128-255 stage B; each takes 8
+            // rows at ((t%128)%8)*8 and two consecutive K values 2*((t%128)/8)
+            // (positions beyond k_hi are zero) and writes 8 packed pairs
+            const int tt = t & 127, rc = (tt & 7) << 3, kk = (tt >> 3) << 1;
             const int kpos = k0 + kk;
-            const bool in = kpos < k_hi;
-            uint4 av = {0u, 0u, 0u, 0u}, bv = {0u, 0u, 0u, 0u};
-            if (in) {
-                av = load_a_col<MODE>(g, m0 + rc, kpos);
-                bv = load_b_col<MODE>(g, n0 + rc, kpos);
+            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+            if (t < 128) {
+                if (kpos < k_hi) v0 = load_a_col<MODE>(g, m0 + rc, kpos);
+                if (kpos + 1 < k_hi) v1 = load_a_col<MODE>(g, m0 + rc, kpos + 1);
+            } else {
+                if (kpos < k_hi) v0 = load_b_col<MODE>(g, n0 + rc, kpos);
+                if (kpos + 1 < k_hi) v1 = load_b_col<MODE>(g, n0 + rc, kpos + 1);
             }
-            const uint16_t* ae = reinterpret_cast<const uint16_t*>(&av);
-            const uint16_t* be = reinterpret_cast<const uint16_t*>(&bv);
+            const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&v0);
+            const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&v1);
+            uint16_t (*dst)[kBK + kLdsPad] = t < 128 ? As : Bs;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                As[rc + j][kk] = ae[j];
-                Bs[rc + j][kk] = be[j];
+            for (int j = 0; j < 4; ++j) {
+                // rows rc+2j (low halves) and rc+2j+1 (high halves): K pair (kk, kk+1)
+                const uint32_t lo = __builtin_amdgcn_perm(w1[j], w0[j], 0x05040100u);
+                const uint32_t hi = __builtin_amdgcn_perm(w1[j], w0[j], 0x07060302u);
+                *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j][kk]) = lo;
+                *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j + 1][kk]) = hi;
             }
         }
         __syncthreads();
@@ -212,16 +221,35 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                               cx = 2 * x + (abc & 1);
                     const size_t child = (size_t(cz) * (2 * g.a.H) + cy) * (2 * g.a.W) + cx;
                     g.b.p[child * g.b.stride + g.b.off + o] = f2bf(v + g.bias[o]);
-                } else if (MODE == kConvWgrad) {
-                    // row m = output channel, column n = tap * C_in_padded + c
-                    const int tap = n / g.a.C, c = n - tap * g.a.C;
-                    if (c < g.cin && v != 0.f)
-                        atomicAdd(g.wgrad + (size_t(m) * g.cin + c) * 27 + tap, v);
-                } else {   // kTconvWgrad: row m = input channel, column n = abc * cout + o
-                    const int abc = n / g.cout, o = n - abc * g.cout;
-                    if (v != 0.f) atomicAdd(g.wgrad + (size_t(m) * g.cout + o) * 8 + abc, v);
+                } else {
+                    // weight gradients: this split's partial sum, reduced over
+                    // the splits by k_wgrad_reduce (no atomics, fixed order)
+                    g.partial[(size_t(blockIdx.z) * g.M + m) * g.N + n] = v;
                 }
             }
+}
+
+// Sum of the split-K partials of a weight gradient, written in the reference
+// layout: conv (MODE kConvWgrad) row m = output channel, column n = tap *
+// C_in_padded + c; transposed conv: row m = input channel, column n =
+// child * cout + o.
+template <int MODE>
+__global__ void k_wgrad_reduce(const float* partial, int splits, int M, int N, int c_pad, int cin,
+                               int cout, float* wgrad) {
+    const int64_t total = int64_t(M) * N;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        float v = 0.f;
+        for (int z = 0; z < splits; ++z) v += partial[size_t(z) * total + i];
+        const int m = int(i / N), n = int(i - int64_t(m) * N);
+        if (MODE == kConvWgrad) {
+            const int tap = n / c_pad, c = n - tap * c_pad;
+            if (c < cin) wgrad[(size_t(m) * cin + c) * 27 + tap] = v;
+        } else {
+            const int abc = n / cout, o = n - abc * cout;
+            wgrad[(size_t(m) * cout + o) * 8 + abc] = v;
+        }
+    }
 }
 
 // ---- element-wise / reduction kernels ---------------------------------------
@@ -298,44 +326,77 @@ __global__ void k_loss(const float* pred, const float* tgt, int P, float* gy, do
     if ((threadIdx.x & 63) == 0) atomicAdd(loss_parts + (blockIdx.x & 63), s / double(P));
 }
 
-// head backward: d head.w[c] += sum_p gy h, d head.b += sum_p gy,
-// g[p][c] = w[c] gy[p] masked by h > 0
-__global__ void k_head_bwd(View h, const float* hw, const float* gy, int P, float* ghw, float* ghb,
-                           View g) {
-    __shared__ float s_w[256];
-    __shared__ float s_b;
+// Head backward: per-position gradient into the last decoder output (masked
+// by its ReLU) and the head's weight / bias gradients.  Each thread takes
+// whole positions (C <= 32 channels, 8 per 16-byte load) and keeps its weight
+// gradient in registers; waves reduce with shuffles, blocks through LDS.
+__global__ void __launch_bounds__(256) k_head_bwd(View h, const float* hw, const float* gy, int P,
+                                                  float* ghw, float* ghb, View g) {
+    __shared__ float s_w[33];
     const int C = h.C;
-    for (int c = threadIdx.x; c < C; c += blockDim.x) s_w[c] = 0.f;
-    if (threadIdx.x == 0) s_b = 0.f;
+    if (threadIdx.x < 33) s_w[threadIdx.x] = 0.f;
     __syncthreads();
+    float acc[32], accb = 0.f;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = 0.f;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         const float gp = gy[p];
-        atomicAdd(&s_b, gp);
-        for (int c = 0; c < C; ++c) {
-            const float hv = bf2f(h.p[size_t(p) * h.stride + h.off + c]);
-            atomicAdd(&s_w[c], gp * hv);
-            g.p[size_t(p) * g.stride + g.off + c] = f2bf(hv > 0.f ? hw[c] * gp : 0.f);
+        accb += gp;
+#pragma unroll
+        for (int c8 = 0; c8 < 32; c8 += 8) {
+            if (c8 < C) {
+                const uint4 hv = load8(h, p, c8);
+                const uint16_t* he = reinterpret_cast<const uint16_t*>(&hv);
+                uint16_t out[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float x = bf2f(he[j]);
+                    acc[c8 + j] = fmaf(gp, x, acc[c8 + j]);
+                    out[j] = f2bf(x > 0.f ? hw[c8 + j] * gp : 0.f);
+                }
+                *reinterpret_cast<uint4*>(g.p + size_t(p) * g.stride + g.off + c8) =
+                    *reinterpret_cast<const uint4*>(out);
+            }
         }
     }
+    // wave sums, then one LDS add per wave and channel
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        float v = acc[c];
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[c] = v;
+    }
+    for (int off = 32; off >= 1; off >>= 1) accb += __shfl_xor(accb, off, 64);
+    if ((threadIdx.x & 63) == 0) {
+        for (int c = 0; c < C; ++c) atomicAdd(&s_w[c], acc[c]);
+        atomicAdd(&s_w[32], accb);
+    }
     __syncthreads();
-    for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(ghw + c, s_w[c]);
-    if (threadIdx.x == 0) atomicAdd(ghb, s_b);
+    if (threadIdx.x < C) atomicAdd(ghw + threadIdx.x, s_w[threadIdx.x]);
+    if (threadIdx.x == 32) atomicAdd(ghb, s_w[32]);
 }
 
-// bias gradient: column sums of a gradient view over all positions
-__global__ void k_bias_grad(View g, int P, float* gb) {
+// bias gradient: column sums of a gradient view over all positions.  A
+// thread sums 8 channels (one 16-byte load) over a strided set of positions;
+// the block adds its partial sums in LDS, then once per channel globally.
+__global__ void __launch_bounds__(256) k_bias_grad(View g, int P, float* gb) {
     __shared__ float s[256];
-    const int C = g.C;
+    const int C = g.C;                 // multiple of 8, at most 256
+    const int groups = C >> 3;         // channel groups of 8
     for (int c = threadIdx.x; c < C; c += blockDim.x) s[c] = 0.f;
     __syncthreads();
-    const int per = (P + gridDim.x - 1) / gridDim.x;
-    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    for (int c = threadIdx.x % C; c < C; c += C) {
-        // threads sharing a column stride over positions
-        float acc = 0.f;
-        for (int p = p0 + threadIdx.x / C; p < p1; p += blockDim.x / C)
-            acc += bf2f(g.p[size_t(p) * g.stride + g.off + c]);
-        atomicAdd(&s[c], acc);
+    const int per_block = blockDim.x / groups;     // positions in flight per block
+    const int grp = threadIdx.x % groups, row = threadIdx.x / groups;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (row < per_block) {
+        for (int p = blockIdx.x * per_block + row; p < P; p += gridDim.x * per_block) {
+            const uint4 v = load8(g, p, grp * 8);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += bf2f(e[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) atomicAdd(&s[grp * 8 + j], acc[j]);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < C; c += blockDim.x) atomicAdd(gb + c, s[c]);
@@ -408,6 +469,7 @@ struct UNet {
     Tconv up[kLevels];
     int64_t head_w = 0, head_b = 0;
     DevBuf params, grads, adam_m, adam_v, packed;
+    DevBuf wpart;          // split-K partial sums of the weight gradients
     // activations (BF16 channels-last) and gradients per level
     DevBuf x0, cat[kLevels], enc_a_out[kLevels], dec_a_out[kLevels], dec_b_out[kLevels],
         bottom_b, pooled[kLevels], arg[kLevels], g1[kLevels], g2[kLevels], gcat[kLevels], pred,
@@ -453,9 +515,61 @@ void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     gemm_launch(kConvFwd, g, s);
 }
 
-int wgrad_splits(int64_t positions) {
-    return int(std::max<int64_t>(1, std::min<int64_t>(positions / 2048, 512)));
+// bias gradient over P positions: enough blocks that every thread sums a
+// few dozen positions
+void bias_grad(View g, int64_t P, float* gb, hipStream_t s) {
+    const int64_t rows = 256 / (g.C / 8);
+    const int blocks = int(std::max<int64_t>(1, std::min<int64_t>((P + 32 * rows - 1) / (32 * rows), 4096)));
+    hipLaunchKernelGGL(k_bias_grad, dim3(blocks), dim3(256), 0, s, g, int(P), gb);
 }
+
+// Split-K of a weight gradient over `positions`: about 2048 workgroups in
+// all, at least 1024 positions per split.
+int wgrad_splits(int64_t positions, int M, int N) {
+    const int64_t tiles = int64_t((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const int64_t by_grid = std::max<int64_t>(1, 2048 / tiles);
+    return int(std::max<int64_t>(1, std::min<int64_t>(positions / 1024, by_grid)));
+}
+
+// Weight-gradient GEMM with split-K into the partial buffer, then the
+// reduction into the gradient array.
+void wgrad_launch(int mode, GemmArgs g, int64_t positions, int c_pad, const UNet& u,
+                  hipStream_t s) {
+    const int splits0 = wgrad_splits(positions, g.M, g.N);
+    g.k_per_split = int(((positions + splits0 - 1) / splits0 + kBK - 1) / kBK * kBK);
+    const int splits = int((positions + g.k_per_split - 1) / g.k_per_split);
+    PSL_CHECK(u.wpart.bytes >= size_t(splits) * g.M * g.N * 4, "weight-gradient scratch too small");
+    g.partial = u.wpart.as<float>();
+    gemm_launch(mode, g, s, splits);
+    const int64_t total = int64_t(g.M) * g.N;
+    const int blocks = int(std::min<int64_t>((total + 255) / 256, 2048));
+    if (mode == kConvWgrad)
+        hipLaunchKernelGGL(k_wgrad_reduce<kConvWgrad>, dim3(blocks), dim3(256), 0, s, g.partial,
+                           splits, g.M, g.N, c_pad, g.cin, g.cout, g.wgrad);
+    else
+        hipLaunchKernelGGL(k_wgrad_reduce<kTconvWgrad>, dim3(blocks), dim3(256), 0, s, g.partial,
+                           splits, g.M, g.N, c_pad, g.cin, g.cout, g.wgrad);
+    PSL_HIP(hipGetLastError());
+}
+
+// Floats of split-K scratch the largest weight gradient of the network needs.
+size_t wpart_floats(const UNet& u) {
+    size_t most = 0;
+    auto need = [&](int64_t positions, int M, int N) {
+        most = std::max(most, size_t(wgrad_splits(positions, M, N)) * M * N);
+    };
+    for (int k = 0; k < kLevels; ++k) {
+        need(u.P(k), u.enc_a[k].cout, 27 * u.enc_a[k].cin_pad);
+        need(u.P(k), u.enc_b[k].cout, 27 * u.enc_b[k].cin_pad);
+    }
+    for (int k = 0; k < kLevels - 1; ++k) {
+        need(u.P(k), u.dec_a[k].cout, 27 * u.dec_a[k].cin_pad);
+        need(u.P(k), u.dec_b[k].cout, 27 * u.dec_b[k].cin_pad);
+        need(u.P(k + 1), u.ch(k + 1), 8 * u.ch(k));
+    }
+    return most;
+}
+
 
 // conv backward: gz (gradient at the conv output, ReLU already applied) ->
 // weight and bias gradients, and (optional) gradient at the input masked by
@@ -471,10 +585,8 @@ void conv_bwd(const UNet& u, const UNet::Conv& L, View in, View gz, View* gin, h
     g.K = int(P);
     g.cin = L.cin;
     g.cout = L.cout;
-    const int splits = wgrad_splits(P);
-    g.k_per_split = int(((P + splits - 1) / splits + kBK - 1) / kBK * kBK);
-    gemm_launch(kConvWgrad, g, s, int((P + g.k_per_split - 1) / g.k_per_split));
-    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gz, int(P), u.grads.as<float>() + L.b);
+    wgrad_launch(kConvWgrad, g, P, L.cin_pad, u, s);
+    bias_grad(gz, P, u.grads.as<float>() + L.b, s);
     if (gin) {
         GemmArgs d{};
         d.a = gz;
@@ -650,11 +762,8 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
         w.K = int(u.P(k + 1));
         w.cin = u.ch(k + 1);
         w.cout = C;
-        const int splits = wgrad_splits(u.P(k + 1));
-        w.k_per_split = int(((u.P(k + 1) + splits - 1) / splits + kBK - 1) / kBK * kBK);
-        gemm_launch(kTconvWgrad, w, s, int((u.P(k + 1) + w.k_per_split - 1) / w.k_per_split));
-        hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, s, gup, int(u.P(k)),
-                           u.grads.as<float>() + u.up[k].b);
+        wgrad_launch(kTconvWgrad, w, u.P(k + 1), 0, u, s);
+        bias_grad(gup, u.P(k), u.grads.as<float>() + u.up[k].b, s);
         View gh = view(u.g1[k + 1], u, k + 1, u.ch(k + 1), u.ch(k + 1), 0);
         GemmArgs d{};
         d.a = gup;
@@ -774,6 +883,7 @@ extern "C" int psl_unet_create(int32_t base_width, int32_t d, int32_t h, int32_t
         u->pred.alloc(size_t(u->P(0)) * 4);
         u->gy.alloc(size_t(u->P(0)) * 4);
         u->loss.alloc(64 * 8);
+        u->wpart.alloc(wpart_floats(*u) * 4);
         hipLaunchKernelGGL(k_zero_f, dim3(grid1(int64_t(np))), dim3(256), 0, nullptr,
                            u->adam_m.as<float>(), int64_t(np));
         hipLaunchKernelGGL(k_zero_f, dim3(grid1(int64_t(np))), dim3(256), 0, nullptr,
