@@ -19,7 +19,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevels = 4;
-constexpr int kBM = 64, kBN = 64, kBK = 32, kLdsPad = 8;
+constexpr int kBK = 32, kLdsPad = 8;
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -123,12 +123,18 @@ __device__ __forceinline__ uint4 load_b_col(const GemmArgs& g, int n, int k) {
     }
 }
 
-template <int MODE>
+// Tiles of BM x BN outputs per workgroup of four waves, each wave 32 x 32
+// (2 x 2 MFMA tiles of 16 x 16): 64 x 64, or 128 x 32 / 32 x 128 when one
+// GEMM dimension is only 32 (the outermost level's channels), so that no
+// wave computes padding.
+template <int MODE, int BM, int BN>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-    __shared__ uint16_t As[kBM][kBK + kLdsPad];
-    __shared__ uint16_t Bs[kBN][kBK + kLdsPad];
+    static_assert(BM * BN == 4096 && BM % 32 == 0 && BN % 32 == 0, "four 32 x 32 wave tiles");
+    constexpr int WN = BN / 32;   // waves along N
+    __shared__ uint16_t As[BM][kBK + kLdsPad];
+    __shared__ uint16_t Bs[BN][kBK + kLdsPad];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     constexpr bool kWgrad = MODE == kConvWgrad || MODE == kTconvWgrad;
     int k_lo = 0, k_hi = g.K;
     if (kWgrad) {
@@ -140,42 +146,55 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int wr = (w / WN) * 32, wc = (w % WN) * 32;
 
     for (int k0 = k_lo; k0 < k_hi; k0 += kBK) {
         if (!kWgrad) {
-            // direct: row = t/4, 8 K values at (t%4)*8
-            const int r = t >> 2, kc = (t & 3) << 3;
-            const uint4 av = load_a_row<MODE>(g, m0 + r, k0 + kc);
-            *reinterpret_cast<uint4*>(&As[r][kc]) = av;
-            uint4 bv = {0u, 0u, 0u, 0u};
-            if (n0 + r < g.N && k0 + kc < g.K)
-                bv = *reinterpret_cast<const uint4*>(g.wt + size_t(n0 + r) * g.K + k0 + kc);
-            *reinterpret_cast<uint4*>(&Bs[r][kc]) = bv;
-        } else {
-            // transposed: threads 0-127 stage A, 128-255 stage B; each takes 8
-            // rows at ((t%128)%8)*8 and two consecutive K values 2*((t%128)/8)
-            // (positions beyond k_hi are zero) and writes 8 packed pairs
-            const int tt = t & 127, rc = (tt & 7) << 3, kk = (tt >> 3) << 1;
-            const int kpos = k0 + kk;
-            uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-            if (t < 128) {
-                if (kpos < k_hi) v0 = load_a_col<MODE>(g, m0 + rc, kpos);
-                if (kpos + 1 < k_hi) v1 = load_a_col<MODE>(g, m0 + rc, kpos + 1);
-            } else {
-                if (kpos < k_hi) v0 = load_b_col<MODE>(g, n0 + rc, kpos);
-                if (kpos + 1 < k_hi) v1 = load_b_col<MODE>(g, n0 + rc, kpos + 1);
-            }
-            const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&v0);
-            const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&v1);
-            uint16_t (*dst)[kBK + kLdsPad] = t < 128 ? As : Bs;
+            // direct: item = (row, 8 K values at a multiple of 8)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                // rows rc+2j (low halves) and rc+2j+1 (high halves): K pair (kk, kk+1)
-                const uint32_t lo = __builtin_amdgcn_perm(w1[j], w0[j], 0x05040100u);
-                const uint32_t hi = __builtin_amdgcn_perm(w1[j], w0[j], 0x07060302u);
-                *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j][kk]) = lo;
-                *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j + 1][kk]) = hi;
+            for (int it = t; it < BM * (kBK / 8); it += 256) {
+                const int r = it >> 2, kc = (it & 3) << 3;
+                *reinterpret_cast<uint4*>(&As[r][kc]) = load_a_row<MODE>(g, m0 + r, k0 + kc);
+            }
+#pragma unroll
+            for (int it = t; it < BN * (kBK / 8); it += 256) {
+                const int r = it >> 2, kc = (it & 3) << 3;
+                uint4 bv = {0u, 0u, 0u, 0u};
+                if (n0 + r < g.N && k0 + kc < g.K)
+                    bv = *reinterpret_cast<const uint4*>(g.wt + size_t(n0 + r) * g.K + k0 + kc);
+                *reinterpret_cast<uint4*>(&Bs[r][kc]) = bv;
+            }
+        } else {
+            // transposed: item = (8 rows from a multiple of 8, two consecutive
+            // K values); A's items first, then B's (positions beyond k_hi are
+            // zero); each writes 8 packed (K, K+1) pairs
+            constexpr int kAT = (BM / 8) * (kBK / 2), kBT = (BN / 8) * (kBK / 2);
+#pragma unroll
+            for (int it = t; it < kAT + kBT; it += 256) {
+                const bool isA = it < kAT;
+                const int x = isA ? it : it - kAT;
+                const int rows8 = isA ? BM / 8 : BN / 8;
+                const int rc = (x % rows8) << 3, kk = (x / rows8) << 1;
+                const int kpos = k0 + kk;
+                uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+                if (isA) {
+                    if (kpos < k_hi) v0 = load_a_col<MODE>(g, m0 + rc, kpos);
+                    if (kpos + 1 < k_hi) v1 = load_a_col<MODE>(g, m0 + rc, kpos + 1);
+                } else {
+                    if (kpos < k_hi) v0 = load_b_col<MODE>(g, n0 + rc, kpos);
+                    if (kpos + 1 < k_hi) v1 = load_b_col<MODE>(g, n0 + rc, kpos + 1);
+                }
+                const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&v0);
+                const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&v1);
+                uint16_t (*dst)[kBK + kLdsPad] = isA ? As : Bs;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // rows rc+2j (low halves) and rc+2j+1 (high halves): K pair (kk, kk+1)
+                    const uint32_t lo = __builtin_amdgcn_perm(w1[j], w0[j], 0x05040100u);
+                    const uint32_t hi = __builtin_amdgcn_perm(w1[j], w0[j], 0x07060302u);
+                    *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j][kk]) = lo;
+                    *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j + 1][kk]) = hi;
+                }
             }
         }
         __syncthreads();
@@ -486,15 +505,33 @@ View view(const DevBuf& b, const UNet& u, int level, int C, int stride, int off)
     return View{b.as<uint16_t>(), u.dims[level][0], u.dims[level][1], u.dims[level][2], C, stride, off};
 }
 
+// Tile of a GEMM: 128 x 32 for a direct GEMM with N <= 32, 32 x 128 for a
+// weight gradient with M <= 32, else 64 x 64.
+struct Tile { int bm, bn; };
+Tile tile_for(int mode, int M, int N) {
+    const bool wg = mode == kConvWgrad || mode == kTconvWgrad;
+    if (!wg && N <= 32) return {128, 32};
+    if (wg && M <= 32) return {32, 128};
+    return {64, 64};
+}
+
+template <int MODE>
+void launch_mode(const GemmArgs& g, dim3 grid, Tile tl, hipStream_t s) {
+    if (tl.bm == 128) hipLaunchKernelGGL((k_gemm<MODE, 128, 32>), grid, dim3(256), 0, s, g);
+    else if (tl.bm == 32) hipLaunchKernelGGL((k_gemm<MODE, 32, 128>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_gemm<MODE, 64, 64>), grid, dim3(256), 0, s, g);
+}
+
 void gemm_launch(int mode, const GemmArgs& g, hipStream_t s, int splits = 1) {
-    dim3 grid((g.M + kBM - 1) / kBM, (g.N + kBN - 1) / kBN, splits), block(256);
+    const Tile tl = tile_for(mode, g.M, g.N);
+    dim3 grid((g.M + tl.bm - 1) / tl.bm, (g.N + tl.bn - 1) / tl.bn, splits);
     switch (mode) {
-        case kConvFwd: hipLaunchKernelGGL(k_gemm<kConvFwd>, grid, block, 0, s, g); break;
-        case kConvBwdData: hipLaunchKernelGGL(k_gemm<kConvBwdData>, grid, block, 0, s, g); break;
-        case kConvWgrad: hipLaunchKernelGGL(k_gemm<kConvWgrad>, grid, block, 0, s, g); break;
-        case kTconvFwd: hipLaunchKernelGGL(k_gemm<kTconvFwd>, grid, block, 0, s, g); break;
-        case kTconvBwdData: hipLaunchKernelGGL(k_gemm<kTconvBwdData>, grid, block, 0, s, g); break;
-        default: hipLaunchKernelGGL(k_gemm<kTconvWgrad>, grid, block, 0, s, g); break;
+        case kConvFwd: launch_mode<kConvFwd>(g, grid, tl, s); break;
+        case kConvBwdData: launch_mode<kConvBwdData>(g, grid, tl, s); break;
+        case kConvWgrad: launch_mode<kConvWgrad>(g, grid, tl, s); break;
+        case kTconvFwd: launch_mode<kTconvFwd>(g, grid, tl, s); break;
+        case kTconvBwdData: launch_mode<kTconvBwdData>(g, grid, tl, s); break;
+        default: launch_mode<kTconvWgrad>(g, grid, tl, s); break;
     }
     PSL_HIP(hipGetLastError());
 }
@@ -526,7 +563,8 @@ void bias_grad(View g, int64_t P, float* gb, hipStream_t s) {
 // Split-K of a weight gradient over `positions`: about 2048 workgroups in
 // all, at least 1024 positions per split.
 int wgrad_splits(int64_t positions, int M, int N) {
-    const int64_t tiles = int64_t((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+    const Tile tl = tile_for(kConvWgrad, M, N);
+    const int64_t tiles = int64_t((M + tl.bm - 1) / tl.bm) * ((N + tl.bn - 1) / tl.bn);
     const int64_t by_grid = std::max<int64_t>(1, 2048 / tiles);
     return int(std::max<int64_t>(1, std::min<int64_t>(positions / 1024, by_grid)));
 }
