@@ -179,7 +179,7 @@ def ceilings(N, torch, dose, cnt, value, hist_per_step):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="water128_10")
     ap.add_argument("--max-batch", type=int, default=0, help="0 = autotune")
