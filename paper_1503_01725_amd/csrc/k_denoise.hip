@@ -19,7 +19,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLevels = 4;
-constexpr int kBK = 32, kLdsPad = 8;
+constexpr int kBK = 32;    // K of one MFMA (16 x 16 x 32)
+constexpr int kKT = 64;    // K of one LDS tile (two MFMA K steps per barrier)
+constexpr int kLdsPad = 8;
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -30,9 +32,16 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 // A channels-last BF16 view: element (pos, c) at p[pos * stride + off + c].
+// Positions are split into (z, y, x) by multiply-shift division by W and H
+// (and by W/2, H/2 for the coarse grid under a transposed convolution): for
+// n < 2^31, n / d = (umulhi(n, mul) + n) >> sh with sh = ceil(log2 d) and
+// mul = floor(2^32 (2^sh - d) / d) + 1.  C is a power of two (cs = log2 C).
 struct View {
     uint16_t* p;
     int D, H, W, C, stride, off;
+    uint32_t wm, ws, hm, hs;       // division by W, H
+    uint32_t w2m, w2s, h2m, h2s;   // division by W/2, H/2
+    int cs;
 };
 
 enum Mode { kConvFwd = 0, kConvBwdData, kConvWgrad, kTconvFwd, kTconvBwdData, kTconvWgrad };
@@ -47,6 +56,7 @@ struct GemmArgs {
     float* partial;      // wgrad: [splits][M][N] FP32 per-split sums (reduced afterwards)
     int M, N, K;
     int cin, cout;       // channels of the layer (real, not padded)
+    int cout_sh;         // log2(cout) (cout is a power of two)
     int relu;
     int k_per_split;     // wgrad: positions per blockIdx.z
 };
@@ -56,6 +66,26 @@ __device__ __forceinline__ void pos3(int m, int D, int H, int W, int& z, int& y,
     const int t = m / W;
     y = t % H;
     z = t / H;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t mul, uint32_t sh) {
+    return (__umulhi(n, mul) + n) >> sh;
+}
+
+// (z, y, x) of position m on the view's grid / on its half-resolution grid
+__device__ __forceinline__ void pos3v(const View& v, int m, int& z, int& y, int& x) {
+    const uint32_t q = fdiv(uint32_t(m), v.wm, v.ws);
+    x = m - int(q) * v.W;
+    const uint32_t r = fdiv(q, v.hm, v.hs);
+    y = int(q) - int(r) * v.H;
+    z = int(r);
+}
+__device__ __forceinline__ void pos3c(const View& v, int m, int& z, int& y, int& x) {
+    const uint32_t q = fdiv(uint32_t(m), v.w2m, v.w2s);
+    x = m - int(q) * (v.W >> 1);
+    const uint32_t r = fdiv(q, v.h2m, v.h2s);
+    y = int(q) - int(r) * (v.H >> 1);
+    z = int(r);
 }
 
 __device__ __forceinline__ uint4 load8(const View& v, int pos, int c) {
@@ -69,9 +99,9 @@ __device__ __forceinline__ uint4 load_a_row(const GemmArgs& g, int m, int k) {
     if (m >= g.M || k >= g.K) return zero;
     const View& v = g.a;
     if (MODE == kConvFwd || MODE == kConvBwdData) {
-        const int tap = k / v.C, c = k - tap * v.C;
+        const int tap = k >> v.cs, c = k & (v.C - 1);
         int z, y, x;
-        pos3(m, v.D, v.H, v.W, z, y, x);
+        pos3v(v, m, z, y, x);
         z += tap / 9 - 1;
         y += (tap / 3) % 3 - 1;
         x += tap % 3 - 1;
@@ -81,9 +111,9 @@ __device__ __forceinline__ uint4 load_a_row(const GemmArgs& g, int m, int k) {
         return load8(v, m, k);
     } else {   // kTconvBwdData: m is a coarse voxel, v the fine-grid gradient;
                // k = abc * cout + o picks child abc, channel o
-        const int abc = k / g.cout, o = k - abc * g.cout;
+        const int abc = k >> g.cout_sh, o = k & (g.cout - 1);
         int z, y, x;
-        pos3(m, v.D >> 1, v.H >> 1, v.W >> 1, z, y, x);
+        pos3c(v, m, z, y, x);
         const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1), cx = 2 * x + (abc & 1);
         return load8(v, (cz * v.H + cy) * v.W + cx, o);
     }
@@ -107,8 +137,8 @@ __device__ __forceinline__ uint4 load_b_col(const GemmArgs& g, int n, int k) {
     int z, y, x;
     if (MODE == kConvWgrad) {
         const View& v = g.a;
-        const int tap = n / v.C, c = n - tap * v.C;
-        pos3(k, v.D, v.H, v.W, z, y, x);
+        const int tap = n >> v.cs, c = n & (v.C - 1);
+        pos3v(v, k, z, y, x);
         z += tap / 9 - 1;
         y += (tap / 3) % 3 - 1;
         x += tap % 3 - 1;
@@ -116,8 +146,8 @@ __device__ __forceinline__ uint4 load_b_col(const GemmArgs& g, int n, int k) {
         return load8(v, (z * v.H + y) * v.W + x, c);
     } else {   // kTconvWgrad: n = abc * cout + o, dY at the child voxel of position k
         const View& v = g.a;   // coarse grid
-        const int abc = n / g.cout, o = n - abc * g.cout;
-        pos3(k, v.D, v.H, v.W, z, y, x);
+        const int abc = n >> g.cout_sh, o = n & (g.cout - 1);
+        pos3v(v, k, z, y, x);
         const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1), cx = 2 * x + (abc & 1);
         return load8(g.b, (cz * (2 * v.H) + cy) * (2 * v.W) + cx, o);
     }
@@ -131,8 +161,8 @@ template <int MODE, int BM, int BN>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     static_assert(BM * BN == 4096 && BM % 32 == 0 && BN % 32 == 0, "four 32 x 32 wave tiles");
     constexpr int WN = BN / 32;   // waves along N
-    __shared__ uint16_t As[BM][kBK + kLdsPad];
-    __shared__ uint16_t Bs[BN][kBK + kLdsPad];
+    __shared__ uint16_t As[BM][kKT + kLdsPad];
+    __shared__ uint16_t Bs[BN][kKT + kLdsPad];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
     constexpr bool kWgrad = MODE == kConvWgrad || MODE == kTconvWgrad;
@@ -148,66 +178,115 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int wr = (w / WN) * 32, wc = (w % WN) * 32;
 
-    for (int k0 = k_lo; k0 < k_hi; k0 += kBK) {
+    // Staging: the next K tile is fetched into registers while the current
+    // one is multiplied from LDS.  Direct operands: item = (row, 8 K values);
+    // transposed operands: item = (8 rows, 2 consecutive K values), A's items
+    // first, then B's, each written as 8 packed (K, K+1) pairs.
+    constexpr int kDA = (BM * (kKT / 8) + 255) / 256, kDB = (BN * (kKT / 8) + 255) / 256;
+    constexpr int kAT = (BM / 8) * (kKT / 2), kBT = (BN / 8) * (kKT / 2);
+    constexpr int kTT = (kAT + kBT + 255) / 256;
+    constexpr int kRegs = kWgrad ? 2 * kTT : kDA + kDB;
+    uint4 reg[kRegs];
+    auto fetch = [&](int k0) {
+        const uint4 zero = {0u, 0u, 0u, 0u};
         if (!kWgrad) {
-            // direct: item = (row, 8 K values at a multiple of 8)
 #pragma unroll
-            for (int it = t; it < BM * (kBK / 8); it += 256) {
-                const int r = it >> 2, kc = (it & 3) << 3;
-                *reinterpret_cast<uint4*>(&As[r][kc]) = load_a_row<MODE>(g, m0 + r, k0 + kc);
+            for (int q = 0; q < kDA; ++q) {
+                const int it = t + 256 * q;
+                const int r = it >> 3, kc = (it & 7) << 3;
+                reg[q] = it < BM * (kKT / 8) ? load_a_row<MODE>(g, m0 + r, k0 + kc) : zero;
             }
 #pragma unroll
-            for (int it = t; it < BN * (kBK / 8); it += 256) {
-                const int r = it >> 2, kc = (it & 3) << 3;
-                uint4 bv = {0u, 0u, 0u, 0u};
-                if (n0 + r < g.N && k0 + kc < g.K)
+            for (int q = 0; q < kDB; ++q) {
+                const int it = t + 256 * q;
+                const int r = it >> 3, kc = (it & 7) << 3;
+                uint4 bv = zero;
+                if (it < BN * (kKT / 8) && n0 + r < g.N && k0 + kc < g.K)
                     bv = *reinterpret_cast<const uint4*>(g.wt + size_t(n0 + r) * g.K + k0 + kc);
-                *reinterpret_cast<uint4*>(&Bs[r][kc]) = bv;
+                reg[kDA + q] = bv;
             }
         } else {
-            // transposed: item = (8 rows from a multiple of 8, two consecutive
-            // K values); A's items first, then B's (positions beyond k_hi are
-            // zero); each writes 8 packed (K, K+1) pairs
-            constexpr int kAT = (BM / 8) * (kBK / 2), kBT = (BN / 8) * (kBK / 2);
 #pragma unroll
-            for (int it = t; it < kAT + kBT; it += 256) {
-                const bool isA = it < kAT;
-                const int x = isA ? it : it - kAT;
-                const int rows8 = isA ? BM / 8 : BN / 8;
-                const int rc = (x % rows8) << 3, kk = (x / rows8) << 1;
-                const int kpos = k0 + kk;
-                uint4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
-                if (isA) {
-                    if (kpos < k_hi) v0 = load_a_col<MODE>(g, m0 + rc, kpos);
-                    if (kpos + 1 < k_hi) v1 = load_a_col<MODE>(g, m0 + rc, kpos + 1);
-                } else {
-                    if (kpos < k_hi) v0 = load_b_col<MODE>(g, n0 + rc, kpos);
-                    if (kpos + 1 < k_hi) v1 = load_b_col<MODE>(g, n0 + rc, kpos + 1);
+            for (int q = 0; q < kTT; ++q) {
+                const int it = t + 256 * q;
+                uint4 v0 = zero, v1 = zero;
+                if (it < kAT + kBT) {
+                    const bool isA = it < kAT;
+                    const int x = isA ? it : it - kAT;
+                    const int rows8 = isA ? BM / 8 : BN / 8;
+                    const int rc = (x % rows8) << 3, kk = (x / rows8) << 1;
+                    const int kpos = k0 + kk;
+                    if (isA) {
+                        if (kpos < k_hi) v0 = load_a_col<MODE>(g, m0 + rc, kpos);
+                        if (kpos + 1 < k_hi) v1 = load_a_col<MODE>(g, m0 + rc, kpos + 1);
+                    } else {
+                        if (kpos < k_hi) v0 = load_b_col<MODE>(g, n0 + rc, kpos);
+                        if (kpos + 1 < k_hi) v1 = load_b_col<MODE>(g, n0 + rc, kpos + 1);
+                    }
                 }
-                const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&v0);
-                const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&v1);
-                uint16_t (*dst)[kBK + kLdsPad] = isA ? As : Bs;
+                reg[2 * q] = v0;
+                reg[2 * q + 1] = v1;
+            }
+        }
+    };
+    auto stage = [&]() {
+        if (!kWgrad) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    // rows rc+2j (low halves) and rc+2j+1 (high halves): K pair (kk, kk+1)
-                    const uint32_t lo = __builtin_amdgcn_perm(w1[j], w0[j], 0x05040100u);
-                    const uint32_t hi = __builtin_amdgcn_perm(w1[j], w0[j], 0x07060302u);
-                    *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j][kk]) = lo;
-                    *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j + 1][kk]) = hi;
+            for (int q = 0; q < kDA; ++q) {
+                const int it = t + 256 * q;
+                if (it < BM * (kKT / 8))
+                    *reinterpret_cast<uint4*>(&As[it >> 3][(it & 7) << 3]) = reg[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kDB; ++q) {
+                const int it = t + 256 * q;
+                if (it < BN * (kKT / 8))
+                    *reinterpret_cast<uint4*>(&Bs[it >> 3][(it & 7) << 3]) = reg[kDA + q];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kTT; ++q) {
+                const int it = t + 256 * q;
+                if (it < kAT + kBT) {
+                    const bool isA = it < kAT;
+                    const int x = isA ? it : it - kAT;
+                    const int rows8 = isA ? BM / 8 : BN / 8;
+                    const int rc = (x % rows8) << 3, kk = (x / rows8) << 1;
+                    const uint32_t* w0 = reinterpret_cast<const uint32_t*>(&reg[2 * q]);
+                    const uint32_t* w1 = reinterpret_cast<const uint32_t*>(&reg[2 * q + 1]);
+                    uint16_t (*dst)[kKT + kLdsPad] = isA ? As : Bs;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        // rows rc+2j (low halves) and rc+2j+1 (high halves): K pair (kk, kk+1)
+                        const uint32_t lo = __builtin_amdgcn_perm(w1[j], w0[j], 0x05040100u);
+                        const uint32_t hi = __builtin_amdgcn_perm(w1[j], w0[j], 0x07060302u);
+                        *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j][kk]) = lo;
+                        *reinterpret_cast<uint32_t*>(&dst[rc + 2 * j + 1][kk]) = hi;
+                    }
                 }
             }
         }
+    };
+
+    if (k_lo < k_hi) fetch(k_lo);
+    for (int k0 = k_lo; k0 < k_hi; k0 += kKT) {
+        stage();
         __syncthreads();
+        if (k0 + kKT < k_hi) fetch(k0 + kKT);   // in flight during the MFMAs below
         const int lr = lane & 15, kq = (lane >> 4) << 3;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const uint4 araw = *reinterpret_cast<const uint4*>(&As[wr + 16 * i + lr][kq]);
-            const bf16x8 a = __builtin_bit_cast(bf16x8, araw);
+        for (int ks = 0; ks < kKT; ks += kBK) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const uint4 braw = *reinterpret_cast<const uint4*>(&Bs[wc + 16 * j + lr][kq]);
-                const bf16x8 b = __builtin_bit_cast(bf16x8, braw);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i) {
+                const uint4 araw = *reinterpret_cast<const uint4*>(&As[wr + 16 * i + lr][ks + kq]);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint4 braw =
+                        *reinterpret_cast<const uint4*>(&Bs[wc + 16 * j + lr][ks + kq]);
+                    const bf16x8 b = __builtin_bit_cast(bf16x8, braw);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -233,9 +312,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                         v = 0.f;
                     g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(v);
                 } else if (MODE == kTconvFwd) {
-                    const int abc = n / g.cout, o = n - abc * g.cout;
+                    const int abc = n >> g.cout_sh, o = n & (g.cout - 1);
                     int z, y, x;
-                    pos3(m, g.a.D, g.a.H, g.a.W, z, y, x);
+                    pos3v(g.a, m, z, y, x);
                     const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1),
                               cx = 2 * x + (abc & 1);
                     const size_t child = (size_t(cz) * (2 * g.a.H) + cy) * (2 * g.a.W) + cx;
@@ -501,8 +580,24 @@ struct UNet {
 
 namespace {
 
+// Multiply-shift constants for unsigned division by d >= 1 of n < 2^31.
+void magic_div(uint32_t d, uint32_t& mul, uint32_t& sh) {
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    mul = uint32_t(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    sh = l;
+}
+
 View view(const DevBuf& b, const UNet& u, int level, int C, int stride, int off) {
-    return View{b.as<uint16_t>(), u.dims[level][0], u.dims[level][1], u.dims[level][2], C, stride, off};
+    View v{b.as<uint16_t>(), u.dims[level][0], u.dims[level][1], u.dims[level][2], C, stride, off,
+           0, 0, 0, 0, 0, 0, 0, 0, 0};
+    PSL_CHECK(C > 0 && (C & (C - 1)) == 0, "channel counts must be powers of two");
+    magic_div(uint32_t(v.W), v.wm, v.ws);
+    magic_div(uint32_t(v.H), v.hm, v.hs);
+    magic_div(uint32_t(std::max(1, v.W >> 1)), v.w2m, v.w2s);
+    magic_div(uint32_t(std::max(1, v.H >> 1)), v.h2m, v.h2s);
+    while ((1 << v.cs) < C) ++v.cs;
+    return v;
 }
 
 // Tile of a GEMM: 128 x 32 for a direct GEMM with N <= 32, 32 x 128 for a
@@ -522,7 +617,13 @@ void launch_mode(const GemmArgs& g, dim3 grid, Tile tl, hipStream_t s) {
     else hipLaunchKernelGGL((k_gemm<MODE, 64, 64>), grid, dim3(256), 0, s, g);
 }
 
-void gemm_launch(int mode, const GemmArgs& g, hipStream_t s, int splits = 1) {
+void gemm_launch(int mode, const GemmArgs& g0, hipStream_t s, int splits = 1) {
+    GemmArgs g = g0;
+    if (mode == kTconvFwd || mode == kTconvBwdData || mode == kTconvWgrad) {
+        PSL_CHECK(g.cout > 0 && (g.cout & (g.cout - 1)) == 0, "channel counts must be powers of two");
+        g.cout_sh = 0;
+        while ((1 << g.cout_sh) < g.cout) ++g.cout_sh;
+    }
     const Tile tl = tile_for(mode, g.M, g.N);
     dim3 grid((g.M + tl.bm - 1) / tl.bm, (g.N + tl.bn - 1) / tl.bn, splits);
     switch (mode) {
@@ -574,7 +675,7 @@ int wgrad_splits(int64_t positions, int M, int N) {
 void wgrad_launch(int mode, GemmArgs g, int64_t positions, int c_pad, const UNet& u,
                   hipStream_t s) {
     const int splits0 = wgrad_splits(positions, g.M, g.N);
-    g.k_per_split = int(((positions + splits0 - 1) / splits0 + kBK - 1) / kBK * kBK);
+    g.k_per_split = int(((positions + splits0 - 1) / splits0 + kKT - 1) / kKT * kKT);
     const int splits = int((positions + g.k_per_split - 1) / g.k_per_split);
     PSL_CHECK(u.wpart.bytes >= size_t(splits) * g.M * g.N * 4, "weight-gradient scratch too small");
     g.partial = u.wpart.as<float>();
