@@ -148,6 +148,11 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1503_01725_amd.build` (no CPU fallback exists)")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one libpsl.so links; loading torch first makes the library
+        # bind to that already-loaded runtime, so that one runtime serves the
+        # tensors the caller allocates and the library's own calls.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
