@@ -17,8 +17,10 @@
  *     returns.
  *   - Calls taking a `stream` (a hipStream_t, NULL = default stream) are
  *     asynchronous: they validate arguments on the host, enqueue work and
- *     return.  Faults detected on the device (stack overflow, non-finite
- *     energies) set a device status word that psl_tally_stats reports.
+ *     return.  Conditions detected on the device (a particle stack too small,
+ *     a particle column beyond the tally, the step guard of a transport loop)
+ *     are counted in the tally's event counters, which psl_tally_stats
+ *     reads (it returns PSL_EOVERFLOW after an overflow).
  *   - Distinct handles may be used from different host threads; one handle
  *     must not be used by two threads at once.
  */
@@ -280,9 +282,9 @@ int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose
  * uint64 [16]: histories, entered, Woodcock steps, real interactions, electrons
  * pushed, local electron deposits, electron steps, atomic deposits, uncollided
  * escapes, Kahn trials, electron face crossings, step-guard hits,
- * electron-stack overflows, replicas folded) and the device status word.
- * Returns PSL_EOVERFLOW if a stack overflowed since the last RESET.  Either
- * output may be NULL. */
+ * overflows (a particle stack too small, or a particle column beyond the
+ * tally), replicas folded; the rest are zero).  Returns PSL_EOVERFLOW if an
+ * overflow was counted since the last RESET.  Either output may be NULL. */
 int psl_tally_stats(psl_tally* tally, double* ledger, uint64_t* counters);
 
 /* ------------------------------------------------------------------------
