@@ -170,7 +170,10 @@ def ceilings(N, torch, dose, cnt, value, hist_per_step):
     bounds = {"hbm": copy_gbs * 1e9 / bytes_h, "atomic": atomic_rate / atoms_h,
               "valu": PEAK_FP32_TFLOPS * 1e12 / flop_h}
     binding = min(bounds, key=bounds.get)
+    step_s = hist_per_step / value
     return {"hbm_copy_GBs": copy_gbs, "atomic_adds_per_s": atomic_rate,
+            "achieved_atomic_adds_per_s": cnt["deposits"] / step_s,
+            "achieved_algorithmic_GBs": bytes_h * hist_per_step / step_s / 1e9,
             "bytes_per_history": bytes_h, "atomics_per_history": atoms_h,
             "flop_per_history": flop_h, "bound_histories_per_s": bounds, "binding": binding,
             "frac_of_binding": value / bounds[binding]}
