@@ -104,3 +104,108 @@ def test_full_size_sampled_histories_match_oracle(full, eng, orc, N):
         assert cnt["e_pushed"] == pytest.approx(cnt_ref["e_pushed"], rel=3e-3, abs=5)
         assert cnt["e_steps"] == pytest.approx(cnt_ref["e_steps"], rel=3e-3)
     assert seen == {0, 1, 2}
+
+
+def _sampled_ranges_match(eng, orc, N, W, plan, ph, prm, replica, n=20000, max_batch=1 << 22,
+                          band_width=24, tally_kw=None):
+    """sample_batch + transport_batch over n consecutive histories in the middle
+    of one batch of each sub-source, against the oracle on the same histories."""
+    import torch
+    tally_kw = tally_kw or {}
+    ref_w, _ = orc.psl_build(W.model)
+    op = orc.plan_build(W.model, ref_w, W.beams, plan.n_hist, **tally_kw.get("plan_kw", {}))
+    nb = plan.set_batching(max_batch, band_width)
+    seen = set()
+    for i in range(nb):
+        b = plan.batch(i)
+        if b.stype in seen or b.n < 4 * n:
+            continue
+        seen.add(b.stype)
+        h0 = b.h0 + b.n // 2
+        print(f"[fullsize] {W.name}: stype {b.stype} beam {b.beam} h [{h0}, {h0 + n}) replica "
+              f"{replica}", flush=True)
+        tally = eng.Tally(ph, **tally_kw.get("tally_kw", {}))
+        stack = eng.Particles(n)
+        el = eng.Particles(eng.electron_capacity(n, plan.info.e_max, prm.e_cut_electron))
+        stack.zero_count()
+        N.sample_batch(plan.h, ph.h, replica, h0, n, W.seed, stack.c, 0, tally.h, 0)
+        N.transport_batch(ph.h, stack.c, el.c, tally.h, prm, W.seed, 0)
+        torch.cuda.synchronize()
+        led, cnt = tally.stats()
+        _, _, led_ref, cnt_ref = orc.run(W.model, op, W.beams, W.phantom, W.seed, 1, h0, h0 + n,
+                                         rep0=replica, **tally_kw.get("run_kw", {}))
+        assert cnt["hist"] == cnt_ref["hist"] == n
+        assert led["src"] == pytest.approx(led_ref["src"], rel=1e-6)
+        assert cnt["entered"] == pytest.approx(cnt_ref["entered"], rel=1e-3, abs=2)
+        assert led["dep"] == pytest.approx(led_ref["dep"], rel=3e-3)
+        assert cnt["e_pushed"] == pytest.approx(cnt_ref["e_pushed"], rel=3e-3, abs=5)
+    return seen
+
+
+def test_heterogeneous_five_beams_full_size(eng, orc, wl, N):
+    """256 x 128 x 256 heterogeneous phantom, five fields, 2e8 histories in
+    the benchmark's launch configuration: the energy ledger closes, every
+    history is counted, and sampled histories of every sub-source agree with
+    the oracle."""
+    import torch
+    W = wl.workload("hetero256_5beam")
+    model = eng.Model(W.model)
+    per = W.n_hist // W.n_replica
+    plan = eng.Plan(model, W.beams, per, n_replica=W.n_replica)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    prm = eng.transport_params()
+    print("[fullsize] hetero256_5beam, 2e8 histories, graph replay, two pipelines", flush=True)
+    eng.run_plan(plan, ph, tally, prm, eng.run_opts(use_graph=True, seed=W.seed, **OPTS))
+    d, s = tally.finalize(plan)
+    torch.cuda.synchronize()
+    led, cnt = tally.stats()
+    assert cnt["hist"] == W.n_hist and cnt["folds"] == W.n_replica
+    assert cnt["overflow"] == 0 and cnt["guard"] == 0
+    assert abs(led["src"] - sum(led[k] for k in LEDGER_OUT)) / led["src"] < 1e-9
+    # heterogeneous: fictitious Woodcock steps exist
+    assert cnt["real"] < cnt["wc_steps"]
+    d = d.cpu().numpy()
+    assert np.isfinite(d).all() and (d >= 0).all() and d.max() > 0
+    seen = _sampled_ranges_match(eng, orc, N, W, plan, ph, prm, replica=4)
+    assert seen == {0, 1, 2}
+
+
+def test_commissioning_full_size(eng, orc, wl, N):
+    """The commissioning plan at 1e6 histories per (field, basis) (2.47e9
+    histories) in one replayed graph through the index-map tally: the ledger
+    closes, every basis column that holds histories receives dose, and sampled
+    ranges of the stratified plan agree with the oracle."""
+    import torch
+    W = wl.workload("commission60")
+    imap, n_rows = W.extra["index_map"], W.extra["n_rows"]
+    bmap = W.extra["basis_map"]
+    n_cols = len(W.beams) * W.extra["n_basis"]
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, 0, n_replica=1, basis_map=bmap,
+                    hist_per_basis=W.extra["hist_per_basis"])
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph, index_map=imap, n_rows=n_rows, n_cols=n_cols)
+    prm = eng.transport_params()
+    print(f"[fullsize] commission60, {plan.n_hist} histories, one graph", flush=True)
+    eng.run_plan(plan, ph, tally, prm, eng.run_opts(1 << 20, 24, use_graph=True,
+                                                    sort_electrons=False, seed=W.seed))
+    A, _ = tally.finalize(plan)
+    torch.cuda.synchronize()
+    led, cnt = tally.stats()
+    assert cnt["hist"] == plan.n_hist and cnt["overflow"] == 0 and cnt["guard"] == 0
+    assert abs(led["src"] - sum(led[k] for k in LEDGER_OUT)) / led["src"] < 1e-9
+    A = A.cpu().numpy()
+    col_w = plan.col_weight()
+    used = col_w > 0
+    # columns without histories receive nothing; of those with histories,
+    # the ones whose particles all miss the tallied voxels (jaw-rejected
+    # outer rings of the small fields) stay empty too
+    assert np.all(A[:, ~used] == 0)
+    assert (A[:, used].sum(axis=0) > 0).mean() > 0.5
+    seen = _sampled_ranges_match(
+        eng, orc, N, W, plan, ph, prm, replica=0, max_batch=1 << 20,
+        tally_kw=dict(plan_kw=dict(basis_map=bmap, hist_per_basis=W.extra["hist_per_basis"]),
+                      tally_kw=dict(index_map=imap, n_rows=n_rows, n_cols=n_cols),
+                      run_kw=dict(index_map=imap, n_rows=n_rows, n_cols=n_cols)))
+    assert seen == {0, 1, 2}
