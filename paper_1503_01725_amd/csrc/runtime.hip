@@ -169,7 +169,7 @@ int n_pipes_of(const psl_run_opts& o, const psl_plan* plan) {
 
 // Enqueues all launches of replicas [rep0, rep0 + n_rep) on stream s; with
 // several pipelines the batches of each replica fork onto the pipelines' streams
-// and join back on s before the replica's fold (batch i on pipeline i mod n).
+// and join back on s before the replica's fold.
 void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
              const psl_transport_params* prm, const psl_run_opts& o, uint32_t rep0, uint32_t n_rep,
              hipStream_t s) {
@@ -177,6 +177,25 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     const int np = n_pipes_of(o, plan);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, rep, rep0);
     const size_t nb = plan->batches.size();
+    // Batches to pipelines, largest first onto the least loaded one (cost ~
+    // histories), so that the pipelines finish a replica together; the two
+    // largest batches land on different pipelines, so none is left empty.
+    std::vector<int> pipe_of(nb, 0);
+    if (np > 1) {
+        std::vector<size_t> order(nb);
+        for (size_t i = 0; i < nb; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            return plan->batches[x].n > plan->batches[y].n;
+        });
+        std::array<uint64_t, kMaxPipes> load{};
+        for (size_t i : order) {
+            int best = 0;
+            for (int p = 1; p < np; ++p)
+                if (load[p] < load[best]) best = p;
+            pipe_of[i] = best;
+            load[best] += plan->batches[i].n;
+        }
+    }
     for (uint32_t r = 0; r < n_rep; ++r) {
         if (np > 1) {
             PSL_HIP(hipEventRecord(R.fork, s));
@@ -184,7 +203,7 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
         }
         for (size_t i = 0; i < nb; ++i) {
             const psl_batch& b = plan->batches[i];
-            Pipe& P = R.pipes[i % np];
+            Pipe& P = R.pipes[pipe_of[i]];
             hipStream_t q = np > 1 ? P.st : s;
             P.phs.ptype = b.stype == 2 ? 1 : 0;
             int ts = -1;
