@@ -91,6 +91,10 @@ struct DevBuf {
 // counters / offsets of the electron energy sort and the electron order.
 constexpr int kSortBands = 32;      // electron energy bands of the counting sort
 constexpr int kSortBlocks = 1024;   // fixed grid of the counting sort
+// Histories per entry of a plan's chunk index (the sampling kernel's search
+// starts from it).
+constexpr int kChunkShift = 10;
+
 struct TransportWs {
     uint32_t* queues = nullptr;     // [64]
     uint32_t* bands = nullptr;      // [2 * kSortBands * kSortBlocks]
@@ -205,6 +209,9 @@ struct psl_plan {
     // device copies, uploaded on first use (set-up itself needs no GPU)
     mutable psl::DevBuf d_list;        // PslEntry [n_list]
     mutable psl::DevBuf d_cum;         // uint64 [n_list]
+    // uint32 [(n_hist >> kChunkShift) + 2]: entry c = first list index whose
+    // inclusive count prefix exceeds c << kChunkShift (n_list past the end)
+    mutable psl::DevBuf d_chunk;
     mutable psl::DevBuf d_beams;       // BeamDev [n_beams]
 };
 

@@ -136,6 +136,20 @@ void ensure_device(const psl_plan* p) {
     ensure_device(p->model);
     if (!p->d_list.p) p->d_list.upload(p->list_host);
     if (!p->d_cum.p) p->d_cum.upload(p->cum);
+    if (!p->d_chunk.p) {
+        // one merge pass over the prefix: entry c is the first j with
+        // cum[j] > c * 2^kChunkShift
+        const uint64_t n_chunk = (p->n_hist >> kChunkShift) + 2;
+        PSL_CHECK(p->cum.size() < (size_t(1) << 32), "plan list too long for the chunk index");
+        std::vector<uint32_t> chunk(n_chunk);
+        size_t j = 0;
+        for (uint64_t c = 0; c < n_chunk; ++c) {
+            const uint64_t h = c << kChunkShift;
+            while (j < p->cum.size() && !(p->cum[j] > h)) ++j;
+            chunk[c] = uint32_t(j);
+        }
+        p->d_chunk.upload(chunk);
+    }
     if (!p->d_beams.p) p->d_beams.upload(p->beams_host);
 }
 

@@ -9,6 +9,7 @@ namespace {
 struct SampleArgs {
     const PslEntry* list;
     const uint64_t* cum;
+    const uint32_t* chunk;       // chunk index of the count prefix (see psl_plan)
     int64_t jlo, jhi;            // list range holding the batch's histories
     uint64_t h0, n_hist;
     uint32_t n, rep;
@@ -51,13 +52,18 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     // The block's histories are consecutive, so their PSLs lie between the
     // PSLs of its first and last history: two threads locate those, then every
     // thread searches only that short range (cached) instead of the whole list.
+    // The two searches start from the chunk index, which brackets the answer
+    // for any h by the entries of h's chunk and of the next one.
     __shared__ int64_t s_range[2];
     {
         const uint32_t first = blockIdx.x * blockDim.x;
         const uint32_t last = min(first + blockDim.x, a.n) - 1u;
-        if (threadIdx.x == 0) s_range[0] = upper_bound(a.cum, a.jlo, a.jhi, a.h0 + first);
+        const uint64_t hf = a.h0 + first, hl = a.h0 + last;
+        const int64_t lo = max(a.jlo, int64_t(a.chunk[hf >> kChunkShift]));
+        const int64_t hi = min(a.jhi, int64_t(a.chunk[(hl >> kChunkShift) + 1]) + 1);
+        if (threadIdx.x == 0) s_range[0] = upper_bound(a.cum, lo, hi, hf);
         if (threadIdx.x == 64 || (blockDim.x <= 64 && threadIdx.x == 0))
-            s_range[1] = upper_bound(a.cum, a.jlo, a.jhi, a.h0 + last) + 1;
+            s_range[1] = upper_bound(a.cum, lo, hi, hl) + 1;
     }
     __syncthreads();
     const int64_t jb0 = s_range[0], jb1 = s_range[1];
@@ -234,6 +240,7 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
     SampleArgs a{};
     a.list = plan->d_list.as<PslEntry>();
     a.cum = plan->d_cum.as<uint64_t>();
+    a.chunk = plan->d_chunk.as<uint32_t>();
     a.jlo = jlo;
     a.jhi = jhi;
     a.h0 = h0;
