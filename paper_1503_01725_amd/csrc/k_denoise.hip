@@ -327,6 +327,100 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             }
 }
 
+// Direct 3x3x3 convolution (forward, or input gradient as the forward
+// convolution of the output gradient with the flipped packed weights) for
+// bricks of 4 x 8 x 8 output positions and NT output channels.  The input
+// brick with its one-voxel halo (6 x 10 x 10 positions) is staged in LDS one
+// 32-channel chunk at a time and read by all 27 taps, instead of gathering
+// every tap's operand from global memory; the weights (packed [N][27 C],
+// small and shared by all workgroups) are read from the caches.  Wave w
+// computes the 64 positions of brick layer w: four row groups of 16
+// positions (two x-rows of 8) by NT / 16 column groups.
+constexpr int kDZ = 4, kDY = 8, kDX = 8;
+constexpr int kHZ = kDZ + 2, kHY = kDY + 2, kHX = kDX + 2;
+constexpr int kHalo = kHZ * kHY * kHX;     // 600 positions
+constexpr int kCC = 32;                    // input channels per staged chunk
+
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256) k_conv_direct(GemmArgs g) {
+    static_assert(NT == 32 || NT == 64, "32 or 64 output channels per workgroup");
+    constexpr int NJ = NT / 16;
+    __shared__ uint16_t halo[kHalo][kCC + 8];
+    const View& v = g.a;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int bx_n = v.W / kDX, by_n = v.H / kDY;
+    const int b = blockIdx.x;
+    const int bx = b % bx_n, by = (b / bx_n) % by_n, bz = b / (bx_n * by_n);
+    const int z0 = bz * kDZ - 1, y0 = by * kDY - 1, x0 = bx * kDX - 1;
+    const int n0 = blockIdx.y * NT;
+    const int C = v.C;
+    floatx4 acc[4][NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int r = lane & 15, kg = (lane >> 4) << 3;
+    // halo coordinates of this lane's row in row group i at tap (0, 0, 0)
+    const int base_q = ((w + 1) * kHY + 1) * kHX + 1 + (r & 7);
+    for (int c0 = 0; c0 < C; c0 += kCC) {
+        // stage the halo brick of channels [c0, c0 + 32): item = (position, 8 channels)
+        for (int it = t; it < kHalo * (kCC / 8); it += 256) {
+            const int hq = it >> 2, cc = (it & 3) << 3;
+            const int hx = hq % kHX, hy = (hq / kHX) % kHY, hz = hq / (kHX * kHY);
+            const int z = z0 + hz, y = y0 + hy, x = x0 + hx;
+            uint4 val = {0u, 0u, 0u, 0u};
+            if (z >= 0 && z < v.D && y >= 0 && y < v.H && x >= 0 && x < v.W)
+                val = load8(v, (z * v.H + y) * v.W + x, c0 + cc);
+            *reinterpret_cast<uint4*>(&halo[hq][cc]) = val;
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int tq = (dz * kHY + dy) * kHX + dx;
+            bf16x8 bop[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const uint4 braw = *reinterpret_cast<const uint4*>(
+                    g.wt + size_t(n0 + 16 * j + r) * g.K + tap * C + c0 + kg);
+                bop[j] = __builtin_bit_cast(bf16x8, braw);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // row group i: x-rows 2i (lanes r < 8) and 2i + 1 (r >= 8)
+                const int q = base_q + (2 * i + (r >> 3)) * kHX + tq;
+                const uint4 araw = *reinterpret_cast<const uint4*>(&halo[q][kg]);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bop[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16 tile
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 4 * (lane >> 4) + e;           // 0..15 within row group i
+                const int z = bz * kDZ + w, y = by * kDY + 2 * i + (row >> 3),
+                          x = bx * kDX + (row & 7);
+                const int m = (z * v.H + y) * v.W + x;
+                const int n = n0 + 16 * j + (lane & 15);
+                float val = acc[i][j][e];
+                if (MODE == kConvFwd) {
+                    val += g.bias[n];
+                    if (g.relu) val = fmaxf(val, 0.f);
+                } else if (g.mask.p &&
+                           !(bf2f(g.mask.p[size_t(m) * g.mask.stride + g.mask.off + n]) > 0.f)) {
+                    val = 0.f;
+                }
+                g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(val);
+            }
+}
+
 // Sum of the split-K partials of a weight gradient, written in the reference
 // layout: conv (MODE kConvWgrad) row m = output channel, column n = tap *
 // C_in_padded + c; transposed conv: row m = input channel, column n =
@@ -637,6 +731,28 @@ void gemm_launch(int mode, const GemmArgs& g0, hipStream_t s, int splits = 1) {
     PSL_HIP(hipGetLastError());
 }
 
+// Convolution GEMM (forward or input gradient): the direct brick kernel
+// where the grid and the channels fit its tiles, else the implicit GEMM.
+void conv_launch(int mode, const GemmArgs& g, hipStream_t s) {
+    const View& v = g.a;
+    const bool direct = v.D % kDZ == 0 && v.H % kDY == 0 && v.W % kDX == 0 && v.C % kCC == 0 &&
+                        g.K == 27 * v.C && g.N % 32 == 0 && int64_t(v.D) * v.H * v.W == g.M;
+    if (!direct) {
+        gemm_launch(mode, g, s);
+        return;
+    }
+    const int nt = g.N % 64 == 0 ? 64 : 32;
+    dim3 grid((v.D / kDZ) * (v.H / kDY) * (v.W / kDX), g.N / nt);
+    if (mode == kConvFwd) {
+        if (nt == 64) hipLaunchKernelGGL((k_conv_direct<kConvFwd, 64>), grid, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_conv_direct<kConvFwd, 32>), grid, dim3(256), 0, s, g);
+    } else {
+        if (nt == 64) hipLaunchKernelGGL((k_conv_direct<kConvBwdData, 64>), grid, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_conv_direct<kConvBwdData, 32>), grid, dim3(256), 0, s, g);
+    }
+    PSL_HIP(hipGetLastError());
+}
+
 // forward conv: in (cin_pad channels view) -> out view, bias, ReLU
 void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t s) {
     GemmArgs g{};
@@ -650,7 +766,7 @@ void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     g.cin = L.cin;
     g.cout = L.cout;
     g.relu = 1;
-    gemm_launch(kConvFwd, g, s);
+    conv_launch(kConvFwd, g, s);
 }
 
 // bias gradient over P positions: enough blocks that every thread sums a
@@ -737,7 +853,7 @@ void conv_bwd(const UNet& u, const UNet::Conv& L, View in, View gz, View* gin, h
         d.K = 27 * L.cout;
         d.cin = L.cin;
         d.cout = L.cout;
-        gemm_launch(kConvBwdData, d, s);
+        conv_launch(kConvBwdData, d, s);
     }
 }
 
@@ -886,7 +1002,7 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
             d.K = 27 * C;
             d.cin = 2 * C;
             d.cout = C;
-            gemm_launch(kConvBwdData, d, s);
+            conv_launch(kConvBwdData, d, s);
         }
         // tconv backward: weights, bias, gradient at its input (masked by the
         // lower level's ReLU output)
