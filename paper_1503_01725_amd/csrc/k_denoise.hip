@@ -421,6 +421,126 @@ __global__ void __launch_bounds__(256) k_conv_direct(GemmArgs g) {
             }
 }
 
+// Weight gradient of a 3x3x3 convolution by the same bricks:
+// gW[o][tap][c] = sum over positions p of gz[p][o] * x[p + tap][c], with the
+// positions as the GEMM's K.  A workgroup takes 32 output channels, 32 input
+// channels and all 27 taps (a 32 x 864 tile of the [M][27 C] gradient) over a
+// run of bricks, and writes its partial sum for k_wgrad_reduce.  Each input
+// value is staged once per brick (with the halo, 600 / 256 times) instead of
+// being gathered once per tap.  Both MFMA operands need 8 consecutive
+// positions per lane, so the channels-last data is transposed while staged:
+// the brick's gz as [x-row][o] -> 8 x values, the input with its halo as three
+// copies [halo row][c] -> 8 x values shifted by dx = -1, 0, +1, so that every
+// LDS read stays 16-byte aligned.  v_mfma_f32_32x32x16_bf16: one K step is two
+// x-rows of 8 (lanes 0-31 the first, 32-63 the second); wave w owns taps
+// 7w .. 7w + 6 (wave 3 six of them) and reuses its gz operand for each.
+constexpr int kWRows = kDZ * kDY;          // x-rows of 8 positions per brick
+constexpr int kHRows = kHZ * kHY;          // x-rows of 10 in the halo brick
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Column of element (row, col) in a [row][32] array of 16-byte entries: bits
+// 0-2 of col are XORed with a function of the row and of col's bit 4, so that
+// the 16 lanes of one staging write (4 rows x 4 channel groups) fall on 16
+// distinct entries modulo 16; a row keeps all its 32 entries.
+__device__ __forceinline__ int swz(int row, int col) { return col ^ ((row & 3) | ((col >> 2) & 4)); }
+
+// Channel j of 8 consecutive positions v[0..7] (8 channels each), packed.
+__device__ __forceinline__ uint4 transpose_channel(const uint4* v, int j) {
+    const uint32_t sel = (j & 1) ? 0x07060302u : 0x05040100u;
+    uint32_t out[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t* lo = reinterpret_cast<const uint32_t*>(&v[2 * k]);
+        const uint32_t* hi = reinterpret_cast<const uint32_t*>(&v[2 * k + 1]);
+        out[k] = __builtin_amdgcn_perm(hi[j >> 1], lo[j >> 1], sel);
+    }
+    return uint4{out[0], out[1], out[2], out[3]};
+}
+
+__global__ void __launch_bounds__(256) k_conv_wgrad_direct(GemmArgs g, int bricks_per_split) {
+    __shared__ uint4 gzT[kWRows][32];        // 16 KB
+    __shared__ uint4 xT[3][kHRows][32];      // 90 KB
+    const View& v = g.a;
+    const View& gz = g.b;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int bx_n = v.W / kDX, by_n = v.H / kDY;
+    const int nbricks = bx_n * by_n * (v.D / kDZ);
+    const int o0 = blockIdx.y * 32, c0 = blockIdx.z * 32;
+    const int b_lo = blockIdx.x * bricks_per_split;
+    const int b_hi = min(nbricks, b_lo + bricks_per_split);
+    const int tap0 = 7 * w, ntap = w == 3 ? 6 : 7;
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    floatx16 acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
+
+    for (int b = b_lo; b < b_hi; ++b) {
+        const int bx = b % bx_n, by = (b / bx_n) % by_n, bz = b / (bx_n * by_n);
+        for (int it = t; it < (kHRows + kWRows) * 4; it += 256) {
+            if (it < kHRows * 4) {
+                // input: halo row hr, channels c0 + cg .. + 7, all 10 x
+                const int hr = it >> 2, cg = (it & 3) << 3;
+                const int z = bz * kDZ - 1 + hr / kHY, y = by * kDY - 1 + hr % kHY;
+                const bool row_in = z >= 0 && z < v.D && y >= 0 && y < v.H;
+                uint4 val[kHX];
+#pragma unroll
+                for (int hx = 0; hx < kHX; ++hx) {
+                    const int x = bx * kDX - 1 + hx;
+                    val[hx] = row_in && x >= 0 && x < v.W ? load8(v, (z * v.H + y) * v.W + x, c0 + cg)
+                                                          : zero;
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) xT[d][hr][swz(hr, cg + j)] = transpose_channel(val + d, j);
+            } else {
+                // output gradient: brick x-row r, channels o0 + og .. + 7
+                const int k = it - kHRows * 4;
+                const int r = k >> 2, og = (k & 3) << 3;
+                const int z = bz * kDZ + r / kDY, y = by * kDY + r % kDY;
+                uint4 val[kDX];
+#pragma unroll
+                for (int i = 0; i < kDX; ++i) val[i] = load8(gz, (z * gz.H + y) * gz.W + bx * kDX + i, o0 + og);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) gzT[r][swz(r, og + j)] = transpose_channel(val, j);
+            }
+        }
+        __syncthreads();
+        const int col = lane & 31;
+#pragma unroll 2
+        for (int ks = 0; ks < kWRows / 2; ++ks) {
+            const int row = 2 * ks + (lane >> 5);
+            const int rz = row / kDY, ry = row % kDY;
+            const bf16x8 a = __builtin_bit_cast(bf16x8, gzT[row][swz(row, col)]);
+#pragma unroll
+            for (int tt = 0; tt < 7; ++tt) {
+                if (tt < ntap) {
+                    const int tap = tap0 + tt;
+                    const int hr = (rz + tap / 9) * kHY + ry + (tap / 3) % 3;
+                    const bf16x8 bop = __builtin_bit_cast(bf16x8, xT[tap % 3][hr][swz(hr, col)]);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop, acc[tt], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // lane holds column lane % 32 and rows 8 (e / 4) + 4 (lane / 32) + e % 4
+    float* out = g.partial + size_t(blockIdx.x) * g.M * g.N;
+#pragma unroll
+    for (int tt = 0; tt < 7; ++tt) {
+        if (tt >= ntap) continue;
+        const int n = (tap0 + tt) * v.C + c0 + (lane & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int m = o0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+            out[size_t(m) * g.N + n] = acc[tt][e];
+        }
+    }
+}
+
 // Sum of the split-K partials of a weight gradient, written in the reference
 // layout: conv (MODE kConvWgrad) row m = output channel, column n = tap *
 // C_in_padded + c; transposed conv: row m = input channel, column n =
@@ -786,16 +906,50 @@ int wgrad_splits(int64_t positions, int M, int N) {
     return int(std::max<int64_t>(1, std::min<int64_t>(positions / 1024, by_grid)));
 }
 
+// Direct (brick) weight gradient of a convolution: the grid divides into
+// bricks, and the input channels (c_pad) and output channels (M) into 32s.
+bool wgrad_direct(int D, int H, int W, int c_pad, int M) {
+    return D % kDZ == 0 && H % kDY == 0 && W % kDX == 0 && c_pad % 32 == 0 && M % 32 == 0;
+}
+
+// Bricks per workgroup of the direct weight gradient: about 512 workgroups
+// in all (two rounds of one per CU; each takes 106 KB of LDS), at least 4
+// bricks each.
+int direct_bricks_per_split(int D, int H, int W, int c_pad, int M) {
+    const int64_t bricks = int64_t(D / kDZ) * (H / kDY) * (W / kDX);
+    const int64_t tiles = int64_t(M / 32) * (c_pad / 32);
+    const int64_t splits = std::max<int64_t>(1, std::min<int64_t>(bricks / 4, 512 / tiles));
+    return int((bricks + splits - 1) / splits);
+}
+
+int64_t direct_splits(int D, int H, int W, int c_pad, int M) {
+    const int64_t bricks = int64_t(D / kDZ) * (H / kDY) * (W / kDX);
+    const int per = direct_bricks_per_split(D, H, W, c_pad, M);
+    return (bricks + per - 1) / per;
+}
+
 // Weight-gradient GEMM with split-K into the partial buffer, then the
 // reduction into the gradient array.
 void wgrad_launch(int mode, GemmArgs g, int64_t positions, int c_pad, const UNet& u,
                   hipStream_t s) {
-    const int splits0 = wgrad_splits(positions, g.M, g.N);
-    g.k_per_split = int(((positions + splits0 - 1) / splits0 + kKT - 1) / kKT * kKT);
-    const int splits = int((positions + g.k_per_split - 1) / g.k_per_split);
-    PSL_CHECK(u.wpart.bytes >= size_t(splits) * g.M * g.N * 4, "weight-gradient scratch too small");
     g.partial = u.wpart.as<float>();
-    gemm_launch(mode, g, s, splits);
+    int splits = 0;
+    const View& v = g.a;
+    if (mode == kConvWgrad && wgrad_direct(v.D, v.H, v.W, c_pad, g.M)) {
+        PSL_CHECK(v.C == c_pad && g.b.C == g.M && g.N == 27 * c_pad, "direct weight-gradient shapes");
+        const int per = direct_bricks_per_split(v.D, v.H, v.W, c_pad, g.M);
+        splits = int(direct_splits(v.D, v.H, v.W, c_pad, g.M));
+        PSL_CHECK(u.wpart.bytes >= size_t(splits) * g.M * g.N * 4, "weight-gradient scratch too small");
+        hipLaunchKernelGGL(k_conv_wgrad_direct, dim3(splits, g.M / 32, c_pad / 32), dim3(256), 0, s,
+                           g, per);
+        PSL_HIP(hipGetLastError());
+    } else {
+        const int splits0 = wgrad_splits(positions, g.M, g.N);
+        g.k_per_split = int(((positions + splits0 - 1) / splits0 + kKT - 1) / kKT * kKT);
+        splits = int((positions + g.k_per_split - 1) / g.k_per_split);
+        PSL_CHECK(u.wpart.bytes >= size_t(splits) * g.M * g.N * 4, "weight-gradient scratch too small");
+        gemm_launch(mode, g, s, splits);
+    }
     const int64_t total = int64_t(g.M) * g.N;
     const int blocks = int(std::min<int64_t>((total + 255) / 256, 2048));
     if (mode == kConvWgrad)
@@ -813,13 +967,20 @@ size_t wpart_floats(const UNet& u) {
     auto need = [&](int64_t positions, int M, int N) {
         most = std::max(most, size_t(wgrad_splits(positions, M, N)) * M * N);
     };
+    auto conv = [&](int k, const UNet::Conv& L) {
+        const int* d = u.dims[k];
+        need(u.P(k), L.cout, 27 * L.cin_pad);
+        if (wgrad_direct(d[0], d[1], d[2], L.cin_pad, L.cout))
+            most = std::max(most, size_t(direct_splits(d[0], d[1], d[2], L.cin_pad, L.cout)) *
+                                      L.cout * 27 * L.cin_pad);
+    };
     for (int k = 0; k < kLevels; ++k) {
-        need(u.P(k), u.enc_a[k].cout, 27 * u.enc_a[k].cin_pad);
-        need(u.P(k), u.enc_b[k].cout, 27 * u.enc_b[k].cin_pad);
+        conv(k, u.enc_a[k]);
+        conv(k, u.enc_b[k]);
     }
     for (int k = 0; k < kLevels - 1; ++k) {
-        need(u.P(k), u.dec_a[k].cout, 27 * u.dec_a[k].cin_pad);
-        need(u.P(k), u.dec_b[k].cout, 27 * u.dec_b[k].cin_pad);
+        conv(k, u.dec_a[k]);
+        conv(k, u.dec_b[k]);
         need(u.P(k + 1), u.ch(k + 1), 8 * u.ch(k));
     }
     return most;
