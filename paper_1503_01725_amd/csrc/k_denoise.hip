@@ -327,89 +327,176 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             }
 }
 
-// Direct 3x3x3 convolution (forward, or input gradient as the forward
-// convolution of the output gradient with the flipped packed weights) for
-// bricks of 4 x 8 x 8 output positions and NT output channels.  The input
-// brick with its one-voxel halo (6 x 10 x 10 positions) is staged in LDS one
-// 32-channel chunk at a time and read by all 27 taps, instead of gathering
-// every tap's operand from global memory; the weights (packed [N][27 C],
-// small and shared by all workgroups) are read from the caches.  Wave w
-// computes the 64 positions of brick layer w: four row groups of 16
-// positions (two x-rows of 8) by NT / 16 column groups.
+// Bricks of the direct weight-gradient kernel: 4 x 8 x 8 positions.
 constexpr int kDZ = 4, kDY = 8, kDX = 8;
 constexpr int kHZ = kDZ + 2, kHY = kDY + 2, kHX = kDX + 2;
-constexpr int kHalo = kHZ * kHY * kHX;     // 600 positions
 constexpr int kCC = 32;                    // input channels per staged chunk
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Direct 3x3x3 convolution (forward, or input gradient as the forward
+// convolution of the output gradient with the flipped packed weights) for
+// bricks of 8 x 8 x 8 output positions and NT output channels.  The input
+// brick with its one-voxel halo (10^3 positions) is staged in LDS one
+// 32-channel chunk at a time and read by all 27 taps, instead of gathering
+// every tap's operand from global memory.  v_mfma_f32_32x32x16_bf16: wave w
+// computes brick layers w and w + 4 as four row tiles of 32 positions by
+// NT / 32 column tiles, so that each weight operand (packed [N][27 C], read
+// from the caches one tap ahead of its use) serves four MFMAs.  LDS bank
+// conflicts, measured on gfx950: a 16-byte read serves 32 lanes at a time
+// from 512 bytes of banks, a 16-byte write 8 lanes from 128 bytes.  With the
+// 80-byte position pitch, the x-rows of a row tile lie 0, 8, 16 and 24
+// (mod 32) positions apart, so the 32 lanes of a read hit distinct banks; a
+// staging write covers 8 consecutive positions of one channel group.
+constexpr int kFB = 8;                          // brick edge
+constexpr int kFH = kFB + 2;                    // halo edge
+constexpr int kFHalo = kFH * kFH * kFH;         // 1000 positions
+constexpr int kFPitch = kCC + 8;                // BF16 per staged position
+
+// (z, y, x) within the brick of row `row` of row tile i of wave w: the four
+// x-rows (w, i), (w, i + 4), (w + 4, i), (w + 4, i + 4), 0, 40, 400 and 440
+// halo positions apart
+__device__ __forceinline__ void tile_pos(int w, int i, int row, int& z, int& y, int& x) {
+    z = w + 4 * (row >> 4);
+    y = i + 4 * ((row >> 3) & 1);
+    x = row & 7;
+}
+
 template <int MODE, int NT>
-__global__ void __launch_bounds__(256) k_conv_direct(GemmArgs g) {
+__global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
     static_assert(NT == 32 || NT == 64, "32 or 64 output channels per workgroup");
-    constexpr int NJ = NT / 16;
-    __shared__ uint16_t halo[kHalo][kCC + 8];
+    constexpr int NJ = NT / 32;
+    __shared__ uint16_t halo[kFHalo * kFPitch];
     const View& v = g.a;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int bx_n = v.W / kDX, by_n = v.H / kDY;
+    const int bx_n = v.W / kFB, by_n = v.H / kFB;
     const int b = blockIdx.x;
     const int bx = b % bx_n, by = (b / bx_n) % by_n, bz = b / (bx_n * by_n);
-    const int z0 = bz * kDZ - 1, y0 = by * kDY - 1, x0 = bx * kDX - 1;
     const int n0 = blockIdx.y * NT;
     const int C = v.C;
-    floatx4 acc[4][NJ];
+    // independent accumulation chains: a 32x32x16 MFMA's result is not
+    // ready for a dependent MFMA until several others have issued, so with
+    // one column tile the even and odd K steps accumulate separately (eight
+    // chains per wave either way), summed in the epilogue
+    constexpr int KS = NJ == 1 ? 2 : 1;
+    floatx16 acc[4][NJ * KS];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int r = lane & 15, kg = (lane >> 4) << 3;
-    // halo coordinates of this lane's row in row group i at tap (0, 0, 0)
-    const int base_q = ((w + 1) * kHY + 1) * kHX + 1 + (r & 7);
-    for (int c0 = 0; c0 < C; c0 += kCC) {
-        // stage the halo brick of channels [c0, c0 + 32): item = (position, 8 channels)
-        for (int it = t; it < kHalo * (kCC / 8); it += 256) {
-            const int hq = it >> 2, cc = (it & 3) << 3;
-            const int hx = hq % kHX, hy = (hq / kHX) % kHY, hz = hq / (kHX * kHY);
-            const int z = z0 + hz, y = y0 + hy, x = x0 + hx;
-            uint4 val = {0u, 0u, 0u, 0u};
-            if (z >= 0 && z < v.D && y >= 0 && y < v.H && x >= 0 && x < v.W)
-                val = load8(v, (z * v.H + y) * v.W + x, c0 + cc);
-            *reinterpret_cast<uint4*>(&halo[hq][cc]) = val;
-        }
-        __syncthreads();
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int tq = (dz * kHY + dy) * kHX + dx;
-            bf16x8 bop[NJ];
+        for (int j = 0; j < NJ * KS; ++j)
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const uint4 braw = *reinterpret_cast<const uint4*>(
-                    g.wt + size_t(n0 + 16 * j + r) * g.K + tap * C + c0 + kg);
-                bop[j] = __builtin_bit_cast(bf16x8, braw);
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+    const int r = lane & 31, kc = (lane >> 5) << 3;
+    int qrow[4];   // halo position of this lane's row of tile i, centre tap
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int z, y, x;
+        tile_pos(w, i, r, z, y, x);
+        qrow[i] = ((z + 1) * kFH + y + 1) * kFH + x + 1;
+    }
+    const uint16_t* wrow[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) wrow[j] = g.wt + size_t(n0 + 32 * j + r) * g.K + kc;
+
+    for (int c0 = 0; c0 < C; c0 += kCC) {
+        // stage the halo brick of channels [c0, c0 + 32): item = (position, 8
+        // channels), 8 consecutive positions per channel group.  A batch of
+        // loads is issued before its first LDS write (addresses clamped into
+        // the grid, outside values zeroed as they are written, so that no
+        // branch separates the loads), which costs one memory latency per
+        // batch instead of one per item.  The empty asm keeps the compiler
+        // from holding every item's address across the chunk loop (registers
+        // the accumulators need).
+        constexpr int kItems = kFHalo * (kCC / 8), kPer = (kItems + 255) / 256;
+        constexpr int kBatch = kPer / 4;
+#pragma unroll
+        for (int k0 = 0; k0 < kPer; k0 += kBatch) {
+            uint4 stg[kBatch];
+            uint32_t outside = 0u;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                int it = min(t + 256 * (k0 + k), kItems - 1);
+                asm volatile("" : "+v"(it));
+                const int q = ((it >> 5) << 3) + (it & 7), cg = ((it >> 3) & 3) << 3;
+                const int hz = q / (kFH * kFH), hy = (q / kFH) % kFH, hx = q % kFH;
+                const int z = bz * kFB - 1 + hz, y = by * kFB - 1 + hy, x = bx * kFB - 1 + hx;
+                const int zc = min(max(z, 0), v.D - 1), yc = min(max(y, 0), v.H - 1),
+                          xc = min(max(x, 0), v.W - 1);
+                stg[k] = load8(v, (zc * v.H + yc) * v.W + xc, c0 + cg);
+                outside |= uint32_t(z != zc || y != yc || x != xc) << k;
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                // row group i: x-rows 2i (lanes r < 8) and 2i + 1 (r >= 8)
-                const int q = base_q + (2 * i + (r >> 3)) * kHX + tq;
-                const uint4 araw = *reinterpret_cast<const uint4*>(&halo[q][kg]);
-                const bf16x8 a = __builtin_bit_cast(bf16x8, araw);
+            for (int k = 0; k < kBatch; ++k) {
+                const int it = t + 256 * (k0 + k);
+                const int q = ((it >> 5) << 3) + (it & 7), cg = ((it >> 3) & 3) << 3;
+                const uint4 val = (outside >> k) & 1u ? uint4{0u, 0u, 0u, 0u} : stg[k];
+                if (it < kItems) *reinterpret_cast<uint4*>(&halo[q * kFPitch + cg]) = val;
+            }
+        }
+        __syncthreads();
+        // 54 K steps of 16 channels: step st is tap st / 2, channels
+        // c0 + 16 (st % 2) .. + 15.  Software pipelined: the A operands of
+        // step st + 1 are read from LDS while the MFMAs of step st run, and
+        // the weights (from the L2: a layer's packed weights exceed the L1)
+        // are loaded three steps ahead into a ring.  Past the last step the
+        // addresses are clamped to it (loaded, never used), so that no
+        // branch breaks the pipeline.
+        auto a_ptr = [&](int st, int i) {
+            const int tap = st >> 1;
+            const int dq = ((tap / 9 - 1) * kFH + (tap / 3) % 3 - 1) * kFH + tap % 3 - 1;
+            return reinterpret_cast<const uint4*>(&halo[(qrow[i] + dq) * kFPitch + 16 * (st & 1) + kc]);
+        };
+        auto w_ptr = [&](int st, int j) {
+            return reinterpret_cast<const uint4*>(wrow[j] + (st >> 1) * C + c0 + 16 * (st & 1));
+        };
+        constexpr int kSteps = 54;
+        uint4 ring[3][NJ], acur[4];
 #pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bop[j], acc[i][j], 0, 0, 0);
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) ring[p][j] = *w_ptr(p, j);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acur[i] = *a_ptr(0, i);
+#pragma unroll 1
+        for (int s0 = 0; s0 < kSteps; s0 += 6) {
+#pragma unroll
+            for (int u = 0; u < 6; ++u) {
+                const int st = s0 + u;
+                uint4 anext[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) anext[i] = *a_ptr(min(st + 1, kSteps - 1), i);
+                // keep the scheduler from sinking these reads to their use
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        const int c = j * KS + (KS == 2 ? (u & 1) : 0);
+                        acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            __builtin_bit_cast(bf16x8, acur[i]), __builtin_bit_cast(bf16x8, ring[u % 3][j]),
+                            acc[i][c], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) ring[u % 3][j] = *w_ptr(min(st + 3, kSteps - 1), j);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acur[i] = anext[i];
             }
         }
         __syncthreads();
     }
-    // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16 tile
+    // epilogue: lane holds column lane % 32 and rows 8 (e / 4) + 4 (lane / 32) + e % 4
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
+        for (int e = 0; e < 16; ++e) {
+            int z, y, x;
+            tile_pos(w, i, 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), z, y, x);
+            const int m = ((bz * kFB + z) * v.H + by * kFB + y) * v.W + bx * kFB + x;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = 4 * (lane >> 4) + e;           // 0..15 within row group i
-                const int z = bz * kDZ + w, y = by * kDY + 2 * i + (row >> 3),
-                          x = bx * kDX + (row & 7);
-                const int m = (z * v.H + y) * v.W + x;
-                const int n = n0 + 16 * j + (lane & 15);
-                float val = acc[i][j][e];
+            for (int j = 0; j < NJ; ++j) {
+                const int n = n0 + 32 * j + (lane & 31);
+                float val = acc[i][j * KS][e];
+                if (KS == 2) val += acc[i][j * KS + 1][e];
                 if (MODE == kConvFwd) {
                     val += g.bias[n];
                     if (g.relu) val = fmaxf(val, 0.f);
@@ -419,6 +506,7 @@ __global__ void __launch_bounds__(256) k_conv_direct(GemmArgs g) {
                 }
                 g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(val);
             }
+        }
 }
 
 // Weight gradient of a 3x3x3 convolution by the same bricks:
@@ -437,13 +525,13 @@ __global__ void __launch_bounds__(256) k_conv_direct(GemmArgs g) {
 constexpr int kWRows = kDZ * kDY;          // x-rows of 8 positions per brick
 constexpr int kHRows = kHZ * kHY;          // x-rows of 10 in the halo brick
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-
 // Column of element (row, col) in a [row][32] array of 16-byte entries: bits
-// 0-2 of col are XORed with a function of the row and of col's bit 4, so that
-// the 16 lanes of one staging write (4 rows x 4 channel groups) fall on 16
-// distinct entries modulo 16; a row keeps all its 32 entries.
-__device__ __forceinline__ int swz(int row, int col) { return col ^ ((row & 3) | ((col >> 2) & 4)); }
+// 0-2 of col are XORed with col's channel group (bits 3-4) and the row's
+// parity, so that the 8 lanes of one staging write phase (2 rows x 4 channel
+// groups) fall on 8 distinct entries modulo 8; a row keeps all its 32
+// entries, so the MFMA operand reads (32 lanes on one 512-byte row) stay
+// conflict-free.
+__device__ __forceinline__ int swz(int row, int col) { return col ^ (((col >> 3) & 3) | ((row & 1) << 2)); }
 
 // Channel j of 8 consecutive positions v[0..7] (8 channels each), packed.
 __device__ __forceinline__ uint4 transpose_channel(const uint4* v, int j) {
@@ -855,14 +943,14 @@ void gemm_launch(int mode, const GemmArgs& g0, hipStream_t s, int splits = 1) {
 // where the grid and the channels fit its tiles, else the implicit GEMM.
 void conv_launch(int mode, const GemmArgs& g, hipStream_t s) {
     const View& v = g.a;
-    const bool direct = v.D % kDZ == 0 && v.H % kDY == 0 && v.W % kDX == 0 && v.C % kCC == 0 &&
+    const bool direct = v.D % kFB == 0 && v.H % kFB == 0 && v.W % kFB == 0 && v.C % kCC == 0 &&
                         g.K == 27 * v.C && g.N % 32 == 0 && int64_t(v.D) * v.H * v.W == g.M;
     if (!direct) {
         gemm_launch(mode, g, s);
         return;
     }
     const int nt = g.N % 64 == 0 ? 64 : 32;
-    dim3 grid((v.D / kDZ) * (v.H / kDY) * (v.W / kDX), g.N / nt);
+    dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / nt);
     if (mode == kConvFwd) {
         if (nt == 64) hipLaunchKernelGGL((k_conv_direct<kConvFwd, 64>), grid, dim3(256), 0, s, g);
         else hipLaunchKernelGGL((k_conv_direct<kConvFwd, 32>), grid, dim3(256), 0, s, g);

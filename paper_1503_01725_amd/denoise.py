@@ -226,9 +226,10 @@ def main():
     ap.add_argument("--save", default="")
     ap.add_argument("--bench", action="store_true",
                     help="only time forward / training step at --width, --n")
+    ap.add_argument("--iters", type=int, default=10, help="timed repetitions of --bench")
     args = ap.parse_args()
     if args.bench:
-        print(json.dumps(bench_unet(args.width, args.n)))
+        print(json.dumps(bench_unet(args.width, args.n, args.iters)))
         return
 
     def log(m):
