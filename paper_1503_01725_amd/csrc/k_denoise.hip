@@ -565,41 +565,76 @@ __global__ void __launch_bounds__(256) k_conv_wgrad_direct(GemmArgs g, int brick
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[i][e] = 0.f;
 
-    for (int b = b_lo; b < b_hi; ++b) {
+    // Staging items of this thread: item A = t (a halo row of the input if
+    // t < 240, else an x-row of the output gradient), item B = t + 256 (an
+    // x-row of the output gradient if t < 112).  The next brick's items are
+    // loaded into registers while the current brick's MFMAs run; addresses
+    // are clamped into the grid and outside values zeroed when written.
+    constexpr int kXItems = kHRows * 4, kGItems = kWRows * 4;
+    const bool a_is_x = t < kXItems;
+    const int kA = t - kXItems, kB = t + 256 - kXItems;
+    const bool has_b = kB < kGItems;
+    uint4 ra[kHX], rb[kDX];
+    uint32_t outside = 0u;
+    auto fetch = [&](int b) {
         const int bx = b % bx_n, by = (b / bx_n) % by_n, bz = b / (bx_n * by_n);
-        for (int it = t; it < (kHRows + kWRows) * 4; it += 256) {
-            if (it < kHRows * 4) {
-                // input: halo row hr, channels c0 + cg .. + 7, all 10 x
-                const int hr = it >> 2, cg = (it & 3) << 3;
-                const int z = bz * kDZ - 1 + hr / kHY, y = by * kDY - 1 + hr % kHY;
-                const bool row_in = z >= 0 && z < v.D && y >= 0 && y < v.H;
-                uint4 val[kHX];
+        outside = 0u;
+        if (a_is_x) {
+            const int hr = t >> 2, cg = (t & 3) << 3;
+            const int z = bz * kDZ - 1 + hr / kHY, y = by * kDY - 1 + hr % kHY;
+            const int zc = min(max(z, 0), v.D - 1), yc = min(max(y, 0), v.H - 1);
+            const bool row_out = z != zc || y != yc;
 #pragma unroll
-                for (int hx = 0; hx < kHX; ++hx) {
-                    const int x = bx * kDX - 1 + hx;
-                    val[hx] = row_in && x >= 0 && x < v.W ? load8(v, (z * v.H + y) * v.W + x, c0 + cg)
-                                                          : zero;
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) xT[d][hr][swz(hr, cg + j)] = transpose_channel(val + d, j);
-            } else {
-                // output gradient: brick x-row r, channels o0 + og .. + 7
-                const int k = it - kHRows * 4;
-                const int r = k >> 2, og = (k & 3) << 3;
-                const int z = bz * kDZ + r / kDY, y = by * kDY + r % kDY;
-                uint4 val[kDX];
-#pragma unroll
-                for (int i = 0; i < kDX; ++i) val[i] = load8(gz, (z * gz.H + y) * gz.W + bx * kDX + i, o0 + og);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) gzT[r][swz(r, og + j)] = transpose_channel(val, j);
+            for (int hx = 0; hx < kHX; ++hx) {
+                const int x = bx * kDX - 1 + hx;
+                const int xc = min(max(x, 0), v.W - 1);
+                ra[hx] = load8(v, (zc * v.H + yc) * v.W + xc, c0 + cg);
+                outside |= uint32_t(row_out || x != xc) << hx;
             }
+        } else {
+            const int r = kA >> 2, og = (kA & 3) << 3;
+            const int z = bz * kDZ + r / kDY, y = by * kDY + r % kDY;
+#pragma unroll
+            for (int i = 0; i < kDX; ++i) ra[i] = load8(gz, (z * gz.H + y) * gz.W + bx * kDX + i, o0 + og);
         }
+        if (has_b) {
+            const int r = kB >> 2, og = (kB & 3) << 3;
+            const int z = bz * kDZ + r / kDY, y = by * kDY + r % kDY;
+#pragma unroll
+            for (int i = 0; i < kDX; ++i) rb[i] = load8(gz, (z * gz.H + y) * gz.W + bx * kDX + i, o0 + og);
+        }
+    };
+    auto stage = [&]() {
+        if (a_is_x) {
+            const int hr = t >> 2, cg = (t & 3) << 3;
+#pragma unroll
+            for (int hx = 0; hx < kHX; ++hx)
+                if ((outside >> hx) & 1u) ra[hx] = zero;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) xT[d][hr][swz(hr, cg + j)] = transpose_channel(ra + d, j);
+        } else {
+            const int r = kA >> 2, og = (kA & 3) << 3;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gzT[r][swz(r, og + j)] = transpose_channel(ra, j);
+        }
+        if (has_b) {
+            const int r = kB >> 2, og = (kB & 3) << 3;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) gzT[r][swz(r, og + j)] = transpose_channel(rb, j);
+        }
+    };
+
+    if (b_lo < b_hi) fetch(b_lo);
+    for (int b = b_lo; b < b_hi; ++b) {
+        stage();
         __syncthreads();
+        if (b + 1 < b_hi) fetch(b + 1);
         const int col = lane & 31;
 #pragma unroll 2
         for (int ks = 0; ks < kWRows / 2; ++ks) {
+            // K step ks: brick x-rows 2 ks (lanes 0-31) and 2 ks + 1 (lanes 32-63)
             const int row = 2 * ks + (lane >> 5);
             const int rz = row / kDY, ry = row % kDY;
             const bf16x8 a = __builtin_bit_cast(bf16x8, gzT[row][swz(row, col)]);
@@ -639,8 +674,14 @@ __global__ void k_wgrad_reduce(const float* partial, int splits, int M, int N, i
     const int64_t total = int64_t(M) * N;
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * blockDim.x) {
-        float v = 0.f;
-        for (int z = 0; z < splits; ++z) v += partial[size_t(z) * total + i];
+        // eight independent partial sums keep eight loads in flight
+        float v8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int z = 0;
+        for (; z + 8 <= splits; z += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v8[k] += partial[size_t(z + k) * total + i];
+        for (; z < splits; ++z) v8[0] += partial[size_t(z) * total + i];
+        const float v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
         const int m = int(i / N), n = int(i - int64_t(m) * N);
         if (MODE == kConvWgrad) {
             const int tap = n / c_pad, c = n - tap * c_pad;
@@ -706,9 +747,15 @@ __global__ void k_pool_bwd(View gcoarse, const uint8_t* arg, View gskip, View h,
 // head: pred = sum_c w[c] h[p][c] + b + dose[p]
 __global__ void k_head_fwd(View h, const float* hw, const float* hb, const float* dose, int P,
                            float* pred) {
+    // C is a multiple of 8: one 16-byte load per 8 channels
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
         float s = hb[0] + dose[p];
-        for (int c = 0; c < h.C; ++c) s += hw[c] * bf2f(h.p[size_t(p) * h.stride + h.off + c]);
+        for (int c8 = 0; c8 < h.C; c8 += 8) {
+            const uint4 v = load8(h, p, c8);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += hw[c8 + k] * bf2f(e[k]);
+        }
         pred[p] = s;
     }
 }
