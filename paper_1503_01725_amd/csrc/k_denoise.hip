@@ -2,9 +2,11 @@
 // 2x2x2 max pooling down, 2x2x2 stride-2 transposed conv up, skip
 // concatenation, 1x1x1 head plus the scaled input dose) trained with Adam on
 // MSE.  Activations and weights are BF16 in channels-last layout
-// ([position][channel]); every convolution is an implicit GEMM on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation; weight gradients and the
-// master weights are FP32.
+// ([position][channel]), accumulation is FP32 on the MFMA units; weight
+// gradients and the master weights are FP32.  3x3x3 convolutions run as
+// direct brick kernels (input brick staged once in LDS for all 27 taps)
+// where the grid and channels fit their tiles, everything else as an
+// implicit GEMM.
 #include <cmath>
 #include <cstring>
 #include <memory>
