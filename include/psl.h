@@ -250,8 +250,9 @@ void psl_tally_free(psl_tally* tally);
  * histories) are skipped.  Electrons set in motion by photons go through
  * `electrons`, a caller stack whose capacity must cover
  * in->capacity * (floor(e_max / e_cut_electron) + 1): each push costs the
- * photon at least e_cut_electron, and the stack is filled in chunks of 64 per
- * wavefront whose unused ends stay in it as empty (skipped) entries.  The
+ * photon at least e_cut_electron, and the stack is filled in chunks of 256
+ * per wavefront (64 where the grid's wavefronts times 255 exceed
+ * in->capacity) whose unused ends stay in it as empty (skipped) entries.  The
  * electron stack is grouped into energy bands before electron transport.  The
  * persistent transport grids hold ceil(in->capacity / 1024) workgroups of 256
  * (at most 2048), about four histories per lane.  Random numbers: Philox4x32-10 keyed

@@ -56,6 +56,7 @@ struct TransportArgs {
     float e_cut_e, e_cut_g, step_frac;
     int ms;
     uint32_t seed_lo, seed_hi;
+    uint32_t push_chunk;       // electron-stack entries a wave reserves per atomic
 };
 
 // ---- hardware transcendentals ---------------------------------------------
@@ -144,12 +145,15 @@ __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, 
     ++n_atomic;
 }
 
-// Two deposits (v < 0: none) whose index-map lookups are both issued before
-// either atomic, so that no lookup waits behind an atomic.
-__device__ __forceinline__ void deposit2(const TallyDev& T, int v0, float e0, int v1, float e1,
-                                         uint32_t tag, uint32_t& n_atomic) {
-    const int c0 = v0 >= 0 && e0 != 0.f ? tally_cell(T, v0, tag) : -1;
-    const int c1 = v1 >= 0 && e1 != 0.f ? tally_cell(T, v1, tag) : -1;
+// Three deposits (v < 0: none; the first two of particle tag01, the third of
+// tag2) whose index-map lookups are all issued before any atomic, so that no
+// lookup waits behind an atomic.
+__device__ __forceinline__ void deposit3(const TallyDev& T, int v0, float e0, int v1, float e1,
+                                         uint32_t tag01, int v2, float e2, uint32_t tag2,
+                                         uint32_t& n_atomic) {
+    const int c0 = v0 >= 0 && e0 != 0.f ? tally_cell(T, v0, tag01) : -1;
+    const int c1 = v1 >= 0 && e1 != 0.f ? tally_cell(T, v1, tag01) : -1;
+    const int c2 = v2 >= 0 && e2 != 0.f ? tally_cell(T, v2, tag2) : -1;
     if (c0 >= 0) {
         atomicAdd(T.grid + c0, e0);
         ++n_atomic;
@@ -158,18 +162,45 @@ __device__ __forceinline__ void deposit2(const TallyDev& T, int v0, float e0, in
         atomicAdd(T.grid + c1, e1);
         ++n_atomic;
     }
+    if (c2 >= 0) {
+        atomicAdd(T.grid + c2, e2);
+        ++n_atomic;
+    }
 }
 
+// Waits until every vector memory operation of the wave has completed
+// (s_waitcnt vmcnt(0), expcnt and lgkmcnt left free).  Loads, stores and
+// atomics share one in-order counter, so a load that is used after a later
+// store or atomic can only be waited on together with it; the kernels below
+// end the loads of an iteration with this wait before issuing its deposits
+// and stores, so that the next iteration uses its loaded values without
+// waiting for writes it has just made.
+__device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---- work queue -------------------------------------------------------------
-// A wave reserves kChunk consecutive stack entries with one atomic and hands
-// them to its idle lanes over the following iterations; lanes whose particle
-// has finished take the next entry of the wave's chunk.
-constexpr uint32_t kChunk = 64;
+// Entries [0, n) of a stack are split in two.  Three quarters go out
+// statically, an equal share to each wave of the grid, with no atomics.  The
+// rest is handed out dynamically, kChunk entries per returning atomic on one
+// global counter, which evens out the waves' differing amounts of work; each
+// such atomic stalls its wave for a device-wide round trip, so they are kept
+// to the tail.  A wave hands its entries to its idle lanes over the
+// following iterations.
+constexpr uint32_t kChunk = 128;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct WaveQueue {
-    uint32_t base = 0, left = 0;
-    bool drained = false;
+    uint32_t base, left, dyn0;   // dyn0: first entry of the dynamic part
+    bool drained;
+    __device__ explicit WaveQueue(uint32_t n) {
+        const uint32_t per_block = blockDim.x >> 6;
+        const uint32_t waves = gridDim.x * per_block;
+        const uint32_t w = blockIdx.x * per_block + (threadIdx.x >> 6);
+        const uint32_t share = uint32_t(uint64_t(n) * 3u / 4u / waves);
+        base = w * share;
+        left = share;
+        dyn0 = waves * share;
+        drained = false;
+    }
 };
 
 __device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t* head, uint32_t n) {
@@ -179,7 +210,7 @@ __device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t*
     if (q.left == 0 && !q.drained) {
         uint32_t b = 0;
         if (lane == 0) b = atomicAdd(head, kChunk);
-        b = __shfl(b, 0, 64);
+        b = q.dyn0 + __shfl(b, 0, 64);
         if (b >= n) {
             q.drained = true;
         } else {
@@ -227,7 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     uint32_t tag = 0, n_push = 0, phase = kFlight, trials = 0;
     int steps = 0, cv = 0;   // cv: voxel of the current collision
     bool collided = false, alive = false;
-    WaveQueue wq;
+    WaveQueue wq(n);
     dev::PoolStream<kPhotonPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
     // Order of an iteration: the physics step (no global writes), then the
     // refill of idle lanes (their loads are waited on), then this step's
@@ -356,28 +387,43 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 alive = false;
             }
         }
-        // refill idle lanes from the wave's chunk of the photon stack
+        // refill idle lanes from the wave's chunk of the photon stack: the
+        // entry's tag and data are loaded together (one memory latency), the
+        // data kept only if the tag marks a live entry
         {
             const uint32_t i = take_work(!alive, wq, a.queue, n);
-            const uint32_t tg = i != kNone ? a.in.tag[i] : 0u;
-            if (i != kNone && (tg >> 24) == 0u) {   // skip entries marked rejected / empty
-                px = a.in.x[i]; py = a.in.y[i]; pz = a.in.z[i];
-                du = a.in.u[i]; dv = a.in.v[i]; dw = a.in.w[i];
-                e = a.in.e[i];
-                g = a.in.hid[i];
-                tag = tg & 0xFFFFu;
-                st.init(g, dev::kTagTransport, 0);
-                n_push = 0;
-                steps = 0;
-                phase = kFlight;
-                collided = false;
-                alive = true;
+            if (i != kNone) {
+                const uint32_t tg = a.in.tag[i];
+                const float nx = a.in.x[i], ny = a.in.y[i], nz = a.in.z[i];
+                const float nu = a.in.u[i], nv = a.in.v[i], nw = a.in.w[i];
+                const float ne = a.in.e[i];
+                const uint64_t ng = a.in.hid[i];
+                // the empty asm takes every loaded value, so that the
+                // compiler keeps the data loads ahead of the tag test
+                // instead of moving them into it (one wait for all)
+                asm volatile("" ::"v"(tg), "v"(nx), "v"(ny), "v"(nz), "v"(nu), "v"(nv), "v"(nw),
+                             "v"(ne), "v"(ng));
+                const bool take = (tg >> 24) == 0u;   // skip entries marked rejected / empty
+                px = take ? nx : px; py = take ? ny : py; pz = take ? nz : pz;
+                du = take ? nu : du; dv = take ? nv : dv; dw = take ? nw : dw;
+                e = take ? ne : e;
+                g = take ? ng : g;
+                if (take) {
+                    tag = tg & 0xFFFFu;
+                    st.init(g, dev::kTagTransport, 0);
+                    n_push = 0;
+                    steps = 0;
+                    phase = kFlight;
+                    collided = false;
+                    alive = true;
+                }
             }
         }
+        wait_loads();
         // this step's writes: the electron first (its chunk reservation
         // returns a value, which must not wait behind the deposit's atomic)
         // wave-convergent push: slots from the wave's reserved chunk of the
-        // electron stack, a new chunk of kChunk when it runs out
+        // electron stack, a new chunk of push_chunk when it runs out
         const unsigned long long m = __ballot(push);
         if (m != 0ull) {
             const int lane = threadIdx.x & 63;
@@ -385,13 +431,13 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             const uint32_t rank = uint32_t(__popcll(m & ((1ull << lane) - 1ull)));
             uint32_t fresh = 0;
             if (k_push > el_left) {
-                if (lane == 0) fresh = atomicAdd(a.el.count, kChunk);
+                if (lane == 0) fresh = atomicAdd(a.el.count, a.push_chunk);
                 fresh = __shfl(fresh, 0, 64);
             }
             const uint32_t slot = rank < el_left ? el_base + rank : fresh + (rank - el_left);
             if (k_push > el_left) {
                 el_base = fresh + (k_push - el_left);
-                el_left = kChunk - (k_push - el_left);
+                el_left = a.push_chunk - (k_push - el_left);
             } else {
                 el_base += k_push;
                 el_left -= k_push;
@@ -566,7 +612,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     int ix = 0, iy = 0, iz = 0, cur_v = 0, pend_v = 0, steps = 0;
     uint32_t tag = 0;
     bool alive = false;
-    WaveQueue wq;
+    WaveQueue wq(n);
     dev::PoolStream<kElectronPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
     // Order of an iteration as in k_photon: the CSDA step (deposits
     // deferred), the refill of idle lanes, then this step's deposits.
@@ -575,10 +621,18 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
         // one multiple-scattering deflection (two uniforms) per step, at most
         // one step per iteration
         st.topup(alive && a.ms, 2, 5);
-        // this step's deposits, deferred: the voxel left and the last voxel
-        int w_v0 = -1, w_v1 = -1;
-        float w_e0 = 0.f, w_e1 = 0.f;
+        // the next step's density, loaded into its own register (written
+        // by nothing else before the end of the iteration, so that the load
+        // is not waited on early) and taken over after the iteration's wait
+        float rho_nx;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(rho_nx));   // not sunk into the other paths
+        bool new_rho = false;
+        // this step's deposits, deferred: the voxel left and the last voxel,
+        // and a refilled electron that is below the cut-off on entry
+        int w_v0 = -1, w_v1 = -1, w_v2 = -1;
+        float w_e0 = 0.f, w_e1 = 0.f, w_e2 = 0.f;
         const uint32_t w_tag = tag;
+        uint32_t w_tag2 = 0;
         if (alive) {
             bool done = false;
             if (steps >= kMaxElectronSteps) {
@@ -641,7 +695,8 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                             cur_v = (iz * G.ny + iy) * G.nx + ix;
                             // the next step's density, loaded while the rest
                             // of this iteration runs
-                            rho = G.dens[cur_v];
+                            rho_nx = G.dens[cur_v];
+                            new_rho = true;
                             w_v0 = pend_v;
                             w_e0 = pend_e;
                             pend_v = cur_v;
@@ -680,39 +735,56 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                 alive = false;
             }
         }
-        // refill idle lanes from the wave's chunk of the (band-ordered) stack
+        // refill idle lanes from the wave's chunk of the (band-ordered) stack;
+        // tag and data loaded together as in k_photon
         {
             const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
             const uint32_t i = q != kNone ? (a.perm ? a.perm[q] : q) : 0u;
-            const uint32_t tg = q != kNone ? s.tag[i] : 0u;
-            if (q != kNone && (tg >> 24) == 0u) {   // skip entries marked rejected / empty
-                px = s.x[i]; py = s.y[i]; pz = s.z[i];
-                dx = s.u[i]; dy = s.v[i]; dz = s.w[i];
-                t = s.e[i];
-                const uint64_t g = s.hid[i];
+            uint32_t tg = 1u << 24;
+            float nx = 0.f, ny = 0.f, nz = 0.f, nu = 0.f, nv = 0.f, nw = 0.f, ne = 0.f;
+            uint64_t g = 0;
+            if (q != kNone) {
+                tg = s.tag[i];
+                nx = s.x[i]; ny = s.y[i]; nz = s.z[i];
+                nu = s.u[i]; nv = s.v[i]; nw = s.w[i];
+                ne = s.e[i];
+                g = s.hid[i];
+                asm volatile("" ::"v"(tg), "v"(nx), "v"(ny), "v"(nz), "v"(nu), "v"(nv), "v"(nw),
+                             "v"(ne), "v"(g));
+            }
+            const bool take = (tg >> 24) == 0u;   // skip entries marked rejected / empty
+            px = take ? nx : px; py = take ? ny : py; pz = take ? nz : pz;
+            dx = take ? nu : dx; dy = take ? nv : dy; dz = take ? nw : dz;
+            t = take ? ne : t;
+            if (take) {
                 tag = tg & 0xFFFFu;
                 ix = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
                 iy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
                 iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
                 cur_v = (iz * G.ny + iy) * G.nx + ix;
                 if (t < tcut) {
-                    // below the cut-off on entry: local deposit (after the
-                    // refill's loads, so not deferred)
-                    deposit(a.tally, cur_v, tag, t, c_atom);
+                    // below the cut-off on entry: local deposit, deferred
+                    // with this iteration's others (its own tag)
+                    w_v2 = cur_v;
+                    w_e2 = t;
+                    w_tag2 = tag;
                     dep += t;
                     ++c_local;
                 } else {
                     st.init(g, dev::kTagTransport, (tg >> 16) & 0xFFu);
                     pend_v = cur_v;
                     pend_e = 0.f;
-                    rho = G.dens[cur_v];
+                    rho_nx = G.dens[cur_v];
+                    new_rho = true;
                     steps = 0;
                     alive = true;
                 }
             }
         }
+        wait_loads();
+        if (new_rho) rho = rho_nx;
         // this step's deposits
-        deposit2(a.tally, w_v0, w_e0, w_v1, w_e1, w_tag, c_atom);
+        deposit3(a.tally, w_v0, w_e0, w_v1, w_e1, w_tag, w_v2, w_e2, w_tag2, c_atom);
     }
     dev::flush_stats(a.tally.stats, ls);
 }
@@ -864,6 +936,13 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     // history among 64 short ones.
     const int64_t per_block = int64_t(kBlock) * std::max(1, lane_load);
     const int tg = int(std::max<int64_t>(1, std::min<int64_t>((int64_t(in->capacity) + per_block - 1) / per_block, 2048)));
+    // A wave reserves electron-stack entries push_chunk at a time (one
+    // returning atomic each); the unused ends of the waves' last chunks
+    // (fewer than push_chunk per wave) must fit in the one spare entry per
+    // photon that the stack's capacity provides: 256 where the grid allows,
+    // else 64 as the capacity rule states.
+    const int64_t waves = int64_t(tg) * (kBlock / 64);
+    a.push_chunk = waves * 255 <= int64_t(in->capacity) ? 256u : 64u;
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream,
                        in->ptype == 0 ? el->count : nullptr, a.queue);
     if (in->ptype == 0) {
