@@ -336,10 +336,12 @@ int psl_run_get_timing(psl_tally* tally, psl_run_timing* out);
 /* Autotuner: times one replica (`replica`) of the plan for every candidate
  * (max_batch[i], band_width[j], lane_load[l], sort_electrons s in {0, 1},
  * pipelines p in {1, 2}) with graph replay, writes the measured milliseconds
- * to ms_out[(((i * n_w + j) * n_l + l) * 2 + s) * 2 + p - 1] (nullable) and
- * to *best the first candidate in that order within 3 % of the fastest
- * (use_graph = 1, seed as given), so that near-ties resolve alike from run to
- * run.  Resets the tally afterwards.  Synchronous. */
+ * to ms_out[(((i * n_w + j) * n_l + l) * 2 + s) * 2 + p - 1] (nullable).  The
+ * candidates within 5 % of the fastest are timed again over three
+ * back-to-back replays; *best is the first of them in that order within 1 %
+ * of the fastest of that round (use_graph = 1, seed as given), so that
+ * near-ties resolve alike from run to run.  Resets the tally afterwards.
+ * Synchronous. */
 int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
                  const psl_transport_params* params, uint64_t seed, const uint32_t* max_batch,
                  int32_t n_m, const int32_t* band_width, int32_t n_w, const int32_t* lane_load,

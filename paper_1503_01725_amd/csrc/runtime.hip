@@ -413,14 +413,32 @@ extern "C" int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tall
                     cand.push_back(o);
                     times.push_back(ms);
                 }
-        // the first candidate (in the order of the arrays, sort off and one
-        // pipeline first)
-        // within 3 % of the fastest, so that near-ties resolve the same way
-        // from run to run
+        // Second round: the candidates within 5 % of the fastest are timed
+        // again over three back-to-back replays (a single replay leaves a few
+        // percent of noise and misses the sustained rate); the pick is the
+        // first of them in the order of the arrays (sort off and one pipeline
+        // first) within 1 % of the fastest, so that near-ties resolve the same
+        // way from run to run.
         const double best_ms = *std::min_element(times.begin(), times.end());
+        std::vector<size_t> fin;
         for (size_t c = 0; c < cand.size(); ++c)
-            if (times[c] <= 1.03 * best_ms) {
-                *best = cand[c];
+            if (times[c] <= 1.05 * best_ms) fin.push_back(c);
+        std::vector<double> t2(fin.size());
+        for (size_t k = 0; k < fin.size(); ++k) {
+            const psl_run_opts& o = cand[fin[k]];
+            run_impl(plan, phantom, tally, params, o, replica, 1, nullptr);
+            PSL_HIP(hipEventRecord(e0, nullptr));
+            for (int rep = 0; rep < 3; ++rep) run_impl(plan, phantom, tally, params, o, replica, 1, nullptr);
+            PSL_HIP(hipEventRecord(e1, nullptr));
+            PSL_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
+            t2[k] = ms / 3.0;
+        }
+        const double best2 = *std::min_element(t2.begin(), t2.end());
+        for (size_t k = 0; k < fin.size(); ++k)
+            if (t2[k] <= 1.01 * best2) {
+                *best = cand[fin[k]];
                 break;
             }
         (void)hipEventDestroy(e0);

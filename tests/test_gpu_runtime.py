@@ -61,13 +61,11 @@ def test_autotuner_picks_a_candidate(eng, N, wl):
     assert best.lane_load in (2, 8)
     assert best.pipelines in (1, 2)
     assert ms.shape == (2, 2, 2, 2, 2) and np.all(ms > 0)
-    # the choice: the first candidate in array order within 3 % of the fastest
+    # the choice comes from the second round, which only times the
+    # candidates within 5 % of the fastest of the first
     chosen = ms[[4096, 32768].index(best.max_batch), [1, 4].index(best.band_width),
                 [2, 8].index(best.lane_load), best.sort_electrons, best.pipelines - 1]
-    assert chosen <= 1.03 * ms.min()
-    flat = ms.ravel()
-    first = int(np.flatnonzero(flat <= 1.03 * ms.min())[0])
-    assert flat[first] == chosen
+    assert chosen <= 1.05 * ms.min()
     led, cnt = tally.stats()
     assert cnt["hist"] == 0                       # the tally was reset
 
