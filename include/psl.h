@@ -191,11 +191,19 @@ typedef struct {
 } psl_particles;
 
 enum {
-    PSL_SAMPLE_DENSE = 1    /* write history h0+i at slot i with its status
+    PSL_SAMPLE_DENSE = 1,   /* write history h0+i at slot i with its status
                                (every history, also rejected ones, whose slot
                                holds the beam-frame plane position and
                                direction) and set *count = n, instead of
                                compacting accepted particles                */
+    PSL_SAMPLE_PLANE = 2    /* dense phase-space-plane records: every history
+                               at slot i with its beam-frame position
+                               (x, y, z = 0) and direction at the plane, its
+                               energy and id, tag = column | beam << 16 |
+                               status << 24 (status 0, or 3 for an invalid
+                               direction); no jaw test and no transform (the
+                               records of a particle-file source; the plan may
+                               hold at most 255 beams)                       */
 };
 
 /* Samples histories [h0, h0+n) of replica `replica` (global id
@@ -216,6 +224,22 @@ enum {
 int sample_batch(const psl_plan* plan, const psl_phantom* phantom, uint32_t replica,
                  uint64_t h0, uint32_t n, uint64_t seed, psl_particles* out,
                  uint32_t flags, psl_tally* tally, void* stream);
+
+/* The second half of sample_batch for phase-space-plane records (a source
+ * read from particle files, as the paper's earlier PSL-file source model
+ * does: particles at the plane translated and rotated on the GPU,
+ * Sec. 3.1, Table 1): for the first n records of `plane` (written with
+ * PSL_SAMPLE_PLANE for the same plan, possibly stored and read back), jaw
+ * rejection, beam -> patient transform and phantom entry, with the same
+ * arithmetic as sample_batch, so that the output is bit for bit what
+ * sample_batch with PSL_SAMPLE_DENSE writes for those histories.  Dense
+ * output in `out` (capacity >= n, *out->count = n, out->ptype = plane->ptype);
+ * the tally receives the jaw and phantom-miss part of the ledger (the plane
+ * sampling entered the rest).  A record whose beam index is not in the plan
+ * is rejected as invalid.  Asynchronous on `stream`. */
+int psl_transform_batch(const psl_plan* plan, const psl_phantom* phantom,
+                        const psl_particles* plane, uint32_t n, psl_particles* out,
+                        psl_tally* tally, void* stream);
 
 /* ------------------------------------------------------------------------
  * Transport and tally

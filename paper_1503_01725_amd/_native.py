@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libpsl.so")
 
 PSL_OK, PSL_EINVAL, PSL_ENOMEM, PSL_EDEVICE, PSL_EOVERFLOW, PSL_ENOTCONV = 0, -1, -2, -3, -4, -5
 PSL_SAMPLE_DENSE = 1
+PSL_SAMPLE_PLANE = 2
 PSL_TALLY_RESET, PSL_TALLY_FOLD, PSL_TALLY_FINALIZE = 1, 2, 4
 
 P = C.POINTER
@@ -106,6 +107,7 @@ _SIGS = {
     "psl_phantom_free": [vp],
     "sample_batch": [vp, vp, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint64, P(psl_particles),
                      C.c_uint32, vp, vp],
+    "psl_transform_batch": [vp, vp, P(psl_particles), C.c_uint32, P(psl_particles), vp, vp],
     "psl_tally_create": [vp, vp, C.c_int32, C.c_int32, P(vp)],
     "psl_tally_free": [vp],
     "transport_batch": [vp, P(psl_particles), P(psl_particles), vp, P(psl_transport_params),
@@ -217,6 +219,11 @@ def psl_tally_create(phantom, index_map_ptr, n_rows, n_cols):
 def sample_batch(plan, phantom, replica, h0, n, seed, particles, flags, tally, stream):
     return _call("sample_batch", plan, phantom, replica, h0, n, seed, C.byref(particles), flags,
                  tally, vp(stream))
+
+
+def psl_transform_batch(plan, phantom, plane, n, out, tally, stream):
+    return _call("psl_transform_batch", plan, phantom, C.byref(plane), n, C.byref(out), tally,
+                 vp(stream))
 
 
 def transport_batch(phantom, particles, electrons, tally, params, seed, stream):

@@ -28,7 +28,8 @@ struct SampleArgs {
     uint32_t* tag;
     uint32_t* count;
     uint32_t capacity;
-    int dense;                   // 0 compact, 1 dense (full records), 2 dense (tags only if rejected)
+    int dense;                   // 0 compact, 1 dense (full records), 2 dense (tags only if
+                                 // rejected), 3 phase-space-plane records (no jaws, no transform)
     double* stats;
     unsigned long long* counters;
 };
@@ -43,6 +44,47 @@ __device__ __forceinline__ int64_t upper_bound(const uint64_t* cum, int64_t lo, 
         if (cum[mid] > h) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+// Second half of a history's source step: jaw rejection at the upper jaw
+// surfaces (closed intervals), beam frame -> patient frame (the plane is the
+// isocentre plane), then the entry of the particle's line into the phantom
+// box (slab method).  Shared by the fused sampler and the transform of
+// phase-space-plane records, so both give the same bits.  Returns kOk, kJaw
+// or kMissed; p* and d* are set for kOk.
+__device__ __forceinline__ uint32_t to_patient(const BeamDev& B, float zjy, float zjx,
+                                               const float* box_lo, const float* box_hi, float x,
+                                               float y, float ub, float vb, float wb, float& px,
+                                               float& py, float& pz, float& du, float& dv,
+                                               float& dw) {
+    const float yj = fmaf(vb / wb, zjy, y);
+    const float xj = fmaf(ub / wb, zjx, x);
+    if (!(yj >= B.jy1 && yj <= B.jy2 && xj >= B.jx1 && xj <= B.jx2)) return kJaw;
+    const float p0 = B.iso[0] + B.R[0] * x + B.R[1] * y;
+    const float p1 = B.iso[1] + B.R[3] * x + B.R[4] * y;
+    const float p2 = B.iso[2] + B.R[6] * x + B.R[7] * y;
+    du = B.R[0] * ub + B.R[1] * vb + B.R[2] * wb;
+    dv = B.R[3] * ub + B.R[4] * vb + B.R[5] * wb;
+    dw = B.R[6] * ub + B.R[7] * vb + B.R[8] * wb;
+    const float pp[3] = {p0, p1, p2}, dd[3] = {du, dv, dw};
+    float tmin = -INFINITY, tmax = INFINITY;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (dd[ax] != 0.f) {
+            const float inv = 1.f / dd[ax];
+            const float t1 = (box_lo[ax] - pp[ax]) * inv;
+            const float t2 = (box_hi[ax] - pp[ax]) * inv;
+            tmin = fmaxf(tmin, fminf(t1, t2));
+            tmax = fminf(tmax, fmaxf(t1, t2));
+        } else if (pp[ax] < box_lo[ax] || pp[ax] > box_hi[ax]) {
+            tmax = -INFINITY;
+        }
+    }
+    if (!(tmax > tmin)) return kMissed;
+    px = fmaf(tmin, du, p0);
+    py = fmaf(tmin, dv, p1);
+    pz = fmaf(tmin, dw, p2);
+    return kOk;
 }
 
 template <int STYPE>
@@ -146,51 +188,24 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
         if (invalid) {
             status = kInvalid;
             ls.l[L_INVALID] = en;
+        } else if (a.dense == 3) {
+            // phase-space-plane record: the beam travels in the tag
+            tag |= uint32_t(ent.beam) << 16;
         } else {
-            const BeamDev& B = a.beams[ent.beam];
-            // jaw rejection at the upper jaw surfaces (closed intervals)
-            const float yj = fmaf(vb / wb, a.zjy, y);
-            const float xj = fmaf(ub / wb, a.zjx, x);
-            if (!(yj >= B.jy1 && yj <= B.jy2 && xj >= B.jx1 && xj <= B.jx2)) {
-                status = kJaw;
+            status = to_patient(a.beams[ent.beam], a.zjy, a.zjx, a.box_lo, a.box_hi, x, y, ub, vb,
+                                wb, px, py, pz, du, dv, dw);
+            if (status == kOk) {
+                accept = true;
+                ls.c[C_ENTERED] = 1;
+            } else if (status == kJaw) {
                 ls.l[L_JAW] = en;
             } else {
-                // beam frame -> patient frame (the plane is the isocentre plane)
-                const float p0 = B.iso[0] + B.R[0] * x + B.R[1] * y;
-                const float p1 = B.iso[1] + B.R[3] * x + B.R[4] * y;
-                const float p2 = B.iso[2] + B.R[6] * x + B.R[7] * y;
-                du = B.R[0] * ub + B.R[1] * vb + B.R[2] * wb;
-                dv = B.R[3] * ub + B.R[4] * vb + B.R[5] * wb;
-                dw = B.R[6] * ub + B.R[7] * vb + B.R[8] * wb;
-                // entry of the particle's line into the phantom box (slab method)
-                const float pp[3] = {p0, p1, p2}, dd[3] = {du, dv, dw};
-                float tmin = -INFINITY, tmax = INFINITY;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    if (dd[ax] != 0.f) {
-                        const float inv = 1.f / dd[ax];
-                        const float t1 = (a.box_lo[ax] - pp[ax]) * inv;
-                        const float t2 = (a.box_hi[ax] - pp[ax]) * inv;
-                        tmin = fmaxf(tmin, fminf(t1, t2));
-                        tmax = fminf(tmax, fmaxf(t1, t2));
-                    } else if (pp[ax] < a.box_lo[ax] || pp[ax] > a.box_hi[ax]) {
-                        tmax = -INFINITY;
-                    }
-                }
-                if (!(tmax > tmin)) {
-                    status = kMissed;
-                    ls.l[L_MISSED] = en;
-                } else {
-                    px = fmaf(tmin, du, p0);
-                    py = fmaf(tmin, dv, p1);
-                    pz = fmaf(tmin, dw, p2);
-                    accept = true;
-                    ls.c[C_ENTERED] = 1;
-                }
+                ls.l[L_MISSED] = en;
             }
         }
         if (!accept) {
-            // rejected particles keep their beam-frame state for dense output
+            // rejected particles (and plane records) keep their beam-frame
+            // state for dense output
             px = x;
             py = y;
             pz = 0.f;
@@ -203,7 +218,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     if (a.dense) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.count = a.n;
         if (live) {
-            if (accept || a.dense == 1) {
+            if (accept || a.dense == 1 || a.dense == 3) {
                 a.x[i] = px; a.y[i] = py; a.z[i] = pz;
                 a.u[i] = du; a.v[i] = dv; a.w[i] = dw;
                 a.e[i] = en;
@@ -225,6 +240,66 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
             }
         }
     }
+    dev::flush_stats(a.stats, ls);
+}
+
+// Phase-space-plane records -> transport stack: the second half of k_sample
+// for a source that comes from particle files (the paper's PSL-file source
+// model, which reads particles at the plane and translates / rotates them on
+// the GPU; Sec. 3.1, Table 1).  One thread per record; dense output in the
+// layout of PSL_SAMPLE_DENSE.
+struct TransformArgs {
+    const float *x, *y, *u, *v, *w, *e;
+    const uint64_t* hid;
+    const uint32_t* tag;
+    uint32_t n;
+    float zjy, zjx;
+    const BeamDev* beams;
+    int n_beams;
+    float box_lo[3], box_hi[3];
+    float *ox, *oy, *oz, *ou, *ov, *ow, *oe;
+    uint64_t* ohid;
+    uint32_t* otag;
+    uint32_t* ocount;
+    double* stats;
+};
+
+__global__ void __launch_bounds__(256) k_transform(TransformArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    dev::LocalStats ls;
+    if (i < a.n) {
+        const uint32_t tg = a.tag[i];
+        uint32_t status = tg >> 24;
+        const float x = a.x[i], y = a.y[i], ub = a.u[i], vb = a.v[i], wb = a.w[i], en = a.e[i];
+        float px = x, py = y, pz = 0.f, du = ub, dv = vb, dw = wb;
+        if (status == kOk) {
+            const int beam = int((tg >> 16) & 0xFFu);
+            if (beam >= a.n_beams) {
+                // not a record of this plan: rejected as invalid
+                status = kInvalid;
+                ls.l[L_INVALID] = en;
+            } else {
+                float qx, qy, qz, qu, qv, qw;
+                status = to_patient(a.beams[beam], a.zjy, a.zjx, a.box_lo, a.box_hi, x, y, ub, vb,
+                                    wb, qx, qy, qz, qu, qv, qw);
+                if (status == kOk) {
+                    px = qx; py = qy; pz = qz;
+                    du = qu; dv = qv; dw = qw;
+                    ls.c[C_ENTERED] = 1;
+                } else if (status == kJaw) {
+                    ls.l[L_JAW] = en;
+                } else {
+                    ls.l[L_MISSED] = en;
+                }
+            }
+        }
+        a.ox[i] = px; a.oy[i] = py; a.oz[i] = pz;
+        a.ou[i] = du; a.ov[i] = dv; a.ow[i] = dw;
+        a.oe[i] = en;
+        a.ohid[i] = a.hid[i];
+        a.otag[i] = (tg & 0xFFFFu) | (status << 24);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.ocount = a.n;
     dev::flush_stats(a.stats, ls);
 }
 
@@ -287,6 +362,9 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
     PSL_HIP(hipGetLastError());
 }
 
+// Plane records carry the beam index in tag bits 16-23.
+bool plane_beams_fit(const psl_plan* plan) { return plan->beams.size() <= 255; }
+
 }  // namespace psl
 
 using namespace psl;
@@ -305,9 +383,11 @@ extern "C" int sample_batch(const psl_plan* plan, const psl_phantom* phantom, ui
         PSL_CHECK(out->x && out->y && out->z && out->u && out->v && out->w && out->e &&
                       out->hid && out->tag && out->count,
                   "particle stack has a null array");
-        const bool dense = (flags & PSL_SAMPLE_DENSE) != 0;
+        const bool plane = (flags & PSL_SAMPLE_PLANE) != 0;
+        const bool dense = plane || (flags & PSL_SAMPLE_DENSE) != 0;
         PSL_CHECK(!dense || out->capacity >= n, "dense output needs capacity >= n");
         PSL_CHECK(dense || out->capacity >= n, "stack capacity must be >= n");
+        PSL_CHECK(!plane || plane_beams_fit(plan), "plane records carry the beam in 8 bits: at most 255 beams");
         const auto b0 = std::upper_bound(plan->cum.begin(), plan->cum.end(), h0);
         const auto b1 = std::upper_bound(plan->cum.begin(), plan->cum.end(), h0 + n - 1);
         const int64_t jlo = b0 - plan->cum.begin(), jhi = (b1 - plan->cum.begin()) + 1;
@@ -319,6 +399,51 @@ extern "C" int sample_batch(const psl_plan* plan, const psl_phantom* phantom, ui
                       "histories [h0, h0+n) span more than one sub-source");
         out->ptype = stype == 2 ? 1 : 0;
         launch_sample(plan, phantom, replica, nullptr, h0, n, jlo, jhi, stype, seed, out,
-                      dense ? 1 : 0, tally, static_cast<hipStream_t>(stream));
+                      plane ? 3 : dense ? 1 : 0, tally, static_cast<hipStream_t>(stream));
+    });
+}
+
+extern "C" int psl_transform_batch(const psl_plan* plan, const psl_phantom* phantom,
+                                   const psl_particles* plane, uint32_t n, psl_particles* out,
+                                   psl_tally* tally, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(plan && phantom && plane && out && tally, "psl_transform_batch: null argument");
+        PSL_CHECK(n >= 1, "n must be >= 1");
+        PSL_CHECK(plane->capacity >= n && out->capacity >= n, "stack capacities must be >= n");
+        PSL_CHECK(plane->x && plane->y && plane->u && plane->v && plane->w && plane->e &&
+                      plane->hid && plane->tag,
+                  "plane stack has a null array");
+        PSL_CHECK(out->x && out->y && out->z && out->u && out->v && out->w && out->e && out->hid &&
+                      out->tag && out->count,
+                  "particle stack has a null array");
+        PSL_CHECK(plane->x != out->x && plane->tag != out->tag, "in-place transform not supported");
+        PSL_CHECK(tally->phantom == phantom, "tally belongs to another phantom");
+        ensure_device(plan);
+        const psl_model& m = *plan->model;
+        TransformArgs a{};
+        a.x = plane->x; a.y = plane->y; a.u = plane->u; a.v = plane->v; a.w = plane->w;
+        a.e = plane->e;
+        a.hid = plane->hid;
+        a.tag = plane->tag;
+        a.n = n;
+        a.zjy = float(m.d.z_jaw_y - m.d.z_plane);
+        a.zjx = float(m.d.z_jaw_x - m.d.z_plane);
+        a.beams = plan->d_beams.as<BeamDev>();
+        a.n_beams = int(plan->beams.size());
+        for (int k = 0; k < 3; ++k) {
+            a.box_lo[k] = phantom->g.origin[k];
+            a.box_hi[k] = phantom->g.hi[k];
+        }
+        a.ox = out->x; a.oy = out->y; a.oz = out->z;
+        a.ou = out->u; a.ov = out->v; a.ow = out->w;
+        a.oe = out->e;
+        a.ohid = out->hid;
+        a.otag = out->tag;
+        a.ocount = out->count;
+        a.stats = tally->dev().stats;
+        out->ptype = plane->ptype;
+        hipLaunchKernelGGL(k_transform, dim3((n + 255) / 256), dim3(256), 0,
+                           static_cast<hipStream_t>(stream), a);
+        PSL_HIP(hipGetLastError());
     });
 }
