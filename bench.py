@@ -12,8 +12,13 @@ replayed from one captured hipGraph are timed afterwards (graph_replay).
 Inputs (model tables, plan, phantom) are resident in device memory before
 timing starts.
 
-Prints one JSON line (see the design doc for the roofline and CPU-baseline
-definitions).
+Prints one JSON line.  Besides the contract's fields it carries the
+roofline of the dominant kernel (algorithmic FLOP and bytes per unit of work
+below, divided by that kernel's mean launch time from the HIP events of the
+timed steps), the three ceilings of the path (HBM copy, FP32 atomic and VALU
+rates measured by the library's probes in the same process, each turned into
+a histories/s bound with the step's event counters), and the CPU oracle's
+rate on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -29,7 +34,7 @@ METRICS = {"water128_10": METRIC}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work per unit ("Roofline"): FP32 operations the
+# Algorithmic work per unit: FP32 operations the
 # method performs per electron step / per Woodcock step / per real Compton
 # interaction (an FMA counts 2, a transcendental 1), and HBM bytes per unit.
 FLOP_PER_E_STEP = 104.0
@@ -128,12 +133,14 @@ def describe_phantom(ph):
     d = ph.density
     kind = "water" if float(d.min()) == float(d.max()) == 1.0 else \
         f"heterogeneous, density {float(d.min()):.2f}-{float(d.max()):.2f}"
-    return f"{nx}x{ny}x{nz} {kind}, {ph.vox[0]:g} cm voxels"
+    v = ph.vox
+    vs = f"{v[0]:g}" if v[0] == v[1] == v[2] else f"{v[0]:g}x{v[1]:g}x{v[2]:g}"
+    return f"{nx}x{ny}x{nz} {kind}, {vs} cm voxels"
 
 
 def describe_beams(beams):
     return [f"{b.x2 - b.x1:.1f}x{b.y2 - b.y1:.1f} cm at gantry {b.gantry_deg:.0f} deg"
-            for b in beams]
+            + (f", couch {b.couch_deg:.0f} deg" if b.couch_deg else "") for b in beams]
 
 
 def ceilings(N, torch, dose, cnt, value, hist_per_step):

@@ -216,6 +216,83 @@ def hetero_beams(seed: int, n_beams: int = 5) -> list:
     return beams
 
 
+def _grid(nx, ny, nz, vox):
+    ext = np.array([nx, ny, nz], dtype=np.float64) * np.asarray(vox, dtype=np.float64)
+    origin = -ext / 2.0
+    xc = origin[0] + (np.arange(nx) + 0.5) * vox[0]
+    yc = origin[1] + (np.arange(ny) + 0.5) * vox[1]
+    zc = origin[2] + (np.arange(nz) + 0.5) * vox[2]
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    return X, Y, Z, origin
+
+
+def head_phantom(seed: int, nx: int = 160, ny: int = 176, nz: int = 160,
+                 vox=(0.137, 0.125, 0.137)) -> Phantom:
+    """Head-and-neck-like phantom on the paper's H&N voxel size (0.137 cm
+    transverse, 0.125 cm along the patient axis y), centred on the isocentre:
+    an ellipsoidal head of soft tissue (1.04) in air (0.0012) with a 0.6 cm
+    skull shell (1.85), two air sinuses and a cervical spine column (1.6);
+    sizes jittered from the seed."""
+    rng = _rng(seed, TAG_PHANTOM + 100)
+    X, Y, Z, origin = _grid(nx, ny, nz, vox)
+    a = np.array([8.0, 10.0, 9.5]) * rng.uniform(0.95, 1.05, 3)       # semi-axes x, y, z
+    r = (X / a[0]) ** 2 + (Y / a[1]) ** 2 + (Z / a[2]) ** 2
+    dens = np.full(X.shape, 0.0012, dtype=np.float32)
+    dens[r <= 1.0] = 1.04
+    ai = a - 0.6
+    ri = (X / ai[0]) ** 2 + (Y / ai[1]) ** 2 + (Z / ai[2]) ** 2
+    dens[(r <= 1.0) & (ri > 1.0) & (Y > -3.0)] = 1.85                 # skull above the neck
+    for sx in (-1.0, 1.0):
+        c = np.array([sx * 2.0, 3.0, -4.5]) + rng.uniform(-0.5, 0.5, 3)
+        dens[((X - c[0]) / 1.5) ** 2 + ((Y - c[1]) / 1.8) ** 2 + ((Z - c[2]) / 1.5) ** 2 <= 1.0] = 0.0012
+    dens[(X ** 2 + (Z - 4.0) ** 2 <= 1.2 ** 2) & (Y < 2.0)] = 1.6       # spine column
+    return Phantom(dens, tuple(float(v) for v in vox), tuple(float(v) for v in origin))
+
+
+def hn_beams(seed: int) -> list:
+    """Five coplanar fields at 72 degree spacing and one non-coplanar field
+    at couch 90 (the paper's H&N plan shape), jaws U[4, 8] cm."""
+    rng = _rng(seed, TAG_BEAMS + 100)
+    beams = []
+    for i in range(5):
+        fx, fy = rng.uniform(4.0, 8.0, size=2)
+        beams.append(Beam(-fx / 2, fx / 2, -fy / 2, fy / 2, 72.0 * i, 0.0, (0.0, 0.0, 0.0)))
+    fx, fy = rng.uniform(4.0, 8.0, size=2)
+    beams.append(Beam(-fx / 2, fx / 2, -fy / 2, fy / 2, 40.0, 90.0, (0.0, 0.0, 0.0)))
+    return beams
+
+
+def pelvis_phantom(seed: int, nx: int = 200, ny: int = 96, nz: int = 128,
+                   vox=(0.195, 0.25, 0.195)) -> Phantom:
+    """Pelvis-like phantom on the paper's prostate voxel size (0.195 cm
+    transverse, 0.25 cm along y): an elliptic body cylinder of soft tissue
+    (1.02) in air, two femoral heads and a sacrum of bone (1.85), a rectal gas
+    pocket (0.0012); sizes jittered from the seed."""
+    rng = _rng(seed, TAG_PHANTOM + 200)
+    X, Y, Z, origin = _grid(nx, ny, nz, vox)
+    ax, az = 18.0 * rng.uniform(0.95, 1.05), 11.5 * rng.uniform(0.95, 1.05)
+    dens = np.full(X.shape, 0.0012, dtype=np.float32)
+    dens[(X / ax) ** 2 + (Z / az) ** 2 <= 1.0] = 1.02
+    for sx in (-1.0, 1.0):
+        c = np.array([sx * 8.5, 0.0, 0.5]) + rng.uniform(-0.5, 0.5, 3)
+        dens[((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) <= 2.4 ** 2] = 1.85
+    dens[((X / 4.0) ** 2 + ((Z - 7.5) / 1.6) ** 2 <= 1.0)] = 1.85      # sacrum
+    c = np.array([0.0, 0.0, 4.2]) + rng.uniform(-0.3, 0.3, 3)
+    dens[((X - c[0]) ** 2 + (Y - c[1]) ** 2 / 4.0 + (Z - c[2]) ** 2) <= 0.8 ** 2] = 0.0012
+    return Phantom(dens, tuple(float(v) for v in vox), tuple(float(v) for v in origin))
+
+
+def prostate_beams(seed: int) -> list:
+    """Seven coplanar fields at 360/7 spacing (the paper's prostate plan
+    shape), jaws U[7, 10] cm."""
+    rng = _rng(seed, TAG_BEAMS + 200)
+    beams = []
+    for i in range(7):
+        fx, fy = rng.uniform(7.0, 10.0, size=2)
+        beams.append(Beam(-fx / 2, fx / 2, -fy / 2, fy / 2, 360.0 * i / 7, 0.0, (0.0, 0.0, 0.0)))
+    return beams
+
+
 def commissioning_basis_map(model: PsrModel, rings_per_group: int = 3) -> np.ndarray:
     """Basis id per PSR: s * (n_ebin * groups) + b * groups + ring // rings_per_group."""
     groups = (model.n_ring + rings_per_group - 1) // rings_per_group
@@ -275,6 +352,10 @@ def workload(name: str, seed: int = 20150306) -> Workload:
     * ``water128_{5,10,20}``: 128^3 water at 0.25 cm, one square field, 1e8 histories.
     * ``hetero256_5beam``: 256x128x256 heterogeneous phantom at 0.2 cm, 5 coplanar
       fields of random jaw sizes, 2e8 histories over all beams.
+    * ``hn_6beam``: head-and-neck-like phantom at 0.137 x 0.125 x 0.137 cm,
+      five coplanar fields and one at couch 90, 2e8 histories over all beams.
+    * ``prostate_7beam``: pelvis-like phantom at 0.195 x 0.25 x 0.195 cm,
+      seven coplanar fields, 2e8 histories over all beams.
     * ``commission60``: 60^3 water, fields 3/6/10/20 cm, 720 basis doses, 1e6
       histories per basis and field.
     """
@@ -289,6 +370,11 @@ def workload(name: str, seed: int = 20150306) -> Workload:
     if name == "hetero256_5beam":
         return Workload(name, model, hetero_phantom(seed), hetero_beams(seed),
                         2 * 10 ** 8, 10, seed)
+    if name == "hn_6beam":
+        return Workload(name, model, head_phantom(seed), hn_beams(seed), 2 * 10 ** 8, 10, seed)
+    if name == "prostate_7beam":
+        return Workload(name, model, pelvis_phantom(seed), prostate_beams(seed), 2 * 10 ** 8, 10,
+                        seed)
     if name == "commission60":
         imap, n_rows = commissioning_index_map(60, 0.5)
         beams = [square_beam(s) for s in (3.0, 6.0, 10.0, 20.0)]

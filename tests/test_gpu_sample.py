@@ -71,7 +71,8 @@ def _check_segment(gpu, ref, stype, beams):
     return acc.sum(), rej.sum()
 
 
-@pytest.mark.parametrize("name,n_hist", [("water60_10x10", 100000), ("hetero256_5beam", 150000)])
+@pytest.mark.parametrize("name,n_hist", [("water60_10x10", 100000), ("hetero256_5beam", 150000),
+                                         ("hn_6beam", 120000)])
 def test_sample_batch_matches_oracle(eng, N, orc, wl, name, n_hist):
     W = wl.workload(name)
     model = eng.Model(W.model)

@@ -110,6 +110,23 @@ def test_heterogeneous_multibeam_matches_oracle(eng, orc, wl):
     assert frac >= 0.95, frac
 
 
+def test_noncoplanar_anisotropic_matches_oracle(eng, orc, wl):
+    """The head-and-neck plan shape (a couch-90 field among coplanar ones) on
+    a head-like phantom with anisotropic voxels, air cavities and bone."""
+    W0 = wl.workload("hn_6beam")
+    small = wl.head_phantom(20150306, nx=40, ny=44, nz=40, vox=(0.548, 0.5, 0.548))
+    W = wl.Workload("hn_small", W0.model, small, W0.beams, 20000, 10, 5)
+    print("[transport parity] oracle hn_small", flush=True)
+    d_ref, s_ref, led_ref, cnt_ref = _oracle_run(orc, W, 4000, 77)
+    print("[transport parity] gpu hn_small", flush=True)
+    d, s, led, cnt, plan = _gpu_run(eng, W, 4000, 77)
+    assert abs(_closure(led)) < 1e-5
+    assert led["dep"] == pytest.approx(led_ref["dep"], rel=1e-3)
+    assert cnt["real"] == pytest.approx(cnt_ref["real"], rel=3e-3)
+    frac, nvox = _agreement(d, s, d_ref, s_ref)
+    assert frac >= 0.95, frac
+
+
 def test_electron_csda_path_matches_range(eng, N, orc, wl):
     """Multiple scattering off, electrons stopped inside water: the GPU's total
     path equals the sum of CSDA ranges to the accuracy of its FP32 tables."""
