@@ -412,9 +412,14 @@ typedef struct {
  * x+ = max(0, x - s grad F(x)) with Armijo's rule; the trial step is the
  * Barzilai-Borwein step of the previous iteration.  A: host FP64 m x n,
  * column-major; b: host m; x: host n, in = start (e.g. all ones, the original
- * PSR weights), out = solution.  The products with A and A^T run as FP64
- * kernels on the current device.  Synchronous.  Returns PSL_ENOTCONV (with x
- * and report filled) when max_iter is reached. */
+ * PSR weights), out = solution.  All vector work and the accept / stop
+ * decisions run as FP64 kernels on the current device, on a stream of the
+ * solver's own; each iteration tests up to 8 Armijo steps per pass over A and
+ * takes the first that passes, i.e. the step of the sequential rule, and at
+ * most 200 trials per iteration.  Sums have a fixed order, so a solve is
+ * reproducible bit for bit.  Device memory: A plus 8 m ceil(n/32) + 9 m + 11 n
+ * doubles, freed on return.  Synchronous.  Returns PSL_ENOTCONV (with x and
+ * report filled) when max_iter is reached or the line search fails. */
 int commission_nnls(const double* A, int64_t m, int64_t n, const double* b, double* x,
                     const psl_nnls_opts* opts, psl_nnls_report* report);
 
