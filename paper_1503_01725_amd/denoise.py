@@ -21,6 +21,7 @@ from . import workloads as wl
 
 # history counts of the evaluated plain / denoised doses
 EVAL_COUNTS = (1e6, 3e6, 1e7, 3e7, 1e8)
+RMS_TARGETS = (2.0, 1.0, 0.6)   # stated RMS errors, % of Dmax
 
 
 def case_geometry(seed, n=128, vox=0.25):
@@ -320,10 +321,24 @@ def summarize(res):
         t_d = nl / rate + out[k]["t_infer_s"]
         equal[k] = {"denoised_rms": out[k]["denoised_rms"], "plain_histories_same_rms": n_eq,
                     "speedup": (n_eq / rate) / t_d}
+    # stated RMS errors (% of Dmax): plain histories from the same fit, and
+    # the fewest evaluated histories whose denoised dose reaches the error
+    stated = {}
+    for e in RMS_TARGETS:
+        n_p = 1e6 * (out["1e+06"]["plain_rms"] / e) ** 2
+        n_d = t_d = None
+        for k, nl in zip(keys, EVAL_COUNTS):
+            if out[k]["denoised_rms"] <= e:
+                n_d, t_d = nl, nl / rate + out[k]["t_infer_s"]
+                break
+        stated[f"{e:g}"] = {"plain_histories": n_p, "plain_s": n_p / rate,
+                            "denoised_histories": n_d, "denoised_s": t_d,
+                            "speedup": (n_p / rate) / t_d if t_d else None}
     return {"per_history_count": out, "hist_per_s": rate,
             "time_to_1pct": {"rms_error_percent_of_dmax": rms_at_1pct,
                              "plain_histories": n1, "plain_s": t_plain,
                              "denoised_histories": n_den, "denoised_s": t_den},
+            "time_to_rms": stated,
             "equal_rms": equal}
 
 

@@ -39,3 +39,23 @@ def test_time_to_one_percent_summary():
     eq = out["equal_rms"]["1e+06"]
     assert eq["plain_histories_same_rms"] == pytest.approx(1e6 * (2.0 / 0.3) ** 2)
     assert eq["speedup"] == pytest.approx((1e6 * (2.0 / 0.3) ** 2 / 1e8) / (1e6 / 1e8 + 0.01))
+    # stated RMS errors: plain (2.0 / e)^2 * 1e6 histories; the denoised 0.3 % is
+    # reached at the first count for every stated error above it
+    for e in (2.0, 1.0, 0.6):
+        st = out["time_to_rms"][f"{e:g}"]
+        assert st["plain_histories"] == pytest.approx(1e6 * (2.0 / e) ** 2)
+        assert st["denoised_histories"] == 1e6
+        assert st["speedup"] == pytest.approx((1e6 * (2.0 / e) ** 2 / 1e8) / (1e6 / 1e8 + 0.01))
+
+
+def test_time_to_stated_rms_unreachable_is_null():
+    from paper_1503_01725_amd.denoise import summarize, EVAL_COUNTS
+    case = {"hist_per_s": 1e8}
+    for nl in EVAL_COUNTS:
+        case[f"{nl:.0e}"] = {"plain_rms": 2.0 * (1e6 / nl) ** 0.5, "denoised_rms": 0.8,
+                             "plain_gamma": 0.8, "denoised_gamma": 0.9, "sigma_rel": 0.05,
+                             "t_infer_s": 0.01}
+    out = summarize({"cases": [case]})
+    assert out["time_to_rms"]["1"]["denoised_histories"] == 1e6
+    assert out["time_to_rms"]["0.6"]["denoised_histories"] is None
+    assert out["time_to_rms"]["0.6"]["speedup"] is None
