@@ -94,7 +94,7 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(W, n_hist_rep, seconds):
+def cpu_baseline(W, n_hist_rep, seconds, density_effect=False):
     """The oracle on a bounded, evenly strided sample of replica 0's histories:
     the sample grows until one run takes about `seconds` on all threads; a
     single-thread rate is measured on a sample a quarter as long."""
@@ -107,6 +107,8 @@ def cpu_baseline(W, n_hist_rep, seconds):
     def timed(stride, nt):
         t0 = time.perf_counter()
         _, _, led, cnt = orc.run(W.model, op, W.beams, W.phantom, 7, 1, 0, n_hist_rep,
+                                 tparams=orc.params(W.e_cut_electron, W.e_cut_photon,
+                                                    density_effect=density_effect),
                                  stride=stride, n_threads=nt)
         return cnt["hist"], time.perf_counter() - t0
 
@@ -206,6 +208,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true",
                     help="skip the HBM-copy and atomic-rate probes")
+    ap.add_argument("--density-effect", action="store_true",
+                    help="electron stopping power less the density-effect correction")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -230,7 +234,8 @@ def main():
     plan = eng.Plan(model, W.beams, n_hist_rep, n_replica=n_rep)
     ph = eng.Phantom(W.phantom)
     tally = eng.Tally(ph)
-    prm = eng.transport_params(W.e_cut_electron, W.e_cut_photon)
+    prm = eng.transport_params(W.e_cut_electron, W.e_cut_photon,
+                               density_effect=args.density_effect)
 
     tune = None
     srt = 1
@@ -319,7 +324,7 @@ def main():
                       "replicas": n_rep, "phantom": describe_phantom(W.phantom),
                       "fields": describe_beams(W.beams), "max_batch": mb, "band_width": bw,
                       "lane_load": ll, "pipelines": npipe,
-                      "sort_electrons": srt,
+                      "sort_electrons": srt, "density_effect": bool(args.density_effect),
                       "launch": "eager+events" if not args.no_timing else
                       ("graph" if not args.no_graph else "eager"), "autotune": tune}}
     if graph_replay:
@@ -342,7 +347,8 @@ def main():
             bytes_ = 40.0 * cnt["entered"] / launches
         achieved = flop / avg_s / 1e12
         traffic = measured_traffic(f"k_{phase}", {"max_batch": mb, "band_width": bw,
-                                                  "lane_load": ll, "pipelines": npipe, "sort_electrons": srt})
+                                                  "lane_load": ll, "pipelines": npipe, "sort_electrons": srt,
+                                                  "density_effect": int(args.density_effect)})
         out["roofline"] = {"bound": "alu", "kernel": f"k_{phase}", "achieved": achieved,
                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
@@ -357,7 +363,7 @@ def main():
                                                                 "esc_e", "dep"))) / led["src"]
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(W, n_hist_rep, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(W, n_hist_rep, args.cpu_seconds, args.density_effect)
     print(json.dumps(out))
 
 

@@ -248,7 +248,8 @@ int psl_transform_batch(const psl_plan* plan, const psl_phantom* phantom,
 /* Physics switches.  Photons: free-electron Klein-Nishina Compton scattering
  * with Woodcock tracking; absorbed locally below e_cut_photon.  Electrons:
  * continuous slowing down with the Bethe collision stopping power of water
- * scaled by density, steps ending at voxel faces or after losing step_frac of
+ * (optionally less the density-effect correction) scaled by density, steps
+ * ending at voxel faces or after losing step_frac of
  * their energy, Highland Gaussian multiple scattering (ms_enable); absorbed
  * locally below e_cut_electron (Sec. 2.3 names the cut-offs). */
 typedef struct {
@@ -256,6 +257,9 @@ typedef struct {
     float e_cut_photon;     /* MeV, e.g. 0.01  */
     float step_frac;        /* e.g. 0.1        */
     int32_t ms_enable;      /* 1 = on          */
+    int32_t density_effect; /* 1 = collision stopping power less Sternheimer's
+                               density-effect correction delta(T) of water;
+                               0 = Bethe without it; other values: error */
 } psl_transport_params;
 
 /* A dose tally on `phantom`.  index_map_dev == NULL: one cell per voxel.

@@ -153,7 +153,8 @@ typedef struct {
 
 typedef struct {
     double e_cut_e, e_cut_g, step_frac;
-    int32_t ms_enable, pad;
+    int32_t ms_enable;
+    int32_t density_effect;  /* 1 = collision stopping power with delta(T) */
 } or_params;
 
 typedef struct {
@@ -703,12 +704,36 @@ void or_kn_sample_cos(double e, uint64_t seed, int n, double* cos_out)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Electron physics: Bethe collision stopping power (ICRU 37 form, no density */
-/* effect), CSDA range and its inverse, Highland multiple-scattering width.   */
+/* Electron physics: Bethe collision stopping power (ICRU 37 form, optionally */
+/* with the density-effect correction), CSDA range and its inverse, Highland  */
+/* multiple-scattering width.                                                 */
 /* ------------------------------------------------------------------------ */
 
-/* Mass collision stopping power of water for electrons, MeV cm^2 / g. */
-double or_s_col(double t)
+/* Density-effect correction delta(T) of liquid water in Sternheimer's
+ * parametrisation (Sternheimer, Berger and Seltzer 1984, I = 75 eV), with
+ * x = log10(beta gamma) = log10(p / m c):
+ *   0                                   for x < x0 (an insulator: delta0 = 0),
+ *   2 ln(10) x - Cbar + a (x1 - x)^m     for x0 <= x < x1,
+ *   2 ln(10) x - Cbar                   for x >= x1.
+ * Cbar = 2 ln(I / hbar omega_p) + 1 with the plasma energy of water. */
+#define OR_DE_CBAR 3.5017
+#define OR_DE_X0 0.2400
+#define OR_DE_X1 2.8004
+#define OR_DE_A 0.09116
+#define OR_DE_M 3.4773
+double or_density_delta(double t)
+{
+    double tau = t / OR_ME;
+    double x = log10(sqrt(tau * (tau + 2.0)));
+    if (x < OR_DE_X0) return 0.0;
+    double d = 2.0 * log(10.0) * x - OR_DE_CBAR;
+    if (x < OR_DE_X1) d += OR_DE_A * pow(OR_DE_X1 - x, OR_DE_M);
+    return d;
+}
+
+/* Mass collision stopping power of water for electrons, MeV cm^2 / g; the
+ * Bethe bracket less delta(T) when dens is set. */
+double or_s_col_d(double t, int dens)
 {
     double tau = t / OR_ME;
     double gam = tau + 1.0;
@@ -716,8 +741,10 @@ double or_s_col(double t)
     double i_rel = OR_I_WATER / OR_ME;
     double f_minus = 1.0 - beta2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * log(2.0)) / (gam * gam);
     double bracket = log(tau * tau * (tau + 2.0) / (2.0 * i_rel * i_rel)) + f_minus;
+    if (dens) bracket -= or_density_delta(t);
     return 2.0 * OR_PI * OR_RE * OR_RE * OR_ME * OR_NA * OR_ZA_WATER / beta2 * bracket;
 }
+double or_s_col(double t) { return or_s_col_d(t, 0); }
 
 /* Gauss-Legendre nodes/weights on [-1, 1] from Newton iteration on P_n. */
 #define OR_GL_N 8
@@ -744,11 +771,31 @@ static void gl_init(void)
     }
 }
 
-static double gl_integral_inv_s(double a, double b)
+static double gl_panel_inv_s(double a, double b, int dens)
 {
     double c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
-    for (int i = 0; i < OR_GL_N; ++i) s += gl_w[i] / or_s_col(c + h * gl_x[i]);
+    for (int i = 0; i < OR_GL_N; ++i) s += gl_w[i] / or_s_col_d(c + h * gl_x[i], dens);
     return s * h;
+}
+
+/* Kinetic energy at which log10(beta gamma) = x. */
+static double t_of_x(double x)
+{
+    double bg = pow(10.0, x);
+    return OR_ME * (sqrt(1.0 + bg * bg) - 1.0);
+}
+
+/* int_a^b dT / S(T); with the density effect the integrand has kinks where
+ * delta(T) changes branch (x0, x1), so panels are split there. */
+static double gl_integral_inv_s(double a, double b, int dens)
+{
+    if (dens) {
+        const double knots[2] = {t_of_x(OR_DE_X0), t_of_x(OR_DE_X1)};
+        for (int k = 0; k < 2; ++k)
+            if (a < knots[k] && knots[k] < b)
+                return gl_integral_inv_s(a, knots[k], dens) + gl_integral_inv_s(knots[k], b, dens);
+    }
+    return gl_panel_inv_s(a, b, dens);
 }
 
 /* Range nodes: T_k log-spaced from t_cut upwards, C_k = int_{t_cut}^{T_k} dT/S. */
@@ -756,19 +803,21 @@ static double gl_integral_inv_s(double a, double b)
 #define OR_RNG_TMAX 30.0
 typedef struct {
     double t_cut, ratio;
+    int dens, pad;
     double t[OR_RNG_N], c[OR_RNG_N];
 } or_range_table;
 
-static void range_table_init(or_range_table* rt, double t_cut)
+static void range_table_init(or_range_table* rt, double t_cut, int dens)
 {
     gl_init();
     rt->t_cut = t_cut;
+    rt->dens = dens;
     rt->ratio = pow(OR_RNG_TMAX / t_cut, 1.0 / (OR_RNG_N - 1));
     rt->t[0] = t_cut;
     rt->c[0] = 0.0;
     for (int k = 1; k < OR_RNG_N; ++k) {
         rt->t[k] = t_cut * pow(rt->ratio, (double)k);
-        rt->c[k] = rt->c[k - 1] + gl_integral_inv_s(rt->t[k - 1], rt->t[k]);
+        rt->c[k] = rt->c[k - 1] + gl_integral_inv_s(rt->t[k - 1], rt->t[k], dens);
     }
 }
 
@@ -781,7 +830,7 @@ static double range_of(const or_range_table* rt, double t)
     if (k > OR_RNG_N - 1) k = OR_RNG_N - 1;
     while (k > 0 && rt->t[k] > t) --k;
     while (k < OR_RNG_N - 1 && rt->t[k + 1] <= t) ++k;
-    return rt->c[k] + gl_integral_inv_s(rt->t[k], t);
+    return rt->c[k] + gl_integral_inv_s(rt->t[k], t, rt->dens);
 }
 
 /* Inverse of range_of by bracketing on the nodes, then safeguarded Newton. */
@@ -797,9 +846,9 @@ static double range_inverse(const or_range_table* rt, double rr)
     double a = rt->t[lo], b = rt->t[hi];
     double t = a + (b - a) * (rr - rt->c[lo]) / (rt->c[hi] - rt->c[lo]);
     for (int it = 0; it < 60; ++it) {
-        double f = rt->c[lo] + gl_integral_inv_s(rt->t[lo], t) - rr;
+        double f = rt->c[lo] + gl_integral_inv_s(rt->t[lo], t, rt->dens) - rr;
         if (f > 0.0) b = t; else a = t;
-        double tn = t - f * or_s_col(t);
+        double tn = t - f * or_s_col_d(t, rt->dens);
         if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
         if (fabs(tn - t) <= 1e-15 * t) { t = tn; break; }
         t = tn;
@@ -810,12 +859,27 @@ static double range_inverse(const or_range_table* rt, double rr)
 /* test hooks */
 static or_range_table g_test_rt;
 static double g_test_rt_cut = -1.0;
-static void ensure_test_rt(double t_cut)
+static int g_test_rt_dens = -1;
+static void ensure_test_rt(double t_cut, int dens)
 {
-    if (g_test_rt_cut != t_cut) { range_table_init(&g_test_rt, t_cut); g_test_rt_cut = t_cut; }
+    if (g_test_rt_cut != t_cut || g_test_rt_dens != dens) {
+        range_table_init(&g_test_rt, t_cut, dens);
+        g_test_rt_cut = t_cut;
+        g_test_rt_dens = dens;
+    }
 }
-double or_range(double t, double t_cut) { ensure_test_rt(t_cut); return range_of(&g_test_rt, t); }
-double or_range_inv(double rr, double t_cut) { ensure_test_rt(t_cut); return range_inverse(&g_test_rt, rr); }
+double or_range_d(double t, double t_cut, int dens)
+{
+    ensure_test_rt(t_cut, dens);
+    return range_of(&g_test_rt, t);
+}
+double or_range_inv_d(double rr, double t_cut, int dens)
+{
+    ensure_test_rt(t_cut, dens);
+    return range_inverse(&g_test_rt, rr);
+}
+double or_range(double t, double t_cut) { return or_range_d(t, t_cut, 0); }
+double or_range_inv(double rr, double t_cut) { return or_range_inv_d(rr, t_cut, 0); }
 
 /* Highland width (PDG) of the projected multiple-scattering angle for an
  * electron of kinetic energy t over t_x radiation lengths; 0 where the
@@ -1074,7 +1138,7 @@ int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_b
     for (int b = 0; b < n_beams; ++b) beam_rotation(&beams[b], R[b]);
     or_sampler S = {m, cdf, plan, beams, R, ph};
     or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
-    range_table_init(rt, tp->e_cut_e);
+    range_table_init(rt, tp->e_cut_e, tp->density_effect);
     double rho_max = phantom_rho_max(ph);
     int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
     int nt = n_threads_of(n_threads);
@@ -1156,7 +1220,7 @@ int or_transport(const or_phantom* ph, const or_params* tp, uint64_t seed, int64
 {
     gl_init();
     or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
-    range_table_init(rt, tp->e_cut_e);
+    range_table_init(rt, tp->e_cut_e, tp->density_effect);
     double rho_max = phantom_rho_max(ph);
     int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
     int nt = n_threads_of(n_threads);

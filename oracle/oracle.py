@@ -73,7 +73,7 @@ class OrPhantom(C.Structure):
 
 class OrParams(C.Structure):
     _fields_ = [("e_cut_e", C.c_double), ("e_cut_g", C.c_double), ("step_frac", C.c_double),
-                ("ms_enable", C.c_int32), ("pad", C.c_int32)]
+                ("ms_enable", C.c_int32), ("density_effect", C.c_int32)]
 
 
 class OrPlan(C.Structure):
@@ -111,6 +111,14 @@ def _declare(L):
     L.or_kn_sample_cos.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
     L.or_s_col.argtypes = [C.c_double]
     L.or_s_col.restype = C.c_double
+    L.or_s_col_d.argtypes = [C.c_double, C.c_int]
+    L.or_s_col_d.restype = C.c_double
+    L.or_density_delta.argtypes = [C.c_double]
+    L.or_density_delta.restype = C.c_double
+    L.or_range_d.argtypes = [C.c_double, C.c_double, C.c_int]
+    L.or_range_d.restype = C.c_double
+    L.or_range_inv_d.argtypes = [C.c_double, C.c_double, C.c_int]
+    L.or_range_inv_d.restype = C.c_double
     L.or_range.argtypes = [C.c_double, C.c_double]
     L.or_range.restype = C.c_double
     L.or_range_inv.argtypes = [C.c_double, C.c_double]
@@ -171,8 +179,8 @@ class Phantom:
         self.n_vox = nx * ny * nz
 
 
-def params(e_cut_e=0.2, e_cut_g=0.01, step_frac=0.1, ms=True):
-    return OrParams(e_cut_e, e_cut_g, step_frac, 1 if ms else 0, 0)
+def params(e_cut_e=0.2, e_cut_g=0.01, step_frac=0.1, ms=True, density_effect=False):
+    return OrParams(e_cut_e, e_cut_g, step_frac, 1 if ms else 0, 1 if density_effect else 0)
 
 
 def philox(ctr, key):
@@ -346,16 +354,23 @@ def kn_sample_cos(e, seed, n):
     return out
 
 
-def s_col(t):
-    return lib().or_s_col(t)
+def s_col(t, density_effect=False):
+    """Mass collision stopping power of water, MeV cm^2/g (Bethe, ICRU 37 form;
+    less the density-effect term when density_effect is set)."""
+    return lib().or_s_col_d(t, 1 if density_effect else 0)
 
 
-def csda_range(t, t_cut=0.2):
-    return lib().or_range(t, t_cut)
+def density_delta(t):
+    """Sternheimer density-effect correction delta(T) of liquid water."""
+    return lib().or_density_delta(t)
 
 
-def csda_range_inv(r, t_cut=0.2):
-    return lib().or_range_inv(r, t_cut)
+def csda_range(t, t_cut=0.2, density_effect=False):
+    return lib().or_range_d(t, t_cut, 1 if density_effect else 0)
+
+
+def csda_range_inv(r, t_cut=0.2, density_effect=False):
+    return lib().or_range_inv_d(r, t_cut, 1 if density_effect else 0)
 
 
 def highland(t, t_x):

@@ -63,7 +63,8 @@ class psl_particles(C.Structure):
 
 class psl_transport_params(C.Structure):
     _fields_ = [("e_cut_electron", C.c_float), ("e_cut_photon", C.c_float),
-                ("step_frac", C.c_float), ("ms_enable", C.c_int32)]
+                ("step_frac", C.c_float), ("ms_enable", C.c_int32),
+                ("density_effect", C.c_int32)]
 
 
 class psl_run_opts(C.Structure):

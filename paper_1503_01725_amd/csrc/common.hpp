@@ -218,8 +218,11 @@ struct psl_plan {
 struct psl_phantom {
     psl::PhantomDev g{};
     int device = 0;
-    // physics tables per transport-parameter set
+    // physics tables per transport-parameter set; tab_gen counts rebuilds, so
+    // that a captured graph holding the old table address is never replayed
     float t_cut_tab = -1.f;
+    int32_t dens_tab = -1;
+    uint64_t tab_gen = 0;
     psl::DevBuf tabs;
     psl::PhysicsDev phys{};
 };

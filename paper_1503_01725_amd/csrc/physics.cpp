@@ -3,8 +3,8 @@
 //   * n_e * sigma_KN(E): free-electron Klein-Nishina total cross-section times
 //     the electron density of water at unit mass density (1/cm), on a log-E grid;
 //   * R(T): CSDA range above the electron cut-off, integral of 1/S_col with the
-//     Bethe collision stopping power of water (ICRU 37 form, I = 75 eV, no
-//     density effect), on a log-T grid;
+//     Bethe collision stopping power of water (ICRU 37 form, I = 75 eV), with
+//     or without Sternheimer's density-effect correction, on a log-T grid;
 //   * T(R): its inverse, on a grid uniform in ln(R + R_off).
 #include <cmath>
 
@@ -22,6 +22,10 @@ constexpr double kIwater = 75.0e-6;            // MeV
 constexpr double kEmin = 1.0e-3, kEmax = 30.0; // photon table range, MeV
 constexpr double kTmax = 30.0;                 // electron table top, MeV
 constexpr double kROff = 1.0e-4;               // g/cm^2, offset of the inverse grid
+// Density-effect parameters of liquid water (Sternheimer, Berger and Seltzer
+// 1984): delta = 2 ln10 x - Cbar + a (x1 - x)^m on [x0, x1), 2 ln10 x - Cbar
+// above x1 and 0 below x0, where x = log10(p / m c).
+constexpr double kCbar = 3.5017, kX0 = 0.2400, kX1 = 2.8004, kDa = 0.09116, kDm = 3.4773;
 
 double klein_nishina(double e) {
     const double k = e / kMe;
@@ -33,28 +37,51 @@ double klein_nishina(double e) {
     return 2.0 * kPi * kRe * kRe * (t1 + t2 - t3);
 }
 
-double bethe(double t) {
+double density_delta(double t) {
+    const double tau = t / kMe;
+    const double x = 0.5 * std::log10(tau * (tau + 2.0));
+    if (x < kX0) return 0.0;
+    const double lin = 2.0 * std::log(10.0) * x - kCbar;
+    return x < kX1 ? lin + kDa * std::pow(kX1 - x, kDm) : lin;
+}
+
+// kinetic energy at log10(p / m c) = x
+double t_at_x(double x) {
+    const double p = std::pow(10.0, x);
+    return kMe * (std::sqrt(1.0 + p * p) - 1.0);
+}
+
+double bethe(double t, bool dens) {
     const double tau = t / kMe;
     const double gamma = 1.0 + tau;
     const double b2 = 1.0 - 1.0 / (gamma * gamma);
     const double ir = kIwater / kMe;
     const double fm = 1.0 - b2 + (0.125 * tau * tau - (2.0 * tau + 1.0) * std::log(2.0)) / (gamma * gamma);
     const double lg = std::log(tau * tau * (tau + 2.0) / (2.0 * ir * ir));
-    return 2.0 * kPi * kRe * kRe * kMe * kNa * kZoverA * (lg + fm) / b2;
+    const double d = dens ? density_delta(t) : 0.0;
+    return 2.0 * kPi * kRe * kRe * kMe * kNa * kZoverA * (lg + fm - d) / b2;
 }
 
-// Simpson integral of 1/S over [a, b] with m (even) panels.
-double inv_s_integral(double a, double b, int m) {
+// Simpson integral of 1/S over [a, b] with m (even) panels; with the density
+// effect the integrand has a kink where delta leaves zero (x0) and another at
+// x1, and an interval across one is split there.
+double inv_s_integral(double a, double b, int m, bool dens) {
+    if (dens) {
+        for (double k : {t_at_x(kX0), t_at_x(kX1)})
+            if (a < k && k < b) return inv_s_integral(a, k, m, dens) + inv_s_integral(k, b, m, dens);
+    }
     const double h = (b - a) / m;
-    double s = 1.0 / bethe(a) + 1.0 / bethe(b);
-    for (int i = 1; i < m; ++i) s += (i % 2 ? 4.0 : 2.0) / bethe(a + i * h);
+    double s = 1.0 / bethe(a, dens) + 1.0 / bethe(b, dens);
+    for (int i = 1; i < m; ++i) s += (i % 2 ? 4.0 : 2.0) / bethe(a + i * h, dens);
     return s * h / 3.0;
 }
 
 }  // namespace
 
 void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
-    if (ph->t_cut_tab == p->e_cut_electron && ph->tabs.p) return;
+    PSL_CHECK(p->density_effect == 0 || p->density_effect == 1, "density_effect must be 0 or 1");
+    const bool dens = p->density_effect == 1;
+    if (ph->t_cut_tab == p->e_cut_electron && ph->dens_tab == p->density_effect && ph->tabs.p) return;
     const double tcut = p->e_cut_electron;
     PSL_CHECK(tcut > 2.0e-3 && tcut < 10.0, "e_cut_electron must be in (0.002, 10) MeV");
 
@@ -75,7 +102,7 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     rf[0] = 0.0;
     for (int i = 1; i < fine; ++i) {
         tf[i] = std::exp(lt0 + i * dlf);
-        rf[i] = rf[i - 1] + inv_s_integral(tf[i - 1], tf[i], 8);
+        rf[i] = rf[i - 1] + inv_s_integral(tf[i - 1], tf[i], 8, dens);
     }
     for (int i = 0; i < RNG_TAB_N; ++i) rng[i] = float(rf[size_t(i) * 16]);
     // inverse on u = ln(R + R_off): monotone interpolation in the fine table,
@@ -90,8 +117,8 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
         while (k + 1 < size_t(fine) - 1 && rf[k + 1] < r) ++k;
         double t = tf[k] + (tf[k + 1] - tf[k]) * (r - rf[k]) / (rf[k + 1] - rf[k]);
         for (int it = 0; it < 4; ++it) {
-            const double rt = rf[k] + inv_s_integral(tf[k], t, 8);
-            t -= (rt - r) * bethe(t);
+            const double rt = rf[k] + inv_s_integral(tf[k], t, 8, dens);
+            t -= (rt - r) * bethe(t, dens);
         }
         inv[i] = float(t);
     }
@@ -111,6 +138,8 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     d.rng = d.kn + KN_TAB_N;
     d.inv = d.rng + RNG_TAB_N;
     ph->t_cut_tab = p->e_cut_electron;
+    ph->dens_tab = p->density_effect;
+    ++ph->tab_gen;
 }
 
 }  // namespace psl

@@ -52,6 +52,8 @@ struct GraphKey {
     int32_t ms = 0;
     uint32_t ph_cap = 0, el_cap = 0;
     uint64_t n_batches = 0;
+    uint64_t tab_gen = 0;   // physics-table generation of the phantom
+    int32_t dens = 0;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
 };
 
@@ -311,6 +313,8 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     k.cut_g = prm->e_cut_photon;
     k.frac = prm->step_frac;
     k.ms = prm->ms_enable;
+    k.dens = prm->density_effect;
+    k.tab_gen = ph->tab_gen;
     k.pipes = n_pipes_of(o, plan);
     k.ph_cap = R.pipes[0].ph_cap;
     k.el_cap = R.pipes[0].el_cap;

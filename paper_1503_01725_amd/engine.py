@@ -237,8 +237,10 @@ class Particles:
         return out
 
 
-def transport_params(e_cut_electron=0.2, e_cut_photon=0.01, step_frac=0.1, ms=True):
-    return N.psl_transport_params(e_cut_electron, e_cut_photon, step_frac, 1 if ms else 0)
+def transport_params(e_cut_electron=0.2, e_cut_photon=0.01, step_frac=0.1, ms=True,
+                     density_effect=False):
+    return N.psl_transport_params(e_cut_electron, e_cut_photon, step_frac, 1 if ms else 0,
+                                  1 if density_effect else 0)
 
 
 def electron_capacity(photon_capacity, e_max, e_cut_electron):

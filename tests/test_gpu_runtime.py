@@ -38,6 +38,46 @@ def test_graph_run_equals_eager_loop(eng, N, wl):
         assert np.allclose(d[hi], d0[hi], rtol=1e-4)
 
 
+def test_graph_recaptured_after_tables_rebuilt(eng, N, wl):
+    """A captured run, then a direct transport call with another physics-table
+    set on the same phantom (which rebuilds the tables), then the first set
+    again: the runtime captures anew rather than replaying a graph that still
+    holds the first tables' address, and the replay equals the eager run."""
+    import torch
+    W, model, plan, ph, tally = _setup(eng, wl)
+    prm = eng.transport_params()
+    eng.run_plan_eager(plan, ph, tally, prm, 77, max_batch=20000, band_width=2)
+    d0, s0, (led0, cnt0) = _dose(eng, N, tally, plan)
+    opts = eng.run_opts(20000, 2, use_graph=True, seed=77)
+    for k in range(2):
+        if k == 1:
+            print("[runtime] direct transport with density effect on the same phantom",
+                  flush=True)
+            st = eng.Particles(256)
+            st.t["x"][:] = 0.0
+            st.t["y"][:] = 0.0
+            st.t["z"][:] = 1.0
+            st.t["u"][:] = 0.0
+            st.t["v"][:] = 0.0
+            st.t["w"][:] = 1.0
+            st.t["e"][:] = 1.0
+            st.t["hid"][:] = torch.arange(256)
+            st.t["tag"][:] = 0
+            st.t["count"][:] = 256
+            st.c.ptype = 1
+            side = eng.Tally(ph)
+            N.transport_batch(ph.h, st.c, st.c, side.h, eng.transport_params(density_effect=True),
+                              5, eng._stream_ptr())
+            torch.cuda.synchronize()
+        tally.op(N.PSL_TALLY_RESET)
+        eng.run_plan(plan, ph, tally, prm, opts)
+        d, s, (led, cnt) = _dose(eng, N, tally, plan)
+        assert cnt["real"] == cnt0["real"] and cnt["e_steps"] == cnt0["e_steps"]
+        assert led["dep"] == pytest.approx(led0["dep"], rel=1e-6)
+        hi = d0 > 0.01 * d0.max()
+        assert np.allclose(d[hi], d0[hi], rtol=1e-4)
+
+
 def test_run_timing_counts_launches(eng, N, wl):
     W, model, plan, ph, tally = _setup(eng, wl, n_rep=2)
     prm = eng.transport_params()

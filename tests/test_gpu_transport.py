@@ -30,11 +30,11 @@ def _gpu_run(eng, W, n_hist, seed, max_batch=131072, band=1, n_rep=None, phantom
     return dose.cpu().numpy().ravel(), sig.cpu().numpy().ravel(), led, cnt, plan
 
 
-def _oracle_run(orc, W, n_hist, seed, n_rep=None):
+def _oracle_run(orc, W, n_hist, seed, n_rep=None, tparams=None):
     ref_w, _ = orc.psl_build(W.model)
     op = orc.plan_build(W.model, ref_w, W.beams, n_hist)
     R = n_rep or W.n_replica
-    s, s2, led, cnt = orc.run(W.model, op, W.beams, W.phantom, seed, R)
+    s, s2, led, cnt = orc.run(W.model, op, W.beams, W.phantom, seed, R, tparams=tparams)
     dose, sig = orc.finalize(W.phantom, s, s2, R, op.group_w[0] / n_hist)
     return dose, sig, led, cnt
 
@@ -127,9 +127,31 @@ def test_noncoplanar_anisotropic_matches_oracle(eng, orc, wl):
     assert frac >= 0.95, frac
 
 
-def test_electron_csda_path_matches_range(eng, N, orc, wl):
+def test_dose_with_density_effect_matches_oracle(eng, orc, wl):
+    """Collision stopping power less the density-effect correction on both
+    sides: same parity bar as the plain method, and the electrons travel
+    further than without it (same histories, same streams)."""
+    W = wl.workload("water60_10x10")
+    print("[transport parity] density effect: oracle water60_10x10", flush=True)
+    d_ref, s_ref, led_ref, cnt_ref = _oracle_run(orc, W, 10000, 778,
+                                                 tparams=orc.params(density_effect=True))
+    print("[transport parity] density effect: gpu", flush=True)
+    d, s, led, cnt, plan = _gpu_run(eng, W, 10000, 778,
+                                    tparams=eng.transport_params(density_effect=True))
+    assert abs(_closure(led)) < 1e-5
+    assert led["dep"] == pytest.approx(led_ref["dep"], rel=1e-3)
+    frac, nvox = _agreement(d, s, d_ref, s_ref)
+    assert nvox > 1000 and frac >= 0.95, frac
+    assert cnt["e_steps"] == pytest.approx(cnt_ref["e_steps"], rel=3e-3)
+    d0, s0, led0, cnt0, _ = _gpu_run(eng, W, 10000, 778)
+    assert led["e_path"] > led0["e_path"]
+
+
+@pytest.mark.parametrize("dens", [False, True])
+def test_electron_csda_path_matches_range(eng, N, orc, wl, dens):
     """Multiple scattering off, electrons stopped inside water: the GPU's total
-    path equals the sum of CSDA ranges to the accuracy of its FP32 tables."""
+    path equals the sum of CSDA ranges to the accuracy of its FP32 tables
+    (Bethe stopping power with and without the density-effect correction)."""
     import torch
     ph_src = wl.water_phantom(40, 0.25)
     ph = eng.Phantom(ph_src)
@@ -150,10 +172,10 @@ def test_electron_csda_path_matches_range(eng, N, orc, wl):
     st.t["tag"][:] = 0
     st.t["count"][:] = n
     st.c.ptype = 1
-    prm = eng.transport_params(ms=False)
+    prm = eng.transport_params(ms=False, density_effect=dens)
     N.transport_batch(ph.h, st.c, st.c, tally.h, prm, 5, eng._stream_ptr())
     led, cnt = tally.stats()
-    expect = sum(orc.csda_range(float(x), 0.2) for x in e0)
+    expect = sum(orc.csda_range(float(x), 0.2, density_effect=dens) for x in e0)
     assert led["e_path"] == pytest.approx(expect, rel=2e-4)
     assert led["dep"] == pytest.approx(float(e0.astype(np.float64).sum()), rel=1e-6)
     assert led["esc_e"] == 0.0

@@ -97,3 +97,71 @@ def test_highland_zero_and_monotone(orc):
     assert orc.highland(1.0, 1e-20) == 0.0      # log term clamps the width at 0
     a, b = orc.highland(1.0, 0.01), orc.highland(2.0, 0.01)
     assert a > b > 0
+
+
+# --- density-effect correction (Sternheimer parametrisation, liquid water) ---
+
+HW_P = 28.816e-6 * math.sqrt(1.0 * 10.0 / 18.0153)   # plasma energy of water, MeV
+I_W = 75e-6
+
+
+def _bg(t):
+    tau = t / ME
+    return math.sqrt(tau * (tau + 2.0))
+
+
+@pytest.mark.parametrize("t", [400.0, 1000.0, 5000.0])
+def test_density_effect_fermi_limit(orc, t):
+    """Above x1 the correction is the high-energy limit
+    2 ln(beta gamma) + 2 ln(hbar omega_p / I) - 1, fixed by the electron
+    density and I alone (the parametrisation's Cbar must equal
+    2 ln(I / hbar omega_p) + 1)."""
+    ref = 2.0 * math.log(_bg(t)) + 2.0 * math.log(HW_P / I_W) - 1.0
+    assert orc.density_delta(t) == pytest.approx(ref, abs=2e-4)
+
+
+def test_density_effect_zero_below_x0_and_continuous(orc):
+    # x0 = 0.24: beta gamma = 10^0.24
+    bg0 = 10 ** 0.24
+    t0 = ME * (math.sqrt(1.0 + bg0 * bg0) - 1.0)
+    for t in (0.01, 0.1, 0.3, t0 * (1 - 1e-9)):
+        assert orc.density_delta(t) == 0.0
+        assert orc.s_col(t, density_effect=True) == orc.s_col(t)
+    # the middle branch meets the zero branch at x0 (insulator: delta0 = 0)
+    assert abs(orc.density_delta(t0 * (1 + 1e-9))) < 5e-4
+    # and the Fermi-limit branch at x1 = 2.8004
+    bg1 = 10 ** 2.8004
+    t1 = ME * (math.sqrt(1.0 + bg1 * bg1) - 1.0)
+    assert orc.density_delta(t1 * (1 - 1e-9)) == pytest.approx(orc.density_delta(t1 * (1 + 1e-9)),
+                                                              abs=1e-6)
+    # delta grows with energy and lowers the stopping power above x0
+    ts = np.geomspace(t0 * 1.01, 30.0, 40)
+    d = [orc.density_delta(t) for t in ts]
+    assert np.all(np.diff(d) > 0)
+    for t in ts:
+        assert orc.s_col(t, density_effect=True) < orc.s_col(t)
+
+
+def test_collision_stopping_power_plateau_is_independent_of_i(orc):
+    """With the full correction, the Bethe bracket at high energy loses its
+    dependence on I: ln(tau^2 (tau+2) / 2) - 2 ln(hbar omega_p / m c^2)
+    - 2 ln(beta gamma) + 1 + F-(tau)."""
+    t = 1000.0
+    tau = t / ME
+    g = tau + 1.0
+    b2 = 1.0 - 1.0 / g ** 2
+    fm = 1.0 - b2 + (tau * tau / 8.0 - (2.0 * tau + 1.0) * math.log(2.0)) / g ** 2
+    bracket = (math.log(tau * tau * (tau + 2.0) / 2.0) - 2.0 * math.log(HW_P / ME)
+               - 2.0 * math.log(_bg(t)) + 1.0 + fm)
+    k = 2.0 * math.pi * RE ** 2 * ME * 6.02214076e23 * 10.0 / 18.0153 / b2
+    assert orc.s_col(t, density_effect=True) == pytest.approx(k * bracket, rel=2e-5)
+
+
+@pytest.mark.parametrize("t", [0.7, 3.0, 6.0])
+def test_csda_range_with_density_effect(orc, t):
+    ref, err = integrate.quad(lambda x: 1.0 / orc.s_col(x, density_effect=True), 0.2, t,
+                              epsabs=0, epsrel=1e-13, limit=200)
+    r = orc.csda_range(t, 0.2, density_effect=True)
+    assert r == pytest.approx(ref, rel=1e-10)
+    assert orc.csda_range_inv(r, 0.2, density_effect=True) == pytest.approx(t, rel=1e-12)
+    assert r > orc.csda_range(t, 0.2)
