@@ -707,42 +707,75 @@ __global__ void k_pack_input(const float* in, int P, uint16_t* x0) {
 // 2x2x2 max pooling of view `in` (fine) into `out` (coarse); argmax = first
 // maximum in (z, y, x) order of the block
 __global__ void k_pool_fwd(View in, View out, uint8_t* arg) {
-    const int C = in.C;
-    const int total = out.D * out.H * out.W * C;
+    // 8 channels per thread (C is a multiple of 8): 16-byte loads and stores
+    const int C8 = in.C >> 3;
+    const int total = out.D * out.H * out.W * C8;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int c = i % C, q = i / C;
+        const int c = (i % C8) << 3, q = i / C8;
         int z, y, x;
         pos3(q, out.D, out.H, out.W, z, y, x);
-        float best = -INFINITY;
-        int bi = 0;
+        float best[8];
+        uint8_t bi[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            best[k] = -INFINITY;
+            bi[k] = 0;
+        }
+#pragma unroll
         for (int a = 0; a < 8; ++a) {
             const int fz = 2 * z + (a >> 2), fy = 2 * y + ((a >> 1) & 1), fx = 2 * x + (a & 1);
-            const float v = bf2f(in.p[size_t((fz * in.H + fy) * in.W + fx) * in.stride + in.off + c]);
-            if (v > best) {
-                best = v;
-                bi = a;
+            const uint4 v = load8(in, (fz * in.H + fy) * in.W + fx, c);
+            const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float f = bf2f(e[k]);
+                if (f > best[k]) {
+                    best[k] = f;
+                    bi[k] = uint8_t(a);
+                }
             }
         }
-        out.p[size_t(q) * out.stride + out.off + c] = f2bf(best);
-        arg[i] = uint8_t(bi);
+        uint4 o;
+        uint2 ab;
+        uint16_t* oe = reinterpret_cast<uint16_t*>(&o);
+        uint8_t* ae = reinterpret_cast<uint8_t*>(&ab);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            oe[k] = f2bf(best[k]);
+            ae[k] = bi[k];
+        }
+        *reinterpret_cast<uint4*>(out.p + size_t(q) * out.stride + out.off + c) = o;
+        *reinterpret_cast<uint2*>(arg + size_t(q) * in.C + c) = ab;
     }
 }
 
 // gradient of the fine level: routed pool gradient + skip gradient, masked by
-// the ReLU output `h` of that level
+// the ReLU output `h` of that level; 8 channels per thread
 __global__ void k_pool_bwd(View gcoarse, const uint8_t* arg, View gskip, View h, View gfine) {
-    const int C = gfine.C;
-    const int total = gfine.D * gfine.H * gfine.W * C;
+    const int C = gfine.C, C8 = C >> 3;
+    const int total = gfine.D * gfine.H * gfine.W * C8;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int c = i % C, p = i / C;
+        const int c = (i % C8) << 3, p = i / C8;
         int z, y, x;
         pos3(p, gfine.D, gfine.H, gfine.W, z, y, x);
         const int q = ((z >> 1) * gcoarse.H + (y >> 1)) * gcoarse.W + (x >> 1);
         const int a = ((z & 1) << 2) | ((y & 1) << 1) | (x & 1);
-        float v = bf2f(gskip.p[size_t(p) * gskip.stride + gskip.off + c]);
-        if (arg[size_t(q) * C + c] == a) v += bf2f(gcoarse.p[size_t(q) * gcoarse.stride + gcoarse.off + c]);
-        if (!(bf2f(h.p[size_t(p) * h.stride + h.off + c]) > 0.f)) v = 0.f;
-        gfine.p[size_t(p) * gfine.stride + gfine.off + c] = f2bf(v);
+        const uint4 vs = load8(gskip, p, c), vh = load8(h, p, c), vc = load8(gcoarse, q, c);
+        const uint2 av = *reinterpret_cast<const uint2*>(arg + size_t(q) * C + c);
+        const uint16_t* es = reinterpret_cast<const uint16_t*>(&vs);
+        const uint16_t* eh = reinterpret_cast<const uint16_t*>(&vh);
+        const uint16_t* ec = reinterpret_cast<const uint16_t*>(&vc);
+        const uint8_t* ea = reinterpret_cast<const uint8_t*>(&av);
+        uint4 o;
+        uint16_t* oe = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float v = bf2f(es[k]);
+            if (ea[k] == a) v += bf2f(ec[k]);
+            if (!(bf2f(eh[k]) > 0.f)) v = 0.f;
+            oe[k] = f2bf(v);
+        }
+        *reinterpret_cast<uint4*>(gfine.p + size_t(p) * gfine.stride + gfine.off + c) = o;
     }
 }
 
@@ -838,7 +871,21 @@ __global__ void __launch_bounds__(256) k_bias_grad(View g, int P, float* gb) {
     const int grp = threadIdx.x % groups, row = threadIdx.x / groups;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (row < per_block) {
-        for (int p = blockIdx.x * per_block + row; p < P; p += gridDim.x * per_block) {
+        // four loads in flight per pass; the sums keep the order of p
+        const int step = gridDim.x * per_block;
+        int p = blockIdx.x * per_block + row;
+        for (; p + 3 * step < P; p += 4 * step) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = load8(g, p + u * step, grp * 8);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint16_t* e = reinterpret_cast<const uint16_t*>(&v[u]);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[j] += bf2f(e[j]);
+            }
+        }
+        for (; p < P; p += step) {
             const uint4 v = load8(g, p, grp * 8);
             const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
@@ -1222,7 +1269,7 @@ void forward(UNet& u, const float* input, hipStream_t s) {
         const int C = u.ch(k);
         if (k > 0) {
             View pooled = view(u.pooled[k], u, k, u.ch(k - 1), u.ch(k - 1), 0);
-            hipLaunchKernelGGL(k_pool_fwd, dim3(grid1(u.P(k) * u.ch(k - 1))), dim3(256), 0, s, h,
+            hipLaunchKernelGGL(k_pool_fwd, dim3(grid1(u.P(k) * u.ch(k - 1) / 8)), dim3(256), 0, s, h,
                                pooled, u.arg[k].as<uint8_t>());
             h = pooled;
         }
@@ -1349,7 +1396,7 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
             View gskip = view(u.gcat[k - 1], u, k - 1, Cf, 2 * Cf, 0);
             View hfine = view(u.cat[k - 1], u, k - 1, Cf, 2 * Cf, 0);
             View gfine = view(u.g1[k - 1], u, k - 1, Cf, Cf, 0);
-            hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(u.P(k - 1) * Cf)), dim3(256), 0, s, gp,
+            hipLaunchKernelGGL(k_pool_bwd, dim3(grid1(u.P(k - 1) * Cf / 8)), dim3(256), 0, s, gp,
                                u.arg[k].as<uint8_t>(), gskip, hfine, gfine);
             gz = gfine;
         }
