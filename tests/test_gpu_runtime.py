@@ -170,6 +170,48 @@ def test_commission_nnls_long_line_searches_match_oracle(eng, orc):
     assert np.array_equal(x == 0, xo == 0)
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 1), (40, 33), (257, 65)])
+def test_commission_nnls_edge_shapes_match_oracle(eng, orc, m, n):
+    """A single row and column, a single column, and shapes whose last column
+    chunk (32 columns) and last row block (256 rows) hold one element: the
+    overdetermined problems have one minimiser, which both solvers reach."""
+    rng = np.random.default_rng(1000 * m + n)
+    A = rng.uniform(0.1, 1.0, (m, n)) + 0.5 * np.eye(m, n)
+    b = A @ rng.uniform(-0.5, 1.5, n) + 0.01 * rng.standard_normal(m)
+    x, rep = eng.commission_nnls(A, b)
+    xo, repo = orc.nnls_gp(A, b)
+    assert rep["converged"] and repo["converged"]
+    assert rep["f"] == pytest.approx(repo["f"], rel=1e-9, abs=1e-24)
+    assert np.allclose(x, xo, atol=2e-5 * max(np.abs(xo).max(), 1e-12))
+    assert np.array_equal(x == 0, xo == 0)
+
+
+def test_commission_nnls_underdetermined_reaches_zero_residual(eng, orc):
+    """One row, 33 non-negative columns, b > 0: many exact solutions; both
+    solvers drive the residual to (nearly) zero with x >= 0."""
+    rng = np.random.default_rng(3)
+    A = rng.uniform(0.1, 1.0, (1, 33))
+    b = np.array([2.0])
+    x, rep = eng.commission_nnls(A, b)
+    xo, repo = orc.nnls_gp(A, b)
+    for xx in (x, xo):
+        assert np.all(xx >= 0)
+        assert abs(float((A @ xx - b)[0])) < 1e-6
+    assert rep["f"] < 1e-12 and repo["f"] < 1e-12
+
+
+def test_commission_nnls_zero_iterations_returns_projected_start(eng, orc):
+    rng = np.random.default_rng(5)
+    A = rng.uniform(0, 1, (20, 10))
+    b = rng.uniform(0, 1, 20)
+    x0 = rng.uniform(-1, 1, 10)
+    x, rep = eng.commission_nnls(A, b, x0=x0, max_iter=0)
+    assert rep["iters"] == 0 and not rep["converged"]
+    assert np.array_equal(x, np.maximum(x0, 0.0))
+    r = A @ np.maximum(x0, 0.0) - b
+    assert rep["f"] == pytest.approx(r @ r, rel=1e-12)
+
+
 def test_commission_nnls_reports_iteration_limit(eng, N):
     rng = np.random.default_rng(4)
     A = rng.uniform(0, 1, (40, 30))
