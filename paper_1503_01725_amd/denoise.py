@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--width", type=int, default=32)
-    ap.add_argument("--out", default="gpurun_out/denoise.json")
+    ap.add_argument("--out", default="out/denoise.json")
     ap.add_argument("--save", default="")
     ap.add_argument("--bench", action="store_true",
                     help="only time forward / training step at --width, --n")

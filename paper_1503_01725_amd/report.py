@@ -47,7 +47,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--histories", type=float, default=1e8)
     ap.add_argument("--replicas", type=int, default=10)
-    ap.add_argument("--out", default="gpurun_out/report_water128.json")
+    ap.add_argument("--out", default="out/report_water128.json")
     args = ap.parse_args()
     full, summary = {}, {}
     for size in (5, 10, 20):
