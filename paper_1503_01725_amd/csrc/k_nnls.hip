@@ -320,6 +320,9 @@ struct Solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~Solver() {
+        // work still in flight (an error path) finishes before its graph and
+        // buffers go
+        if (s) (void)hipStreamSynchronize(s);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (s) (void)hipStreamDestroy(s);

@@ -104,6 +104,8 @@ struct Runner {
         if (cs) (void)hipStreamDestroy(cs);
     }
     void drop_graph() {
+        // a launch of the old graph may still run (psl_run returns at once)
+        if (exec && cs) (void)hipStreamSynchronize(cs);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
