@@ -175,15 +175,15 @@ __global__ void __launch_bounds__(kB) k_trial_residual(const double* part, int c
     double v = 0.0;
     if (i < m) {
         const double* p = part + int64_t(trial) * chunks * m + i;
-        int c = 0;
-        for (; c + 8 <= chunks; c += 8) {
+        // groups of 8 guarded loads in flight; the sum keeps chunk order
+        for (int c = 0; c < chunks; c += 8) {
             double q[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) q[k] = p[int64_t(c + k) * m];
+            for (int k = 0; k < 8; ++k) q[k] = c + k < chunks ? p[int64_t(c + k) * m] : 0.0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v += q[k];
+            for (int k = 0; k < 8; ++k)
+                if (c + k < chunks) v += q[k];
         }
-        for (; c < chunks; ++c) v += p[int64_t(c) * m];
         v -= b[i];
         r[int64_t(trial) * m + i] = v;
     }
@@ -204,19 +204,19 @@ __global__ void __launch_bounds__(kB) k_trial_select(const double* rpart, int ro
     if (threadIdx.x < kTrials) {
         const double* p = rpart + threadIdx.x * row_blocks;
         double t = 0.0;
-        int k = 0;
-        for (; k + 8 <= row_blocks; k += 8) {
+        for (int k = 0; k < row_blocks; k += 8) {
             double q[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) q[u] = p[k + u];
+            for (int u = 0; u < 8; ++u) q[u] = k + u < row_blocks ? p[k + u] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t += q[u];
+            for (int u = 0; u < 8; ++u)
+                if (k + u < row_blocks) t += q[u];
         }
-        for (; k < row_blocks; ++k) t += p[k];
         fn[threadIdx.x] = t;
     }
     double d[kTrials];
     for (int t = 0; t < kTrials; ++t) d[t] = 0.0;
+#pragma unroll 4
     for (int64_t j = threadIdx.x; j < n; j += kB) {
         const double gj = g[j], xj = x[j];
         for (int t = 0; t < kTrials; ++t) d[t] = fma(gj, xn[int64_t(t) * n + j] - xj, d[t]);
@@ -260,18 +260,18 @@ __global__ void __launch_bounds__(kB) k_trial_grad(const double* A, const double
     if (j >= n) return;
     const double* col = A + j * m;
     double v = 0.0;
-    int64_t i = lane;
-    for (; i + 7 * 64 < m; i += 8 * 64) {
+    for (int64_t i = lane; i < m; i += 8 * 64) {
         double a[8], q[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            a[k] = col[i + k * 64];
-            q[k] = ra[i + k * 64];
+            const bool in = i + k * 64 < m;
+            a[k] = in ? col[i + k * 64] : 0.0;
+            q[k] = in ? ra[i + k * 64] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v = fma(a[k], q[k], v);
+        for (int k = 0; k < 8; ++k)
+            if (i + k * 64 < m) v = fma(a[k], q[k], v);
     }
-    for (; i < m; i += 64) v = fma(col[i], ra[i], v);
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) gn[j] = 2.0 * v;
 }
@@ -284,6 +284,7 @@ __global__ void __launch_bounds__(kB) k_accept(const double* xn, const double* g
     if (st->done || st->acc < 0) return;
     const double* xa = xn + int64_t(st->acc) * n;
     double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int64_t k = threadIdx.x; k < n; k += kB) {
         const double dx = xa[k] - x[k];
         const double dg = gn[k] - g[k];
