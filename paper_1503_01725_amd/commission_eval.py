@@ -82,6 +82,18 @@ def n_basis(model) -> int:
     return 2 * model.n_ebin * model.n_ring + model.n_ebin
 
 
+def smoothness_rows(model) -> np.ndarray:
+    """First differences of the correction factors between neighbouring rings
+    (same photon sub-source and energy bin): one row (+1, -1) per pair."""
+    bm = basis_map(model).astype(np.int64)
+    pairs = [(bm[s, b, r], bm[s, b, r + 1]) for s in (0, 1) for b in range(model.n_ebin)
+             for r in range(model.n_ring - 1)]
+    D = np.zeros((len(pairs), n_basis(model)))
+    for k, (i, j) in enumerate(pairs):
+        D[k, i], D[k, j] = 1.0, -1.0
+    return D
+
+
 def corrected_model(model, x_basis: np.ndarray):
     """The model with each PSR weight times its basis' correction factor."""
     f = x_basis[basis_map(model).astype(np.int64)]
@@ -235,22 +247,37 @@ def basis_doses(eng, model_src, fields, hist_per_basis, seed, phantom, opts, prm
     return A, rows, plan.n_hist, time.perf_counter() - t0
 
 
-def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int):
-    """Eq. (8) with column scaling (the solver sees unit-norm columns); bases
-    that no row sees keep their factor 1."""
+def scaled_system(A: np.ndarray, b: np.ndarray, D=None, smooth: float = 0.0):
+    """The least-squares system the solver sees: used columns (some row sees
+    them) scaled to unit norm and b by its maximum, so y = x * cn over the used
+    bases.  With smooth > 0 the rows sqrt(smooth) * D follow; an unused basis
+    keeps its factor 1, which moves to the right-hand side.  Then
+    |A1 y - b1|^2 = |A x - b|^2 / scale^2 + smooth |D x|^2."""
     used = np.abs(A).max(axis=0) > 0
     Au = A[:, used]
     cn = np.linalg.norm(Au, axis=0)
     scale = float(np.abs(b).max())
-    y, rep = eng.commission_nnls(Au / cn / scale, b / scale, x0=np.ones(Au.shape[1]) * cn,
-                                 max_iter=max_iter)
+    A1, b1 = Au / cn / scale, b / scale
+    if D is not None and smooth > 0.0:
+        keep = np.abs(D[:, used]).sum(axis=1) > 0
+        w = np.sqrt(smooth)
+        A1 = np.vstack([A1, w * (D[:, used] / cn)[keep]])
+        b1 = np.concatenate([b1, -w * D[:, ~used].sum(axis=1)[keep]])
+    return A1, b1, used, cn, scale
+
+
+def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int, D=None, smooth: float = 0.0):
+    """Eq. (8) on the scaled system (plus the smoothness rows when smooth > 0);
+    bases that no row sees keep their factor 1."""
+    A1, b1, used, cn, _ = scaled_system(A, b, D, smooth)
+    y, rep = eng.commission_nnls(A1, b1, x0=np.ones(int(used.sum())) * cn, max_iter=max_iter)
     x = np.ones(A.shape[1])
     x[used] = y / cn
     return x, used, rep
 
 
 def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_iter=100000,
-             seed=20150306, log=print) -> dict:
+             seed=20150306, smooth=0.0, log=print) -> dict:
     """The whole experiment; returns the result dictionary printed by main()."""
     from . import engine as eng
     from . import workloads as wl
@@ -285,7 +312,7 @@ def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_ite
             bvec.append(meas[s][name])
     As, bs = np.vstack(blocks), np.concatenate(bvec)
     t0 = time.perf_counter()
-    x, used, rep = fit(eng, As, bs, max_iter)
+    x, used, rep = fit(eng, As, bs, max_iter, smoothness_rows(src), smooth)
     t_fit = time.perf_counter() - t0
     log(f"[commission_eval] NNLS: {rep['iters']} iterations, {t_fit:.2f} s")
     # 4. the commissioned model on every field
@@ -314,6 +341,7 @@ def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_ite
     fitted = As @ x
     result.update({
         "bases": int(nb), "bases_used": int(used.sum()), "rows": int(As.shape[0]),
+        "smooth": float(smooth),
         "basis_histories": int(n_a), "t_basis_doses_s": t_a,
         "hist_per_field": int(hist_per_field), "hist_measured": int(hist_measured),
         "nnls": {"iters": rep["iters"], "converged": rep["converged"], "t_s": t_fit,
@@ -334,13 +362,15 @@ def main():
                     help="histories per field of the measured beam")
     ap.add_argument("--max-iter", type=int, default=100000)
     ap.add_argument("--seed", type=int, default=20150306)
+    ap.add_argument("--smooth", type=float, default=0.0,
+                    help="weight of the ring-to-ring smoothness term of the fit (0 = Eq. 8 alone)")
     args = ap.parse_args()
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
     print(json.dumps(evaluate(args.hist_per_basis, args.hist_per_field, args.hist_measured,
-                              args.max_iter, args.seed, log)))
+                              args.max_iter, args.seed, smooth=args.smooth, log=log)))
 
 
 if __name__ == "__main__":

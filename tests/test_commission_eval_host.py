@@ -107,3 +107,42 @@ def test_profile_regions():
     assert m["inner_max_pct"] == pytest.approx(1.0 * prof[prof / prof[80] >= 0.8].max() / prof[80],
                                                rel=1e-9)
     assert m["penumbra_dta_max_cm"] < 0.1
+
+
+def test_smoothness_rows_pair_neighbouring_photon_rings():
+    from paper_1503_01725_amd import commission_eval as ce
+    m = ce.wide_model(3)
+    D = ce.smoothness_rows(m)
+    assert D.shape == (2 * m.n_ebin * (m.n_ring - 1), ce.n_basis(m))
+    bm = ce.basis_map(m).astype(np.int64)
+    electron = set(bm[2].ravel().tolist())
+    for row in D:
+        i, j = np.flatnonzero(row == 1.0), np.flatnonzero(row == -1.0)
+        assert len(i) == 1 and len(j) == 1 and np.count_nonzero(row) == 2
+        s, b, r = np.argwhere(bm[:2] == i[0])[0]
+        assert bm[s, b, r + 1] == j[0]
+        assert i[0] not in electron and j[0] not in electron
+    # a constant correction is not penalised
+    assert np.allclose(D @ np.full(D.shape[1], 1.7), 0.0)
+
+
+def test_scaled_system_adds_the_smoothness_term():
+    """|A1 y - b1|^2 = |A x - b|^2 / scale^2 + smooth |D x|^2 with y = x * cn on
+    the used bases and x = 1 on the unused ones."""
+    from paper_1503_01725_amd import commission_eval as ce
+    rng = np.random.default_rng(11)
+    A = rng.uniform(0, 1, (30, 12))
+    A[:, [3, 7, 8]] = 0.0                      # bases no row sees
+    b = rng.uniform(0, 2, 30)
+    D = np.zeros((11, 12))
+    for k in range(11):
+        D[k, k], D[k, k + 1] = 1.0, -1.0
+    for lam in (0.0, 0.3):
+        A1, b1, used, cn, scale = ce.scaled_system(A, b, D, lam)
+        x = rng.uniform(0, 2, 12)
+        x[~used] = 1.0
+        y = x[used] * cn
+        lhs = np.sum((A1 @ y - b1) ** 2)
+        rhs = np.sum((A @ x - b) ** 2) / scale ** 2 + lam * np.sum((D @ x) ** 2)
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+    assert A1.shape[0] == 30 + 10                  # the row of unused bases 7 and 8 is dropped
