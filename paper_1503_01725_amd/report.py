@@ -59,7 +59,9 @@ def main():
         tally = eng.Tally(ph)
         prm = eng.transport_params()
         t0 = time.perf_counter()
-        eng.run_plan(plan, ph, tally, prm, eng.run_opts(1 << 21, 24, seed=W.seed, lane_load=8))
+        # the launch shape the autotuner picks for these fields on MI355X
+        eng.run_plan(plan, ph, tally, prm, eng.run_opts(1 << 22, 24, seed=W.seed, lane_load=32,
+                                                        sort_electrons=False, pipelines=2))
         d, s = tally.finalize(plan)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
