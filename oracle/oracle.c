@@ -492,15 +492,19 @@ static void voxel_clamped(const or_phantom* ph, const double p[3], int idx[3])
     }
 }
 
-/* Turns direction d by polar angle theta (given by cos) and azimuth phi. */
+/* Turns direction d by polar angle theta (given by cos) and azimuth phi about
+ * the old direction: the new direction makes angle theta with d, and phi is
+ * measured from the plane of d and the z axis (from the x axis when d lies on
+ * the z axis).  The transverse length t = sqrt(u^2 + v^2) is taken from u and
+ * v, not from 1 - w^2, so that the rotation stays exact next to the axis. */
 static void rotate_direction(double d[3], double cos_t, double phi)
 {
     double sin_t = sqrt(fmax(0.0, 1.0 - cos_t * cos_t));
     double cp = cos(phi), sp = sin(phi);
     double u = d[0], v = d[1], w = d[2];
     double nu, nv, nw;
-    if (fabs(w) < 0.99999) {
-        double t = sqrt(1.0 - w * w);
+    double t = sqrt(u * u + v * v);
+    if (t > 1e-30) {
         nu = u * cos_t + sin_t * (u * w * cp - v * sp) / t;
         nv = v * cos_t + sin_t * (v * w * cp + u * sp) / t;
         nw = w * cos_t - sin_t * cp * t;
@@ -511,6 +515,13 @@ static void rotate_direction(double d[3], double cos_t, double phi)
     }
     double norm = sqrt(nu * nu + nv * nv + nw * nw);
     d[0] = nu / norm; d[1] = nv / norm; d[2] = nw / norm;
+}
+
+/* test hook: rotate_direction applied to a copy of d */
+void or_rotate_direction(const double d[3], double cos_t, double phi, double out[3])
+{
+    out[0] = d[0]; out[1] = d[1]; out[2] = d[2];
+    rotate_direction(out, cos_t, phi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -689,6 +700,32 @@ static double kahn_sample(or_stream* st, double k, uint64_t* trials)
             if (r3 <= 0.5 * (c * c + 1.0 / x)) return x;
         }
     }
+}
+
+/* Compton scattering of a photon of energy e moving along d on a free
+ * electron at rest, for x = E/E' (cos theta = 1 - (x - 1)/k, k = E/mc^2) and
+ * azimuth phi: scattered energy E' = E/x and direction d1 (d turned by theta,
+ * phi); the electron takes T = E - E' and the momentum E d - E' d1 (units of
+ * MeV/c), whose direction is returned in de. */
+static void compton_kinematics(double e, const double d[3], double x, double phi, double* e1,
+                               double d1[3], double* te, double de[3])
+{
+    double k = e / OR_ME;
+    double cos_t = 1.0 - (x - 1.0) / k;
+    *e1 = e / x;
+    *te = e - *e1;
+    d1[0] = d[0]; d1[1] = d[1]; d1[2] = d[2];
+    rotate_direction(d1, cos_t, phi);
+    double nrm = 0.0;
+    for (int a = 0; a < 3; ++a) { de[a] = e * d[a] - (*e1) * d1[a]; nrm += de[a] * de[a]; }
+    nrm = sqrt(nrm);
+    for (int a = 0; a < 3; ++a) de[a] /= nrm;
+}
+
+/* test hook: compton_kinematics; out = {E', T, d1[3], de[3]} */
+void or_compton(double e, const double d[3], double x, double phi, double out[8])
+{
+    compton_kinematics(e, d, x, phi, &out[0], &out[2], &out[1], &out[5]);
 }
 
 /* test hook: n Klein-Nishina scattering cosines at energy e (stream g = i) */
@@ -892,6 +929,14 @@ double or_highland(double t, double t_x)
     return th > 0.0 ? th : 0.0;
 }
 
+/* Multiple-scattering width of one electron step: the Highland width at the
+ * step's mean kinetic energy t_mid for a path of s cm in water-like medium of
+ * density rho (thickness rho s / X0 radiation lengths). */
+double or_ms_width(double t_mid, double rho, double s)
+{
+    return or_highland(t_mid, rho * s / OR_X0_WATER);
+}
+
 /* Polar deflection for projected-angle width theta0: |theta| of a 2D Gaussian,
  * theta = theta0 sqrt(-2 ln(1-u)), capped at pi. */
 static double ms_polar(double theta0, double u)
@@ -998,7 +1043,7 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
             e = e_new;
             if (e < tcut) { deposit(T, v, e, tag); return; }
             if (T->tp->ms_enable) {
-                double th0 = or_highland(0.5 * (e_old + e), rho * sf / OR_X0_WATER);
+                double th0 = or_ms_width(0.5 * (e_old + e), rho, sf);
                 double u1 = stream_u01(&st), u2 = stream_u01(&st);
                 rotate_direction(d, cos(ms_polar(th0, u1)), 2.0 * OR_PI * u2);
             }
@@ -1017,7 +1062,7 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
                 return;
             }
             if (T->tp->ms_enable) {
-                double th0 = or_highland(0.5 * (e_old + e), rho * sb / OR_X0_WATER);
+                double th0 = or_ms_width(0.5 * (e_old + e), rho, sb);
                 double u1 = stream_u01(&st), u2 = stream_u01(&st);
                 rotate_direction(d, cos(ms_polar(th0, u1)), 2.0 * OR_PI * u2);
             }
@@ -1060,19 +1105,12 @@ static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
         T->cnt[C_REAL]++;
         double k = e / OR_ME;
         double x = kahn_sample(&st, k, &T->cnt[C_KAHN_TRIALS]);
-        double cos_t = 1.0 - (x - 1.0) / k;
         double phi = 2.0 * OR_PI * stream_u01(&st);
-        double e1 = e / x;
-        double te = e - e1;
-        double d1[3] = {d[0], d[1], d[2]};
-        rotate_direction(d1, cos_t, phi);
+        double e1, te, d1[3], de[3];
+        compton_kinematics(e, d, x, phi, &e1, d1, &te, de);
         if (te >= T->tp->e_cut_e) {
-            /* electron direction from momentum conservation: p_e = E d - E' d' */
-            double pe[3], nrm = 0.0;
-            for (int a = 0; a < 3; ++a) { pe[a] = e * d[a] - e1 * d1[a]; nrm += pe[a] * pe[a]; }
-            nrm = sqrt(nrm);
             or_electron* el = &stack[n_e++];
-            for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = pe[a] / nrm; }
+            for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = de[a]; }
             el->e = te;
             el->sub = 1 + n_push++;
             T->cnt[C_E_PUSHED]++;

@@ -126,6 +126,10 @@ def _declare(L):
     L.or_highland.argtypes = [C.c_double, C.c_double]
     L.or_highland.restype = C.c_double
     L.or_ms_sample.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
+    L.or_ms_width.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.or_ms_width.restype = C.c_double
+    L.or_rotate_direction.argtypes = [dp, C.c_double, C.c_double, dp]
+    L.or_compton.argtypes = [C.c_double, dp, C.c_double, C.c_double, dp]
     L.or_run.argtypes = [P(OrModel), P(OrPlan), P(OrBeam), C.c_int, P(OrPhantom), P(OrParams),
                          C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64,
                          i32p, C.c_int64, C.c_int64, dp, dp, dp, u64p, C.c_int]
@@ -375,6 +379,27 @@ def csda_range_inv(r, t_cut=0.2, density_effect=False):
 
 def highland(t, t_x):
     return lib().or_highland(t, t_x)
+
+
+def ms_width(t_mid, rho, s):
+    """Highland width of one electron step (s cm at density rho, mean energy t_mid)."""
+    return lib().or_ms_width(t_mid, rho, s)
+
+
+def rotate_direction(d, cos_t, phi):
+    """The transport's direction rotation applied to a copy of d."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(3)
+    lib().or_rotate_direction(_ptr(d, dp), cos_t, phi, _ptr(out, dp))
+    return out
+
+
+def compton(e, d, x, phi):
+    """Compton kinematics for x = E/E' and azimuth phi: (E', T, photon dir, electron dir)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(8)
+    lib().or_compton(e, _ptr(d, dp), x, phi, _ptr(out, dp))
+    return out[0], out[1], out[2:5].copy(), out[5:8].copy()
 
 
 def ms_sample(theta0, seed, n):

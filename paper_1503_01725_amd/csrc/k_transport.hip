@@ -103,8 +103,9 @@ __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t
                                        float sphi) {
     const float sin_t = hw_sqrt(fmaxf(0.f, 1.f - cos_t * cos_t));
     float nu, nv, nw;
-    if (fabsf(w) < 0.99999f) {
-        const float t = hw_sqrt(1.f - w * w);
+    // transverse length from u and v (exact next to the axis, unlike 1 - w^2)
+    const float t = hw_sqrt(u * u + v * v);
+    if (t > 1e-30f) {
         const float it = hw_rcp(t);
         nu = u * cos_t + sin_t * (u * w * cphi - v * sphi) * it;
         nv = v * cos_t + sin_t * (v * w * cphi + u * sphi) * it;

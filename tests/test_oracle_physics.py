@@ -91,8 +91,7 @@ def test_ms_polar_sampler(orc):
 
 
 def test_highland_zero_and_monotone(orc):
-    # parity unpinned for the Highland constants themselves (PDG definition);
-    # only structural properties are checked here
+    # structural properties; the constants are pinned against the PDG form below
     assert orc.highland(1.0, 0.0) == 0.0
     assert orc.highland(1.0, 1e-20) == 0.0      # log term clamps the width at 0
     a, b = orc.highland(1.0, 0.01), orc.highland(2.0, 0.01)
@@ -165,3 +164,142 @@ def test_csda_range_with_density_effect(orc, t):
     assert r == pytest.approx(ref, rel=1e-10)
     assert orc.csda_range_inv(r, 0.2, density_effect=True) == pytest.approx(t, rel=1e-12)
     assert r > orc.csda_range(t, 0.2)
+
+
+# --- direction rotation, Compton kinematics, Highland width ------------------
+
+def _random_dirs(rng, n):
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    # directions within 1e-5 of the z axis take the rotation's other branch
+    near = np.array([[1e-7, 2e-7, 1.0], [0.0, 0.0, -1.0], [3e-6, -1e-6, -1.0],
+                     [0.0, 0.0, 1.0]])
+    near /= np.linalg.norm(near, axis=1, keepdims=True)
+    return np.vstack([d, near])
+
+
+def _frame(d):
+    """Two unit vectors perpendicular to d and to each other."""
+    a = np.array([1.0, 0.0, 0.0]) if abs(d[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(d, a)
+    e1 /= np.linalg.norm(e1)
+    return e1, np.cross(d, e1)
+
+
+def test_rotate_direction_polar_angle_and_norm(orc):
+    """The turned direction makes exactly the requested angle with the old one
+    and stays a unit vector, on both branches of the rotation."""
+    rng = np.random.default_rng(7)
+    for d in _random_dirs(rng, 200):
+        for c, phi in zip(rng.uniform(-1, 1, 5), rng.uniform(0, 2 * math.pi, 5)):
+            n = orc.rotate_direction(d, c, phi)
+            assert np.linalg.norm(n) == pytest.approx(1.0, abs=1e-13)
+            assert float(n @ d) == pytest.approx(c, abs=1e-12)
+    # theta = 0 leaves the direction unchanged, theta = pi reverses it
+    for d in _random_dirs(rng, 20):
+        assert np.allclose(orc.rotate_direction(d, 1.0, 1.3), d, atol=1e-12)
+        assert np.allclose(orc.rotate_direction(d, -1.0, 0.4), -d, atol=1e-12)
+
+
+def test_rotate_direction_azimuth_is_an_isometry(orc):
+    """At fixed theta the azimuth of the new direction about the old one moves
+    rigidly with phi (phi -> +-phi + const), so a uniform phi gives a uniform
+    azimuth; checked against a frame built independently around d."""
+    rng = np.random.default_rng(8)
+    for d in _random_dirs(rng, 60):
+        e1, e2 = _frame(d)
+        c = rng.uniform(-0.95, 0.95)
+        phis = rng.uniform(0, 2 * math.pi, 12)
+        az = []
+        for phi in phis:
+            n = orc.rotate_direction(d, c, phi)
+            az.append(math.atan2(n @ e2, n @ e1))
+        az = np.array(az)
+        dphi = np.angle(np.exp(1j * (phis - phis[0])))
+        daz = np.angle(np.exp(1j * (az - az[0])))
+        same = np.allclose(np.angle(np.exp(1j * (daz - dphi))), 0, atol=1e-9)
+        mirror = np.allclose(np.angle(np.exp(1j * (daz + dphi))), 0, atol=1e-9)
+        assert same or mirror
+    # uniform phi -> uniform azimuth (KS) for one tilted direction
+    d = np.array([0.3, -0.5, 0.81])
+    d /= np.linalg.norm(d)
+    e1, e2 = _frame(d)
+    az = np.array([math.atan2(n @ e2, n @ e1) for n in
+                   (orc.rotate_direction(d, 0.2, p) for p in rng.uniform(0, 2 * math.pi, 4000))])
+    assert stats.kstest(az, stats.uniform(-math.pi, 2 * math.pi).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("e", [0.015, 0.2, 1.0, 5.9])
+def test_compton_kinematics_closed_forms(orc, e):
+    """Free-electron Compton kinematics: E' = E / (1 + k (1 - cos theta)),
+    T = E - E', the electron at cot(theta_e) = (1 + k) tan(theta / 2) on the
+    opposite side of the incident direction (azimuth phi + pi), and momentum
+    conserved with |p_e| = sqrt(T (T + 2 m c^2))."""
+    rng = np.random.default_rng(int(e * 1000))
+    k = e / ME
+    for d in _random_dirs(rng, 40):
+        for _ in range(3):
+            cos_t = rng.uniform(-1, 0.999)
+            x = 1.0 + k * (1.0 - cos_t)
+            phi = rng.uniform(0, 2 * math.pi)
+            e1, t, d1, de = orc.compton(e, d, x, phi)
+            assert e1 == pytest.approx(e / (1.0 + k * (1.0 - cos_t)), rel=1e-13)
+            assert t == pytest.approx(e - e1, rel=1e-12, abs=1e-15)
+            assert float(d1 @ d) == pytest.approx(cos_t, abs=1e-12)
+            assert np.linalg.norm(de) == pytest.approx(1.0, abs=1e-13)
+            th = math.acos(cos_t)
+            the = math.acos(max(-1.0, min(1.0, float(de @ d))))
+            # cot theta_e = (1 + k) tan(theta / 2)
+            assert math.cos(the) * math.cos(th / 2) == pytest.approx(
+                (1.0 + k) * math.sin(th / 2) * math.sin(the), abs=1e-10)
+            # coplanar with d and d1, on the other side of d
+            assert abs(np.linalg.det(np.array([d, d1, de]))) < 1e-10
+            if th > 1e-3:
+                assert float(np.cross(d, d1) @ np.cross(d, de)) < 0.0
+            pe = math.sqrt(t * (t + 2.0 * ME))
+            assert np.allclose(e * d, e1 * d1 + pe * de, atol=1e-10 * e)
+
+
+def _highland_constants():
+    return {l.split()[0]: float(l.split()[1]) for l in open(os.path.join(GOLDEN, "highland_pdg.txt"))
+            if l.strip() and not l.startswith("#")}
+
+
+def _tsai_x0(z, a, l_rad, l_rad_p):
+    """Radiation length (g/cm^2) from Tsai's formula with the Coulomb correction."""
+    alpha = 1.0 / 137.035999084
+    az2 = (alpha * z) ** 2
+    f = az2 * (1.0 / (1.0 + az2) + 0.20206 - 0.0369 * az2 + 0.0083 * az2 ** 2
+               - 0.002 * az2 ** 3)
+    inv = 4.0 * alpha * RE ** 2 * 6.02214076e23 / a * (z * z * (l_rad - f) + z * l_rad_p)
+    return 1.0 / inv
+
+
+def test_radiation_length_of_water_from_tsai():
+    """X0 of water (the value the Highland width uses) from Tsai's formula for
+    hydrogen and oxygen combined by mass fraction, 1/X0 = sum w_i / X0_i."""
+    k = _highland_constants()
+    x0_h = _tsai_x0(1, 1.008, 5.31, 6.144)
+    x0_o = _tsai_x0(8, 15.999, math.log(184.15 * 8 ** (-1 / 3)), math.log(1194.0 * 8 ** (-2 / 3)))
+    assert x0_h == pytest.approx(k["X0_hydrogen_g_cm2"], rel=1e-3)
+    assert x0_o == pytest.approx(k["X0_oxygen_g_cm2"], rel=1e-3)
+    w_h = 2 * 1.008 / (2 * 1.008 + 15.999)
+    x0 = 1.0 / (w_h / x0_h + (1 - w_h) / x0_o)
+    assert x0 == pytest.approx(k["X0_water_g_cm2"], rel=1e-3)
+
+
+@pytest.mark.parametrize("t,rho,s", [(0.25, 1.0, 0.05), (1.0, 1.0, 0.125), (3.0, 0.26, 0.4),
+                                     (5.5, 1.85, 0.02), (0.6, 1.0, 2.0)])
+def test_highland_width_against_pdg(orc, t, rho, s):
+    """The step's multiple-scattering width equals the PDG Highland formula with
+    beta c p built from the kinetic energy through gamma and beta, and the
+    thickness rho s / X0 in radiation lengths of water."""
+    k = _highland_constants()
+    gamma = 1.0 + t / ME
+    beta = math.sqrt(1.0 - 1.0 / gamma ** 2)
+    p = gamma * beta * ME                      # MeV/c
+    x = rho * s / k["X0_water_g_cm2"]
+    ref = k["A_MeV"] / (beta * p) * math.sqrt(x) * (1.0 + k["B"] * math.log(x))
+    assert orc.ms_width(t, rho, s) == pytest.approx(ref, rel=1e-12)
+    # and the width of a thin step vanishes only where the log term does
+    assert orc.ms_width(t, rho, 0.0) == 0.0

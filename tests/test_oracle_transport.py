@@ -126,3 +126,87 @@ def test_depth_dose_shape(orc, wl):
     assert cax[50] < 0.6 * cax.max()
     prof = e[20, 28:32, :].sum(axis=0)
     assert prof[:15].mean() < 0.15 * prof[25:35].mean()
+
+
+# SI: 1 MeV = 1e6 x 1.602176634e-19 J (exact); a mass of rho V g is rho V 1e-3 kg
+GY_PER_MEV_PER_G = 1e6 * 1.602176634e-19 / 1e-3
+
+
+def test_finalize_closed_form(orc, wl):
+    """Dose = mean replica energy (MeV) converted to J over the voxel mass in
+    kg, times the model particles per history; sigma = standard error of the
+    replica mean (sample standard deviation over sqrt(R))."""
+    ph = wl.Phantom(np.array([[[1.0, 0.5, 0.0]]], dtype=np.float32), (0.5, 0.4, 0.3),
+                    (0.0, 0.0, 0.0))
+    reps = np.array([[1.0, 4.0, 2.0], [2.0, 4.0, 3.0], [3.0, 4.0, 1.0]])
+    s, s2 = reps.sum(axis=0), (reps ** 2).sum(axis=0)
+    w = 2.5
+    dose, sig = orc.finalize(ph, s, s2, 3, w)
+    vol = 0.5 * 0.4 * 0.3
+    assert dose[0] == pytest.approx(2.0 * GY_PER_MEV_PER_G / (1.0 * vol) * w, rel=1e-14, abs=0)
+    assert sig[0] == pytest.approx(math.sqrt(1.0 / 3.0) * GY_PER_MEV_PER_G / vol * w, rel=1e-12,
+                                   abs=0)
+    assert dose[1] == pytest.approx(4.0 * GY_PER_MEV_PER_G / (0.5 * vol) * w, rel=1e-14, abs=0)
+    assert sig[1] == 0.0
+    assert dose[2] == 0.0 and sig[2] == 0.0         # no mass, no dose
+
+
+def test_commissioning_columns_sum_to_open_field_dose(orc, wl):
+    """Sec. 2.2.2-2.2.3: with every correction factor at 1 the basis doses add
+    up to the dose of the model itself.  The basis columns come from a
+    stratified plan (each basis gets the same number of histories, weighted
+    by its in-area weight over its count); the open-field dose from the
+    Eq. (3) plan through the oracle's finalisation.  Both are normalised
+    independently; they must agree row by row within the statistical error."""
+    W = wl.workload("water60_10x10")
+    imap, n_rows = wl.commissioning_index_map(60, 0.5)
+    j = np.arange(W.model.n_ring)
+    bmap = np.zeros((3, W.model.n_ebin, W.model.n_ring), dtype=np.uint16)
+    for s in range(3):
+        bmap[s] = s * 3 + np.minimum(j // 10, 2)[None, :]
+    n_cols, n_rep = 9, 8
+    w_psl, _ = orc.psl_build(W.model)
+    pc = orc.plan_build(W.model, w_psl, W.beams, 0, basis_map=bmap, hist_per_basis=20000)
+    n_open = 180000
+    po = orc.plan_build(W.model, w_psl, W.beams, n_open)
+    sel = np.flatnonzero(imap.ravel())
+    rows = imap.ravel()[sel] - 1
+    used = pc.group_n > 0
+    assert used.sum() >= 6
+    # basis columns in Gy per model particle: (energy / n_k) * S_k / (rho V),
+    # one replica at a time so that sums over rows get their own spread
+    col_w = np.where(used, pc.group_w / np.maximum(pc.group_n, 1), 0.0)
+    k = GY_PER_MEV_PER_G * col_w[None, :] / (1.0 * 0.5 ** 3)
+    a_r, d_r = [], []
+    for r in range(n_rep):
+        t, _, _, _ = orc.run(W.model, pc, W.beams, W.phantom, 61, 1, rep0=r, index_map=imap,
+                             n_rows=n_rows, n_cols=n_cols)
+        a_r.append((k * t.reshape(n_rows, n_cols)).sum(axis=1))
+        e, e2, _, _ = orc.run(W.model, po, W.beams, W.phantom, 62, 1, rep0=r)
+        dose, _ = orc.finalize(W.phantom, e, e2, 1, po.w.sum() / n_open)
+        d_rows = np.zeros(n_rows)
+        d_rows[rows] = dose[sel]
+        d_r.append(d_rows)
+    a_r, d_r = np.array(a_r), np.array(d_r)
+    a, d = a_r.mean(axis=0), d_r.mean(axis=0)
+    sa, sd = a_r.std(axis=0, ddof=1) / math.sqrt(n_rep), d_r.std(axis=0, ddof=1) / math.sqrt(n_rep)
+    hi = d > 0.2 * d.max()
+    assert hi.sum() > 80
+    z = (a[hi] - d[hi]) / np.sqrt(sa[hi] ** 2 + sd[hi] ** 2)
+    assert np.mean(np.abs(z) < 3) > 0.95
+    assert abs(np.mean(z)) < 0.5
+
+    def z_sum(scale):
+        """The sum over the compared rows against its replica spread."""
+        sa_, sd_ = (a_r[:, hi] * scale).sum(axis=1), d_r[:, hi].sum(axis=1)
+        diff = sa_ - sd_
+        return diff.mean() / (diff.std(ddof=1) / math.sqrt(n_rep))
+
+    assert abs(z_sum(1.0)) < 3
+    # a dose scaled by a misplaced model-weight factor (here the primary
+    # sub-source's share of the weight) fails the same comparisons
+    w_frac = pc.group_w[:3].sum() / pc.group_w.sum()
+    assert w_frac < 0.9
+    z_bad = (a[hi] * w_frac - d[hi]) / np.sqrt(sa[hi] ** 2 + sd[hi] ** 2)
+    assert abs(np.mean(z_bad)) > 0.5
+    assert abs(z_sum(w_frac)) > 3
