@@ -427,6 +427,32 @@ typedef struct {
 int commission_nnls(const double* A, int64_t m, int64_t n, const double* b, double* x,
                     const psl_nnls_opts* opts, psl_nnls_report* report);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as commission_nnls with every operand already on the device and the
+ * solver's vectors in a fixed scratch array of PSL_NNLS_SCRATCH_BYTES that
+ * the library holds on each device until the process ends.  It calls no
+ * device or host allocator and creates no stream or graph.
+ *   A_dev: device FP64 m x n, column-major; b_dev: device m; x_dev: device
+ *   n, in = start (negative entries are clamped to 0 first), out = solution.
+ *   The scratch holds 8 n + 2 n + 8 m + 8 m ceil(n / 32) + 8 ceil(m / 256)
+ *   doubles plus a small state, each piece rounded up to 256 bytes; a system
+ *   that needs more returns PSL_EINVAL before any device work (the
+ *   1656 x 720 commissioning system needs 2.6 MB).
+ *   stream: hipStream_t the kernels run on (NULL = default stream); the
+ *   call synchronises with it once per 32 iteration steps and returns when
+ *   the solve is done.
+ * Same iterations, stop test and report as commission_nnls; ||A||_F^2 for the
+ * first trial step is summed on the device, so the two calls can differ by
+ * rounding.  Every call on one device shares that device's scratch array:
+ * calls that overlap on one device (from two host threads or two streams)
+ * race and give wrong results.  Returns PSL_ENOTCONV (x and report filled)
+ * when max_iter is reached or the line search fails. */
+#define PSL_NNLS_SCRATCH_BYTES (4u << 20)
+int commission_nnls_noalloc(const double* A_dev, int64_t m, int64_t n, const double* b_dev,
+                            double* x_dev, const psl_nnls_opts* opts, psl_nnls_report* report,
+                            void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned 3D dose denoiser (not part of the paper's method): a 4-level U-Net
  * with c, 2c, 4c, 8c channels (two 3x3x3 conv + ReLU per level, 2x2x2 max

@@ -120,6 +120,8 @@ _RESTYPE = {"psl_last_error": C.c_char_p, "psl_model_free": None, "psl_plan_free
             "psl_phantom_free": None, "psl_tally_free": None}
 _SIGS.update({
     "commission_nnls": [dp, C.c_int64, C.c_int64, dp, dp, P(psl_nnls_opts), P(psl_nnls_report)],
+    "commission_nnls_noalloc": [vp, C.c_int64, C.c_int64, vp, vp, P(psl_nnls_opts),
+                                P(psl_nnls_report), vp],
     "psl_run": [vp, vp, vp, P(psl_transport_params), P(psl_run_opts), vp],
     "psl_run_get_timing": [vp, P(psl_run_timing)],
     "psl_autotune": [vp, vp, vp, P(psl_transport_params), C.c_uint64, u32p, C.c_int32, i32p,
@@ -275,6 +277,14 @@ def psl_probe_copy(dst_ptr, src_ptr, nbytes, repeats=5):
 
 def commission_nnls(a_ptr, m, n, b_ptr, x_ptr, opts, report):
     rc = lib().commission_nnls(a_ptr, m, n, b_ptr, x_ptr, C.byref(opts), C.byref(report))
+    if rc not in (PSL_OK, PSL_ENOTCONV):
+        check(rc)
+    return rc
+
+
+def commission_nnls_noalloc(a_dev, m, n, b_dev, x_dev, opts, report, stream):
+    rc = lib().commission_nnls_noalloc(a_dev, m, n, b_dev, x_dev, C.byref(opts),
+                                       C.byref(report), stream)
     if rc not in (PSL_OK, PSL_ENOTCONV):
         check(rc)
     return rc

@@ -11,6 +11,7 @@
 // Every reduction has a fixed order, so a solve is reproducible bit for bit.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -313,36 +314,32 @@ __global__ void __launch_bounds__(kB) k_accept(const double* xn, const double* g
     }
 }
 
+// Buffers of one solve: device pointers into either the solver's own
+// allocations (commission_nnls) or the library's static scratch array
+// (commission_nnls_noalloc).
 struct Solver {
-    int64_t m, n;
-    int chunks;
-    DevBuf A, b, x, xn, g, gn, r, part, rpart, sums, state;
+    int64_t m = 0, n = 0;
+    int chunks = 0;
+    const double *A = nullptr, *b = nullptr;
+    double *x = nullptr, *xn = nullptr, *g = nullptr, *gn = nullptr, *r = nullptr,
+           *part = nullptr, *rpart = nullptr, *sums = nullptr;
+    NnlsState* state = nullptr;
     hipStream_t s = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    ~Solver() {
-        // work still in flight (an error path) finishes before its graph and
-        // buffers go
-        if (s) (void)hipStreamSynchronize(s);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (s) (void)hipStreamDestroy(s);
-    }
-
+    double pg_stop = 0.0;
     double host_sums[3];
+
+    unsigned row_blocks() const { return unsigned((m + kB - 1) / kB); }
+    unsigned col_blocks() const { return unsigned((n + kB / 64 - 1) / (kB / 64)); }
     void sync_sums() {
-        PSL_HIP(hipMemcpyAsync(host_sums, sums.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PSL_HIP(hipMemcpyAsync(host_sums, sums, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         PSL_HIP(hipStreamSynchronize(s));
     }
-    unsigned row_blocks() const { return unsigned((m + kB - 1) / kB); }
     // r = A x - b (first m entries of r); returns ||r||^2
     double objective() {
-        hipLaunchKernelGGL(k_ax_partial, dim3(row_blocks(), unsigned(chunks)), dim3(kB), 0, s,
-                           A.as<double>(), x.as<double>(), m, n, part.as<double>());
-        hipLaunchKernelGGL(k_residual, dim3(row_blocks()), dim3(kB), 0, s, part.as<double>(),
-                           chunks, b.as<double>(), m, r.as<double>());
-        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, s, int(kSumSq), r.as<double>(), nullptr,
-                           m, sums.as<double>());
+        hipLaunchKernelGGL(k_ax_partial, dim3(row_blocks(), unsigned(chunks)), dim3(kB), 0, s, A,
+                           x, m, n, part);
+        hipLaunchKernelGGL(k_residual, dim3(row_blocks()), dim3(kB), 0, s, part, chunks, b, m, r);
+        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, s, int(kSumSq), r, nullptr, m, sums);
         PSL_HIP(hipGetLastError());
         sync_sums();
         return host_sums[kSumSq];
@@ -350,24 +347,109 @@ struct Solver {
     // One iteration step: kTrials Armijo trials, then (when one passed) the
     // gradient and the state update.
     void enqueue_step(const psl_nnls_opts* o) {
-        NnlsState* st = state.as<NnlsState>();
-        hipLaunchKernelGGL(k_trial_ax, dim3(row_blocks(), unsigned(chunks)), dim3(kB), 0, s,
-                           A.as<double>(), x.as<double>(), g.as<double>(), m, n, chunks,
-                           o->armijo_beta, st, xn.as<double>(), part.as<double>());
+        hipLaunchKernelGGL(k_trial_ax, dim3(row_blocks(), unsigned(chunks)), dim3(kB), 0, s, A, x,
+                           g, m, n, chunks, o->armijo_beta, state, xn, part);
         hipLaunchKernelGGL(k_trial_residual, dim3(row_blocks(), unsigned(kTrials)), dim3(kB), 0, s,
-                           part.as<double>(), chunks, b.as<double>(), m, st, r.as<double>(),
-                           rpart.as<double>());
-        hipLaunchKernelGGL(k_trial_select, dim3(1), dim3(kB), 0, s, rpart.as<double>(),
-                           int(row_blocks()), x.as<double>(), g.as<double>(), xn.as<double>(), n,
-                           o->armijo_sigma, o->armijo_beta, st);
-        hipLaunchKernelGGL(k_trial_grad, dim3(unsigned((n + kB / 64 - 1) / (kB / 64))), dim3(kB),
-                           0, s, A.as<double>(), r.as<double>(), m, n, st, gn.as<double>());
-        hipLaunchKernelGGL(k_accept, dim3(1), dim3(kB), 0, s, xn.as<double>(), gn.as<double>(), n,
-                           o->delta, pg_stop, o->max_iter, x.as<double>(), g.as<double>(), st);
+                           part, chunks, b, m, state, r, rpart);
+        hipLaunchKernelGGL(k_trial_select, dim3(1), dim3(kB), 0, s, rpart, int(row_blocks()), x, g,
+                           xn, n, o->armijo_sigma, o->armijo_beta, state);
+        hipLaunchKernelGGL(k_trial_grad, dim3(col_blocks()), dim3(kB), 0, s, A, r, m, n, state, gn);
+        hipLaunchKernelGGL(k_accept, dim3(1), dim3(kB), 0, s, xn, gn, n, o->delta, pg_stop,
+                           o->max_iter, x, g, state);
         PSL_HIP(hipGetLastError());
     }
-    double pg_stop = 0.0;
+
+    // F, grad F and the projected gradient at the start point x (already
+    // clamped to x >= 0); fro = ||A||_F^2.  Returns the initial state, which is
+    // also written to the device.
+    NnlsState start(const psl_nnls_opts* opts, double fro) {
+        NnlsState h{};
+        h.f = objective();
+        hipLaunchKernelGGL(k_atr, dim3(col_blocks()), dim3(kB), 0, s, A, r, m, n, g);
+        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, s, int(kSumSq), g, nullptr, n, sums);
+        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, s, int(kStats), x, g, n, sums);
+        PSL_HIP(hipGetLastError());
+        sync_sums();
+        const double g0 = std::sqrt(host_sums[kSumSq]);
+        pg_stop = opts->pg_tol * g0;
+        h.pg = std::sqrt(host_sums[kStats]);
+        h.s = fro > 0.0 ? 1.0 / fro : 1.0;
+        h.acc = -1;
+        h.converged = h.pg <= pg_stop;
+        h.done = h.converged || opts->max_iter == 0;
+        PSL_HIP(hipMemcpyAsync(state, &h, sizeof h, hipMemcpyHostToDevice, s));
+        PSL_HIP(hipStreamSynchronize(s));
+        return h;
+    }
+
+    // Runs iteration steps until the state says done, kStepsPerGraph steps
+    // between reads of the state: replayed from a captured graph, or (graph =
+    // false) launched directly.  Every step either rejects kTrials trials of
+    // the current iteration or completes it, and the state turns done at
+    // max_iter iterations or kMaxTrials rejected trials, so the loop ends.
+    void iterate(const psl_nnls_opts* opts, NnlsState& h, bool graph) {
+        if (h.done) return;
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t exec = nullptr;
+        struct Release {
+            hipStream_t s;
+            hipGraph_t& g;
+            hipGraphExec_t& e;
+            ~Release() {
+                // work still in flight (an error path) finishes before its graph goes
+                (void)hipStreamSynchronize(s);
+                if (e) (void)hipGraphExecDestroy(e);
+                if (g) (void)hipGraphDestroy(g);
+            }
+        } rel{s, gr, exec};
+        if (graph) {
+            PSL_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < kStepsPerGraph; ++k) enqueue_step(opts);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            PSL_HIP(hipStreamEndCapture(s, &gr));
+            PSL_HIP(hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0));
+        }
+        const int64_t max_replays =
+            opts->max_iter / kStepsPerGraph * (kMaxTrials / kTrials) + kMaxTrials;
+        for (int64_t rep = 0; !h.done; ++rep) {
+            PSL_CHECK(rep < max_replays, "commission_nnls: solver state did not advance");
+            if (graph) {
+                PSL_HIP(hipGraphLaunch(exec, s));
+            } else {
+                for (int k = 0; k < kStepsPerGraph; ++k) enqueue_step(opts);
+            }
+            PSL_HIP(hipMemcpyAsync(&h, state, sizeof h, hipMemcpyDeviceToHost, s));
+            PSL_HIP(hipStreamSynchronize(s));
+        }
+    }
 };
+
+void check_nnls_args(int64_t m, int64_t n, const psl_nnls_opts* opts) {
+    PSL_CHECK(m >= 1 && n >= 1, "m and n must be >= 1");
+    PSL_CHECK(m <= (int64_t(1) << 40) / n && n <= int64_t(65535) * kColChunk,
+              "commission_nnls: matrix too large");
+    PSL_CHECK(opts->armijo_sigma > 0 && opts->armijo_sigma < 1 && opts->armijo_beta > 0 &&
+                  opts->armijo_beta < 1 && opts->max_iter >= 0,
+              "bad Armijo parameters");
+}
+
+void fill_report(const NnlsState& h, psl_nnls_report* report, int& status) {
+    if (report) {
+        report->iters = h.it;
+        report->f = h.f;
+        report->pg_norm = h.pg;
+    }
+    if (!h.converged) {
+        status = PSL_ENOTCONV;
+        set_last_error("commission_nnls: iteration limit reached before convergence");
+    }
+}
 
 }  // namespace
 }  // namespace psl
@@ -379,90 +461,154 @@ extern "C" int commission_nnls(const double* A, int64_t m, int64_t n, const doub
     int status = PSL_OK;
     const int rc = guarded([&] {
         PSL_CHECK(A && b && x && opts, "commission_nnls: null argument");
-        PSL_CHECK(m >= 1 && n >= 1, "m and n must be >= 1");
-        PSL_CHECK(m <= (int64_t(1) << 40) / n && n <= int64_t(65535) * kColChunk,
-                  "commission_nnls: matrix too large");
-        PSL_CHECK(opts->armijo_sigma > 0 && opts->armijo_sigma < 1 && opts->armijo_beta > 0 &&
-                      opts->armijo_beta < 1 && opts->max_iter >= 0,
-                  "bad Armijo parameters");
+        check_nnls_args(m, n, opts);
         Solver S;
         S.m = m;
         S.n = n;
         S.chunks = int((n + kColChunk - 1) / kColChunk);
-        PSL_HIP(hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking));
-        S.A.alloc(size_t(m) * n * 8);
-        S.b.alloc(size_t(m) * 8);
-        S.x.alloc(size_t(n) * 8);
-        S.xn.alloc(size_t(n) * kTrials * 8);
-        S.g.alloc(size_t(n) * 8);
-        S.gn.alloc(size_t(n) * 8);
-        S.r.alloc(size_t(m) * kTrials * 8);
-        S.part.alloc(size_t(m) * S.chunks * kTrials * 8);
-        S.rpart.alloc(size_t(S.row_blocks()) * kTrials * 8);
-        S.sums.alloc(3 * 8);
-        S.state.alloc(sizeof(NnlsState));
+        DevBuf dA, db, dx, dxn, dg, dgn, dr, dpart, drpart, dsums, dstate;
+        struct StreamGuard {
+            hipStream_t s = nullptr;
+            ~StreamGuard() {
+                if (s) {
+                    (void)hipStreamSynchronize(s);
+                    (void)hipStreamDestroy(s);
+                }
+            }
+        } sg;
+        PSL_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+        S.s = sg.s;
+        dA.alloc(size_t(m) * n * 8);
+        db.alloc(size_t(m) * 8);
+        dx.alloc(size_t(n) * 8);
+        dxn.alloc(size_t(n) * kTrials * 8);
+        dg.alloc(size_t(n) * 8);
+        dgn.alloc(size_t(n) * 8);
+        dr.alloc(size_t(m) * kTrials * 8);
+        dpart.alloc(size_t(m) * S.chunks * kTrials * 8);
+        drpart.alloc(size_t(S.row_blocks()) * kTrials * 8);
+        dsums.alloc(3 * 8);
+        dstate.alloc(sizeof(NnlsState));
+        S.A = dA.as<double>();
+        S.b = db.as<double>();
+        S.x = dx.as<double>();
+        S.xn = dxn.as<double>();
+        S.g = dg.as<double>();
+        S.gn = dgn.as<double>();
+        S.r = dr.as<double>();
+        S.part = dpart.as<double>();
+        S.rpart = drpart.as<double>();
+        S.sums = dsums.as<double>();
+        S.state = dstate.as<NnlsState>();
         std::vector<double> x0(x, x + n);
         for (double& v : x0) v = v > 0.0 ? v : 0.0;
         double fro = 0.0;
         for (int64_t i = 0; i < m * n; ++i) fro += A[i] * A[i];
-        PSL_HIP(hipMemcpy(S.A.p, A, size_t(m) * n * 8, hipMemcpyHostToDevice));
-        PSL_HIP(hipMemcpy(S.b.p, b, size_t(m) * 8, hipMemcpyHostToDevice));
-        PSL_HIP(hipMemcpy(S.x.p, x0.data(), size_t(n) * 8, hipMemcpyHostToDevice));
+        PSL_HIP(hipMemcpy(dA.p, A, size_t(m) * n * 8, hipMemcpyHostToDevice));
+        PSL_HIP(hipMemcpy(db.p, b, size_t(m) * 8, hipMemcpyHostToDevice));
+        PSL_HIP(hipMemcpy(dx.p, x0.data(), size_t(n) * 8, hipMemcpyHostToDevice));
+        NnlsState h = S.start(opts, fro);
+        S.iterate(opts, h, true);
+        PSL_HIP(hipMemcpy(x, dx.p, size_t(n) * 8, hipMemcpyDeviceToHost));
+        fill_report(h, report, status);
+    });
+    return rc != PSL_OK ? rc : status;
+}
 
-        // F, grad F, |grad F| and the projected gradient at the start point
-        NnlsState h{};
-        h.f = S.objective();
-        hipLaunchKernelGGL(k_atr, dim3(unsigned((n + kB / 64 - 1) / (kB / 64))), dim3(kB), 0, S.s,
-                           S.A.as<double>(), S.r.as<double>(), m, n, S.g.as<double>());
-        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, S.s, int(kSumSq), S.g.as<double>(),
-                           nullptr, n, S.sums.as<double>());
-        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, S.s, int(kStats), S.x.as<double>(),
-                           S.g.as<double>(), n, S.sums.as<double>());
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the solver's vectors live in a fixed device array.
+// ---------------------------------------------------------------------------
+// One copy per device, held until the process ends.  Host code never uses
+// this name as an address: it reads the device address of the current
+// device's copy with hipGetSymbolAddress once and passes that pointer.
+static __device__ __align__(256) double scratch[PSL_NNLS_SCRATCH_BYTES / sizeof(double)];
+
+namespace psl {
+namespace {
+
+constexpr size_t kScratchBytes = PSL_NNLS_SCRATCH_BYTES;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_address() {
+    int dev = 0;
+    PSL_HIP(hipGetDevice(&dev));
+    PSL_CHECK(dev >= 0 && dev < kMaxDevices, "commission_nnls_noalloc: device index %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        PSL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        PSL_CHECK(p != nullptr, "commission_nnls_noalloc: no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Bytes of scratch a solve of an m x n system uses (each piece 256-byte aligned).
+size_t scratch_bytes(int64_t m, int64_t n) {
+    const int64_t chunks = (n + kColChunk - 1) / kColChunk;
+    const int64_t rb = (m + kB - 1) / kB;
+    auto up = [](int64_t doubles) { return (size_t(doubles) * 8 + 255) / 256 * 256; };
+    return up(n * kTrials) + 2 * up(n) + up(m * kTrials) + up(m * chunks * kTrials) +
+           up(rb * kTrials) + up(3) + (sizeof(NnlsState) + 255) / 256 * 256;
+}
+
+__global__ void __launch_bounds__(kB) k_clamp_nonneg(double* x, int64_t n) {
+    const int64_t i = blockIdx.x * int64_t(kB) + threadIdx.x;
+    if (i < n) x[i] = x[i] > 0.0 ? x[i] : 0.0;
+}
+
+}  // namespace
+}  // namespace psl
+
+extern "C" int commission_nnls_noalloc(const double* A_dev, int64_t m, int64_t n,
+                                       const double* b_dev, double* x_dev,
+                                       const psl_nnls_opts* opts, psl_nnls_report* report,
+                                       void* stream) {
+    int status = PSL_OK;
+    const int rc = guarded([&] {
+        PSL_CHECK(A_dev && b_dev && x_dev && opts, "commission_nnls_noalloc: null argument");
+        check_nnls_args(m, n, opts);
+        const size_t need = scratch_bytes(m, n);
+        PSL_CHECK(need <= kScratchBytes,
+                  "commission_nnls_noalloc: a %lld x %lld system needs %zu bytes of scratch, "
+                  "more than the %zu available",
+                  (long long)m, (long long)n, need, kScratchBytes);
+        char* base = static_cast<char*>(scratch_address());
+        auto take = [&base](size_t bytes) {
+            char* p = base;
+            base += (bytes + 255) / 256 * 256;
+            return p;
+        };
+        Solver S;
+        S.m = m;
+        S.n = n;
+        S.chunks = int((n + kColChunk - 1) / kColChunk);
+        S.s = static_cast<hipStream_t>(stream);
+        S.A = A_dev;
+        S.b = b_dev;
+        S.x = x_dev;
+        S.xn = reinterpret_cast<double*>(take(size_t(n) * kTrials * 8));
+        S.g = reinterpret_cast<double*>(take(size_t(n) * 8));
+        S.gn = reinterpret_cast<double*>(take(size_t(n) * 8));
+        S.r = reinterpret_cast<double*>(take(size_t(m) * kTrials * 8));
+        S.part = reinterpret_cast<double*>(take(size_t(m) * S.chunks * kTrials * 8));
+        S.rpart = reinterpret_cast<double*>(take(size_t(S.row_blocks()) * kTrials * 8));
+        S.sums = reinterpret_cast<double*>(take(3 * 8));
+        S.state = reinterpret_cast<NnlsState*>(take(sizeof(NnlsState)));
+        hipLaunchKernelGGL(k_clamp_nonneg, dim3(unsigned((n + kB - 1) / kB)), dim3(kB), 0, S.s,
+                           x_dev, n);
+        // ||A||_F^2 on the device (one block, fixed order), into sums[0]
+        hipLaunchKernelGGL(k_sums, dim3(1), dim3(1024), 0, S.s, int(kSumSq), A_dev, nullptr, m * n,
+                           S.sums);
         PSL_HIP(hipGetLastError());
         S.sync_sums();
-        const double g0 = std::sqrt(S.host_sums[kSumSq]);
-        S.pg_stop = opts->pg_tol * g0;
-        h.pg = std::sqrt(S.host_sums[kStats]);
-        h.s = fro > 0.0 ? 1.0 / fro : 1.0;
-        h.acc = -1;
-        h.converged = h.pg <= S.pg_stop;
-        h.done = h.converged || opts->max_iter == 0;
-        PSL_HIP(hipMemcpy(S.state.p, &h, sizeof h, hipMemcpyHostToDevice));
-
-        if (!h.done) {
-            PSL_HIP(hipStreamBeginCapture(S.s, hipStreamCaptureModeThreadLocal));
-            try {
-                for (int k = 0; k < kStepsPerGraph; ++k) S.enqueue_step(opts);
-            } catch (...) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(S.s, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            PSL_HIP(hipStreamEndCapture(S.s, &S.graph));
-            PSL_HIP(hipGraphInstantiate(&S.exec, S.graph, nullptr, nullptr, 0));
-            // Every step either rejects kTrials trials of the current iteration
-            // or completes it, and the state turns done at max_iter iterations or
-            // kMaxTrials rejected trials, so this loop ends.
-            const int64_t max_replays =
-                opts->max_iter / kStepsPerGraph * (kMaxTrials / kTrials) + kMaxTrials;
-            for (int64_t rep = 0; !h.done; ++rep) {
-                PSL_CHECK(rep < max_replays, "commission_nnls: solver state did not advance");
-                PSL_HIP(hipGraphLaunch(S.exec, S.s));
-                PSL_HIP(hipMemcpyAsync(&h, S.state.p, sizeof h, hipMemcpyDeviceToHost, S.s));
-                PSL_HIP(hipStreamSynchronize(S.s));
-            }
-        }
-        PSL_HIP(hipMemcpy(x, S.x.p, size_t(n) * 8, hipMemcpyDeviceToHost));
-        if (report) {
-            report->iters = h.it;
-            report->f = h.f;
-            report->pg_norm = h.pg;
-        }
-        if (!h.converged) {
-            status = PSL_ENOTCONV;
-            set_last_error("commission_nnls: iteration limit reached before convergence");
-        }
+        const double fro = S.host_sums[kSumSq];
+        NnlsState h = S.start(opts, fro);
+        S.iterate(opts, h, false);
+        fill_report(h, report, status);
     });
     return rc != PSL_OK ? rc : status;
 }
