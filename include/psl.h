@@ -253,7 +253,10 @@ int psl_transform_batch(const psl_plan* plan, const psl_phantom* phantom,
  * their energy, Highland Gaussian multiple scattering (ms_enable); absorbed
  * locally below e_cut_electron (Sec. 2.3 names the cut-offs). */
 typedef struct {
-    float e_cut_electron;   /* MeV, e.g. 0.2   */
+    float e_cut_electron;   /* MeV, e.g. 0.2; at least 30/255 MeV, so that a
+                               photon of up to 30 MeV (the top of the physics
+                               tables) sets at most 255 electrons in motion,
+                               the range of their 8-bit sub-stream ids      */
     float e_cut_photon;     /* MeV, e.g. 0.01  */
     float step_frac;        /* e.g. 0.1        */
     int32_t ms_enable;      /* 1 = on          */

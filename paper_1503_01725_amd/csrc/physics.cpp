@@ -84,6 +84,13 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     if (ph->t_cut_tab == p->e_cut_electron && ph->dens_tab == p->density_effect && ph->tabs.p) return;
     const double tcut = p->e_cut_electron;
     PSL_CHECK(tcut > 2.0e-3 && tcut < 10.0, "e_cut_electron must be in (0.002, 10) MeV");
+    // A photon pays at least the cut-off for every electron it sets in
+    // motion, and the electron's random sub-stream id (1 + its push index)
+    // has 8 bits in the particle tag: photons up to the top of the tables
+    // must not push more than 255 electrons.
+    PSL_CHECK(std::floor(kEmax / tcut) <= 255.0,
+              "e_cut_electron must be at least %.4f MeV (at most 255 electrons per photon of "
+              "up to %.0f MeV)", kEmax / 255.0, kEmax);
 
     std::vector<float> host(size_t(KN_TAB_N) + RNG_TAB_N + INV_TAB_N);
     float* kn = host.data();

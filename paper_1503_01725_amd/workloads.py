@@ -164,6 +164,14 @@ def water_phantom(n: int, vox: float, rho: float = 1.0) -> Phantom:
     return Phantom(dens, (vox, vox, vox), (-half, -half, 0.0))
 
 
+def water_box(nx: int, ny: int, nz: int, vox, rho: float = 1.0) -> Phantom:
+    """Water box of nx x ny x nz voxels of size vox = (dx, dy, dz) cm, top face
+    at z = 0 with the isocentre at its centre (SSD 100)."""
+    vox = tuple(float(v) for v in vox)
+    dens = np.full((nz, ny, nx), rho, dtype=np.float32)
+    return Phantom(dens, vox, (-nx * vox[0] / 2.0, -ny * vox[1] / 2.0, 0.0))
+
+
 def slab_phantom(n_xy: int, vox_xy: float, slabs, vox_z: float) -> Phantom:
     """Laterally uniform slabs stacked along z: ``slabs`` = [(n_vox_z, rho), ...]."""
     nz = sum(n for n, _ in slabs)
@@ -356,6 +364,9 @@ def workload(name: str, seed: int = 20150306) -> Workload:
       five coplanar fields and one at couch 90, 2e8 histories over all beams.
     * ``prostate_7beam``: pelvis-like phantom at 0.195 x 0.25 x 0.195 cm,
       seven coplanar fields, 2e8 histories over all beams.
+    * ``water240_table1``: the water phantom shape of the paper's efficiency
+      test (Table 1): 240 x 240 x 300 voxels of 0.25 x 0.25 x 0.2 cm (60 cm
+      cube), one 10x10 field, 1e8 histories.
     * ``commission60``: 60^3 water, fields 3/6/10/20 cm, 720 basis doses, 1e6
       histories per basis and field.
     """
@@ -367,6 +378,9 @@ def workload(name: str, seed: int = 20150306) -> Workload:
         size = float(name.split("_")[1])
         return Workload(name, model, water_phantom(128, 0.25), [square_beam(size)],
                         10 ** 8, 10, seed)
+    if name == "water240_table1":
+        return Workload(name, model, water_box(240, 240, 300, (0.25, 0.25, 0.2)),
+                        [square_beam(10.0)], 10 ** 8, 10, seed)
     if name == "hetero256_5beam":
         return Workload(name, model, hetero_phantom(seed), hetero_beams(seed),
                         2 * 10 ** 8, 10, seed)

@@ -3,7 +3,10 @@
 Tolerance: |gpu - oracle| <= 1e-6 * max(|oracle|, s) with s = 1 cm for
 positions, 1 for direction cosines, 1 MeV for energy.  The phantom entry point
 is the plane point moved a distance t along the direction, so its tolerance
-adds the direction tolerance times |t|.  Integer results (tally
+adds the direction tolerance times |t|; and t itself comes from the face the
+ray crosses, (face - p_i) / d_i, whose error is that of p_i and t d_i divided
+by |d_i|, so the whole bound is scaled by 1 + 1/|d_i| (a ray that grazes the
+face, |d_i| small, has an ill-conditioned entry point).  Integer results (tally
 tag, history id) must be equal.  A status flip is accepted only where the
 oracle puts the particle within 1e-5 cm of a jaw edge, within 1e-4 cm of a
 phantom edge, or (scatter) within 1e-5 cm of a ring edge (where the PSR and so
@@ -45,7 +48,21 @@ def _plane_to_entry(ref, beams):
     return t
 
 
-def _check_segment(gpu, ref, stype, beams):
+def _entry_normal_component(ref, phantom):
+    """|d_i| for the face of the phantom box on which the oracle's entry point
+    lies (the largest over the faces it touches; 1 where it lies on none,
+    which happens only for rejected histories)."""
+    nz, ny, nx = phantom.density.shape
+    lo = np.asarray(phantom.origin, dtype=np.float64)
+    hi = lo + np.array([nx, ny, nz]) * np.asarray(phantom.vox, dtype=np.float64)
+    comp = np.zeros(len(ref))
+    for k, (f, df) in enumerate((("x", "u"), ("y", "v"), ("z", "w"))):
+        on = (np.abs(ref[f] - lo[k]) < 1e-9) | (np.abs(ref[f] - hi[k]) < 1e-9)
+        comp = np.where(on, np.maximum(comp, np.abs(ref[df])), comp)
+    return np.where(comp > 0, comp, 1.0)
+
+
+def _check_segment(gpu, ref, stype, beams, phantom):
     ok_flip = (ref["jaw_margin"] < 1e-5) | (np.abs(ref["box_margin"]) < 1e-4)
     if stype == 1:
         ok_flip |= ref["ring_margin"] < 1e-5
@@ -58,8 +75,10 @@ def _check_segment(gpu, ref, stype, beams):
     acc = m & (ref["status"] == 0)
     rej = m & (ref["status"] != 0)
     slant = _plane_to_entry(ref, beams)
+    cond = 1.0 + 1.0 / _entry_normal_component(ref, phantom)
     for f in ("x", "y", "z"):
-        good = np.abs(gpu[f] - ref[f]) <= 1e-6 * (np.maximum(np.abs(ref[f]), 1.0) + slant)
+        good = (np.abs(gpu[f] - ref[f])
+                <= 1e-6 * (np.maximum(np.abs(ref[f]), 1.0) + slant) * cond)
         assert good[acc].all(), (f, np.flatnonzero(acc & ~good)[:5])
     for f in ("u", "v", "w"):
         good = _close(gpu[f], ref[f], 1.0)
@@ -72,7 +91,7 @@ def _check_segment(gpu, ref, stype, beams):
 
 
 @pytest.mark.parametrize("name,n_hist", [("water60_10x10", 100000), ("hetero256_5beam", 150000),
-                                         ("hn_6beam", 120000)])
+                                         ("hn_6beam", 120000), ("prostate_7beam", 140000)])
 def test_sample_batch_matches_oracle(eng, N, orc, wl, name, n_hist):
     W = wl.workload(name)
     model = eng.Model(W.model)
@@ -91,8 +110,55 @@ def test_sample_batch_matches_oracle(eng, N, orc, wl, name, n_hist):
         gpu = _dense_sample(eng, N, plan, ph, tally, rep, seed, b.h0, b.n)
         ref = orc.sample(W.model, oplan, W.beams, W.phantom, seed, rep * n_hist + b.h0, b.n)
         assert np.array_equal(gpu["hid"], rep * n_hist + b.h0 + np.arange(b.n, dtype=np.uint64))
-        totals += _check_segment(gpu, ref, b.stype, W.beams)
+        totals += _check_segment(gpu, ref, b.stype, W.beams, W.phantom)
     assert totals[0] > 1000 and totals[1] > 1000
+
+
+@pytest.mark.parametrize("name,n_hist", [("water60_10x10", 100000), ("hetero256_5beam", 150000),
+                                         ("hn_6beam", 120000), ("prostate_7beam", 140000)])
+def test_plane_records_match_oracle(eng, N, orc, wl, name, n_hist):
+    """Phase-space-plane records (PSL_SAMPLE_PLANE: the particle-file source,
+    Sec. 3.1) against the oracle's beam-frame plane sample of the same
+    histories: position at the plane, direction, energy, column and beam,
+    every history (jaw-rejected ones included, since the records precede the
+    jaws).  Status: 3 where the oracle finds an invalid direction, else 0.
+    Scatter histories within 1e-5 cm of a ring edge may take the neighbouring
+    ring's direction parameters and are excluded from the value comparison."""
+    import torch
+    W = wl.workload(name)
+    model = eng.Model(W.model)
+    plan = eng.Plan(model, W.beams, n_hist, n_replica=2)
+    ph = eng.Phantom(W.phantom)
+    tally = eng.Tally(ph)
+    ref_w, _ = orc.psl_build(W.model)
+    oplan = orc.plan_build(W.model, ref_w, W.beams, n_hist)
+    seed = 0x9A7E_0001
+    rep = 1
+    nb = plan.set_batching(1 << 30, 24)
+    n_cmp = 0
+    for i in range(nb):
+        b = plan.batch(i)
+        print(f"[plane parity] {name} batch {i} stype {b.stype} beam {b.beam} n {b.n}", flush=True)
+        st = eng.Particles(b.n)
+        N.sample_batch(plan.h, ph.h, rep, b.h0, b.n, seed, st.c, N.PSL_SAMPLE_PLANE, tally.h,
+                       eng._stream_ptr())
+        torch.cuda.synchronize()
+        gpu = st.host(b.n)
+        ref = orc.sample(W.model, oplan, W.beams, W.phantom, seed, rep * n_hist + b.h0, b.n)
+        assert np.array_equal(gpu["hid"], rep * n_hist + b.h0 + np.arange(b.n, dtype=np.uint64))
+        assert np.array_equal(gpu["tag"], ref["tag"].astype(np.uint32))
+        assert np.array_equal(gpu["sub"], ref["beam"].astype(np.uint32))
+        invalid = ref["status"] == 3
+        ok = (ref["ring_margin"] >= 1e-5) if b.stype == 1 else np.ones(b.n, dtype=bool)
+        assert np.array_equal(gpu["status"][ok], np.where(invalid, 3, 0)[ok])
+        assert np.all(gpu["z"] == 0.0)
+        m = ok & ~invalid
+        for f, rf in (("x", "xb"), ("y", "yb"), ("u", "ub"), ("v", "vb"), ("w", "wb"),
+                      ("e", "e")):
+            good = _close(gpu[f], ref[rf], 1.0)
+            assert good[m].all(), (f, np.flatnonzero(m & ~good)[:5])
+        n_cmp += int(m.sum())
+    assert n_cmp > 0.99 * n_hist
 
 
 def test_sample_compacted_equals_dense(eng, N, wl):

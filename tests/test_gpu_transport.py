@@ -43,7 +43,11 @@ def _closure(led):
     return (led["src"] - sum(led[k] for k in LEDGER_OUT)) / led["src"]
 
 
-def _agreement(d1, s1, d2, s2):
+def _agreement(d1, s1, d2, s2, mask=None):
+    """Fraction of the voxels above 10 % of Dmax (over `mask`, default all)
+    where the doses differ by less than 2 sigma of the difference."""
+    if mask is not None:
+        d1, s1, d2, s2 = d1[mask], s1[mask], d2[mask], s2[mask]
     hi = d2 > 0.1 * d2.max()
     sd = np.sqrt(s1 ** 2 + s2 ** 2)
     ok = np.abs(d1 - d2) < 2 * sd
@@ -127,6 +131,46 @@ def test_noncoplanar_anisotropic_matches_oracle(eng, orc, wl):
     assert frac >= 0.95, frac
 
 
+def test_prostate_plan_matches_oracle(eng, orc, wl):
+    """The prostate plan shape (seven coplanar fields) on a pelvis-like
+    phantom with the paper's prostate voxel proportions (0.195 x 0.25 x 0.195
+    cm, here scaled by 2.5 to keep the oracle short), bone and a gas pocket.
+    The body lies in air (0.0012 g/cm^3), where a single deposit gives a dose
+    (E / rho V) far above any in tissue, so Dmax and the voxel comparison are
+    taken over the voxels of the body (rho >= 0.1)."""
+    W0 = wl.workload("prostate_7beam")
+    small = wl.pelvis_phantom(20150306, nx=80, ny=40, nz=52, vox=(0.4875, 0.625, 0.4875))
+    W = wl.Workload("prostate_small", W0.model, small, W0.beams, 10 ** 6, 10, 5)
+    print("[transport parity] oracle prostate_small", flush=True)
+    d_ref, s_ref, led_ref, cnt_ref = _oracle_run(orc, W, 100000, 71)
+    print("[transport parity] gpu prostate_small", flush=True)
+    d, s, led, cnt, plan = _gpu_run(eng, W, 100000, 71)
+    assert abs(_closure(led)) < 1e-5
+    assert led["dep"] == pytest.approx(led_ref["dep"], rel=1e-3)
+    assert cnt["real"] == pytest.approx(cnt_ref["real"], rel=3e-3)
+    body = small.density.ravel() >= 0.1
+    frac, nvox = _agreement(d, s, d_ref, s_ref, mask=body)
+    assert nvox > 1000 and frac >= 0.95, frac
+
+
+def test_table1_water_voxels_match_oracle(eng, orc, wl):
+    """Water with the voxel shape of the paper's efficiency test (Table 1:
+    0.25 x 0.25 x 0.2 cm), a 10 x 10 field; a 64 x 64 x 80 box (16 x 16 x 16
+    cm) stands in for the 240 x 240 x 300 one to keep the oracle short."""
+    W0 = wl.workload("water240_table1")
+    small = wl.water_box(64, 64, 80, (0.25, 0.25, 0.2))
+    W = wl.Workload("table1_small", W0.model, small, W0.beams, 2 * 10 ** 6, 10, 5)
+    print("[transport parity] oracle table1_small", flush=True)
+    d_ref, s_ref, led_ref, cnt_ref = _oracle_run(orc, W, 200000, 73)
+    print("[transport parity] gpu table1_small", flush=True)
+    d, s, led, cnt, plan = _gpu_run(eng, W, 200000, 73)
+    assert abs(_closure(led)) < 1e-5
+    assert led["dep"] == pytest.approx(led_ref["dep"], rel=1e-3)
+    assert cnt["e_boundary"] == pytest.approx(cnt_ref["e_boundary"], rel=3e-3)
+    frac, nvox = _agreement(d, s, d_ref, s_ref)
+    assert nvox > 1000 and frac >= 0.95, frac
+
+
 def test_dose_with_density_effect_matches_oracle(eng, orc, wl):
     """Collision stopping power less the density-effect correction on both
     sides: same parity bar as the plain method, and the electrons travel
@@ -179,3 +223,21 @@ def test_electron_csda_path_matches_range(eng, N, orc, wl, dens):
     assert led["e_path"] == pytest.approx(expect, rel=2e-4)
     assert led["dep"] == pytest.approx(float(e0.astype(np.float64).sum()), rel=1e-6)
     assert led["esc_e"] == 0.0
+
+
+def test_electron_cutoff_below_push_limit_is_refused(eng, N, wl):
+    """An electron cut-off under 30/255 MeV would let a photon at the top of
+    the tables push more electrons than the 8-bit sub-stream id holds: the
+    call is refused before any device work."""
+    ph = eng.Phantom(wl.water_phantom(8, 1.0))
+    tally = eng.Tally(ph)
+    st = eng.Particles(64)
+    el = eng.Particles(64 * 300)
+    st.zero_count()
+    with pytest.raises(N.PslError) as e:
+        N.transport_batch(ph.h, st.c, el.c, tally.h, eng.transport_params(e_cut_electron=0.1), 1,
+                          eng._stream_ptr())
+    assert e.value.code == N.PSL_EINVAL and "e_cut_electron" in str(e.value)
+    N.transport_batch(ph.h, st.c, el.c, tally.h, eng.transport_params(e_cut_electron=0.12), 1,
+                      eng._stream_ptr())
+

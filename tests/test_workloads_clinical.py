@@ -27,3 +27,15 @@ def test_prostate_workload():
     g = [b.gantry_deg for b in W.beams]
     assert len(g) == 7 and np.allclose(np.diff(g), 360.0 / 7)
     assert all(b.couch_deg == 0.0 for b in W.beams)
+
+
+def test_table1_water_workload():
+    """Table 1's water phantom: 240 x 240 x 300 voxels of 0.25 x 0.25 x 0.2 cm,
+    top face at z = 0 centred on the isocentre."""
+    W = wl.workload("water240_table1")
+    ph = W.phantom
+    assert ph.vox == (0.25, 0.25, 0.2)
+    assert ph.density.shape == (300, 240, 240)
+    assert np.allclose(ph.origin, (-30.0, -30.0, 0.0))
+    assert float(ph.density.min()) == float(ph.density.max()) == 1.0
+    assert len(W.beams) == 1 and W.beams[0].x2 - W.beams[0].x1 == 10.0
