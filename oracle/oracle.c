@@ -55,7 +55,8 @@ enum { OR_SUB_PRIMARY = 0, OR_SUB_SCATTER = 1, OR_SUB_ELECTRON = 2 };
 enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, L_N };
 /* counters[] slots */
 enum { C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS,
-       C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_N = 16 };
+       C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD,
+       C_PHOTO = 14, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_N = 20 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
@@ -155,6 +156,7 @@ typedef struct {
     double e_cut_e, e_cut_g, step_frac;
     int32_t ms_enable;
     int32_t density_effect;  /* 1 = collision stopping power with delta(T) */
+    int32_t physics;         /* OR_PHYS_* bits: photoelectric, Rayleigh, pair */
 } or_params;
 
 typedef struct {
@@ -740,6 +742,287 @@ void or_kn_sample_cos(double e, uint64_t seed, int n, double* cos_out)
     }
 }
 
+/* Gauss-Legendre nodes/weights on [-1, 1] from Newton iteration on P_n. */
+#define OR_GL_N 8
+static double gl_x[OR_GL_N], gl_w[OR_GL_N];
+static void gl_init(void)
+{
+    const int n = OR_GL_N;
+    for (int i = 0; i < n; ++i) {
+        double z = cos(OR_PI * ((double)i + 0.75) / ((double)n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabs(z - z1) < 1e-16) break;
+        }
+        gl_x[i] = z;
+        gl_w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fuller photon physics, each switchable: photoelectric absorption, Rayleigh */
+/* (coherent) scattering and pair production in water.  The paper's engine    */
+/* models them (Sec. 2.3 names only its cut-offs) without giving forms; the   */
+/* forms below are published analytic ones.                                   */
+/* ------------------------------------------------------------------------ */
+#define OR_ALPHA 7.2973525693e-3          /* fine-structure constant */
+#define OR_A0 0.529177210903e-8           /* Bohr radius, cm */
+#define OR_RY 13.605693122994e-6          /* Rydberg energy, MeV */
+#define OR_HBARC 1.973269804e-11          /* hbar c, MeV cm */
+#define OR_ZETA3 1.2020569031595942       /* Riemann zeta(3) */
+#define OR_MOL_PER_G (OR_NA / 18.0153)    /* water molecules per gram */
+/* Slater-screened nuclear charges seen by oxygen's 1s and n = 2 electrons
+ * (Slater's rules: 8 - 0.30 and 8 - 2 x 0.85 - 5 x 0.35). */
+#define OR_Z_O_1S 7.70
+#define OR_Z_O_2 4.55
+enum { OR_PHYS_PHOTO = 1, OR_PHYS_RAYLEIGH = 2, OR_PHYS_PAIR = 4 };
+
+/* Photoeffect cross-section (cm^2) of one electron of a hydrogenic K shell of
+ * nuclear charge z, in Stobbe's exact non-relativistic form:
+ *   sigma = (2^9 pi^2 / 3) alpha (a0/z)^2 (I/E)^4 exp(-4 nu arccot nu)
+ *           / (1 - exp(-2 pi nu)),   I = z^2 Ry,  nu = sqrt(I / (E - I)),
+ * zero below the edge E = I. */
+double or_sigma_k_electron(double e, double z)
+{
+    double i_k = z * z * OR_RY;
+    if (!(e > i_k)) return 0.0;
+    double nu = sqrt(i_k / (e - i_k));
+    double r = i_k / e;
+    double a = OR_A0 / z;
+    return 512.0 * OR_PI * OR_PI / 3.0 * OR_ALPHA * a * a * r * r * r * r *
+           exp(-4.0 * nu * atan(1.0 / nu)) / (-expm1(-2.0 * OR_PI * nu));
+}
+
+/* Binding energy of oxygen's K shell in the same hydrogenic model (MeV). */
+double or_photo_binding(void) { return OR_Z_O_1S * OR_Z_O_1S * OR_RY; }
+
+/* Photoelectric attenuation of water per unit density (cm^2/g): the two K
+ * electrons of oxygen (hydrogen's and oxygen's outer shells neglected). */
+double or_mu_photo(double e)
+{
+    return OR_MOL_PER_G * 2.0 * or_sigma_k_electron(e, OR_Z_O_1S);
+}
+
+/* Form factors of one hydrogenic electron, from the Fourier transform of its
+ * charge density, in s = q a0 / z (q the momentum transfer in 1/cm):
+ *   1s: 1 / (1 + s^2/4)^2,  2s: (1 - 3 s^2 + 2 s^4) / (1 + s^2)^4,
+ *   2p (orientation averaged): (1 - s^2) / (1 + s^2)^4. */
+static double ff_1s(double s) { double a = 1.0 + 0.25 * s * s; return 1.0 / (a * a); }
+static double ff_2s(double s)
+{
+    double s2 = s * s, d = 1.0 + s2, d2 = d * d;
+    return (1.0 - 3.0 * s2 + 2.0 * s2 * s2) / (d2 * d2);
+}
+static double ff_2p(double s)
+{
+    double s2 = s * s, d = 1.0 + s2, d2 = d * d;
+    return (1.0 - s2) / (d2 * d2);
+}
+
+/* Squared form factor of a water molecule as independent atoms (interference
+ * between the atoms neglected) at t = (q a0)^2: two hydrogen 1s electrons
+ * (z = 1) and oxygen 1s^2 2s^2 2p^4 with the screened charges above.
+ * F^2(0) = 1 + 1 + 8^2 = 66. */
+double or_ff2_water(double t)
+{
+    double q = sqrt(t);
+    double fh = ff_1s(q);
+    double fo = 2.0 * ff_1s(q / OR_Z_O_1S) + 2.0 * ff_2s(q / OR_Z_O_2) + 4.0 * ff_2p(q / OR_Z_O_2);
+    return 2.0 * fh * fh + fo * fo;
+}
+
+/* Cumulative A(t) = integral_0^t F^2(t') dt' on panels whose ends are spaced
+ * logarithmically (8-point Gauss-Legendre per panel); A(t) between the ends
+ * by the same rule over the partial panel. */
+#define OR_FF_N 4000
+#define OR_FF_TLO 1e-6
+#define OR_FF_THI 1e10
+static double ff_t[OR_FF_N + 1], ff_a[OR_FF_N + 1];
+static int ff_ready = 0;
+
+static double gl_ff2(double a, double b)
+{
+    double m = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
+    for (int i = 0; i < 8; ++i) s += gl_w[i] * or_ff2_water(m + h * gl_x[i]);
+    return h * s;
+}
+
+static void ff_init(void)
+{
+    if (ff_ready) return;
+    gl_init();
+    ff_t[0] = 0.0;
+    ff_a[0] = 0.0;
+    double r = pow(OR_FF_THI / OR_FF_TLO, 1.0 / (OR_FF_N - 1));
+    for (int i = 1; i <= OR_FF_N; ++i) {
+        ff_t[i] = OR_FF_TLO * pow(r, i - 1);
+        ff_a[i] = ff_a[i - 1] + gl_ff2(ff_t[i - 1], ff_t[i]);
+    }
+    ff_ready = 1;
+}
+
+/* index i of the panel [t_i, t_i+1] holding t (t < t_N) */
+static int ff_panel(double t)
+{
+    int lo = 0, hi = OR_FF_N;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (ff_t[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+double or_ff2_cumulative(double t)
+{
+    ff_init();
+    if (t >= ff_t[OR_FF_N]) t = ff_t[OR_FF_N];
+    int i = ff_panel(t);
+    return ff_a[i] + gl_ff2(ff_t[i], t);
+}
+
+/* The t with A(t) = a, for 0 <= a <= A(t_N): the panel by bisection on the
+ * cumulative, then bisection on t inside it. */
+static double ff_invert(double a)
+{
+    int lo = 0, hi = OR_FF_N;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (ff_a[mid] <= a) lo = mid; else hi = mid;
+    }
+    double tl = ff_t[lo], th = ff_t[hi];
+    for (int it = 0; it < 200 && th - tl > 1e-15 * th; ++it) {
+        double tm = 0.5 * (tl + th);
+        if (ff_a[lo] + gl_ff2(ff_t[lo], tm) <= a) tl = tm; else th = tm;
+    }
+    return 0.5 * (tl + th);
+}
+
+/* k a0 for a photon of energy e (MeV): (q a0)^2 ranges over [0, 4 (k a0)^2]. */
+static double ka0_of(double e) { return e * OR_A0 / OR_HBARC; }
+
+/* Rayleigh cross-section of a water molecule (cm^2): the Thomson differential
+ * cross-section (r_e^2/2)(1 + cos^2 theta) times F^2, with
+ * cos theta = 1 - t / (2 x^2), x = k a0, integrated over the sphere:
+ *   sigma = pi r_e^2 / (2 x^2) * integral_0^{4x^2} (1 + cos^2 theta) F^2(t) dt. */
+double or_sigma_rayleigh(double e)
+{
+    ff_init();
+    double x = ka0_of(e), x2 = x * x, tm = 4.0 * x2;
+    double sum = 0.0;
+    for (int i = 0; i < OR_FF_N && ff_t[i] < tm; ++i) {
+        double a = ff_t[i], b = ff_t[i + 1] < tm ? ff_t[i + 1] : tm;
+        double m = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
+        for (int j = 0; j < 8; ++j) {
+            double t = m + h * gl_x[j], c = 1.0 - t / (2.0 * x2);
+            s += gl_w[j] * (1.0 + c * c) * or_ff2_water(t);
+        }
+        sum += h * s;
+    }
+    return OR_PI * OR_RE * OR_RE / (2.0 * x2) * sum;
+}
+
+double or_mu_rayleigh(double e) { return OR_MOL_PER_G * or_sigma_rayleigh(e); }
+
+/* Rayleigh polar angle: t drawn from F^2 on [0, 4x^2] by inverting the
+ * cumulative (one uniform), accepted with (1 + cos^2 theta)/2 (one uniform),
+ * repeated until accepted.  Returns cos theta. */
+static double rayleigh_sample(or_stream* st, double e)
+{
+    ff_init();
+    double x = ka0_of(e), x2 = x * x;
+    double amax = or_ff2_cumulative(4.0 * x2);
+    for (;;) {
+        double u1 = stream_u01(st), u2 = stream_u01(st);
+        double t = ff_invert(u1 * amax);
+        double c = 1.0 - t / (2.0 * x2);
+        if (c < -1.0) c = -1.0;
+        if (u2 <= 0.5 * (1.0 + c * c)) return c;
+    }
+}
+
+/* test hook: n Rayleigh scattering cosines at energy e (stream g = i) */
+void or_rayleigh_sample_cos(double e, uint64_t seed, int n, double* cos_out)
+{
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        cos_out[i] = rayleigh_sample(&st, e);
+    }
+}
+
+/* Pair production in the field of a nucleus, unscreened Bethe-Heitler, per
+ * unit Z^2 (cm^2), in Maximon's expansions (k = E / mc^2):
+ *   2 < k < 4:  (2 pi/3) alpha r_e^2 ((k-2)/k)^3 (1 + e/2 + 23e^2/40 + 11e^3/60
+ *               + 29e^4/960),  e = (2k - 4)/(2 + k + 2 sqrt(2k));
+ *   k >= 4:     alpha r_e^2 [28/9 L - 218/27 + (2/k)^2 (6L - 7/2 + 2/3 L^3 - L^2
+ *               - pi^2/3 L + 2 zeta(3) + pi^2/6) - (2/k)^4 (3/16 L + 1/8)
+ *               - (2/k)^6 (29/(9*256) L - 77/(27*512))],  L = ln 2k. */
+double or_sigma_pair_z2(double e)
+{
+    double k = e / OR_ME;
+    if (!(k > 2.0)) return 0.0;
+    double ar2 = OR_ALPHA * OR_RE * OR_RE;
+    if (k < 4.0) {
+        double ep = (2.0 * k - 4.0) / (2.0 + k + 2.0 * sqrt(2.0 * k));
+        double r = (k - 2.0) / k;
+        return 2.0 * OR_PI / 3.0 * ar2 * r * r * r *
+               (1.0 + ep / 2.0 + 23.0 * ep * ep / 40.0 + 11.0 * ep * ep * ep / 60.0 +
+                29.0 * ep * ep * ep * ep / 960.0);
+    }
+    double l = log(2.0 * k), q2 = (2.0 / k) * (2.0 / k);
+    return ar2 * (28.0 / 9.0 * l - 218.0 / 27.0 +
+                  q2 * (6.0 * l - 3.5 + 2.0 / 3.0 * l * l * l - l * l - OR_PI * OR_PI / 3.0 * l +
+                        2.0 * OR_ZETA3 + OR_PI * OR_PI / 6.0) -
+                  q2 * q2 * (3.0 / 16.0 * l + 0.125) -
+                  q2 * q2 * q2 * (29.0 / (9.0 * 256.0) * l - 77.0 / (27.0 * 512.0)));
+}
+
+/* Pair attenuation of water per unit density (cm^2/g): sum of Z^2 over the
+ * molecule's nuclei, 1 + 1 + 64 = 66 (production on the electrons neglected). */
+double or_mu_pair(double e) { return OR_MOL_PER_G * 66.0 * or_sigma_pair_z2(e); }
+
+/* Fraction eps of the pair's kinetic energy E - 2mc^2 that the electron takes:
+ * density proportional to eps^2 + (1-eps)^2 + (2/3) eps (1-eps) = 1 - (4/3)
+ * eps (1-eps) on [0, 1] (the Bethe-Heitler sharing without its logarithmic
+ * factor), by rejection from the uniform (two uniforms a trial). */
+static double pair_share_sample(or_stream* st)
+{
+    for (;;) {
+        double u1 = stream_u01(st), u2 = stream_u01(st);
+        if (u2 <= 1.0 - 4.0 / 3.0 * u1 * (1.0 - u1)) return u1;
+    }
+}
+
+/* test hook: n pair energy shares (stream g = i) */
+void or_pair_share_sample(uint64_t seed, int n, double* out)
+{
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        out[i] = pair_share_sample(&st);
+    }
+}
+
+/* Attenuation of water per unit density (cm^2/g) of the enabled processes;
+ * parts[4] (nullable) receives Compton, photoelectric, Rayleigh, pair. */
+double or_mu_total(double e, int32_t physics, double parts[4])
+{
+    double mc = ne_water() * or_kn_sigma(e);
+    double mp = (physics & OR_PHYS_PHOTO) ? or_mu_photo(e) : 0.0;
+    double mr = (physics & OR_PHYS_RAYLEIGH) ? or_mu_rayleigh(e) : 0.0;
+    double mx = (physics & OR_PHYS_PAIR) ? or_mu_pair(e) : 0.0;
+    if (parts) { parts[0] = mc; parts[1] = mp; parts[2] = mr; parts[3] = mx; }
+    return mc + mp + mr + mx;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Electron physics: Bethe collision stopping power (ICRU 37 form, optionally */
 /* with the density-effect correction), CSDA range and its inverse, Highland  */
@@ -782,31 +1065,6 @@ double or_s_col_d(double t, int dens)
     return 2.0 * OR_PI * OR_RE * OR_RE * OR_ME * OR_NA * OR_ZA_WATER / beta2 * bracket;
 }
 double or_s_col(double t) { return or_s_col_d(t, 0); }
-
-/* Gauss-Legendre nodes/weights on [-1, 1] from Newton iteration on P_n. */
-#define OR_GL_N 8
-static double gl_x[OR_GL_N], gl_w[OR_GL_N];
-static void gl_init(void)
-{
-    const int n = OR_GL_N;
-    for (int i = 0; i < n; ++i) {
-        double z = cos(OR_PI * ((double)i + 0.75) / ((double)n + 0.5)), pp = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double p1 = 1.0, p2 = 0.0;
-            for (int j = 1; j <= n; ++j) {
-                double p3 = p2;
-                p2 = p1;
-                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
-            }
-            pp = n * (z * p1 - p2) / (z * z - 1.0);
-            double z1 = z;
-            z = z1 - p1 / pp;
-            if (fabs(z - z1) < 1e-16) break;
-        }
-        gl_x[i] = z;
-        gl_w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
-    }
-}
 
 static double gl_panel_inv_s(double a, double b, int dens)
 {
@@ -989,24 +1247,53 @@ static void deposit(or_tracker* T, int64_t v, double e, int32_t tag)
 /* Condensed-history electron (CSDA + Highland Gaussian deflections).
  * Steps end at voxel faces or after a fractional energy loss step_frac;
  * the voxel index is carried explicitly and changes by one at each face. */
+static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
+                             uint64_t seed, uint64_t g, int32_t tag, int secondary);
+
+/* A positron that has come to rest at p annihilates into two photons of mc^2
+ * each, back to back, the first along an isotropic direction (cos theta =
+ * 2u - 1, phi = 2 pi u', two uniforms of the positron's stream).  Each photon
+ * is followed as a photon history of its own, id g | (2 sub + k) << 48 (the
+ * history ids of a plan stay below 2^48). */
+static void annihilate(or_tracker* T, or_stream* st, const double p[3], uint64_t seed,
+                       uint64_t g, uint32_t sub, int32_t tag)
+{
+    double c = 2.0 * stream_u01(st) - 1.0, phi = 2.0 * OR_PI * stream_u01(st);
+    double sn = sqrt(1.0 - c * c);
+    double da[3] = {sn * cos(phi), sn * sin(phi), c};
+    T->cnt[C_ANNIHIL]++;
+    for (int k = 0; k < 2; ++k) {
+        double pp[3] = {p[0], p[1], p[2]};
+        double dd[3] = {k ? -da[0] : da[0], k ? -da[1] : da[1], k ? -da[2] : da[2]};
+        transport_photon(T, pp, dd, OR_ME, seed, g | ((uint64_t)(2u * sub + (uint32_t)k) << 48),
+                         tag, 1);
+    }
+}
+
 static void transport_electron(or_tracker* T, double p[3], double d[3], double e,
-                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag)
+                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag, int positron)
 {
     const or_phantom* ph = T->ph;
     const double tcut = T->tp->e_cut_e, f = T->tp->step_frac;
     const int n[3] = {ph->nx, ph->ny, ph->nz};
     int idx[3];
     voxel_clamped(ph, p, idx);
+    or_stream st;
+    stream_init(&st, seed, g, OR_TAG_TR, sub);
     if (e < tcut) {
         deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
         T->cnt[C_E_LOCAL]++;
+        if (positron) annihilate(T, &st, p, seed, g, sub, tag);
         return;
     }
-    or_stream st;
-    stream_init(&st, seed, g, OR_TAG_TR, sub);
     for (int step = 0;; ++step) {
         int64_t v = ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
-        if (step >= OR_MAX_E_STEPS) { deposit(T, v, e, tag); T->cnt[C_GUARD]++; return; }
+        if (step >= OR_MAX_E_STEPS) {
+            deposit(T, v, e, tag);
+            T->cnt[C_GUARD]++;
+            if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+            return;
+        }
         double rho = (double)ph->density[v];
         /* distance to the exit face of the current voxel */
         double sb = OR_INF;
@@ -1033,6 +1320,7 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
                 /* the residual range ends inside this voxel */
                 T->ledger[L_EPATH] += sf;
                 deposit(T, v, e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
                 return;
             }
             double e_new = range_inverse(T->rt, r0 - rho * sf);
@@ -1041,7 +1329,11 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
             T->ledger[L_EPATH] += sf;
             double e_old = e;
             e = e_new;
-            if (e < tcut) { deposit(T, v, e, tag); return; }
+            if (e < tcut) {
+                deposit(T, v, e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+                return;
+            }
             if (T->tp->ms_enable) {
                 double th0 = or_ms_width(0.5 * (e_old + e), rho, sf);
                 double u1 = stream_u01(&st), u2 = stream_u01(&st);
@@ -1056,9 +1348,15 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
             double e_old = e;
             e = e_new;
             idx[axis] += d[axis] > 0.0 ? 1 : -1;
-            if (idx[axis] < 0 || idx[axis] >= n[axis]) { T->ledger[L_ESC_E] += e; return; }
+            if (idx[axis] < 0 || idx[axis] >= n[axis]) {
+                /* an escaping positron takes its rest energy (2 mc^2, the
+                 * annihilation photons') out of the phantom as well */
+                T->ledger[L_ESC_E] += e + (positron ? 2.0 * OR_ME : 0.0);
+                return;
+            }
             if (e < tcut) {
                 deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
                 return;
             }
             if (T->tp->ms_enable) {
@@ -1070,25 +1368,45 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
     }
 }
 
-typedef struct { double p[3], d[3], e; uint32_t sub; } or_electron;
+typedef struct { double p[3], d[3], e; uint32_t sub; int positron; } or_electron;
 
-/* Woodcock (delta) tracking with the majorant mu_max(E) = n_e rho_max sigma_KN(E);
- * a tentative collision is real with probability rho_voxel / rho_max.
- * Compton electrons at or above the electron cut-off are transported, below it
- * deposited on the spot; the photon is absorbed locally below its cut-off. */
+/* Woodcock (delta) tracking with the majorant mu_max(E) = rho_max mu(E), mu
+ * the attenuation per unit density of the enabled processes; a tentative
+ * collision is real with probability rho_voxel / rho_max.  Without the
+ * optional processes mu = n_e sigma_KN.  With them a real collision picks its
+ * process with one more uniform, in proportion to the processes' attenuations:
+ *   Compton: Klein-Nishina (Kahn), the electron pushed at or above the
+ *            electron cut-off, deposited on the spot below it;
+ *   photoelectric: the photon is absorbed; the photoelectron (E minus the K
+ *            binding energy, along the photon's direction) is pushed or
+ *            deposited like a Compton electron, the binding energy is
+ *            deposited on the spot;
+ *   Rayleigh: the photon is deflected without losing energy;
+ *   pair: the photon is absorbed; the electron takes eps (E - 2 mc^2) and the
+ *            positron the rest, both along the photon's direction; the
+ *            electron is pushed or deposited like a Compton electron, the
+ *            positron is always pushed (it annihilates where it stops).
+ * Pushed particles take sub-ids 1, 2, ... in the order they are created.  The
+ * photon is absorbed locally below its cut-off.  Escapes without a real
+ * collision are counted for source photons only (not `secondary` ones, the
+ * annihilation photons). */
 static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
-                             uint64_t seed, uint64_t g, int32_t tag)
+                             uint64_t seed, uint64_t g, int32_t tag, int secondary)
 {
     const or_phantom* ph = T->ph;
+    const int32_t phys = T->tp->physics;
+    const double ecut = T->tp->e_cut_e;
     or_stream st;
     stream_init(&st, seed, g, OR_TAG_TR, 0);
-    or_electron stack[64];
+    or_electron stack[256];
     int n_e = 0;
     uint32_t n_push = 0;
-    int collided = 0;
+    int collided = secondary;
     const double ne = ne_water();
     for (;;) {
-        double mu_max = ne * T->rho_max * or_kn_sigma(e);
+        double parts[4];
+        double mu_max = phys ? T->rho_max * or_mu_total(e, phys, parts)
+                             : ne * T->rho_max * or_kn_sigma(e);
         double s = -log(1.0 - stream_u01(&st)) / mu_max;
         for (int a = 0; a < 3; ++a) p[a] += s * d[a];
         int idx[3];
@@ -1103,16 +1421,77 @@ static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
         if (!(ur < (double)ph->density[v] / T->rho_max)) continue;
         collided = 1;
         T->cnt[C_REAL]++;
+        int process = 0;   /* 0 Compton, 1 photoelectric, 2 Rayleigh, 3 pair */
+        if (phys) {
+            double up = stream_u01(&st) * (parts[0] + parts[1] + parts[2] + parts[3]);
+            double acc = parts[0];
+            if (up >= acc) { process = 1; acc += parts[1]; }
+            if (process == 1 && up >= acc) { process = 2; acc += parts[2]; }
+            if (process == 2 && up >= acc) process = 3;
+        }
+        if (process == 1) {
+            /* photoelectric absorption */
+            double b = or_photo_binding();
+            double te = e - b;
+            T->cnt[C_PHOTO]++;
+            if (te >= ecut) {
+                or_electron* el = &stack[n_e++];
+                for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = d[a]; }
+                el->e = te;
+                el->sub = 1 + n_push++;
+                el->positron = 0;
+                T->cnt[C_E_PUSHED]++;
+                deposit(T, v, b, tag);
+            } else {
+                deposit(T, v, e, tag);
+                T->cnt[C_E_LOCAL]++;
+            }
+            break;
+        }
+        if (process == 2) {
+            /* Rayleigh: deflection only */
+            double c = rayleigh_sample(&st, e);
+            double phi = 2.0 * OR_PI * stream_u01(&st);
+            rotate_direction(d, c, phi);
+            T->cnt[C_RAYLEIGH]++;
+            continue;
+        }
+        if (process == 3) {
+            /* pair production */
+            double eps = pair_share_sample(&st);
+            double kin = e - 2.0 * OR_ME;
+            double tm = eps * kin, tp = kin - tm;
+            T->cnt[C_PAIR]++;
+            if (tm >= ecut) {
+                or_electron* el = &stack[n_e++];
+                for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = d[a]; }
+                el->e = tm;
+                el->sub = 1 + n_push++;
+                el->positron = 0;
+                T->cnt[C_E_PUSHED]++;
+            } else {
+                deposit(T, v, tm, tag);
+                T->cnt[C_E_LOCAL]++;
+            }
+            or_electron* po = &stack[n_e++];
+            for (int a = 0; a < 3; ++a) { po->p[a] = p[a]; po->d[a] = d[a]; }
+            po->e = tp;
+            po->sub = 1 + n_push++;
+            po->positron = 1;
+            T->cnt[C_E_PUSHED]++;
+            break;
+        }
         double k = e / OR_ME;
         double x = kahn_sample(&st, k, &T->cnt[C_KAHN_TRIALS]);
         double phi = 2.0 * OR_PI * stream_u01(&st);
         double e1, te, d1[3], de[3];
         compton_kinematics(e, d, x, phi, &e1, d1, &te, de);
-        if (te >= T->tp->e_cut_e) {
+        if (te >= ecut) {
             or_electron* el = &stack[n_e++];
             for (int a = 0; a < 3; ++a) { el->p[a] = p[a]; el->d[a] = de[a]; }
             el->e = te;
             el->sub = 1 + n_push++;
+            el->positron = 0;
             T->cnt[C_E_PUSHED]++;
         } else {
             deposit(T, v, te, tag);
@@ -1121,10 +1500,11 @@ static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
         e = e1;
         for (int a = 0; a < 3; ++a) d[a] = d1[a];
         if (e < T->tp->e_cut_g) { deposit(T, v, e, tag); break; }
-        if (n_e == 64) break;   /* cannot happen: at most E/e_cut_e pushes */
+        if (n_e >= 254) break;   /* cannot happen: at most E/e_cut_e + 1 pushes, < 256 */
     }
     for (int i = 0; i < n_e; ++i)
-        transport_electron(T, stack[i].p, stack[i].d, stack[i].e, seed, g, stack[i].sub, tag);
+        transport_electron(T, stack[i].p, stack[i].d, stack[i].e, seed, g, stack[i].sub, tag,
+                           stack[i].positron);
 }
 
 static double phantom_rho_max(const or_phantom* ph)
@@ -1211,9 +1591,9 @@ int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_b
                 T->cnt[C_ENTERED]++;
                 double p[3] = {rec.x, rec.y, rec.z}, d[3] = {rec.u, rec.v, rec.w};
                 if (rec.stype == OR_SUB_ELECTRON)
-                    transport_electron(T, p, d, rec.e, seed, g, 0, rec.tag);
+                    transport_electron(T, p, d, rec.e, seed, g, 0, rec.tag, 0);
                 else
-                    transport_photon(T, p, d, rec.e, seed, g, rec.tag);
+                    transport_photon(T, p, d, rec.e, seed, g, rec.tag, 0);
             }
         }
         for (int64_t c = 0; c < cells; ++c) {
@@ -1280,9 +1660,9 @@ int or_transport(const or_phantom* ph, const or_params* tp, uint64_t seed, int64
             T->cnt[C_HIST]++;
             T->ledger[L_SRC] += e[i];
             if (ptype[i] == 1)
-                transport_electron(T, p, d, e[i], seed, hid[i], 0, tag ? tag[i] : 0);
+                transport_electron(T, p, d, e[i], seed, hid[i], 0, tag ? tag[i] : 0, 0);
             else
-                transport_photon(T, p, d, e[i], seed, hid[i], tag ? tag[i] : 0);
+                transport_photon(T, p, d, e[i], seed, hid[i], tag ? tag[i] : 0, 0);
         }
     }
     for (int64_t c = 0; c < cells; ++c) {

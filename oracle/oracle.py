@@ -73,7 +73,7 @@ class OrPhantom(C.Structure):
 
 class OrParams(C.Structure):
     _fields_ = [("e_cut_e", C.c_double), ("e_cut_g", C.c_double), ("step_frac", C.c_double),
-                ("ms_enable", C.c_int32), ("density_effect", C.c_int32)]
+                ("ms_enable", C.c_int32), ("density_effect", C.c_int32), ("physics", C.c_int32)]
 
 
 class OrPlan(C.Structure):
@@ -91,7 +91,11 @@ SAMPLE_REC = np.dtype([("j", "i4"), ("k", "i4"), ("status", "i4"), ("stype", "i4
 
 LEDGER = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")
 COUNTERS = ("hist", "entered", "wc_steps", "real", "e_pushed", "e_local", "e_steps",
-            "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard")
+            "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard", "overflow",
+            "folds", "photo", "rayleigh", "pair", "annihil")
+N_COUNTERS = 20
+# optional photon processes (bits of params(physics=...))
+PHYS_PHOTO, PHYS_RAYLEIGH, PHYS_PAIR = 1, 2, 4
 ST_OK, ST_JAW, ST_MISSED, ST_INVALID = 0, 1, 2, 3
 
 
@@ -109,6 +113,18 @@ def _declare(L):
     L.or_kn_sigma.argtypes = [C.c_double]
     L.or_kn_sigma.restype = C.c_double
     L.or_kn_sample_cos.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
+    for name in ("or_sigma_pair_z2", "or_mu_pair", "or_mu_photo", "or_mu_rayleigh",
+                 "or_sigma_rayleigh", "or_ff2_water", "or_ff2_cumulative"):
+        getattr(L, name).argtypes = [C.c_double]
+        getattr(L, name).restype = C.c_double
+    L.or_sigma_k_electron.argtypes = [C.c_double, C.c_double]
+    L.or_sigma_k_electron.restype = C.c_double
+    L.or_photo_binding.argtypes = []
+    L.or_photo_binding.restype = C.c_double
+    L.or_mu_total.argtypes = [C.c_double, C.c_int32, dp]
+    L.or_mu_total.restype = C.c_double
+    L.or_rayleigh_sample_cos.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
+    L.or_pair_share_sample.argtypes = [C.c_uint64, C.c_int, dp]
     L.or_s_col.argtypes = [C.c_double]
     L.or_s_col.restype = C.c_double
     L.or_s_col_d.argtypes = [C.c_double, C.c_int]
@@ -183,8 +199,9 @@ class Phantom:
         self.n_vox = nx * ny * nz
 
 
-def params(e_cut_e=0.2, e_cut_g=0.01, step_frac=0.1, ms=True, density_effect=False):
-    return OrParams(e_cut_e, e_cut_g, step_frac, 1 if ms else 0, 1 if density_effect else 0)
+def params(e_cut_e=0.2, e_cut_g=0.01, step_frac=0.1, ms=True, density_effect=False, physics=0):
+    return OrParams(e_cut_e, e_cut_g, step_frac, 1 if ms else 0, 1 if density_effect else 0,
+                    int(physics))
 
 
 def philox(ctr, key):
@@ -300,7 +317,7 @@ def run(model, plan, beams, phantom, seed, n_rep, h0=0, h1=None, rep0=0, tparams
     s = np.zeros(cells)
     s2 = np.zeros(cells)
     led = np.zeros(8)
-    cnt = np.zeros(16, dtype=np.uint64)
+    cnt = np.zeros(N_COUNTERS, dtype=np.uint64)
     rc = lib().or_run(C.byref(M.c), C.byref(pc), b, len(beams), C.byref(ph.c), C.byref(tp),
                       seed, rep0, n_rep, h0, h1, stride, None if imap is None else _ptr(imap, i32p),
                       n_rows, n_cols, _ptr(s, dp), _ptr(s2, dp), _ptr(led, dp),
@@ -329,7 +346,7 @@ def transport(phantom, seed, ptype, pos, dirs, e, hid, tag=None, tparams=None,
         cells = ph.n_vox
     edep = np.zeros(cells)
     led = np.zeros(8)
-    cnt = np.zeros(16, dtype=np.uint64)
+    cnt = np.zeros(N_COUNTERS, dtype=np.uint64)
     lib().or_transport(C.byref(ph.c), C.byref(tp), seed, n, _ptr(ptype, i32p), _ptr(pos, dp),
                        _ptr(dirs, dp), _ptr(e, dp), _ptr(hid, u64p),
                        None if tg is None else _ptr(tg, i32p),
@@ -418,3 +435,63 @@ def nnls_gp(A, b, x0=None, delta=1e-10, pg_tol=1e-8, sigma=1e-4, beta=0.5, max_i
     lib().or_nnls_gp(_ptr(Aflat, dp), m, n, _ptr(b, dp), _ptr(x, dp), delta, pg_tol, sigma, beta,
                      max_iter, _ptr(rep, dp))
     return x, dict(iters=int(rep[0]), f=rep[1], pg=rep[2], converged=bool(rep[3]))
+
+
+# --------------------------------------------------------------------------
+# Optional photon processes (test hooks)
+# --------------------------------------------------------------------------
+def sigma_k_electron(e, z):
+    """Stobbe photoeffect cross-section of one hydrogenic K electron (cm^2)."""
+    return lib().or_sigma_k_electron(e, z)
+
+
+def photo_binding():
+    return lib().or_photo_binding()
+
+
+def mu_photo(e):
+    return lib().or_mu_photo(e)
+
+
+def ff2_water(t):
+    return lib().or_ff2_water(t)
+
+
+def ff2_cumulative(t):
+    return lib().or_ff2_cumulative(t)
+
+
+def sigma_rayleigh(e):
+    return lib().or_sigma_rayleigh(e)
+
+
+def mu_rayleigh(e):
+    return lib().or_mu_rayleigh(e)
+
+
+def sigma_pair_z2(e):
+    return lib().or_sigma_pair_z2(e)
+
+
+def mu_pair(e):
+    return lib().or_mu_pair(e)
+
+
+def mu_total(e, physics):
+    """Attenuation per unit density (cm^2/g) and its parts (Compton,
+    photoelectric, Rayleigh, pair)."""
+    parts = np.zeros(4)
+    tot = lib().or_mu_total(e, physics, _ptr(parts, dp))
+    return tot, parts
+
+
+def rayleigh_sample_cos(e, seed, n):
+    out = np.zeros(n)
+    lib().or_rayleigh_sample_cos(e, seed, n, _ptr(out, dp))
+    return out
+
+
+def pair_share_sample(seed, n):
+    out = np.zeros(n)
+    lib().or_pair_share_sample(seed, n, _ptr(out, dp))
+    return out
