@@ -13,12 +13,14 @@ Inputs (model tables, plan, phantom) are resident in device memory before
 timing starts.
 
 Prints one JSON line.  Besides the contract's fields it carries the
-roofline of the dominant kernel (algorithmic FLOP and bytes per unit of work
-below, divided by that kernel's mean launch time from the HIP events of the
-timed steps), the three ceilings of the path (HBM copy, FP32 atomic and VALU
-rates measured by the library's probes in the same process, each turned into
-a histories/s bound with the step's event counters), and the CPU oracle's
-rate on a bounded sample of the same workload.
+roofline of the dominant kernel (algorithmic VALU lane-cycles and HBM bytes
+per unit of work below, divided by that kernel's mean launch time from the
+HIP events of the timed steps), the ceilings of the path (HBM at the
+published peak and at a copy probe, FP32 atomics replaying the deposit cells
+recorded from one step of this run, the VALU issue peak; each turned into a
+histories/s bound with the step's event counters), the rate of particles
+entering the phantom and each sub-source's share and acceptance, and the CPU
+oracle's rate on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -31,17 +33,56 @@ sys.path.insert(0, ROOT)
 
 METRIC = "histories/s (6MV-like 10×10 field, 128³ water)"
 METRICS = {"water128_10": METRIC}
-PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-cycles per
+# second.  A full-rate VALU operation occupies a lane for one cycle; the
+# transcendental unit (log, rcp, sqrt, rsqrt, sin, cos) and 32-bit integer
+# multiplies run at a quarter of that rate (4 lane-cycles each).
+PEAK_LANE_CYCLES = 256 * 64 * 2.4e9
 
-# Algorithmic work per unit: FP32 operations the
-# method performs per electron step / per Woodcock step / per real Compton
-# interaction (an FMA counts 2, a transcendental 1), and HBM bytes per unit.
-FLOP_PER_E_STEP = 104.0
-FLOP_PER_WC_STEP = 24.0
-FLOP_PER_COMPTON = 96.0
+
+def lane_cycles(full, quarter):
+    return full + 4.0 * quarter
+
+
+# Algorithmic VALU work per unit as (full-rate ops, quarter-rate ops), counted
+# from the arithmetic each step of the method performs (the derivation is
+# tabulated with the roofline in the design notes); bookkeeping of the GPU
+# implementation (queues, ballots, stack compaction) is not counted.
+#   uniform: a quarter of one Philox4x32-10 block (10 rounds of two
+#            32x32->64-bit multiplies and two three-way xors) and its
+#            conversion to a float
+#   history: sampling (2 Philox blocks, PSL search, Box-Muller, Eq. 5-7
+#            directions, rotation, jaw test, beam->patient transform, entry)
+#   wc_step: one Woodcock flight and its real-collision test (2 uniforms)
+#   kahn:    one Kahn trial (3 uniforms)
+#   real:    the Compton kinematics and deflection after the trials (1 uniform)
+#   e_step:  one CSDA step: face distances, two range and one inverse-range
+#            lookup, the energy loss, the Highland width and the Gaussian
+#            deflection (2 uniforms); face crossings add the voxel update
+#   deposit: the tally-cell index of a deposit
+UNIFORM = (8.0, 5.0)
+WORK = {
+    "history": (204.0, 56.0),
+    "wc_step": (49.0 + 2 * UNIFORM[0], 5.0 + 2 * UNIFORM[1]),
+    "kahn": (20.5 + 3 * UNIFORM[0], 3.5 + 3 * UNIFORM[1]),
+    "real": (45.5 + UNIFORM[0], 8.3 + UNIFORM[1]),
+    "e_step": (92.0 + 50.0 + 2 * UNIFORM[0], 7.0 + 13.0 + 2 * UNIFORM[1]),
+    "e_boundary": (12.0, 2.0),
+    "deposit": (3.0, 0.0),
+}
+# Algorithmic HBM bytes per unit: a particle record (x, y, z, u, v, w, E, id,
+# tag = 40 B) written by its producer and read by its consumer, one 4-byte
+# density gather per Woodcock step and per electron voxel entry, and the
+# deposit's share of the dose grid's read-modify-write.
+BYTES_RECORD = 40.0
+BYTES_DENSITY = 4.0
 BYTES_PER_E_STEP = 4.0 + 8.0          # density gather + share of the deposit RMW
-BYTES_PER_ELECTRON = 36.0 + 4.0       # SoA record + sort order
+
+
+def work_lane_cycles(cnt, units):
+    """Algorithmic VALU lane-cycles of the counted events `units`."""
+    return sum(lane_cycles(*WORK[u]) * cnt[k] for u, k in units)
 
 
 def log(msg):
@@ -145,47 +186,124 @@ def describe_beams(beams):
             + (f", couch {b.couch_deg:.0f} deg" if b.couch_deg else "") for b in beams]
 
 
-def ceilings(N, torch, dose, cnt, value, hist_per_step):
+# events of each phase, as (work unit, counter) pairs
+PHASE_WORK = {
+    "sample": [("history", "hist")],
+    "photon": [("wc_step", "wc_steps"), ("kahn", "kahn_trials"), ("real", "real"),
+               ("deposit", "e_local")],
+    "electron": [("e_step", "e_steps"), ("e_boundary", "e_boundary"), ("deposit", "deposits")],
+}
+
+
+def phase_bytes(phase, cnt):
+    """Algorithmic HBM bytes of a phase over the counted events."""
+    if phase == "sample":
+        return BYTES_RECORD * cnt["entered"]
+    if phase == "photon":
+        # photon records read, one density gather per Woodcock step, the
+        # pushed electrons' records written
+        return (BYTES_RECORD * (cnt["entered"] + cnt["e_pushed"])
+                + BYTES_DENSITY * cnt["wc_steps"])
+    # electron records read (pushed and source electrons), a density gather
+    # per voxel entered and the deposits' read-modify-write share
+    return (BYTES_RECORD * (cnt["e_pushed"] + cnt.get("entered_electrons", 0))
+            + BYTES_PER_E_STEP * cnt["e_steps"])
+
+
+def record_deposits(N, torch, eng, plan, ph, tally, prm, mb, bw, srt, ll, npipe, seed):
+    """Cells of every deposit atomic of one whole step, in the order the
+    transport kernels issue them (psl_tally_record; eager launches)."""
+    cap = 1 << 29
+    cells = torch.empty(cap, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    N.check(N.lib().psl_tally_record(tally.h, cells.data_ptr(), cap, count.data_ptr()))
+    try:
+        tally.op(N.PSL_TALLY_RESET)
+        eng.run_plan(plan, ph, tally, prm, eng.run_opts(mb, bw, use_graph=False,
+                                                        sort_electrons=bool(srt), seed=seed,
+                                                        lane_load=ll, pipelines=npipe))
+        torch.cuda.synchronize()
+    finally:
+        N.check(N.lib().psl_tally_record(tally.h, None, 0, None))
+    n = int(count.item()) & 0xFFFFFFFF
+    _, cnt = tally.stats()
+    if n != cnt["deposits"]:
+        raise RuntimeError(f"recorded {n} deposits, counters say {cnt['deposits']}")
+    return cells[:min(n, cap)]
+
+
+def ceilings(N, torch, eng, run_args, dose_cells, cnt, value, hist_per_step):
     """The three ceilings of the dose path, each as a histories/s bound:
-    HBM (streaming copy probe / algorithmic bytes per history), FP32 atomics
-    (atomic-add probe along an address stream drawn from this step's dose
-    distribution / deposits per history) and FP32 VALU (157.3 TFLOP/s /
-    algorithmic FP32 operations per history)."""
+    HBM (the published 8 TB/s and a streaming-copy probe over the algorithmic
+    bytes per history), FP32 atomics (the deposit cells of one step of this
+    run, recorded in issue order and replayed by an atomic-add probe, over the
+    deposits per history) and VALU (the issue peak over the algorithmic
+    lane-cycles per history)."""
     nbytes = 1 << 30
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     ms = N.psl_probe_copy(b.data_ptr(), a.data_ptr(), nbytes, 10)
     copy_gbs = 2.0 * nbytes / (ms * 1e-3) / 1e9
     del a, b
-    # deposit addresses: i.i.d. voxels drawn with probability proportional to
-    # the step's dose (a stand-in for the recorded deposit stream)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(12345)
-    cdf = torch.cumsum(dose.clamp_min(0), 0)
-    cdf = cdf / cdf[-1]
-    n_atom = 1 << 24
-    u = torch.rand(n_atom, generator=g, device="cuda", dtype=torch.float64)
-    addr = torch.searchsorted(cdf, u).clamp_(max=dose.numel() - 1).to(torch.int32)
-    grid = torch.zeros(dose.numel(), dtype=torch.float32, device="cuda")
-    ms_a = N.psl_probe_atomics(grid.data_ptr(), grid.numel(), addr.data_ptr(), n_atom, 10)
-    atomic_rate = n_atom / (ms_a * 1e-3)
-    del addr, grid, u, cdf
+    addr = record_deposits(N, torch, eng, *run_args)
+    grid = torch.zeros(dose_cells, dtype=torch.float32, device="cuda")
+    ms_a = N.psl_probe_atomics(grid.data_ptr(), grid.numel(), addr.data_ptr(), addr.numel(), 3)
+    atomic_rate = addr.numel() / (ms_a * 1e-3)
+    n_rec = addr.numel()
+    del addr, grid
     h = float(hist_per_step)
-    bytes_h = (2 * 40.0 * cnt["entered"] + 80.0 * cnt["e_pushed"] + 4.0 * cnt["wc_steps"]
-               + BYTES_PER_E_STEP * cnt["e_steps"]) / h
+    bytes_h = sum(phase_bytes(p, cnt) for p in ("sample", "photon", "electron")) / h
+    # the record of an accepted particle is written by sampling and read by
+    # the photon or electron kernel: both counted
+    bytes_h += BYTES_RECORD * cnt["entered"] / h
     atoms_h = cnt["deposits"] / h
-    flop_h = (150.0 * cnt["hist"] + FLOP_PER_WC_STEP * cnt["wc_steps"]
-              + FLOP_PER_COMPTON * cnt["real"] + FLOP_PER_E_STEP * cnt["e_steps"]) / h
-    bounds = {"hbm": copy_gbs * 1e9 / bytes_h, "atomic": atomic_rate / atoms_h,
-              "valu": PEAK_FP32_TFLOPS * 1e12 / flop_h}
-    binding = min(bounds, key=bounds.get)
+    cyc_h = sum(work_lane_cycles(cnt, PHASE_WORK[p]) for p in PHASE_WORK) / h
+    bounds = {"hbm_published": PEAK_HBM_GBS * 1e9 / bytes_h,
+              "hbm_copy_probe": copy_gbs * 1e9 / bytes_h,
+              "atomic_replay": atomic_rate / atoms_h,
+              "valu": PEAK_LANE_CYCLES / cyc_h}
+    lowest = min(bounds, key=bounds.get)
     step_s = hist_per_step / value
-    return {"hbm_copy_GBs": copy_gbs, "atomic_adds_per_s": atomic_rate,
-            "achieved_atomic_adds_per_s": cnt["deposits"] / step_s,
+    return {"hbm_published_GBs": PEAK_HBM_GBS, "hbm_copy_probe_GBs": copy_gbs,
+            "bytes_per_history": bytes_h,
             "achieved_algorithmic_GBs": bytes_h * hist_per_step / step_s / 1e9,
-            "bytes_per_history": bytes_h, "atomics_per_history": atoms_h,
-            "flop_per_history": flop_h, "bound_histories_per_s": bounds, "binding": binding,
-            "frac_of_binding": value / bounds[binding]}
+            "atomic_replay": {"stream": f"{n_rec} deposit cells of one step of this run, "
+                                        "recorded in issue order", "adds_per_s": atomic_rate},
+            "atomics_per_history": atoms_h,
+            "achieved_atomic_adds_per_s": cnt["deposits"] / step_s,
+            "valu_peak_lane_cycles_per_s": PEAK_LANE_CYCLES,
+            "lane_cycles_per_history": cyc_h,
+            "bound_histories_per_s": bounds,
+            "frac_of_bound": {k: value / v for k, v in bounds.items()},
+            "lowest_modelled_ceiling": lowest}
+
+
+def sub_source_split(N, torch, eng, plan, ph, seed):
+    """Histories and entered particles per sub-source over replica 0 (each
+    batch sampled alone through sample_batch, untimed): the share of N each
+    sub-source draws and the fraction that passes the jaws and enters the
+    phantom."""
+    names = ("primary", "scatter", "electron")
+    hist = [0, 0, 0]
+    ent = [0, 0, 0]
+    tal = eng.Tally(ph)
+    mb = 1 << 22
+    nb = plan.set_batching(mb, 24)
+    stack = eng.Particles(mb)
+    s = int(torch.cuda.current_stream().cuda_stream)
+    for i in range(nb):
+        b = plan.batch(i)
+        tal.op(N.PSL_TALLY_RESET)
+        stack.zero_count()
+        N.sample_batch(plan.h, ph.h, 0, b.h0, b.n, seed, stack.c, 0, tal.h, s)
+        _, c = tal.stats()
+        hist[b.stype] += c["hist"]
+        ent[b.stype] += c["entered"]
+    tot = float(sum(hist))
+    return {n: {"share_of_histories": hist[k] / tot,
+                "entered_fraction": ent[k] / hist[k] if hist[k] else None,
+                "entered_replica0": ent[k]}
+            for k, n in enumerate(names)}
 
 
 def main():
@@ -329,36 +447,37 @@ def main():
                       ("graph" if not args.no_graph else "eager"), "autotune": tune}}
     if graph_replay:
         out["graph_replay"] = graph_replay
+    out["entered_per_s"] = cnt["entered"] * args.steps / elapsed
+    out["sub_sources"] = sub_source_split(N, torch, eng, plan, ph, seed)
+    # source electrons that enter the phantom (the electron kernel reads their
+    # records too): replica 0's count times the replicas
+    cnt = dict(cnt, entered_electrons=out["sub_sources"]["electron"]["entered_replica0"] * n_rep)
     if timing:
         # roofline of the dominant kernel over the last timed step (counters
         # cover the same step: the tally is reset at the start of each step)
         phase = max(("photon", "electron", "sample"), key=lambda p: timing[p][0])
         ms, launches = timing[phase]
         avg_s = ms / launches / 1e3
-        if phase == "electron":
-            flop = FLOP_PER_E_STEP * cnt["e_steps"] / launches
-            bytes_ = (BYTES_PER_E_STEP * cnt["e_steps"]
-                      + BYTES_PER_ELECTRON * (cnt["e_pushed"] + cnt["entered"] * 0.01)) / launches
-        elif phase == "photon":
-            flop = (FLOP_PER_WC_STEP * cnt["wc_steps"] + FLOP_PER_COMPTON * cnt["real"]) / launches
-            bytes_ = (40.0 * cnt["entered"] + 4.0 * cnt["wc_steps"] + 40.0 * cnt["e_pushed"]) / launches
-        else:
-            flop = 150.0 * cnt["hist"] / launches
-            bytes_ = 40.0 * cnt["entered"] / launches
-        achieved = flop / avg_s / 1e12
+        cyc = work_lane_cycles(cnt, PHASE_WORK[phase]) / launches
+        bytes_ = phase_bytes(phase, cnt) / launches
+        achieved = cyc / avg_s / 1e12
         traffic = measured_traffic(f"k_{phase}", {"max_batch": mb, "band_width": bw,
                                                   "lane_load": ll, "pipelines": npipe, "sort_electrons": srt,
                                                   "density_effect": int(args.density_effect)})
         out["roofline"] = {"bound": "alu", "kernel": f"k_{phase}", "achieved": achieved,
-                           "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                           "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                           "peak": PEAK_LANE_CYCLES / 1e12, "unit": "T VALU lane-cycles/s",
+                           "frac": achieved / (PEAK_LANE_CYCLES / 1e12), "traffic": traffic,
+                           "lane_cycles_per_launch": cyc,
                            "avg_launch_ms": ms / launches, "launches_per_step": launches,
+                           "hbm_algorithmic_bytes_per_launch": bytes_,
                            "hbm_algorithmic_GBs": bytes_ / avg_s / 1e9,
-                           "hbm_frac": bytes_ / avg_s / 1e9 / PEAK_HBM_GBS}
+                           "hbm_frac_of_published": bytes_ / avg_s / 1e9 / PEAK_HBM_GBS}
         out["phase_ms_per_step"] = {p: round(v[0], 3) for p, v in timing.items()}
     if not args.no_ceilings:
-        out["ceilings"] = ceilings(N, torch, dose, cnt, value, hist_per_step)
-    out["counters_per_step"] = {k: int(v) for k, v in cnt.items()}
+        out["ceilings"] = ceilings(N, torch, eng, (plan, ph, tally, prm, mb, bw, srt, ll, npipe,
+                                                   seed), tally.cells, cnt, value,
+                                   hist_per_step)
+    out["counters_per_step"] = {k: int(v) for k, v in cnt.items() if k != "entered_electrons"}
     out["ledger_closure"] = (led["src"] - sum(led[k] for k in ("jaw", "missed", "invalid", "esc_g",
                                                                 "esc_e", "dep"))) / led["src"]
     if not args.no_cpu_baseline:

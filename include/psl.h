@@ -107,7 +107,8 @@ typedef struct {
  *   basis_of_psr: NULL, or host [3][n_ebin][n_ring] basis id of each PSR (the
  *     PSL takes the id of the ring its centre lies in).  A particle then
  *     carries the tally column beam * n_basis + basis (Sec. 2.2.2), where
- *     n_basis = 1 + the largest id.
+ *     n_basis = 1 + the largest id; n_beams * n_basis must not exceed 32768
+ *     (the column travels in 15 bits of the particle tag).
  *   hist_per_basis: 0 -> Eq. (3): n_hist histories spread over the whole list
  *     in proportion to the PSL weights.  > 0 (needs basis_of_psr) ->
  *     commissioning: each (beam, basis) receives hist_per_basis histories
@@ -263,12 +264,35 @@ typedef struct {
     int32_t density_effect; /* 1 = collision stopping power less Sternheimer's
                                density-effect correction delta(T) of water;
                                0 = Bethe without it; other values: error */
+    uint32_t physics;       /* optional photon processes, PSL_PHYS_* bits (0 =
+                               Compton only, the plain method's physics)      */
 } psl_transport_params;
+
+/* Optional photon processes of psl_transport_params.physics (Sec. 2.3: the
+ * paper's engine models them, naming only the cut-offs), all for water with
+ * density scaling:
+ *   PHOTO     photoelectric absorption on oxygen's two K electrons (Stobbe's
+ *             hydrogenic cross-section, Slater-screened charge 7.7); the
+ *             photoelectron (E less the K binding energy, along the photon)
+ *             is transported or deposited like a Compton electron, the
+ *             binding energy is deposited on the spot;
+ *   RAYLEIGH  coherent scattering: the Thomson cross-section times the
+ *             squared form factor of the molecule as independent hydrogenic
+ *             atoms (oxygen 1s^2 2s^2 2p^4 with Slater-screened charges);
+ *   PAIR      pair production in the nuclear field (unscreened Bethe-Heitler
+ *             in Maximon's expansions, Z^2 summed over the molecule); the
+ *             kinetic energy is shared with density 1 - 4/3 eps (1 - eps),
+ *             both particles move along the photon; the positron is
+ *             transported like an electron and annihilates at rest into two
+ *             mc^2 photons, back to back and isotropic, each followed as a
+ *             photon history of its own (id g | (2 sub + k) << 48, history ids
+ *             below 2^48), which needs e_cut_electron <= mc^2. */
+enum { PSL_PHYS_PHOTO = 1, PSL_PHYS_RAYLEIGH = 2, PSL_PHYS_PAIR = 4 };
 
 /* A dose tally on `phantom`.  index_map_dev == NULL: one cell per voxel.
  * Otherwise (Sec. 2.2.2) index_map_dev is a device int32 [nz][ny][nx] map,
  * 0 = voxel not tallied, k > 0 = row k-1, and the tally is a 2D array
- * [n_rows][n_cols] addressed by (row, particle tag).  Holds an FP32 replica
+ * [n_rows][n_cols] addressed by (row, particle tag), n_cols <= 32768.  Holds an FP32 replica
  * array, FP64 sum and sum-of-squares arrays, the energy ledger and event
  * counters.  Synchronous. */
 int psl_tally_create(const psl_phantom* phantom, const int32_t* index_map_dev, int32_t n_rows,
@@ -310,14 +334,31 @@ int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose
 
 /* Synchronises with the device and reads the energy ledger (MeV, host double
  * [8]: source, jaw-rejected, missed phantom, invalid, escaped photons, escaped
- * electrons, deposited, electron path length in cm), the event counters (host
- * uint64 [16]: histories, entered, Woodcock steps, real interactions, electrons
- * pushed, local electron deposits, electron steps, atomic deposits, uncollided
- * escapes, Kahn trials, electron face crossings, step-guard hits,
- * overflows (a particle stack too small, or a particle column beyond the
- * tally), replicas folded; the rest are zero).  Returns PSL_EOVERFLOW if an
- * overflow was counted since the last RESET.  Either output may be NULL. */
+ * electrons (an escaping positron adds its rest energy 2 mc^2), deposited,
+ * electron path length in cm), the event counters (host uint64 [20]:
+ * histories, entered, Woodcock steps, real interactions, particles pushed by
+ * photons, local electron deposits, electron steps, atomic deposits,
+ * uncollided escapes of source photons, Kahn trials, electron face crossings,
+ * step-guard hits, overflows (a particle stack too small, or a particle column
+ * beyond the tally), replicas folded, photoelectric absorptions, Rayleigh
+ * scatterings, pair productions, positron annihilations; the rest are zero).
+ * Returns PSL_EOVERFLOW if an overflow was counted since the last RESET.
+ * Either output may be NULL. */
 int psl_tally_stats(psl_tally* tally, double* ledger, uint64_t* counters);
+
+/* Deposit recording, for measuring the atomic ceiling of the dose tally on
+ * the address stream the transport really produces (Sec. 2.2.2: every
+ * deposit of a run goes into the one shared dose array).  While cells_dev
+ * (device uint32 [capacity]) is set, every FP32 deposit atomic that the
+ * transport kernels issue into this tally also appends its cell index, in the
+ * order the kernels issue them (the lanes of one wave's atomic in ascending
+ * lane order, consecutive in the buffer).  *count_dev (device uint32, zeroed
+ * by the caller) counts every recorded deposit; entries past `capacity` are
+ * counted but not stored.  The recording kernels are separate builds, so
+ * runs without a recording are unaffected.  cells_dev NULL stops the
+ * recording.  The caller owns both buffers and keeps them alive while set. */
+int psl_tally_record(psl_tally* tally, uint32_t* cells_dev, uint32_t capacity,
+                     uint32_t* count_dev);
 
 /* ------------------------------------------------------------------------
  * Batched runtime (Sec. 2.1.3: the sampling and transport kernels are iterated
@@ -496,6 +537,31 @@ int psl_unet_train_step(psl_unet* net, const float* input_dev, const float* targ
  * checking the backward kernels.  Synchronous. */
 int psl_unet_gradients(psl_unet* net, const float* input_dev, const float* target_dev,
                        float* grads_host, double* loss);
+
+/* Error gate of the denoiser, with the plain engine as the judge: compares a
+ * candidate dose (cand_dev, device FP32 [nz][ny][nx], the network's
+ * prediction on the dose scale) with an independent plain-engine dose and its
+ * standard error (plain_dev, plain_sigma_dev, device FP64, same layout; the
+ * plain run must use other random numbers than the run the candidate was made
+ * from).  With M the largest mean of the candidate over blocks of block^3
+ * voxels (edge in [1, 64]; a hot voxel does not set it), the voxels compared
+ * are those where the candidate exceeds cutoff (in [0, 1)) times M (a choice
+ * independent of the plain dose's noise).  With t = (cand - plain)^2 - sigma^2
+ * per voxel and T_b, n_b its sum and voxel count over each block, writes host
+ * double out[10]: voxels compared, M, the sum of (cand - plain)^2, the sum of
+ * sigma^2, the sums over blocks of T_b^2, T_b n_b and n_b^2, the voxel count
+ * and the plain dose summed over the candidate's top region (the blocks whose
+ * candidate mean is at least 95 % of M), and the number of blocks with
+ * compared voxels.  Since the plain dose is the true dose plus
+ * independent noise of variance sigma^2, the mean of t estimates the
+ * candidate's mean squared error against the true dose over those voxels;
+ * the block sums give its standard error allowing for noise correlated
+ * within a block; out[8] / out[7] reads the true dose of the candidate's top
+ * region (a scale that a spurious hot spot of the candidate does not
+ * inflate).  Sums are taken in a fixed order.  Synchronous on `stream`. */
+int psl_dose_gate(const float* cand_dev, const double* plain_dev, const double* plain_sigma_dev,
+                  int32_t nx, int32_t ny, int32_t nz, int32_t block, double cutoff, double* out,
+                  void* stream);
 
 #ifdef __cplusplus
 }

@@ -64,7 +64,12 @@ class psl_particles(C.Structure):
 class psl_transport_params(C.Structure):
     _fields_ = [("e_cut_electron", C.c_float), ("e_cut_photon", C.c_float),
                 ("step_frac", C.c_float), ("ms_enable", C.c_int32),
-                ("density_effect", C.c_int32)]
+                ("density_effect", C.c_int32), ("physics", C.c_uint32)]
+
+
+# optional photon processes (psl_transport_params.physics)
+PSL_PHYS_PHOTO, PSL_PHYS_RAYLEIGH, PSL_PHYS_PAIR = 1, 2, 4
+N_COUNTERS = 20
 
 
 class psl_run_opts(C.Structure):
@@ -115,6 +120,7 @@ _SIGS = {
                         C.c_uint64, vp],
     "tally_dose": [vp, C.c_int32, vp, vp, vp, vp],
     "psl_tally_stats": [vp, dp, u64p],
+    "psl_tally_record": [vp, vp, C.c_uint32, vp],
 }
 _RESTYPE = {"psl_last_error": C.c_char_p, "psl_model_free": None, "psl_plan_free": None,
             "psl_phantom_free": None, "psl_tally_free": None}
@@ -140,6 +146,8 @@ _SIGS.update({
     "psl_unet_forward": [vp, vp, vp, vp],
     "psl_unet_train_step": [vp, vp, vp, C.c_float, vp, vp],
     "psl_unet_gradients": [vp, vp, vp, fp, dp],
+    "psl_dose_gate": [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, dp,
+                      vp],
 })
 _RESTYPE["psl_unet_free"] = None
 _OPTIONAL = {}

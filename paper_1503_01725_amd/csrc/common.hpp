@@ -100,6 +100,10 @@ struct TransportWs {
     uint32_t* bands = nullptr;      // [2 * kSortBands * kSortBlocks]
     uint32_t* perm = nullptr;       // [perm_cap]
     uint32_t perm_cap = 0;
+    // photons from positron annihilation (pair production on): a photon
+    // stack of ann_cap entries (x, y, z, u, v, w, E, id, tag, count)
+    psl_particles ann{};
+    uint32_t ann_cap = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -132,6 +136,13 @@ struct ScatterComp {
 constexpr int KN_TAB_N = 1024;      // sigma_KN(E) n_e on a log-E grid
 constexpr int RNG_TAB_N = 1024;     // CSDA range R(T) on a log-T grid
 constexpr int INV_TAB_N = 2048;     // T(R) on a uniform R grid
+constexpr int RAY_TAB_N = 1024;     // Rayleigh: cumulative of F^2 over t = (q a0)^2
+
+// Optional photon processes (psl_transport_params.physics bits).
+constexpr uint32_t kPhysPhoto = 1u, kPhysRayleigh = 2u, kPhysPair = 4u;
+// Particle tag bit 15 marks a positron (tally columns use bits 0-14).
+constexpr uint32_t kPositronBit = 0x8000u;
+constexpr uint32_t kColumnMask = 0x7FFFu;
 
 struct PhysicsDev {
     float kn_lne0, kn_inv_dlne;     // ln E of node 0, 1 / node spacing in ln E
@@ -142,13 +153,24 @@ struct PhysicsDev {
     const float* kn;                // [KN_TAB_N] n_e sigma_KN (1/cm at unit density)
     const float* rng;               // [RNG_TAB_N] R(T) g/cm^2
     const float* inv;               // [INV_TAB_N] T(R) MeV
+    // optional photon processes (null / zero when none is enabled)
+    uint32_t physics;               // kPhys* bits the tables were built for
+    const float4* xs;               // [KN_TAB_N] cumulative attenuations at unit density
+                                    // (1/cm) on the kn grid: x Compton, y + photoelectric,
+                                    // z + Rayleigh, w + pair (the total)
+    const float* ray_t;             // [RAY_TAB_N] t nodes: 0, then log-spaced
+    const float* ray_a;             // [RAY_TAB_N] integral of F^2 from 0 to t
+    float ray_lt1, ray_inv_dlt;     // ln t of node 1, 1 / spacing in ln t
+    float ka0_per_mev;              // k a0 per MeV of photon energy
+    float photo_bind;               // K binding energy of oxygen (MeV)
 };
 
 // Energy ledger and counter slots (match psl_tally_stats).
 enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, L_N };
 enum {
     C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS, C_DEPOSITS,
-    C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW, C_FOLDS, C_N = 16
+    C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW, C_FOLDS,
+    C_PHOTO, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_N = 20
 };
 
 // Device-side tally state.  `stats` holds kStripes copies of the ledger
@@ -159,6 +181,11 @@ struct TallyDev {
     unsigned long long* counters;   // counters of copy 0
     const int32_t* imap;    // nullable voxel -> row+1
     int32_t n_cols;
+    // nullable: while set, the cell of every deposit atomic is appended here
+    // in the order the transport kernels issue them (measurement only)
+    uint32_t* rec;
+    uint32_t* rec_count;
+    uint32_t rec_cap;
 };
 
 // Geometry of a phantom as seen by the kernels.
@@ -222,6 +249,7 @@ struct psl_phantom {
     // that a captured graph holding the old table address is never replayed
     float t_cut_tab = -1.f;
     int32_t dens_tab = -1;
+    int32_t phys_tab = -1;
     uint64_t tab_gen = 0;
     psl::DevBuf tabs;
     psl::PhysicsDev phys{};
@@ -242,6 +270,9 @@ struct psl_tally {
     psl::TransportWs ws{};
     uint32_t folds = 0;
     psl::Runner* runner = nullptr;     // batched-runtime workspace (runtime.hip)
+    uint32_t* rec = nullptr;           // deposit-cell recording (psl_tally_record)
+    uint32_t* rec_count = nullptr;
+    uint32_t rec_cap = 0;
     ~psl_tally();
     psl::TallyDev dev() const {
         psl::TallyDev t;
@@ -250,6 +281,9 @@ struct psl_tally {
         t.counters = reinterpret_cast<unsigned long long*>(stats.as<double>() + psl::L_N);
         t.imap = imap;
         t.n_cols = n_cols;
+        t.rec = rec;
+        t.rec_count = rec_count;
+        t.rec_cap = rec_cap;
         return t;
     }
 };
@@ -261,8 +295,9 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p);
 void ensure_device(const psl_model* m);
 void ensure_device(const psl_plan* p);
 
-// Allocates the scratch for an electron stack of up to perm_cap entries in buf.
-TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap);
+// Allocates the scratch for an electron stack of up to perm_cap entries in
+// buf, and a stack of ann_cap annihilation photons (0: none).
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap = 0);
 
 
 // Optional HIP events recorded around the transport launches (may be null).

@@ -264,7 +264,9 @@ extern "C" int psl_plan_create(const psl_model* model, const psl_beam* beams, in
             int mx = 0;
             for (size_t i = 0; i < size_t(3) * nb * nr; ++i) mx = std::max(mx, int(basis_of_psr[i]));
             n_basis = mx + 1;
-            PSL_CHECK(int64_t(n_basis) * n_beams <= 65536, "n_beams * n_basis must be <= 65536");
+            // tally columns travel in bits 0-14 of a particle's tag (bit 15
+            // marks a positron)
+            PSL_CHECK(int64_t(n_basis) * n_beams <= 32768, "n_beams * n_basis must be <= 32768");
         }
         p->n_cols = basis_of_psr ? n_basis * n_beams : 1;
 

@@ -1406,6 +1406,127 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
 
 UNet* unet_cast(psl_unet* p) { return reinterpret_cast<UNet*>(p); }
 
+// ---- error gate: a candidate dose judged by an independent plain dose -------
+constexpr int kGateBlocks = 256;
+
+__device__ double block_sum(double v, double* s) {
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+// Mean of the candidate over block (kx, ky, kz) of b^3 voxels (clipped at the
+// grid's edges).
+__device__ double cand_block_mean(const float* cand, int nx, int ny, int nz, int b, int kx,
+                                  int ky, int kz) {
+    double sum = 0.0;
+    int cnt = 0;
+    for (int z = kz * b; z < min(nz, (kz + 1) * b); ++z)
+        for (int y = ky * b; y < min(ny, (ky + 1) * b); ++y)
+            for (int x = kx * b; x < min(nx, (kx + 1) * b); ++x) {
+                sum += double(cand[(int64_t(z) * ny + y) * nx + x]);
+                ++cnt;
+            }
+    return sum / cnt;
+}
+
+// Per-workgroup maxima of the candidate's block means: the candidate's
+// maximum at the scale of a block, which a hot voxel does not set.
+__global__ void __launch_bounds__(256) k_gate_max(const float* cand, int nx, int ny, int nz, int b,
+                                                  double* part) {
+    __shared__ double s[256];
+    const int bx = (nx + b - 1) / b, by = (ny + b - 1) / b, bz = (nz + b - 1) / b;
+    const int64_t nblk = int64_t(bx) * by * bz;
+    double m = 0.0;
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nblk;
+         k += int64_t(gridDim.x) * blockDim.x)
+        m = fmax(m, cand_block_mean(cand, nx, ny, nz, b, int(k % bx), int((k / bx) % by),
+                                    int(k / (int64_t(bx) * by))));
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+constexpr double kGateTop = 0.95;   // the candidate's top region: >= 95 % of its maximum
+constexpr int kGateSums = 9;
+
+// One thread per b^3 block of voxels, with M the candidate's largest block
+// mean: over the voxels where the candidate exceeds cutoff * M, the block's
+// count n_b, sum of (c - p)^2, sum of sigma^2 and T_b = sum of
+// ((c - p)^2 - sigma^2); the block-level sums T_b^2, T_b n_b and n_b^2 give a
+// standard error of the mean of (c - p)^2 - sigma^2 that allows for noise
+// correlated within a block (an electron track deposits in neighbouring
+// voxels); and over the candidate's top region (blocks whose candidate mean
+// is at least kGateTop M) the voxel count and the plain dose.
+// The voxels are chosen by the candidate, which is independent of the plain
+// dose's noise: a choice by the plain dose would favour its upward
+// fluctuations, whose replica variance is large too, and bias the difference
+// low.  part_max holds kGateBlocks maxima.
+__global__ void __launch_bounds__(256) k_gate_sums(const float* cand, const double* plain,
+                                                   const double* sig, int nx, int ny, int nz,
+                                                   int b, const double* part_max, double cutoff,
+                                                   double* part) {
+    __shared__ double s[256];
+    __shared__ double s_thr, s_top;
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int j = 0; j < kGateBlocks; ++j) m = fmax(m, part_max[j]);
+        s_thr = cutoff * m;
+        s_top = kGateTop * m;
+    }
+    __syncthreads();
+    const double thr = s_thr, top = s_top;
+    const int bx = (nx + b - 1) / b, by = (ny + b - 1) / b, bz = (nz + b - 1) / b;
+    const int64_t nblk = int64_t(bx) * by * bz;
+    double acc[kGateSums] = {};
+    for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < nblk;
+         k += int64_t(gridDim.x) * blockDim.x) {
+        const int kx = int(k % bx), ky = int((k / bx) % by), kz = int(k / (int64_t(bx) * by));
+        const bool in_top = cand_block_mean(cand, nx, ny, nz, b, kx, ky, kz) >= top;
+        double nb = 0.0, d2 = 0.0, v2 = 0.0, tb = 0.0, nt = 0.0, st = 0.0;
+        for (int z = kz * b; z < min(nz, (kz + 1) * b); ++z)
+            for (int y = ky * b; y < min(ny, (ky + 1) * b); ++y)
+                for (int x = kx * b; x < min(nx, (kx + 1) * b); ++x) {
+                    const int64_t i = (int64_t(z) * ny + y) * nx + x;
+                    const double p = plain[i];
+                    if (in_top) {
+                        nt += 1.0;
+                        st += p;
+                    }
+                    const double c = double(cand[i]);
+                    if (!(c > thr)) continue;
+                    const double d = c - p;
+                    const double v = sig[i] * sig[i];
+                    nb += 1.0;
+                    d2 += d * d;
+                    v2 += v;
+                    tb += d * d - v;
+                }
+        acc[0] += nb;
+        acc[1] += d2;
+        acc[2] += v2;
+        acc[3] += tb * tb;
+        acc[4] += tb * nb;
+        acc[5] += nb * nb;
+        acc[6] += nt;
+        acc[7] += st;
+        acc[8] += nb > 0.0 ? 1.0 : 0.0;
+    }
+    double r[kGateSums];
+    for (int q = 0; q < kGateSums; ++q) r[q] = block_sum(acc[q], s);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kGateSums; ++q) part[blockIdx.x * kGateSums + q] = r[q];
+}
 }  // namespace
 }  // namespace psl
 
@@ -1573,5 +1694,40 @@ extern "C" int psl_unet_train_step(psl_unet* net, const float* input, const floa
         pack_all(u, s);
         if (loss_dev)
             PSL_HIP(hipMemcpyAsync(loss_dev, u.loss.p, 64 * 8, hipMemcpyDeviceToDevice, s));
+    });
+}
+
+extern "C" int psl_dose_gate(const float* cand, const double* plain, const double* plain_sigma,
+                             int32_t nx, int32_t ny, int32_t nz, int32_t block, double cutoff,
+                             double* out, void* stream) {
+    return guarded([&] {
+        PSL_CHECK(cand && plain && plain_sigma && out, "null argument");
+        PSL_CHECK(nx > 0 && ny > 0 && nz > 0, "empty dose");
+        PSL_CHECK(int64_t(nx) * ny * nz < (int64_t(1) << 40), "dose grid too large");
+        PSL_CHECK(block >= 1 && block <= 64, "block edge must lie in [1, 64]");
+        PSL_CHECK(cutoff >= 0.0 && cutoff < 1.0, "cutoff must lie in [0, 1)");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t n = int64_t(nx) * ny * nz;
+        DevBuf part;
+        part.alloc(size_t(kGateBlocks) * (1 + kGateSums) * sizeof(double));
+        double* pmax = part.as<double>();
+        double* psum = pmax + kGateBlocks;
+        hipLaunchKernelGGL(k_gate_max, dim3(kGateBlocks), dim3(256), 0, s, cand, nx, ny, nz,
+                           block, pmax);
+        hipLaunchKernelGGL(k_gate_sums, dim3(kGateBlocks), dim3(256), 0, s, cand, plain,
+                           plain_sigma, nx, ny, nz, block, pmax, cutoff, psum);
+        PSL_HIP(hipGetLastError());
+        std::vector<double> h(size_t(kGateBlocks) * (1 + kGateSums));
+        PSL_HIP(hipMemcpyAsync(h.data(), part.p, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+        PSL_HIP(hipStreamSynchronize(s));
+        double mx = 0.0, acc[kGateSums] = {};
+        for (int j = 0; j < kGateBlocks; ++j) {
+            mx = std::max(mx, h[j]);
+            for (int k = 0; k < kGateSums; ++k) acc[k] += h[kGateBlocks + j * kGateSums + k];
+        }
+        out[0] = acc[0];
+        out[1] = mx;
+        for (int k = 1; k < kGateSums; ++k) out[k + 1] = acc[k];
     });
 }

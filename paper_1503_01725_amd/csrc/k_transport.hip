@@ -57,6 +57,9 @@ struct TransportArgs {
     int ms;
     uint32_t seed_lo, seed_hi;
     uint32_t push_chunk;       // electron-stack entries a wave reserves per atomic
+    Stack ann;                 // annihilation photons out of the electron kernel
+                               // (count null: none expected)
+    uint32_t secondary;        // photon kernel: the input holds annihilation photons
 };
 
 // ---- hardware transcendentals ---------------------------------------------
@@ -98,6 +101,45 @@ __device__ __forceinline__ float csda_energy(const PhysicsDev& P, const float* t
     return lerp_tab(tab, INV_TAB_N, (hw_log(r + P.r_off) - P.inv_u0) * P.inv_inv_du);
 }
 
+// Cumulative attenuations per unit density at photon energy e (x Compton,
+// y + photoelectric, z + Rayleigh, w the total), linear in ln E.
+__device__ __forceinline__ float4 xs_at(const PhysicsDev& P, const float4* tab, float e) {
+    float x = (hw_log(e) - P.kn_lne0) * P.kn_inv_dlne;
+    x = fminf(fmaxf(x, 0.f), float(KN_TAB_N - 1) - 1e-3f);
+    const int i = int(x);
+    const float f = x - float(i);
+    const float4 lo = tab[i], hi = tab[i + 1];
+    return make_float4(fmaf(f, hi.x - lo.x, lo.x), fmaf(f, hi.y - lo.y, lo.y),
+                       fmaf(f, hi.z - lo.z, lo.z), fmaf(f, hi.w - lo.w, lo.w));
+}
+
+// Rayleigh: cumulative A(t) of the squared form factor (linear in t between
+// the table's nodes: 0, then log-spaced from node 1).
+__device__ __forceinline__ float ray_cumulative(const PhysicsDev& P, float t) {
+    const float t1 = P.ray_t[1];
+    if (t <= t1) return P.ray_a[1] * (t / t1);
+    float x = (hw_log(t) - P.ray_lt1) * P.ray_inv_dlt + 1.f;
+    x = fminf(x, float(RAY_TAB_N - 1) - 1e-3f);
+    const int i = max(int(x), 1);
+    const float ta = P.ray_t[i], tb = P.ray_t[i + 1];
+    const float f = fminf(fmaxf((t - ta) / (tb - ta), 0.f), 1.f);
+    return fmaf(f, P.ray_a[i + 1] - P.ray_a[i], P.ray_a[i]);
+}
+
+// Rayleigh: the t at which A(t) reaches `target` (binary search over the
+// table, linear in t between nodes).
+__device__ __forceinline__ float ray_t_at(const PhysicsDev& P, float target) {
+    int lo = 0, hi = RAY_TAB_N - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P.ray_a[mid] <= target) lo = mid;
+        else hi = mid;
+    }
+    const float a0 = P.ray_a[lo], a1 = P.ray_a[hi];
+    const float f = a1 > a0 ? fminf(fmaxf((target - a0) / (a1 - a0), 0.f), 1.f) : 0.f;
+    return fmaf(f, P.ray_t[hi] - P.ray_t[lo], P.ray_t[lo]);
+}
+
 // ---- geometry -------------------------------------------------------------
 __device__ __forceinline__ void rotate(float& u, float& v, float& w, float cos_t, float cphi,
                                        float sphi) {
@@ -128,7 +170,7 @@ __device__ __forceinline__ int tally_cell(const TallyDev& T, int v, uint32_t tag
     if (!T.imap) return v;
     const int row = T.imap[v];
     if (row <= 0) return -1;
-    const int col = int(tag & 0xFFFFu);
+    const int col = int(tag & kColumnMask);
     if (col >= T.n_cols) {
         // particle tag from a plan with more columns than this tally
         atomicAdd(T.counters + C_OVERFLOW, 1ull);
@@ -137,11 +179,19 @@ __device__ __forceinline__ int tally_cell(const TallyDev& T, int v, uint32_t tag
     return (row - 1) * T.n_cols + col;
 }
 
+// Appends cell c to the deposit recording (kRec builds only).
+__device__ __forceinline__ void record_cell(const TallyDev& T, int c) {
+    const uint32_t slot = atomicAdd(T.rec_count, 1u);
+    if (slot < T.rec_cap) T.rec[slot] = uint32_t(c);
+}
+
+template <bool kRec>
 __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, float e,
                                         uint32_t& n_atomic) {
     if (e == 0.f) return;
     const int c = tally_cell(T, v, tag);
     if (c < 0) return;
+    if constexpr (kRec) record_cell(T, c);
     atomicAdd(T.grid + c, e);
     ++n_atomic;
 }
@@ -149,6 +199,7 @@ __device__ __forceinline__ void deposit(const TallyDev& T, int v, uint32_t tag, 
 // Three deposits (v < 0: none; the first two of particle tag01, the third of
 // tag2) whose index-map lookups are all issued before any atomic, so that no
 // lookup waits behind an atomic.
+template <bool kRec>
 __device__ __forceinline__ void deposit3(const TallyDev& T, int v0, float e0, int v1, float e1,
                                          uint32_t tag01, int v2, float e2, uint32_t tag2,
                                          uint32_t& n_atomic) {
@@ -156,14 +207,17 @@ __device__ __forceinline__ void deposit3(const TallyDev& T, int v0, float e0, in
     const int c1 = v1 >= 0 && e1 != 0.f ? tally_cell(T, v1, tag01) : -1;
     const int c2 = v2 >= 0 && e2 != 0.f ? tally_cell(T, v2, tag2) : -1;
     if (c0 >= 0) {
+        if constexpr (kRec) record_cell(T, c0);
         atomicAdd(T.grid + c0, e0);
         ++n_atomic;
     }
     if (c1 >= 0) {
+        if constexpr (kRec) record_cell(T, c1);
         atomicAdd(T.grid + c1, e1);
         ++n_atomic;
     }
     if (c2 >= 0) {
+        if constexpr (kRec) record_cell(T, c2);
         atomicAdd(T.grid + c2, e2);
         ++n_atomic;
     }
@@ -233,12 +287,24 @@ __device__ __forceinline__ uint32_t take_work(bool need, WaveQueue& q, uint32_t*
 // scattering) that advances as far as the uniforms topped up at the start of
 // the iteration allow and resumes in the next iteration, so every Philox block
 // of the wavefront is generated at the one top-up point.
-enum PhotonPhase : uint32_t { kFlight = 0, kKahn = 1, kScatter = 2 };
+// With the optional processes (kFull) a real collision picks its process
+// with one more uniform; Rayleigh trials (two uniforms each) and the
+// deflection, and the pair's energy-sharing trials (two uniforms each) and the
+// positron's push, are further phases of the same machine.
+enum PhotonPhase : uint32_t {
+    kFlight = 0, kKahn = 1, kScatter = 2, kRayleigh = 3, kRayTurn = 4, kPair = 5, kPairPositron = 6
+};
 
+template <bool kRec, bool kFull>
 __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
-    __shared__ float s_kn[KN_TAB_N];
+    __shared__ float s_kn[kFull ? 1 : KN_TAB_N];
+    __shared__ float4 s_xs[kFull ? KN_TAB_N : 1];
     __shared__ float s_pool[kPhotonPool * kBlock];
-    for (int i = threadIdx.x; i < KN_TAB_N; i += blockDim.x) s_kn[i] = a.phys.kn[i];
+    if constexpr (kFull) {
+        for (int i = threadIdx.x; i < KN_TAB_N; i += blockDim.x) s_xs[i] = a.phys.xs[i];
+    } else {
+        for (int i = threadIdx.x; i < KN_TAB_N; i += blockDim.x) s_kn[i] = a.phys.kn[i];
+    }
     __syncthreads();
 
     const PhantomDev& G = a.ph;
@@ -249,12 +315,16 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     uint32_t &c_wc = ls.c[C_WC_STEPS], &c_real = ls.c[C_REAL], &c_push = ls.c[C_E_PUSHED],
              &c_local = ls.c[C_E_LOCAL], &c_atom = ls.c[C_DEPOSITS],
              &c_unc = ls.c[C_ESC_UNCOLLIDED], &c_kahn = ls.c[C_KAHN_TRIALS],
-             &c_over = ls.c[C_OVERFLOW];
+             &c_over = ls.c[C_OVERFLOW], &c_photo = ls.c[C_PHOTO], &c_ray = ls.c[C_RAYLEIGH],
+             &c_pair = ls.c[C_PAIR];
     // electron-stack slots reserved by this wave and not used yet
     uint32_t el_base = 0, el_left = 0;
     // per-lane photon state
     float px = 0.f, py = 0.f, pz = 0.f, du = 0.f, dv = 0.f, dw = 0.f, e = 0.f;
-    float kx = 1.f;          // Kahn variable E/E' of the current collision
+    // Kahn variable E/E' of the current collision; with kFull also the bound
+    // of the Rayleigh trials' cumulative, then the accepted cos theta, or the
+    // pair positron's kinetic energy
+    float kx = 1.f;
     uint64_t g = 0;
     uint32_t tag = 0, n_push = 0, phase = kFlight, trials = 0;
     int steps = 0, cv = 0;   // cv: voxel of the current collision
@@ -271,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
         // a flight and its collision test (2), two Kahn trials (6) and the
         // azimuth (1) fit in one iteration
-        st.topup(alive, 9, 12);
+        st.topup(alive, kFull ? 10 : 9, 12);
         // this step's writes, deferred: one deposit, one electron
         int w_v = -1;
         float w_e = 0.f;
@@ -295,7 +365,14 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             } else {
                 ++steps;
                 // one Woodcock flight
-                const float mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
+                float4 xs4;
+                float mu;
+                if constexpr (kFull) {
+                    xs4 = xs_at(a.phys, s_xs, e);
+                    mu = xs4.w * G.rho_max;
+                } else {
+                    mu = kn_mu(a.phys, s_kn, e) * G.rho_max;
+                }
                 const float s = -hw_log(1.f - st.pop()) * hw_rcp(mu);
                 px = fmaf(s, du, px);
                 py = fmaf(s, dv, py);
@@ -320,6 +397,45 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                         ++c_real;
                         phase = kKahn;
                         trials = 0;
+                        if constexpr (kFull) {
+                            // the process, in proportion to the attenuations
+                            const float up = st.pop() * xs4.w;
+                            if (up >= xs4.x) {
+                                if (up < xs4.y) {
+                                    // photoelectric absorption: the photoelectron
+                                    // along the photon, the binding energy here
+                                    ++c_photo;
+                                    const float b = a.phys.photo_bind;
+                                    const float tpe = e - b;
+                                    if (tpe >= a.e_cut_e) {
+                                        qx = du; qy = dv; qz = dw;
+                                        te = tpe;
+                                        ++n_push;
+                                        ++c_push;
+                                        push = true;
+                                        ex = px; ey = py; ez = pz;
+                                        w_ptag = tag | (n_push << 16);
+                                        w_v = cv;
+                                        w_e = b;
+                                        dep += b;
+                                    } else {
+                                        w_v = cv;
+                                        w_e = e;
+                                        dep += e;
+                                        ++c_local;
+                                    }
+                                    alive = false;
+                                } else if (up < xs4.z) {
+                                    ++c_ray;
+                                    phase = kRayleigh;
+                                    const float x0 = e * a.phys.ka0_per_mev;
+                                    kx = ray_cumulative(a.phys, 4.f * x0 * x0);
+                                } else {
+                                    ++c_pair;
+                                    phase = kPair;
+                                }
+                            }
+                        }
                     }
                 }
             }
@@ -388,6 +504,68 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 alive = false;
             }
         }
+        if constexpr (kFull) {
+            if (alive && phase == kRayleigh) {
+                // t = (q a0)^2 from the squared form factor below its bound
+                // (kx), accepted with (1 + cos^2 theta) / 2
+                const float x0 = e * a.phys.ka0_per_mev;
+                const float inv2x2 = 0.5f * hw_rcp(x0 * x0);
+                while (st.cnt >= 2u) {
+                    const float u1 = st.pop(), u2 = st.pop();
+                    const float t = ray_t_at(a.phys, u1 * kx);
+                    const float c = fmaxf(1.f - t * inv2x2, -1.f);
+                    if (u2 <= 0.5f * (1.f + c * c)) {
+                        kx = c;
+                        phase = kRayTurn;
+                        break;
+                    }
+                }
+            }
+            if (alive && phase == kRayTurn && st.cnt >= 1u) {
+                float sphi, cphi;
+                sincos_turn(st.pop(), sphi, cphi);
+                rotate(du, dv, dw, kx, cphi, sphi);
+                phase = kFlight;
+            }
+            if (alive && phase == kPair) {
+                // the electron's share eps of E - 2 mc^2, density 1 - 4/3 eps (1 - eps)
+                while (st.cnt >= 2u) {
+                    const float u1 = st.pop(), u2 = st.pop();
+                    if (u2 <= 1.f - (4.f / 3.f) * u1 * (1.f - u1)) {
+                        const float kin = e - 2.f * kMe;
+                        const float tm = u1 * kin;
+                        kx = kin - tm;
+                        if (tm >= a.e_cut_e) {
+                            qx = du; qy = dv; qz = dw;
+                            te = tm;
+                            ++n_push;
+                            ++c_push;
+                            push = true;
+                            ex = px; ey = py; ez = pz;
+                            w_ptag = tag | (n_push << 16);
+                        } else {
+                            w_v = cv;
+                            w_e = tm;
+                            dep += tm;
+                            ++c_local;
+                        }
+                        phase = kPairPositron;
+                        break;
+                    }
+                }
+            } else if (alive && phase == kPairPositron) {
+                // the positron, pushed whatever its energy: it annihilates
+                // where it stops
+                qx = du; qy = dv; qz = dw;
+                te = kx;
+                ++n_push;
+                ++c_push;
+                push = true;
+                ex = px; ey = py; ez = pz;
+                w_ptag = tag | kPositronBit | (n_push << 16);
+                alive = false;
+            }
+        }
         // refill idle lanes from the wave's chunk of the photon stack: the
         // entry's tag and data are loaded together (one memory latency), the
         // data kept only if the tag marks a live entry
@@ -415,7 +593,8 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                     n_push = 0;
                     steps = 0;
                     phase = kFlight;
-                    collided = false;
+                    // uncollided escapes are counted for source photons only
+                    collided = a.secondary != 0u;
                     alive = true;
                 }
             }
@@ -455,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
                 }
             }
         }
-        if (w_v >= 0) deposit(a.tally, w_v, w_tag, w_e, c_atom);
+        if (w_v >= 0) deposit<kRec>(a.tally, w_v, w_tag, w_e, c_atom);
     }
     // the unused rest of the wave's last chunk stays in the stack as empty entries
     if (el_left > 0) {
@@ -591,6 +770,35 @@ __device__ __forceinline__ void face_distance(float p, float d, int i, float o, 
     }
 }
 
+// Writes the two photons of a positron's annihilation at rest at (x, y, z):
+// mc^2 each, back to back along an isotropic direction (cos theta = 2u - 1,
+// azimuth u' in turns), ids g | (2 sub + k) << 48, the positron's column.
+__device__ __forceinline__ void annihilate(const Stack& ann, float x, float y, float z, float u1,
+                                          float u2, uint64_t g, uint32_t sub, uint32_t col,
+                                          uint32_t& c_over) {
+    const float c = 2.f * u1 - 1.f;
+    float sphi, cphi;
+    sincos_turn(u2, sphi, cphi);
+    const float sn = hw_sqrt(fmaxf(0.f, 1.f - c * c));
+    const float ux = sn * cphi, uy = sn * sphi;
+    const uint32_t slot = atomicAdd(ann.count, 2u);
+#pragma unroll
+    for (uint32_t k = 0; k < 2u; ++k) {
+        const uint32_t i = slot + k;
+        if (i >= ann.capacity) {
+            ++c_over;
+            continue;
+        }
+        const float sg = k ? -1.f : 1.f;
+        ann.x[i] = x; ann.y[i] = y; ann.z[i] = z;
+        ann.u[i] = sg * ux; ann.v[i] = sg * uy; ann.w[i] = sg * c;
+        ann.e[i] = kMe;
+        ann.hid[i] = g | (uint64_t(2u * sub + k) << 48);
+        ann.tag[i] = col;
+    }
+}
+
+template <bool kRec, bool kFull>
 __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     __shared__ float s_rng[RNG_TAB_N];
     __shared__ float s_inv[INV_TAB_N];
@@ -606,7 +814,13 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     dev::LocalStats ls;
     double &esc_e = ls.l[L_ESC_E], &dep = ls.l[L_DEP], &path = ls.l[L_EPATH];
     uint32_t &c_steps = ls.c[C_E_STEPS], &c_atom = ls.c[C_DEPOSITS], &c_bnd = ls.c[C_E_BOUNDARY],
-             &c_guard = ls.c[C_GUARD], &c_local = ls.c[C_E_LOCAL];
+             &c_guard = ls.c[C_GUARD], &c_local = ls.c[C_E_LOCAL], &c_ann = ls.c[C_ANNIHIL],
+             &c_over = ls.c[C_OVERFLOW];
+    (void)c_ann;
+    (void)c_over;
+    // positrons annihilate where they stop (kFull builds with an annihilation
+    // stack; otherwise the flag is not read)
+    bool positron = false;
     // per-lane electron state
     float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f, t = 0.f, pend_e = 0.f;
     float rho = 0.f;   // density of the current voxel
@@ -621,7 +835,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
         // one multiple-scattering deflection (two uniforms) per step, at most
         // one step per iteration
-        st.topup(alive && a.ms, 2, 5);
+        st.topup(alive && (a.ms || (kFull && positron)), 2, 5);
         // the next step's density, loaded into its own register (written
         // by nothing else before the end of the iteration, so that the load
         // is not waited on early) and taken over after the iteration's wait
@@ -635,8 +849,12 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
         const uint32_t w_tag = tag;
         uint32_t w_tag2 = 0;
         if (alive) {
-            bool done = false;
-            if (steps >= kMaxElectronSteps) {
+            bool done = false, escaped = false;
+            if (kFull && !(t >= tcut)) {
+                // a positron below the cut-off on entry: its energy went into
+                // the voxel at the refill; it annihilates now
+                done = true;
+            } else if (steps >= kMaxElectronSteps) {
                 pend_e += t;
                 dep += t;
                 ++c_guard;
@@ -690,8 +908,10 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                             out = iz < 0 || iz >= G.nz;
                         }
                         if (out) {
-                            esc_e += t;
+                            // an escaping positron takes its rest energy along
+                            esc_e += t + (kFull && positron ? 2.f * kMe : 0.f);
                             done = true;
+                            escaped = true;
                         } else {
                             cur_v = (iz * G.ny + iy) * G.nx + ix;
                             // the next step's density, loaded while the rest
@@ -734,6 +954,15 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                 w_v1 = pend_v;
                 w_e1 = pend_e;
                 alive = false;
+                if constexpr (kFull) {
+                    if (positron && !escaped) {
+                        const float u1 = st.pop(), u2 = st.pop();
+                        annihilate(a.ann, px, py, pz, u1, u2,
+                                   (uint64_t(st.g1) << 32) | st.g0, st.tagsub & 0xFFFFu,
+                                   tag & kColumnMask, c_over);
+                        ++c_ann;
+                    }
+                }
             }
         }
         // refill idle lanes from the wave's chunk of the (band-ordered) stack;
@@ -759,6 +988,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
             t = take ? ne : t;
             if (take) {
                 tag = tg & 0xFFFFu;
+                if constexpr (kFull) positron = (tg & kPositronBit) != 0u && a.ann.count != nullptr;
                 ix = min(max(int(floorf((px - G.origin[0]) * G.inv_vox[0])), 0), G.nx - 1);
                 iy = min(max(int(floorf((py - G.origin[1]) * G.inv_vox[1])), 0), G.ny - 1);
                 iz = min(max(int(floorf((pz - G.origin[2]) * G.inv_vox[2])), 0), G.nz - 1);
@@ -771,6 +1001,18 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                     w_tag2 = tag;
                     dep += t;
                     ++c_local;
+                    if constexpr (kFull) {
+                        if (positron) {
+                            // kept alive one more iteration to annihilate
+                            // with uniforms of its own stream
+                            st.init(g, dev::kTagTransport, (tg >> 16) & 0xFFu);
+                            pend_v = cur_v;
+                            pend_e = 0.f;
+                            t = 0.f;
+                            steps = 0;
+                            alive = true;
+                        }
+                    }
                 } else {
                     st.init(g, dev::kTagTransport, (tg >> 16) & 0xFFu);
                     pend_v = cur_v;
@@ -785,15 +1027,16 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
         wait_loads();
         if (new_rho) rho = rho_nx;
         // this step's deposits
-        deposit3(a.tally, w_v0, w_e0, w_v1, w_e1, w_tag, w_v2, w_e2, w_tag2, c_atom);
+        deposit3<kRec>(a.tally, w_v0, w_e0, w_v1, w_e1, w_tag, w_v2, w_e2, w_tag2, c_atom);
     }
     dev::flush_stats(a.tally.stats, ls);
 }
 
 // ---- small utility kernels (no hipMemsetAsync, so graphs replay cleanly) --
-__global__ void k_reset_queues(uint32_t* el_count, uint32_t* queue) {
+__global__ void k_reset_queues(uint32_t* el_count, uint32_t* queue, uint32_t* ann_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (el_count) *el_count = 0u;
+        if (ann_count) *ann_count = 0u;
         queue[0] = 0u;
         queue[1] = 0u;
     }
@@ -898,23 +1141,106 @@ void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
 }
 
-TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap) {
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap) {
     const size_t q = 256, b = size_t(2) * kBands * kSortBlocks * 4, pm = size_t(perm_cap) * 4;
-    buf.alloc(q + b + pm);
+    // annihilation photons: seven FP32 arrays, the ids, the tags and a count
+    const size_t an = ann_cap ? size_t(ann_cap) * (7 * 4 + 8 + 4) + 256 + 8 * 16 : 0;
+    buf.alloc(q + b + pm + an);
     TransportWs ws;
     char* base = buf.as<char>();
     ws.queues = reinterpret_cast<uint32_t*>(base);
     ws.bands = reinterpret_cast<uint32_t*>(base + q);
     ws.perm = reinterpret_cast<uint32_t*>(base + q + b);
     ws.perm_cap = perm_cap;
+    if (ann_cap) {
+        size_t off = (q + b + pm + 255) / 256 * 256;
+        auto take = [&](size_t bytes) {
+            void* r = base + off;
+            off += (bytes + 15) / 16 * 16;
+            return r;
+        };
+        psl_particles& p = ws.ann;
+        float** f[7] = {&p.x, &p.y, &p.z, &p.u, &p.v, &p.w, &p.e};
+        for (float** fp : f) *fp = static_cast<float*>(take(size_t(ann_cap) * 4));
+        p.hid = static_cast<uint64_t*>(take(size_t(ann_cap) * 8));
+        p.tag = static_cast<uint32_t*>(take(size_t(ann_cap) * 4));
+        p.count = static_cast<uint32_t*>(take(16));
+        p.capacity = ann_cap;
+        p.ptype = 0;
+        ws.ann_cap = ann_cap;
+    }
     return ws;
 }
+
+namespace {
+
+// Grid of a persistent transport launch over a stack of `capacity` entries.
+int transport_grid(uint32_t capacity, int lane_load) {
+    const int64_t per_block = int64_t(kBlock) * std::max(1, lane_load);
+    return int(std::max<int64_t>(1, std::min<int64_t>((int64_t(capacity) + per_block - 1) / per_block, 2048)));
+}
+
+template <bool kRec, bool kFull>
+void launch_photon(const TransportArgs& a, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((k_photon<kRec, kFull>), dim3(grid), dim3(kBlock), 0, stream, a);
+}
+
+template <bool kRec, bool kFull>
+void launch_electron(const TransportArgs& a, const Stack& s, int grid, hipStream_t stream) {
+    hipLaunchKernelGGL((k_electron<kRec, kFull>), dim3(grid), dim3(kBlock), 0, stream, a, s);
+}
+
+void photon_kernel(const TransportArgs& a, bool full, int grid, hipStream_t stream) {
+    if (a.tally.rec) {
+        if (full) launch_photon<true, true>(a, grid, stream);
+        else launch_photon<true, false>(a, grid, stream);
+    } else {
+        if (full) launch_photon<false, true>(a, grid, stream);
+        else launch_photon<false, false>(a, grid, stream);
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+void electron_kernel(const TransportArgs& a, const Stack& s, bool full, int grid,
+                     hipStream_t stream) {
+    if (a.tally.rec) {
+        if (full) launch_electron<true, true>(a, s, grid, stream);
+        else launch_electron<true, false>(a, s, grid, stream);
+    } else {
+        if (full) launch_electron<false, true>(a, s, grid, stream);
+        else launch_electron<false, false>(a, s, grid, stream);
+    }
+    PSL_HIP(hipGetLastError());
+}
+
+// Electron energy-band order of `estack` into ws.perm (counting sort).
+void sort_bands(const psl_phantom* ph, const TransportWs& ws, const Stack& estack,
+                hipStream_t stream) {
+    uint32_t* hist = ws.bands;
+    uint32_t* offs = hist + kBands * kSortBlocks;
+    PSL_CHECK(ws.perm_cap >= estack.capacity, "electron order buffer too small");
+    const float lt0 = std::log(ph->phys.t_cut);
+    const float inv_w = float(kBands) / (std::log(ph->phys.t_max) - lt0);
+    hipLaunchKernelGGL(k_band_count, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
+                       estack.tag, estack.count, estack.capacity, hist, lt0, inv_w);
+    hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(1024), 0, stream, hist, offs);
+    hipLaunchKernelGGL(k_band_scatter, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
+                       estack.tag, estack.count, estack.capacity, offs, ws.perm, lt0, inv_w);
+}
+
+}  // namespace
 
 void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const TransportWs& ws, const psl_transport_params* prm,
                       uint64_t seed, hipStream_t stream, bool sort_electrons, int lane_load,
                       const PhaseEvents* ev) {
     psl_phantom* ph = const_cast<psl_phantom*>(phc);
+    const bool full = prm->physics != 0u;
+    // positrons (pair production) need a stack for their annihilation photons
+    const bool pair = (prm->physics & kPhysPair) != 0u && in->ptype == 0;
+    PSL_CHECK(!pair || ws.ann_cap >= 2u * in->capacity,
+              "annihilation photon stack too small (%u for %u photons)", ws.ann_cap,
+              in->capacity);
     TransportArgs a{};
     a.in = to_stack(in);
     a.el = to_stack(el);
@@ -929,14 +1255,14 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.seed_lo = uint32_t(seed);
     a.seed_hi = uint32_t(seed >> 32);
     a.queue = ws.queues;
+    if (pair) a.ann = to_stack(&ws.ann);
     Stack estack = a.el;
     // The transport kernels are persistent: every lane takes histories from a
     // queue until it is drained.  The grid is sized to the batch (about
     // lane_load histories per lane), not to the stacks, so that a lane works
     // through several histories and a wave is not held up by the one long
     // history among 64 short ones.
-    const int64_t per_block = int64_t(kBlock) * std::max(1, lane_load);
-    const int tg = int(std::max<int64_t>(1, std::min<int64_t>((int64_t(in->capacity) + per_block - 1) / per_block, 2048)));
+    const int tg = transport_grid(in->capacity, lane_load);
     // A wave reserves electron-stack entries push_chunk at a time (one
     // returning atomic each); the unused ends of the waves' last chunks
     // (fewer than push_chunk per wave) must fit in the one spare entry per
@@ -945,35 +1271,45 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     const int64_t waves = int64_t(tg) * (kBlock / 64);
     a.push_chunk = waves * 255 <= int64_t(in->capacity) ? 256u : 64u;
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream,
-                       in->ptype == 0 ? el->count : nullptr, a.queue);
+                       in->ptype == 0 ? el->count : nullptr, a.queue,
+                       pair ? ws.ann.count : nullptr);
     if (in->ptype == 0) {
         if (ev) PSL_HIP(hipEventRecord(ev->photon0, stream));
-        hipLaunchKernelGGL(k_photon, dim3(tg), dim3(kBlock), 0, stream, a);
-        PSL_HIP(hipGetLastError());
+        photon_kernel(a, full, tg, stream);
         if (ev) PSL_HIP(hipEventRecord(ev->photon1, stream));
     } else {
         estack = a.in;
     }
     if (ev) PSL_HIP(hipEventRecord(ev->sort0, stream));
     if (sort_electrons) {
-        uint32_t* hist = ws.bands;
-        uint32_t* offs = hist + kBands * kSortBlocks;
-        uint32_t* perm = ws.perm;
-        PSL_CHECK(ws.perm_cap >= estack.capacity, "electron order buffer too small");
-        const float lt0 = std::log(ph->phys.t_cut);
-        const float inv_w = float(kBands) / (std::log(ph->phys.t_max) - lt0);
-        hipLaunchKernelGGL(k_band_count, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
-                           estack.tag, estack.count, estack.capacity, hist, lt0, inv_w);
-        hipLaunchKernelGGL(k_band_scan, dim3(1), dim3(1024), 0, stream, hist, offs);
-        hipLaunchKernelGGL(k_band_scatter, dim3(kSortBlocks), dim3(kBlock), 0, stream, estack.e,
-                           estack.tag, estack.count, estack.capacity, offs, perm, lt0, inv_w);
-        a.perm = perm;
+        sort_bands(ph, ws, estack, stream);
+        a.perm = ws.perm;
     }
     if (ev) PSL_HIP(hipEventRecord(ev->sort1, stream));
     if (ev) PSL_HIP(hipEventRecord(ev->electron0, stream));
-    hipLaunchKernelGGL(k_electron, dim3(tg), dim3(kBlock), 0, stream, a, estack);
-    PSL_HIP(hipGetLastError());
+    electron_kernel(a, estack, full, tg, stream);
     if (ev) PSL_HIP(hipEventRecord(ev->electron1, stream));
+    if (pair) {
+        // The photons of the positrons' annihilations, as photon histories of
+        // their own (mc^2 each: they cannot make pairs, so no further pass),
+        // then the electrons they set in motion.
+        TransportArgs b = a;
+        b.in = to_stack(&ws.ann);
+        b.ann = Stack{};
+        b.secondary = 1u;
+        b.perm = nullptr;
+        const int tg2 = transport_grid(ws.ann_cap, lane_load);
+        const int64_t waves2 = int64_t(tg2) * (kBlock / 64);
+        b.push_chunk = waves2 * 255 <= int64_t(ws.ann_cap) ? 256u : 64u;
+        hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream, el->count, b.queue,
+                           nullptr);
+        photon_kernel(b, true, tg2, stream);
+        if (sort_electrons) {
+            sort_bands(ph, ws, estack, stream);
+            b.perm = ws.perm;
+        }
+        electron_kernel(b, estack, true, tg2, stream);
+    }
 }
 
 void launch_fold(psl_tally* t, hipStream_t s) {
@@ -1043,7 +1379,7 @@ extern "C" int psl_tally_create(const psl_phantom* ph, const int32_t* imap, int3
         t->phantom = ph;
         const int64_t nv = int64_t(ph->g.nx) * ph->g.ny * ph->g.nz;
         if (imap) {
-            PSL_CHECK(n_rows >= 1 && n_cols >= 1 && n_cols <= 65536, "bad n_rows / n_cols");
+            PSL_CHECK(n_rows >= 1 && n_cols >= 1 && n_cols <= 32768, "bad n_rows / n_cols");
             t->imap = imap;
             t->n_rows = n_rows;
             t->n_cols = n_cols;
@@ -1103,8 +1439,12 @@ extern "C" int transport_batch(const psl_phantom* phantom, const psl_particles* 
         }
         const psl_particles* es = in->ptype == 0 ? electrons : in;
         ensure_physics(const_cast<psl_phantom*>(phantom), params);
-        if (tally->ws.perm_cap < es->capacity)
-            tally->ws = alloc_transport_ws(tally->ws_mem, es->capacity);
+        const uint32_t ann_need =
+            (params->physics & kPhysPair) && in->ptype == 0 ? 2u * in->capacity : 0u;
+        PSL_CHECK(ann_need == 0 || in->capacity <= (1u << 30), "photon stack too large");
+        if (tally->ws.perm_cap < es->capacity || tally->ws.ann_cap < ann_need)
+            tally->ws = alloc_transport_ws(tally->ws_mem, std::max(es->capacity, tally->ws.perm_cap),
+                                           std::max(ann_need, tally->ws.ann_cap));
         psl_particles dummy = *in;
         launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, tally->ws,
                          params, seed, static_cast<hipStream_t>(stream), true, 4);
@@ -1153,6 +1493,23 @@ extern "C" int tally_dose(psl_tally* t, int32_t ops, const psl_plan* plan, doubl
             PSL_HIP(hipGetLastError());
             PSL_HIP(hipStreamSynchronize(s));   // cw lives on this stack frame
         }
+    });
+}
+
+extern "C" int psl_tally_record(psl_tally* t, uint32_t* cells_dev, uint32_t capacity,
+                                uint32_t* count_dev) {
+    return guarded([&] {
+        PSL_CHECK(t, "psl_tally_record: null tally");
+        if (!cells_dev) {
+            t->rec = nullptr;
+            t->rec_count = nullptr;
+            t->rec_cap = 0;
+            return;
+        }
+        PSL_CHECK(count_dev && capacity > 0, "psl_tally_record: count and capacity required");
+        t->rec = cells_dev;
+        t->rec_count = count_dev;
+        t->rec_cap = capacity;
     });
 }
 

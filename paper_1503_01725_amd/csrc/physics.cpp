@@ -5,7 +5,11 @@
 //   * R(T): CSDA range above the electron cut-off, integral of 1/S_col with the
 //     Bethe collision stopping power of water (ICRU 37 form, I = 75 eV), with
 //     or without Sternheimer's density-effect correction, on a log-T grid;
-//   * T(R): its inverse, on a grid uniform in ln(R + R_off).
+//   * T(R): its inverse, on a grid uniform in ln(R + R_off);
+//   * with optional photon processes: the cumulative attenuations (Compton,
+//     + photoelectric, + Rayleigh, + pair) per unit density on the log-E
+//     grid, and the cumulative integral of the molecule's squared form factor
+//     for sampling the Rayleigh angle.
 #include <cmath>
 
 #include "common.hpp"
@@ -76,12 +80,101 @@ double inv_s_integral(double a, double b, int m, bool dens) {
     return s * h / 3.0;
 }
 
+// ---- optional photon processes (water) --------------------------------------
+constexpr double kAlpha = 7.2973525693e-3;
+constexpr double kBohr = 0.529177210903e-8;     // cm
+constexpr double kRydberg = 13.605693122994e-6; // MeV
+constexpr double kHbarC = 1.973269804e-11;      // MeV cm
+constexpr double kZeta3 = 1.2020569031595942;
+constexpr double kMolPerGram = kNa / 18.0153;
+constexpr double kZ1s = 7.70, kZn2 = 4.55;      // Slater-screened charges of O
+constexpr double kRayTLo = 1.0e-4, kRayTHi = 4.0e8;   // t = (q a0)^2 nodes
+
+// Stobbe: photoeffect of one hydrogenic K electron of nuclear charge z (cm^2).
+double k_shell_electron(double e, double z) {
+    const double ib = z * z * kRydberg;
+    if (e <= ib) return 0.0;
+    const double nu = std::sqrt(ib / (e - ib));
+    const double x = ib / e, x2 = x * x;
+    const double len = kBohr / z;
+    const double coulomb = std::exp(-4.0 * nu * std::atan2(1.0, nu)) / -std::expm1(-2.0 * kPi * nu);
+    return (512.0 / 3.0) * kPi * kPi * kAlpha * len * len * x2 * x2 * coulomb;
+}
+
+// Squared form factor of H2O (independent hydrogenic atoms) at t = (q a0)^2.
+double water_ff2(double t) {
+    auto f1s = [](double s2) { const double a = 1.0 + 0.25 * s2; return 1.0 / (a * a); };
+    auto f2 = [](double s2, double num) {
+        const double d = (1.0 + s2) * (1.0 + s2);
+        return num / (d * d);
+    };
+    const double sa = t / (kZ1s * kZ1s), sb = t / (kZn2 * kZn2);
+    const double hydrogen = f1s(t);
+    const double oxygen = 2.0 * f1s(sa) + 2.0 * f2(sb, 1.0 - 3.0 * sb + 2.0 * sb * sb) +
+                          4.0 * f2(sb, 1.0 - sb);
+    return 2.0 * hydrogen * hydrogen + oxygen * oxygen;
+}
+
+// Unscreened Bethe-Heitler pair cross-section per unit Z^2 (Maximon).
+double pair_per_z2(double e) {
+    const double k = e / kMe;
+    if (k <= 2.0) return 0.0;
+    const double ar2 = kAlpha * kRe * kRe;
+    if (k < 4.0) {
+        const double ep = (2.0 * k - 4.0) / (2.0 + k + 2.0 * std::sqrt(2.0 * k));
+        const double r = (k - 2.0) / k;
+        const double series = 1.0 + ep * (0.5 + ep * (23.0 / 40.0 + ep * (11.0 / 60.0 + ep * 29.0 / 960.0)));
+        return (2.0 * kPi / 3.0) * ar2 * r * r * r * series;
+    }
+    const double l = std::log(2.0 * k), y = 4.0 / (k * k);
+    const double c2 = 6.0 * l - 3.5 + (2.0 / 3.0) * l * l * l - l * l - kPi * kPi / 3.0 * l +
+                      2.0 * kZeta3 + kPi * kPi / 6.0;
+    const double c4 = (3.0 / 16.0) * l + 0.125;
+    const double c6 = (29.0 / 2304.0) * l - 77.0 / 13824.0;
+    return ar2 * ((28.0 / 9.0) * l - 218.0 / 27.0 + y * c2 - y * y * c4 - y * y * y * c6);
+}
+
+// Integral of g over [a, b] (0 < a < b) by Simpson's rule in ln t.
+template <class G>
+double log_simpson(G&& g, double a, double b, int m) {
+    const double la = std::log(a), h = (std::log(b) - la) / m;
+    double s = 0.0;
+    for (int i = 0; i <= m; ++i) {
+        const double t = std::exp(la + i * h);
+        const double w = (i == 0 || i == m) ? 1.0 : (i % 2 ? 4.0 : 2.0);
+        s += w * g(t) * t;
+    }
+    return s * h / 3.0;
+}
+
+// Rayleigh cross-section of one molecule (cm^2) at photon energy e.
+double rayleigh_molecule(double e) {
+    const double x2 = (e * kBohr / kHbarC) * (e * kBohr / kHbarC);
+    const double tmax = 4.0 * x2;
+    auto g = [&](double t) {
+        const double c = 1.0 - t / (2.0 * x2);
+        return (1.0 + c * c) * water_ff2(t);
+    };
+    // [0, t1] with t1 tiny: F^2 and the angular factor are flat there
+    const double t1 = std::min(1e-6, tmax);
+    double sum = g(0.0) * t1;
+    if (tmax > t1) sum += log_simpson(g, t1, tmax, 4000);
+    return kPi * kRe * kRe / (2.0 * x2) * sum;
+}
+
 }  // namespace
 
 void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     PSL_CHECK(p->density_effect == 0 || p->density_effect == 1, "density_effect must be 0 or 1");
     const bool dens = p->density_effect == 1;
-    if (ph->t_cut_tab == p->e_cut_electron && ph->dens_tab == p->density_effect && ph->tabs.p) return;
+    PSL_CHECK((p->physics & ~(kPhysPhoto | kPhysRayleigh | kPhysPair)) == 0,
+              "physics: unknown process bits 0x%x", p->physics);
+    PSL_CHECK(!(p->physics & kPhysPair) || p->e_cut_electron <= float(kMe),
+              "pair production needs e_cut_electron <= mc^2 (every push then costs the "
+              "photon at least the cut-off)");
+    if (ph->t_cut_tab == p->e_cut_electron && ph->dens_tab == p->density_effect &&
+        ph->phys_tab == int32_t(p->physics) && ph->tabs.p)
+        return;
     const double tcut = p->e_cut_electron;
     PSL_CHECK(tcut > 2.0e-3 && tcut < 10.0, "e_cut_electron must be in (0.002, 10) MeV");
     // A photon pays at least the cut-off for every electron it sets in
@@ -92,7 +185,12 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
               "e_cut_electron must be at least %.4f MeV (at most 255 electrons per photon of "
               "up to %.0f MeV)", kEmax / 255.0, kEmax);
 
-    std::vector<float> host(size_t(KN_TAB_N) + RNG_TAB_N + INV_TAB_N);
+    const uint32_t phys = p->physics;
+    // layout: kn, rng, inv, then (optional processes) xs as float4 (kept
+    // 16-byte aligned), ray_t, ray_a
+    const size_t base = size_t(KN_TAB_N) + RNG_TAB_N + INV_TAB_N;
+    const size_t extra = phys ? size_t(4) * KN_TAB_N + 2 * RAY_TAB_N : 0;
+    std::vector<float> host(base + extra);
     float* kn = host.data();
     float* rng = kn + KN_TAB_N;
     float* inv = rng + RNG_TAB_N;
@@ -129,6 +227,40 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
         }
         inv[i] = float(t);
     }
+    double ray_lt1 = 0.0, ray_dlt = 1.0;
+    if (phys) {
+        float* xs = inv + INV_TAB_N;
+        float* ray_t = xs + 4 * KN_TAB_N;
+        float* ray_a = ray_t + RAY_TAB_N;
+        for (int i = 0; i < KN_TAB_N; ++i) {
+            const double e = std::exp(le0 + i * dle);
+            const double mc = ne * klein_nishina(e);
+            const double mp = (phys & kPhysPhoto) ? kMolPerGram * 2.0 * k_shell_electron(e, kZ1s) : 0.0;
+            const double mr = (phys & kPhysRayleigh) ? kMolPerGram * rayleigh_molecule(e) : 0.0;
+            const double mx = (phys & kPhysPair) ? kMolPerGram * 66.0 * pair_per_z2(e) : 0.0;
+            xs[4 * i + 0] = float(mc);
+            xs[4 * i + 1] = float(mc + mp);
+            xs[4 * i + 2] = float(mc + mp + mr);
+            xs[4 * i + 3] = float(mc + mp + mr + mx);
+        }
+        // t nodes: 0, then log-spaced from kRayTLo to kRayTHi; the cumulative
+        // of F^2 between nodes by Simpson's rule in ln t
+        ray_lt1 = std::log(kRayTLo);
+        ray_dlt = (std::log(kRayTHi) - ray_lt1) / (RAY_TAB_N - 2);
+        double acc = water_ff2(0.0) * kRayTLo;   // F^2 is flat below kRayTLo
+        ray_t[0] = 0.f;
+        ray_a[0] = 0.f;
+        double prev = kRayTLo;
+        ray_t[1] = float(kRayTLo);
+        ray_a[1] = float(acc);
+        for (int i = 2; i < RAY_TAB_N; ++i) {
+            const double t = std::exp(ray_lt1 + (i - 1) * ray_dlt);
+            acc += log_simpson(water_ff2, prev, t, 16);
+            ray_t[i] = float(t);
+            ray_a[i] = float(acc);
+            prev = t;
+        }
+    }
     ph->tabs.upload(host);
     PhysicsDev& d = ph->phys;
     d.kn_lne0 = float(le0);
@@ -144,8 +276,17 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     d.kn = ph->tabs.as<float>();
     d.rng = d.kn + KN_TAB_N;
     d.inv = d.rng + RNG_TAB_N;
+    d.physics = phys;
+    d.xs = phys ? reinterpret_cast<const float4*>(d.inv + INV_TAB_N) : nullptr;
+    d.ray_t = phys ? d.inv + INV_TAB_N + 4 * KN_TAB_N : nullptr;
+    d.ray_a = phys ? d.ray_t + RAY_TAB_N : nullptr;
+    d.ray_lt1 = float(ray_lt1);
+    d.ray_inv_dlt = float(1.0 / ray_dlt);
+    d.ka0_per_mev = float(kBohr / kHbarC);
+    d.photo_bind = float(kZ1s * kZ1s * kRydberg);
     ph->t_cut_tab = p->e_cut_electron;
     ph->dens_tab = p->density_effect;
+    ph->phys_tab = int32_t(phys);
     ++ph->tab_gen;
 }
 

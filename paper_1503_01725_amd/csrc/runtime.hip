@@ -54,6 +54,8 @@ struct GraphKey {
     uint64_t n_batches = 0;
     uint64_t tab_gen = 0;   // physics-table generation of the phantom
     int32_t dens = 0;
+    uint32_t physics = 0;        // optional photon processes
+    const void* rec = nullptr;   // deposit recording buffer (kernels differ)
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof o) == 0; }
 };
 
@@ -125,7 +127,7 @@ struct Runner {
             rep.alloc(256);
         }
     }
-    void ensure_stacks(int n_pipes, uint32_t ph, uint32_t el) {
+    void ensure_stacks(int n_pipes, uint32_t ph, uint32_t el, bool pair) {
         for (int i = 0; i < n_pipes; ++i) {
             Pipe& p = pipes[i];
             if (ph > p.ph_cap) {
@@ -139,9 +141,11 @@ struct Runner {
                 p.el_cap = el;
             }
             const uint32_t need = std::max(p.ph_cap, p.el_cap);
-            if (p.ws.perm_cap < need) {
+            const uint32_t ann = pair ? 2u * p.ph_cap : 0u;
+            if (p.ws.perm_cap < need || p.ws.ann_cap < ann) {
                 drop_graph();
-                p.ws = alloc_transport_ws(p.ws_mem, need);
+                p.ws = alloc_transport_ws(p.ws_mem, std::max(need, p.ws.perm_cap),
+                                          std::max(ann, p.ws.ann_cap));
             }
         }
     }
@@ -285,7 +289,13 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     const uint32_t per = uint32_t(std::max(1.0, std::floor(emax / prm->e_cut_electron))) + 1;
     const uint64_t el_need = uint64_t(o.max_batch) * per;
     PSL_CHECK(el_need < (uint64_t(1) << 32), "electron stack would exceed 2^32 entries");
-    R.ensure_stacks(n_pipes_of(o, plan), o.max_batch, uint32_t(el_need));
+    // annihilation photons take ids g | (2 sub + k) << 48
+    PSL_CHECK(!(prm->physics & kPhysPair) ||
+                  double(plan->n_hist) * double(plan->n_replica) < double(uint64_t(1) << 48),
+              "pair production needs history ids below 2^48");
+    PSL_CHECK(o.max_batch <= (1u << 30), "max_batch too large");
+    R.ensure_stacks(n_pipes_of(o, plan), o.max_batch, uint32_t(el_need),
+                    (prm->physics & kPhysPair) != 0u);
     ensure_physics(const_cast<psl_phantom*>(ph), prm);
     ensure_device(plan);
 
@@ -316,7 +326,9 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     k.frac = prm->step_frac;
     k.ms = prm->ms_enable;
     k.dens = prm->density_effect;
+    k.physics = prm->physics;
     k.tab_gen = ph->tab_gen;
+    k.rec = tally->rec;
     k.pipes = n_pipes_of(o, plan);
     k.ph_cap = R.pipes[0].ph_cap;
     k.el_cap = R.pipes[0].el_cap;

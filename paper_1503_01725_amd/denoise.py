@@ -22,6 +22,8 @@ from . import workloads as wl
 # history counts of the evaluated plain / denoised doses
 EVAL_COUNTS = (1e6, 3e6, 1e7, 3e7, 1e8)
 RMS_TARGETS = (2.0, 1.0, 0.6)   # stated RMS errors, % of Dmax
+# stated errors of the gated path (RMS over voxels above 10 % of Dmax, % of Dmax)
+GATED_TARGETS = (4.0, 2.0, 1.0, 0.5)
 
 
 def case_geometry(seed, n=128, vox=0.25):
@@ -45,8 +47,9 @@ class DoseEngine:
         self.seed = seed
         self.prm = eng.transport_params()
 
-    def dose(self, n_hist, n_rep=4, seed_offset=0, max_batch=1 << 20):
-        """Dose and standard error (Gy per model particle, torch on the GPU)."""
+    def dose(self, n_hist, n_rep=4, seed_offset=0, max_batch=1 << 20, fp64=False):
+        """Dose and standard error (Gy per model particle, torch on the GPU;
+        FP32 unless fp64)."""
         import torch
         eng = self.eng
         per = max(1, n_hist // n_rep)
@@ -57,7 +60,30 @@ class DoseEngine:
                                   seed=self.seed * 1000003 + seed_offset))
         d, s = tally.finalize(plan)
         torch.cuda.synchronize()
-        return d.float(), s.float()
+        return (d, s) if fp64 else (d.float(), s.float())
+
+    def dose_independent(self, n_hist, n_rep=4, seed_offset=0, max_batch=1 << 20):
+        """Dose and standard error (FP64) from n_rep replicas whose plans hold
+        N + 1, N + 2, ... histories (N = n_hist / n_rep).  The Eq. (3) counts
+        of one plan are the same in each of its replicas, and with a few
+        histories per phase-space-let their rounding leaves a fluence pattern
+        that replicas of one plan share and their spread does not show;
+        different N round differently, so the spread of these replicas covers
+        it.  Normalised with the first plan's N (relative error < n_rep / N)."""
+        import torch
+        eng = self.eng
+        per = max(1, n_hist // n_rep)
+        tally = eng.Tally(self.phantom)
+        plans = []
+        for r in range(n_rep):
+            plan = eng.Plan(self.model, [self.beam], per + 1 + r, n_replica=1)
+            eng.run_plan(plan, self.phantom, tally, self.prm,
+                         eng.run_opts(min(max_batch, max(4096, per)), 24, use_graph=False,
+                                      seed=self.seed * 1000003 + seed_offset + 7919 * r))
+            plans.append(plan)
+        d, s = tally.finalize(plans[0])
+        torch.cuda.synchronize()
+        return d, s
 
 
 def rms_percent(d, ref, mask=None):
@@ -110,6 +136,126 @@ def sigma_rel(d, s, frac=0.5):
     """RMS of sigma/D over voxels with D above frac * Dmax."""
     sel = d > frac * d.max()
     return float(np.sqrt(np.mean((s[sel] / d[sel]) ** 2)))
+
+
+GATE_CUTOFF = 0.1   # voxels judged: candidate dose above this fraction of its maximum
+GATE_Z = 2.0        # standard errors on each side of the estimate for a decision
+GATE_BLOCK = 4      # edge of the voxel blocks of the correlation-robust standard error
+
+
+def gate_stats(cand, plain, plain_sigma, cutoff=GATE_CUTOFF, z=GATE_Z, block=GATE_BLOCK):
+    """The plain engine's judgement of a candidate dose (psl_dose_gate).
+
+    M is the candidate's largest mean over block^3-voxel blocks.  mse: mean
+    of (cand - plain)^2 - sigma^2 over the voxels where the candidate exceeds
+    `cutoff` of M, an unbiased estimate of the candidate's mean squared error
+    against the true dose; se: its standard error from the blocks (noise
+    correlated within a block counted); dmax: the plain dose's mean over the
+    candidate's top region (blocks whose candidate mean is >= 95 % of M), an
+    unbiased reading of the true dose there that a spurious hot spot of the
+    candidate lowers rather than raises.  Returned in % of dmax:
+    the estimate, its band estimate_lo / estimate_hi at z standard errors, and
+    the plain dose's own RMS standard error over the same voxels."""
+    import ctypes as C
+    import torch
+    from . import _native as N
+    shape = tuple(plain.shape) if plain.dim() == 3 else (1, 1, plain.numel())
+    assert cand.numel() == plain.numel() == plain_sigma.numel()
+    assert cand.dtype == torch.float32 and plain.dtype == plain_sigma.dtype == torch.float64
+    cand, plain, plain_sigma = cand.contiguous(), plain.contiguous(), plain_sigma.contiguous()
+    out = np.zeros(10)
+    nz, ny, nx = shape
+    N.check(N.lib().psl_dose_gate(cand.data_ptr(), plain.data_ptr(), plain_sigma.data_ptr(),
+                                  nx, ny, nz, block, cutoff, out.ctypes.data_as(N.dp),
+                                  C.c_void_p(int(torch.cuda.current_stream().cuda_stream))))
+    n_c, cmax, sd2, ss2, st2, stn, sn2, n_top, sum_top, n_blk = out
+    dmax = sum_top / n_top if n_top > 0 else 0.0
+    if n_c == 0 or not dmax > 0:
+        inf = float("inf")
+        return {"voxels": int(n_c), "estimate": inf, "estimate_lo": inf, "estimate_hi": inf,
+                "plain_rms": inf, "mse": inf, "se": inf, "dmax": dmax}
+    mse = (sd2 - ss2) / n_c
+    var = (st2 - 2.0 * mse * stn + mse * mse * sn2) / (n_c * n_c)
+    if n_blk > 1:
+        var *= n_blk / (n_blk - 1.0)
+    se = float(np.sqrt(max(var, 0.0)))
+    pct = 100.0 / dmax
+    root = lambda v: pct * float(np.sqrt(max(v, 0.0)))
+    return {"voxels": int(n_c), "blocks": int(n_blk), "dmax": float(dmax),
+            "candidate_max": float(cmax), "mse": float(mse), "se": se,
+            "estimate": root(mse), "estimate_lo": root(mse - z * se),
+            "estimate_hi": root(mse + z * se), "plain_rms": root(ss2 / n_c)}
+
+
+def gated_dose(net, E, density, n_input, target_rms, n_judge=None, judge_reps=4,
+               seed_offsets=(11, 12, 13), max_rounds=3):
+    """The denoised dose with the plain engine as its judge and fallback.
+
+    1. A plain dose of n_input histories (one replica) is the network's input.
+    2. An independent plain dose (judge_reps replicas of distinct history
+       counts, DoseEngine.dose_independent, other random numbers; n_judge
+       histories, default 4 n_input) and its standard error judge the
+       prediction (gate_stats): the mean of (denoised - judge)^2 - sigma^2
+       estimates the denoised dose's squared error against the true dose.
+    3. If the estimate plus two standard errors is within target_rms (% of
+       Dmax) the denoised dose is returned.  If the estimate minus two
+       standard errors exceeds it, or the judge would have to grow to half
+       the plain run the target needs, the plain engine takes over.
+       Otherwise (the judge too noisy to decide) the judge runs again with
+       4x the histories, at most max_rounds times.
+    4. The fallback: the plain engine runs to target_rms, with its histories
+       scaled from the judge's own RMS error (sigma ~ N^-1/2) and extended
+       until the run's own RMS standard error meets target_rms; the plain
+       dose is returned.
+    Returns (dose on the device, FP32 or FP64; info dict with the branch
+    taken, the histories run and the gate figures)."""
+    import torch
+    n_judge = int(n_judge or 4 * n_input)
+    t0 = time.perf_counter()
+    d_in, _ = E.dose(int(n_input), n_rep=1, seed_offset=seed_offsets[0])
+    scale = float(d_in.max())
+    if not scale > 0:
+        raise ValueError("the plain input dose is zero everywhere")
+    dens = torch.as_tensor(density, dtype=torch.float32, device="cuda")
+    inp = torch.stack([d_in / scale, dens]).contiguous()
+    pred = net.forward(inp) * scale
+    spent = int(n_input)
+    rounds = []
+    for rnd in range(max_rounds):
+        judge, jsig = E.dose_independent(n_judge, n_rep=judge_reps,
+                                         seed_offset=seed_offsets[1] + 997 * rnd)
+        spent += n_judge
+        g = gate_stats(pred, judge, jsig)
+        rounds.append({"n_judge": n_judge, "estimate": g["estimate"],
+                       "estimate_lo": g["estimate_lo"], "estimate_hi": g["estimate_hi"],
+                       "plain_rms": g["plain_rms"]})
+        if g["estimate_hi"] <= target_rms:
+            torch.cuda.synchronize()
+            return pred, {"gate": g, "rounds": rounds, "target_rms": float(target_rms),
+                          "n_input": int(n_input), "branch": "denoised", "histories": spent,
+                          "seconds": time.perf_counter() - t0, "candidate": pred}
+        n_plain_need = n_judge * (g["plain_rms"] / target_rms) ** 2
+        if g["estimate_lo"] > target_rms or 4 * n_judge > 0.5 * n_plain_need:
+            break
+        n_judge *= 4
+    info = {"gate": g, "rounds": rounds, "target_rms": float(target_rms),
+            "n_input": int(n_input), "candidate": pred}
+    # the plain engine to the stated error: histories scaled from the judge's
+    # own error, then from the run's own (its high-dose region) until that
+    # meets the target
+    n_plain = max(int(np.ceil(n_judge * (g["plain_rms"] / target_rms) ** 2)), judge_reps)
+    for attempt in range(4):
+        d, s = E.dose_independent(n_plain, n_rep=judge_reps,
+                                  seed_offset=seed_offsets[2] + 101 * attempt)
+        spent += n_plain
+        own = gate_stats(d.float(), d, s)["plain_rms"]
+        if own <= target_rms:
+            break
+        n_plain = int(np.ceil(n_plain * 1.1 * (own / target_rms) ** 2))
+    torch.cuda.synchronize()
+    info.update(branch="plain", n_plain=n_plain, plain_rms=own, histories=spent,
+                seconds=time.perf_counter() - t0, sigma=s)
+    return d, info
 
 
 def make_pairs(seeds, n_low, n_high, model_src, n=128, log=print):
@@ -210,6 +356,13 @@ def bench_unet(width=32, n=128, iters=10, log=print):
     return out
 
 
+def rms_percent_region(d, ref, cutoff=GATE_CUTOFF):
+    """Eq. (10) over the voxels where the reference exceeds `cutoff` of its
+    maximum, in % of that maximum (the region and scale the gate judges)."""
+    m = ref > cutoff * ref.max()
+    return 100.0 * float(np.sqrt(np.mean((d[m] - ref[m]).astype(np.float64) ** 2))) / float(ref.max())
+
+
 def main():
     import argparse
     import torch
@@ -217,6 +370,8 @@ def main():
     ap = argparse.ArgumentParser(description="train and evaluate the dose denoiser")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--train", type=int, default=200)
+    ap.add_argument("--val", type=int, default=5,
+                    help="validation cases that choose the gated input size per stated error")
     ap.add_argument("--test", type=int, default=20)
     ap.add_argument("--n-low", type=float, default=1e6)
     ap.add_argument("--n-high", type=float, default=1e9)
@@ -251,11 +406,39 @@ def main():
     del train_pairs
     if args.save:
         np.save(args.save, net.get_params())
-    # evaluation on held-out cases
-    res = {"train_cases": args.train, "test_cases": args.test, "n_low": args.n_low,
-           "n_high": args.n_high, "epochs": args.epochs, "loss_history": hist,
-           "t_data_s": t_data, "t_train_s": t_train, "cases": []}
+    res = {"train_cases": args.train, "val_cases": args.val, "test_cases": args.test,
+           "n_low": args.n_low, "n_high": args.n_high, "epochs": args.epochs,
+           "loss_history": hist, "t_data_s": t_data, "t_train_s": t_train, "cases": []}
     vox = (0.25, 0.25, 0.25)
+    dens_of = lambda ph: torch.as_tensor(ph.density, device="cuda")
+
+    def denoise_once(E, ph, nl, seed_offset):
+        d, _ = E.dose(int(nl), n_rep=1, seed_offset=seed_offset)
+        scale = float(d.max())
+        inp = torch.stack([d / scale, dens_of(ph)]).contiguous()
+        return (net.forward(inp) * scale)
+
+    # validation (seeds of their own): the denoised error per input size
+    val = {f"{nl:.0e}": [] for nl in EVAL_COUNTS}
+    for s in range(7000, 7000 + args.val):
+        ph, beam = case_geometry(s, args.n)
+        E = DoseEngine(model_src, ph, beam, s)
+        ref = E.dose(int(args.n_high), n_rep=1, seed_offset=9)[0].cpu().numpy()
+        for nl in EVAL_COUNTS:
+            dn_ = denoise_once(E, ph, nl, 7).cpu().numpy()
+            val[f"{nl:.0e}"].append(rms_percent_region(dn_, ref))
+        log(f"[denoise] validation case {s}")
+    val_mean = {k: float(np.mean(v)) for k, v in val.items()}
+    # input size of the gated path per stated error: the fewest histories
+    # whose validation denoised error is at most 0.8 of it (None: the
+    # denoiser does not reach it, the gate will hand over to the plain engine)
+    policy = {}
+    for e in GATED_TARGETS:
+        policy[f"{e:g}"] = next((nl for nl in EVAL_COUNTS if val_mean[f"{nl:.0e}"] <= 0.8 * e),
+                                None)
+    res["validation_denoised_rms_region"] = val_mean
+    res["gated_input_policy"] = policy
+    log(f"[denoise] validation {json.dumps(val_mean)} policy {json.dumps(policy)}")
     for s in range(5000, 5000 + args.test):
         ph, beam = case_geometry(s, args.n)
         E = DoseEngine(model_src, ph, beam, s)
@@ -265,24 +448,46 @@ def main():
         t_ref = time.perf_counter() - t0
         rate = args.n_high / t_ref
         refn = ref.cpu().numpy()
-        row = {"seed": s, "hist_per_s": rate}
+        row = {"seed": s, "hist_per_s": rate, "gated": {}}
         for nl in EVAL_COUNTS:
             d, sd = E.dose(int(nl), n_rep=4, seed_offset=int(nl) % 97 + 3)
             scale = float(d.max())
-            inp = torch.stack([d / scale, torch.as_tensor(ph.density, device="cuda")]).contiguous()
+            inp = torch.stack([d / scale, dens_of(ph)]).contiguous()
             t0 = time.perf_counter()
             pred = net.forward(inp)
             torch.cuda.synchronize()
             t_inf = time.perf_counter() - t0
-            dn = (pred * scale).cpu().numpy()
+            dn_ = (pred * scale).cpu().numpy()
             dp = d.cpu().numpy()
             row[f"{nl:.0e}"] = {
-                "plain_rms": rms_percent(dp, refn), "denoised_rms": rms_percent(dn, refn),
+                "plain_rms": rms_percent(dp, refn), "denoised_rms": rms_percent(dn_, refn),
+                "plain_rms_region": rms_percent_region(dp, refn),
+                "denoised_rms_region": rms_percent_region(dn_, refn),
                 "plain_gamma": gamma_pass_rate(dp, refn, vox),
-                "denoised_gamma": gamma_pass_rate(dn, refn, vox),
+                "denoised_gamma": gamma_pass_rate(dn_, refn, vox),
                 "sigma_rel": sigma_rel(dp, sd.cpu().numpy()), "t_infer_s": t_inf}
+        # the gated path at each stated error (region RMS, % of Dmax)
+        for e in GATED_TARGETS:
+            n_in = policy[f"{e:g}"]
+            if n_in is None:
+                # the denoiser does not reach e on validation: plain engine,
+                # histories from the plain error at 1e6 (sigma ~ N^-1/2)
+                n_p = int(np.ceil(1e6 * (row["1e+06"]["plain_rms_region"] / e) ** 2))
+                t0 = time.perf_counter()
+                dd, _ = E.dose(n_p, n_rep=4, seed_offset=41)
+                torch.cuda.synchronize()
+                info = {"branch": "plain (policy)", "histories": n_p,
+                        "seconds": time.perf_counter() - t0}
+            else:
+                dd, info = gated_dose(net, E, ph.density, n_in, e)
+            got = rms_percent_region(dd.float().cpu().numpy(), refn)
+            row["gated"][f"{e:g}"] = {"branch": info["branch"], "histories": info["histories"],
+                                      "seconds": info["seconds"], "rms_region": got,
+                                      "met": got <= e,
+                                      "estimate": info.get("gate", {}).get("estimate")}
         res["cases"].append(row)
-        log(f"[denoise] test case {s}: " + json.dumps(row["1e+06"]))
+        log(f"[denoise] test case {s}: " + json.dumps(row["1e+06"]) + " gated " +
+            json.dumps(row["gated"]))
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(res, f)
@@ -334,7 +539,31 @@ def summarize(res):
         stated[f"{e:g}"] = {"plain_histories": n_p, "plain_s": n_p / rate,
                             "denoised_histories": n_d, "denoised_s": t_d,
                             "speedup": (n_p / rate) / t_d if t_d else None}
-    return {"per_history_count": out, "hist_per_s": rate,
+    # the gated path: per stated error, the branch taken, the fraction of
+    # cases whose returned dose meets it, histories and time, against the
+    # plain engine's histories to the same error (fit at 1e6 per case)
+    gated = {}
+    if res["cases"] and "gated" in res["cases"][0]:
+        for e in GATED_TARGETS:
+            key = f"{e:g}"
+            rows = [c["gated"][key] for c in res["cases"]]
+            n_plain = [1e6 * (c["1e+06"]["plain_rms_region"] / e) ** 2 for c in res["cases"]]
+            t_g = float(np.mean([r["seconds"] for r in rows]))
+            h_g = float(np.mean([r["histories"] for r in rows]))
+            gated[key] = {"denoised_fraction": float(np.mean([r["branch"] == "denoised"
+                                                              for r in rows])),
+                          "met_fraction": float(np.mean([r["met"] for r in rows])),
+                          "mean_rms_region": float(np.mean([r["rms_region"] for r in rows])),
+                          "histories": h_g, "seconds": t_g,
+                          "plain_histories": float(np.mean(n_plain)),
+                          "plain_s": float(np.mean(n_plain)) / rate,
+                          "speedup_histories": float(np.mean(n_plain)) / h_g}
+    for k in keys:
+        if "plain_rms_region" in res["cases"][0][k]:
+            for m in ("plain_rms_region", "denoised_rms_region"):
+                out[k][m] = float(np.mean([c[k][m] for c in res["cases"]]))
+    return {"per_history_count": out, "hist_per_s": rate, "gated": gated,
+            "gated_input_policy": res.get("gated_input_policy"),
             "time_to_1pct": {"rms_error_percent_of_dmax": rms_at_1pct,
                              "plain_histories": n1, "plain_s": t_plain,
                              "denoised_histories": n_den, "denoised_s": t_den},

@@ -186,13 +186,13 @@ class Tally:
 
     def stats(self):
         led = np.zeros(8)
-        cnt = np.zeros(16, dtype=np.uint64)
+        cnt = np.zeros(N.N_COUNTERS, dtype=np.uint64)
         rc = N.lib().psl_tally_stats(self.h, led.ctypes.data_as(N.dp), cnt.ctypes.data_as(N.u64p))
         names_l = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")
         names_c = ("hist", "entered", "wc_steps", "real", "e_pushed", "e_local", "e_steps",
                    "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard", "overflow",
-                   "folds")
-        out = dict(zip(names_l, led.tolist())), dict(zip(names_c, cnt[:14].tolist()))
+                   "folds", "photo", "rayleigh", "pair", "annihil")
+        out = dict(zip(names_l, led.tolist())), dict(zip(names_c, cnt[:len(names_c)].tolist()))
         if rc != N.PSL_OK:
             raise N.PslError(rc, N.lib().psl_last_error().decode())
         return out
@@ -238,9 +238,11 @@ class Particles:
 
 
 def transport_params(e_cut_electron=0.2, e_cut_photon=0.01, step_frac=0.1, ms=True,
-                     density_effect=False):
+                     density_effect=False, physics=0):
+    """psl_transport_params; physics: PSL_PHYS_* bits of the optional photon
+    processes (photoelectric 1, Rayleigh 2, pair 4; 0 = Compton only)."""
     return N.psl_transport_params(e_cut_electron, e_cut_photon, step_frac, 1 if ms else 0,
-                                  1 if density_effect else 0)
+                                  1 if density_effect else 0, int(physics))
 
 
 def electron_capacity(photon_capacity, e_max, e_cut_electron):

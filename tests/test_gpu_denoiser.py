@@ -159,3 +159,49 @@ def test_training_lowers_loss(eng, case):
         torch.cuda.synchronize()
         losses.append(float(lp.sum().item()))
     assert losses[-1] < 0.5 * losses[0], losses[::10]
+
+
+@pytest.fixture(scope="module")
+def case64():
+    """Base width 8 on a 64^3 volume: the four levels hold 64^3, 32^3, 16^3
+    and 8^3 voxels, so no gradient rests on a few-voxel level."""
+    from oracle import denoiser as D
+    rng = np.random.default_rng(8)
+    c, n = 8, 64
+    shapes = D.param_shapes(c, 2)
+    p = D.init_params(4, c=c)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.05 * rng.standard_normal(p[k].shape)
+    p["head.w"] = p["head.w"] * 10.0
+    x = np.stack([rng.uniform(0, 1, (n, n, n)), rng.uniform(0.2, 1.8, (n, n, n))])
+    target = x[0] + 0.1 * rng.standard_normal((n, n, n))
+    print("[denoiser parity] FP64 oracle gradients at 64^3", flush=True)
+    loss, g = D.loss_and_grad(p, x, target)
+    print("[denoiser parity] BF16-emulated oracle gradients at 64^3", flush=True)
+    _, g_bf = _bf16_gradients(D, p, x, target)
+    return dict(D=D, c=c, n=n, shapes=shapes, p=p, x=x, target=target, loss=loss, g=g, g_bf=g_bf)
+
+
+def test_gradients_match_oracle_flat_bound_at_64(eng, case64):
+    """Every parameter gradient within 3 % (relative L2) of the oracle with
+    BF16 rounding emulated where the GPU stores BF16, and pointing the same
+    way as the plain FP64 gradient (cosine >= 0.998), on a volume whose
+    deepest level still holds 8^3 voxels."""
+    net, inp, tgt = _net(eng, case64)
+    g, loss = net.gradients(inp, tgt)
+    assert loss == pytest.approx(case64["loss"], rel=1e-2)
+    gd = _unflat(g.astype(np.float64), case64["shapes"])
+    worst = 0.0
+    for name, _ in case64["shapes"]:
+        ref, ref_bf, got = case64["g"][name], case64["g_bf"][name], gd[name]
+        nr = np.linalg.norm(ref)
+        if nr == 0:
+            continue
+        rel_bf = np.linalg.norm(got - ref_bf) / np.linalg.norm(ref_bf)
+        cos = float(np.dot(got.ravel(), ref.ravel()) / (np.linalg.norm(got) * nr))
+        worst = max(worst, rel_bf)
+        assert rel_bf < 0.03, (name, rel_bf)
+        assert cos >= 0.998, (name, cos)
+    print(f"[denoiser parity] 64^3: worst relative L2 against the BF16-emulated oracle "
+          f"{worst:.4f}", flush=True)
