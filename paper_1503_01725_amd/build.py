@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsl.so")
-SOURCES = ["host_model.cpp", "physics.cpp", "k_sample.hip", "k_transport.hip", "runtime.hip",
+SOURCES = ["host_model.cpp", "physics.cpp", "schedule.cpp", "k_sample.hip", "k_transport.hip", "runtime.hip",
            "k_nnls.hip", "k_denoise.hip", "k_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -32,6 +32,8 @@ constexpr int kBlock = 256;
 // LDS uniform buffers per lane (ring slots) of the photon and electron kernels
 constexpr int kPhotonPool = 16;
 constexpr int kElectronPool = 8;
+// idle lanes of an electron-kernel wavefront that trigger a refill
+constexpr int kRefillLanes = 8;
 
 struct Stack {
     float *x, *y, *z, *u, *v, *w, *e;
@@ -441,24 +443,29 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             }
         }
         if (alive && phase == kKahn) {
-            // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a trial
+            // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a
+            // trial, at most two trials per iteration (a photon that needs
+            // more goes on in the next one, so that the wavefront does not
+            // loop for its few unlucky lanes).  Both proposals come from one
+            // reciprocal and the lane selects, so the two branches of the
+            // method do not diverge across the wavefront.
             const float k = e * (1.f / kMe);
             const float k2 = 2.f * k;
             const float ik = kMe * hw_rcp(e);
-            while (st.cnt >= 3u) {
+            const float p_a = (1.f + k2) * hw_rcp(9.f + k2);
+            const float i1k2 = hw_rcp(1.f + k2);
+            for (int tr = 0; tr < 2 && st.cnt >= 3u; ++tr) {
                 const float r1 = st.pop(), r2 = st.pop(), r3 = st.pop();
                 ++c_kahn;
                 ++trials;
-                bool acc;
-                if (r1 <= (1.f + k2) * hw_rcp(9.f + k2)) {
-                    kx = fmaf(k2, r2, 1.f);
-                    const float ix = hw_rcp(kx);
-                    acc = r3 <= 4.f * (ix - ix * ix);
-                } else {
-                    kx = (1.f + k2) * hw_rcp(fmaf(k2, r2, 1.f));
-                    const float c = 1.f - (kx - 1.f) * ik;
-                    acc = r3 <= 0.5f * (c * c + hw_rcp(kx));
-                }
+                const float xa = fmaf(k2, r2, 1.f);          // proposal of the first branch
+                const float ia = hw_rcp(xa);
+                const float xb = (1.f + k2) * ia;            // proposal of the second branch
+                const float cb = 1.f - (xb - 1.f) * ik;
+                const bool first = r1 <= p_a;
+                const bool acc = first ? r3 <= 4.f * (ia - ia * ia)
+                                       : r3 <= 0.5f * fmaf(cb, cb, xa * i1k2);
+                kx = first ? xa : xb;
                 if (acc || trials >= uint32_t(kMaxKahnTrials)) {
                     phase = kScatter;
                     break;
@@ -968,7 +975,13 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
         // refill idle lanes from the wave's chunk of the (band-ordered) stack;
         // tag and data loaded together as in k_photon
         {
-            const uint32_t q = take_work(!alive, wq, a.queue + 1, n);
+            // Idle lanes refill together, once at least kRefillLanes of them
+            // wait (or none is alive): a refill with only the few lanes whose
+            // electron ended this step would run the whole load sequence for
+            // them, almost every iteration.
+            const unsigned long long idle = __ballot(!alive);
+            const bool refill = __popcll(idle) >= kRefillLanes || idle == ~0ull;
+            const uint32_t q = refill ? take_work(!alive, wq, a.queue + 1, n) : kNone;
             const uint32_t i = q != kNone ? (a.perm ? a.perm[q] : q) : 0u;
             uint32_t tg = 1u << 24;
             float nx = 0.f, ny = 0.f, nz = 0.f, nu = 0.f, nv = 0.f, nw = 0.f, ne = 0.f;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "schedule.hpp"
 
 namespace psl {
 namespace {
@@ -185,33 +186,39 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
     const int np = n_pipes_of(o, plan);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, rep, rep0);
     const size_t nb = plan->batches.size();
-    // Batches to pipelines, largest first onto the least loaded one (cost ~
-    // histories), so that the pipelines finish a replica together; the two
-    // largest batches land on different pipelines, so none is left empty.
-    std::vector<int> pipe_of(nb, 0);
-    if (np > 1) {
-        std::vector<size_t> order(nb);
-        for (size_t i = 0; i < nb; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-            return plan->batches[x].n > plan->batches[y].n;
-        });
-        std::array<uint64_t, kMaxPipes> load{};
-        for (size_t i : order) {
-            int best = 0;
-            for (int p = 1; p < np; ++p)
-                if (load[p] < load[best]) best = p;
-            pipe_of[i] = best;
-            load[best] += plan->batches[i].n;
-        }
-    }
-    for (uint32_t r = 0; r < n_rep; ++r) {
-        if (np > 1) {
+    // The schedule (pipelines of the batches, fork / join / fold order) is
+    // built and checked as host data first, then executed.  Batches go
+    // largest first onto the least loaded pipeline (cost ~ histories), so
+    // that the pipelines finish a replica together; n_pipes_of never gives a
+    // pipeline without a batch.
+    std::vector<uint32_t> sizes(nb);
+    for (size_t i = 0; i < nb; ++i) sizes[i] = plan->batches[i].n;
+    const std::vector<SchedOp> ops = build_schedule(sizes.data(), nb, np, n_rep);
+    const std::string bad = check_schedule(ops, nb, np, n_rep);
+    PSL_CHECK(bad.empty(), "launch schedule: %s", bad.c_str());
+    for (const SchedOp& op : ops) {
+        if (op.kind == SchedOp::kFork) {
             PSL_HIP(hipEventRecord(R.fork, s));
             for (int p = 0; p < np; ++p) PSL_HIP(hipStreamWaitEvent(R.pipes[p].st, R.fork, 0));
-        }
-        for (size_t i = 0; i < nb; ++i) {
+        } else if (op.kind == SchedOp::kJoin) {
+            for (int p = 0; p < np; ++p) {
+                PSL_HIP(hipEventRecord(R.pipes[p].join, R.pipes[p].st));
+                PSL_HIP(hipStreamWaitEvent(s, R.pipes[p].join, 0));
+            }
+        } else if (op.kind == SchedOp::kFold) {
+            int tf = -1;
+            if (o.timing) {
+                tf = R.timed_pair(kFold);
+                PSL_HIP(hipEventRecord(R.pool[R.timed[tf][1]], s));
+            }
+            launch_fold(tally, s);
+            if (o.timing) PSL_HIP(hipEventRecord(R.pool[R.timed[tf][2]], s));
+        } else if (op.kind == SchedOp::kNextRep) {
+            hipLaunchKernelGGL(k_inc_u32, dim3(1), dim3(64), 0, s, rep);
+        } else {
+            const size_t i = size_t(op.batch);
             const psl_batch& b = plan->batches[i];
-            Pipe& P = R.pipes[pipe_of[i]];
+            Pipe& P = R.pipes[size_t(op.pipe)];
             hipStream_t q = np > 1 ? P.st : s;
             P.phs.ptype = b.stype == 2 ? 1 : 0;
             int ts = -1;
@@ -241,20 +248,6 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
                              o.sort_electrons != 0, o.lane_load > 0 ? o.lane_load : 4,
                              o.timing ? &ev : nullptr);
         }
-        if (np > 1) {
-            for (int p = 0; p < np; ++p) {
-                PSL_HIP(hipEventRecord(R.pipes[p].join, R.pipes[p].st));
-                PSL_HIP(hipStreamWaitEvent(s, R.pipes[p].join, 0));
-            }
-        }
-        int tf = -1;
-        if (o.timing) {
-            tf = R.timed_pair(kFold);
-            PSL_HIP(hipEventRecord(R.pool[R.timed[tf][1]], s));
-        }
-        launch_fold(tally, s);
-        if (o.timing) PSL_HIP(hipEventRecord(R.pool[R.timed[tf][2]], s));
-        hipLaunchKernelGGL(k_inc_u32, dim3(1), dim3(64), 0, s, rep);
     }
     PSL_HIP(hipGetLastError());
 }
