@@ -364,11 +364,23 @@ __device__ __forceinline__ void tile_pos(int w, int i, int row, int& z, int& y, 
     x = row & 7;
 }
 
-template <int MODE, int NT>
+// CC = 32: input channels in chunks of 32, two K steps of 16 per tap.
+// CC = 8 (the network's 8-channel input): all channels in one chunk, one K
+// step per two taps (lanes 0-31 tap 2s, lanes 32-63 tap 2s + 1), the
+// operands of taps past the 27th zero.  blockIdx.z splits the input channels
+// (CC = 32) over workgroups when the brick grid alone is too small for the
+// chip: each split writes its FP32 partial sums and k_conv_split_reduce adds
+// them in split order and applies the epilogue.
+template <int MODE, int NT, int CC>
 __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
     static_assert(NT == 32 || NT == 64, "32 or 64 output channels per workgroup");
+    static_assert(CC == 32 || CC == 8, "32 or 8 channels per staged chunk");
     constexpr int NJ = NT / 32;
-    __shared__ uint16_t halo[kFHalo * kFPitch];
+    constexpr int kPitch = CC == 32 ? kFPitch : 8;
+    // the output tile [512 positions][NT + 8] reuses the halo's LDS
+    constexpr int kTP = NT + 8;
+    constexpr int kLds = kFHalo * kPitch > 512 * kTP ? kFHalo * kPitch : 512 * kTP;
+    __shared__ uint16_t halo[kLds];
     const View& v = g.a;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int bx_n = v.W / kFB, by_n = v.H / kFB;
@@ -376,6 +388,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
     const int bx = b % bx_n, by = (b / bx_n) % by_n, bz = b / (bx_n * by_n);
     const int n0 = blockIdx.y * NT;
     const int C = v.C;
+    const int c_per = C / int(gridDim.z);
+    const int c_lo = int(blockIdx.z) * c_per, c_hi = c_lo + c_per;
     // independent accumulation chains: a 32x32x16 MFMA's result is not
     // ready for a dependent MFMA until several others have issued, so with
     // one column tile the even and odd K steps accumulate separately (eight
@@ -388,7 +402,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         for (int j = 0; j < NJ * KS; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-    const int r = lane & 31, kc = (lane >> 5) << 3;
+    const int r = lane & 31, kc = CC == 32 ? (lane >> 5) << 3 : 0;
     int qrow[4];   // halo position of this lane's row of tile i, centre tap
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -400,7 +414,7 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) wrow[j] = g.wt + size_t(n0 + 32 * j + r) * g.K + kc;
 
-    for (int c0 = 0; c0 < C; c0 += kCC) {
+    for (int c0 = c_lo; c0 < c_hi; c0 += CC) {
         // stage the halo brick of channels [c0, c0 + 32): item = (position, 8
         // channels), 8 consecutive positions per channel group.  A batch of
         // loads is issued before its first LDS write (addresses clamped into
@@ -409,8 +423,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         // batch instead of one per item.  The empty asm keeps the compiler
         // from holding every item's address across the chunk loop (registers
         // the accumulators need).
-        constexpr int kItems = kFHalo * (kCC / 8), kPer = (kItems + 255) / 256;
-        constexpr int kBatch = kPer / 4;
+        constexpr int kItems = kFHalo * (CC / 8), kPer = (kItems + 255) / 256;
+        constexpr int kBatch = CC == 32 ? kPer / 4 : kPer;
 #pragma unroll
         for (int k0 = 0; k0 < kPer; k0 += kBatch) {
             uint4 stg[kBatch];
@@ -419,7 +433,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
             for (int k = 0; k < kBatch; ++k) {
                 int it = min(t + 256 * (k0 + k), kItems - 1);
                 asm volatile("" : "+v"(it));
-                const int q = ((it >> 5) << 3) + (it & 7), cg = ((it >> 3) & 3) << 3;
+                const int q = CC == 32 ? ((it >> 5) << 3) + (it & 7) : it;
+                const int cg = CC == 32 ? ((it >> 3) & 3) << 3 : 0;
                 const int hz = q / (kFH * kFH), hy = (q / kFH) % kFH, hx = q % kFH;
                 const int z = bz * kFB - 1 + hz, y = by * kFB - 1 + hy, x = bx * kFB - 1 + hx;
                 const int zc = min(max(z, 0), v.D - 1), yc = min(max(y, 0), v.H - 1),
@@ -430,9 +445,10 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
 #pragma unroll
             for (int k = 0; k < kBatch; ++k) {
                 const int it = t + 256 * (k0 + k);
-                const int q = ((it >> 5) << 3) + (it & 7), cg = ((it >> 3) & 3) << 3;
+                const int q = CC == 32 ? ((it >> 5) << 3) + (it & 7) : it;
+                const int cg = CC == 32 ? ((it >> 3) & 3) << 3 : 0;
                 const uint4 val = (outside >> k) & 1u ? uint4{0u, 0u, 0u, 0u} : stg[k];
-                if (it < kItems) *reinterpret_cast<uint4*>(&halo[q * kFPitch + cg]) = val;
+                if (it < kItems) *reinterpret_cast<uint4*>(&halo[q * kPitch + cg]) = val;
             }
         }
         __syncthreads();
@@ -443,30 +459,44 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         // are loaded three steps ahead into a ring.  Past the last step the
         // addresses are clamped to it (loaded, never used), so that no
         // branch breaks the pipeline.
+        // tap of step st for this lane, and the channel offset within it
+        auto tap_of = [&](int st) {
+            return CC == 32 ? st >> 1 : min(2 * st + (lane >> 5), 26);
+        };
         auto a_ptr = [&](int st, int i) {
-            const int tap = st >> 1;
+            const int tap = tap_of(st);
             const int dq = ((tap / 9 - 1) * kFH + (tap / 3) % 3 - 1) * kFH + tap % 3 - 1;
-            return reinterpret_cast<const uint4*>(&halo[(qrow[i] + dq) * kFPitch + 16 * (st & 1) + kc]);
+            const int co = CC == 32 ? 16 * (st & 1) + kc : 0;
+            return reinterpret_cast<const uint4*>(&halo[(qrow[i] + dq) * kPitch + co]);
         };
         auto w_ptr = [&](int st, int j) {
-            return reinterpret_cast<const uint4*>(wrow[j] + (st >> 1) * C + c0 + 16 * (st & 1));
+            const int co = CC == 32 ? c0 + 16 * (st & 1) : 0;
+            return reinterpret_cast<const uint4*>(wrow[j] + tap_of(st) * C + co);
         };
-        constexpr int kSteps = 54;
+        // the A operand of a step, zero for taps past the 27th (CC = 8)
+        auto a_load = [&](int st, int i) {
+            uint4 a = *a_ptr(st, i);
+            if (CC == 8 && 2 * st + (lane >> 5) > 26) a = uint4{0u, 0u, 0u, 0u};
+            return a;
+        };
+        // CC = 8: 14 steps padded to 15 (taps 27-29 zero) for an unroll of 3
+        constexpr int kSteps = CC == 32 ? 54 : 15;
+        constexpr int kUnroll = CC == 32 ? 6 : 3;
         uint4 ring[3][NJ], acur[4];
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) ring[p][j] = *w_ptr(p, j);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acur[i] = *a_ptr(0, i);
+        for (int i = 0; i < 4; ++i) acur[i] = a_load(0, i);
 #pragma unroll 1
-        for (int s0 = 0; s0 < kSteps; s0 += 6) {
+        for (int s0 = 0; s0 < kSteps; s0 += kUnroll) {
 #pragma unroll
-            for (int u = 0; u < 6; ++u) {
+            for (int u = 0; u < kUnroll; ++u) {
                 const int st = s0 + u;
                 uint4 anext[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) anext[i] = *a_ptr(min(st + 1, kSteps - 1), i);
+                for (int i = 0; i < 4; ++i) anext[i] = a_load(min(st + 1, kSteps - 1), i);
                 // keep the scheduler from sinking these reads to their use
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -487,28 +517,110 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         __syncthreads();
     }
     // epilogue: lane holds column lane % 32 and rows 8 (e / 4) + 4 (lane / 32) + e % 4
+    if (gridDim.z > 1) {
+        // a channel split: its FP32 partial sums
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            int z, y, x;
-            tile_pos(w, i, 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), z, y, x);
-            const int m = ((bz * kFB + z) * v.H + by * kFB + y) * v.W + bx * kFB + x;
+            for (int e = 0; e < 16; ++e) {
+                int z, y, x;
+                tile_pos(w, i, 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), z, y, x);
+                const int m = ((bz * kFB + z) * v.H + by * kFB + y) * v.W + bx * kFB + x;
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int n = n0 + 32 * j + (lane & 31);
+                for (int j = 0; j < NJ; ++j) {
+                    float val = acc[i][j * KS][e];
+                    if (KS == 2) val += acc[i][j * KS + 1][e];
+                    g.partial[(size_t(blockIdx.z) * g.M + m) * g.N + n0 + 32 * j + (lane & 31)] = val;
+                }
+            }
+        return;
+    }
+    // The output tile goes through LDS, so that each lane stores 16 bytes of
+    // consecutive channels of one position (channels-last) instead of one
+    // 2-byte channel: bias and ReLU (forward) before the BF16 rounding, as
+    // in a direct store; the input gradient's mask (0 or 1) after it.  The
+    // loop over chunks ended with a barrier, so the halo is free.
+    uint16_t* tile = halo;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int nl = 32 * j + (lane & 31);
+        const float bias = MODE == kConvFwd ? g.bias[n0 + nl] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                int z, y, x;
+                tile_pos(w, i, 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3), z, y, x);
                 float val = acc[i][j * KS][e];
                 if (KS == 2) val += acc[i][j * KS + 1][e];
                 if (MODE == kConvFwd) {
-                    val += g.bias[n];
+                    val += bias;
                     if (g.relu) val = fmaxf(val, 0.f);
-                } else if (g.mask.p &&
-                           !(bf2f(g.mask.p[size_t(m) * g.mask.stride + g.mask.off + n]) > 0.f)) {
-                    val = 0.f;
                 }
-                g.b.p[size_t(m) * g.b.stride + g.b.off + n] = f2bf(val);
+                tile[((z * kFB + y) * kFB + x) * kTP + nl] = f2bf(val);
             }
+    }
+    __syncthreads();
+    constexpr int kChunks = NT / 8;                 // 16-byte chunks per position
+    constexpr int kOut = 512 * kChunks / 256;       // per thread
+    const int ch = (t % kChunks) * 8;
+#pragma unroll 4
+    for (int k = 0; k < kOut; ++k) {
+        const int p = (t + 256 * k) / kChunks;
+        const int z = p >> 6, y = (p >> 3) & 7, x = p & 7;
+        const int m = ((bz * kFB + z) * v.H + by * kFB + y) * v.W + bx * kFB + x;
+        uint4 o = *reinterpret_cast<const uint4*>(&tile[p * kTP + ch]);
+        if (MODE != kConvFwd && g.mask.p) {
+            const uint4 mk = load8(g.mask, m, n0 + ch);
+            const uint16_t* me = reinterpret_cast<const uint16_t*>(&mk);
+            uint16_t* oe = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (!(bf2f(me[q]) > 0.f)) oe[q] = 0;
         }
+        *reinterpret_cast<uint4*>(g.b.p + size_t(m) * g.b.stride + g.b.off + n0 + ch) = o;
+    }
+}
+
+// Sum of the channel splits of k_conv_direct (in split order) and its
+// epilogue: bias and ReLU (forward) or the ReLU mask (input gradient), BF16
+// out.  8 output channels per thread: 16-byte stores.
+template <int MODE>
+__global__ void k_conv_split_reduce(GemmArgs g, int splits) {
+    const int n8 = g.N >> 3;
+    const int64_t total = int64_t(g.M) * n8;
+    const size_t plane = size_t(g.M) * g.N;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int m = int(i / n8), n = int(i - int64_t(m) * n8) << 3;
+        const float* src = g.partial + size_t(m) * g.N + n;
+        float4 a = *reinterpret_cast<const float4*>(src);
+        float4 b = *reinterpret_cast<const float4*>(src + 4);
+        for (int z = 1; z < splits; ++z) {
+            const float4 pa = *reinterpret_cast<const float4*>(src + z * plane);
+            const float4 pb = *reinterpret_cast<const float4*>(src + z * plane + 4);
+            a.x += pa.x; a.y += pa.y; a.z += pa.z; a.w += pa.w;
+            b.x += pb.x; b.y += pb.y; b.z += pb.z; b.w += pb.w;
+        }
+        float val[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint4 mk{0u, 0u, 0u, 0u};
+        if (MODE != kConvFwd && g.mask.p) mk = load8(g.mask, m, n);
+        const uint16_t* me = reinterpret_cast<const uint16_t*>(&mk);
+        uint4 o;
+        uint16_t* oe = reinterpret_cast<uint16_t*>(&o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float x = val[k];
+            if (MODE == kConvFwd) {
+                x += g.bias[n + k];
+                if (g.relu) x = fmaxf(x, 0.f);
+            } else if (g.mask.p && !(bf2f(me[k]) > 0.f)) {
+                x = 0.f;
+            }
+            oe[k] = f2bf(x);
+        }
+        *reinterpret_cast<uint4*>(g.b.p + size_t(m) * g.b.stride + g.b.off + n) = o;
+    }
 }
 
 // Weight gradient of a 3x3x3 convolution by the same bricks:
@@ -1035,26 +1147,66 @@ void gemm_launch(int mode, const GemmArgs& g0, hipStream_t s, int splits = 1) {
     PSL_HIP(hipGetLastError());
 }
 
+// Launch shape of the direct brick convolution of an input of C channels on
+// a D x H x W grid into N output channels: output channels per workgroup
+// (nt) and channel splits, so that the grid has about 512 workgroups (two
+// per CU) where the bricks alone give fewer.  splits = 0: not direct.
+struct ConvShape { int nt, splits; };
+ConvShape conv_shape(int D, int H, int W, int C, int N) {
+    if (D % kFB || H % kFB || W % kFB || N % 32 || !(C % kCC == 0 || C == 8)) return {0, 0};
+    const int64_t bricks = int64_t(D / kFB) * (H / kFB) * (W / kFB);
+    int nt = N % 64 == 0 ? 64 : 32;
+    int splits = 1;
+    if (C % kCC == 0) {
+        const int chunks = C / kCC;
+        if (nt == 64 && bricks * (N / 64) * chunks < 512) nt = 32;
+        while (bricks * (N / nt) * splits < 512 && chunks % (2 * splits) == 0) splits *= 2;
+    }
+    return {nt, splits};
+}
+
+template <int MODE, int CC>
+void launch_direct(dim3 grid, int nt, const GemmArgs& g, hipStream_t s) {
+    if (nt == 64) hipLaunchKernelGGL((k_conv_direct<MODE, 64, CC>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((k_conv_direct<MODE, 32, CC>), grid, dim3(256), 0, s, g);
+}
+
 // Convolution GEMM (forward or input gradient): the direct brick kernel
-// where the grid and the channels fit its tiles, else the implicit GEMM.
-void conv_launch(int mode, const GemmArgs& g, hipStream_t s) {
+// where the grid and the channels fit its bricks, else the implicit GEMM.
+// Channel splits use `scratch` (floats) for their partial sums.
+void conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scratch_floats) {
     const View& v = g.a;
-    const bool direct = v.D % kFB == 0 && v.H % kFB == 0 && v.W % kFB == 0 && v.C % kCC == 0 &&
-                        g.K == 27 * v.C && g.N % 32 == 0 && int64_t(v.D) * v.H * v.W == g.M;
-    if (!direct) {
+    const ConvShape sh = conv_shape(v.D, v.H, v.W, v.C, g.N);
+    if (sh.splits == 0 || g.K != 27 * v.C || int64_t(v.D) * v.H * v.W != g.M) {
         gemm_launch(mode, g, s);
         return;
     }
-    const int nt = g.N % 64 == 0 ? 64 : 32;
-    dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / nt);
+    dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / sh.nt, sh.splits);
+    if (sh.splits > 1) {
+        PSL_CHECK(scratch && scratch_floats >= size_t(sh.splits) * g.M * g.N,
+                  "convolution split scratch too small");
+        g.partial = scratch;
+    }
+    const bool c8 = v.C == 8;
     if (mode == kConvFwd) {
-        if (nt == 64) hipLaunchKernelGGL((k_conv_direct<kConvFwd, 64>), grid, dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((k_conv_direct<kConvFwd, 32>), grid, dim3(256), 0, s, g);
+        if (c8) launch_direct<kConvFwd, 8>(grid, sh.nt, g, s);
+        else launch_direct<kConvFwd, 32>(grid, sh.nt, g, s);
     } else {
-        if (nt == 64) hipLaunchKernelGGL((k_conv_direct<kConvBwdData, 64>), grid, dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((k_conv_direct<kConvBwdData, 32>), grid, dim3(256), 0, s, g);
+        if (c8) launch_direct<kConvBwdData, 8>(grid, sh.nt, g, s);
+        else launch_direct<kConvBwdData, 32>(grid, sh.nt, g, s);
     }
     PSL_HIP(hipGetLastError());
+    if (sh.splits > 1) {
+        const int64_t items = int64_t(g.M) * (g.N / 8);
+        const int blocks = int(std::min<int64_t>((items + 255) / 256, 4096));
+        if (mode == kConvFwd)
+            hipLaunchKernelGGL(k_conv_split_reduce<kConvFwd>, dim3(blocks), dim3(256), 0, s, g,
+                               sh.splits);
+        else
+            hipLaunchKernelGGL(k_conv_split_reduce<kConvBwdData>, dim3(blocks), dim3(256), 0, s, g,
+                               sh.splits);
+        PSL_HIP(hipGetLastError());
+    }
 }
 
 // forward conv: in (cin_pad channels view) -> out view, bias, ReLU
@@ -1070,7 +1222,7 @@ void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     g.cin = L.cin;
     g.cout = L.cout;
     g.relu = 1;
-    conv_launch(kConvFwd, g, s);
+    conv_launch(kConvFwd, g, s, u.wpart.as<float>(), u.wpart.bytes / 4);
 }
 
 // bias gradient over P positions: enough blocks that every thread sums a
@@ -1151,8 +1303,18 @@ size_t wpart_floats(const UNet& u) {
     auto need = [&](int64_t positions, int M, int N) {
         most = std::max(most, size_t(wgrad_splits(positions, M, N)) * M * N);
     };
+    // channel splits of the direct convolution: forward (cin_pad -> cout),
+    // input gradient (cout -> cin) and the decoder's unmasked half (C -> C)
+    auto split = [&](int k, int C, int N) {
+        const int* d = u.dims[k];
+        const ConvShape sh = conv_shape(d[0], d[1], d[2], C, N);
+        if (sh.splits > 1) most = std::max(most, size_t(sh.splits) * size_t(u.P(k)) * N);
+    };
     auto conv = [&](int k, const UNet::Conv& L) {
         const int* d = u.dims[k];
+        split(k, L.cin_pad, L.cout);
+        split(k, L.cout, L.cin);
+        split(k, L.cout, L.cout);
         need(u.P(k), L.cout, 27 * L.cin_pad);
         if (wgrad_direct(d[0], d[1], d[2], L.cin_pad, L.cout))
             most = std::max(most, size_t(direct_splits(d[0], d[1], d[2], L.cin_pad, L.cout)) *
@@ -1198,7 +1360,7 @@ void conv_bwd(const UNet& u, const UNet::Conv& L, View in, View gz, View* gin, h
         d.K = 27 * L.cout;
         d.cin = L.cin;
         d.cout = L.cout;
-        conv_launch(kConvBwdData, d, s);
+        conv_launch(kConvBwdData, d, s, u.wpart.as<float>(), u.wpart.bytes / 4);
     }
 }
 
@@ -1347,7 +1509,7 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
             d.K = 27 * C;
             d.cin = 2 * C;
             d.cout = C;
-            conv_launch(kConvBwdData, d, s);
+            conv_launch(kConvBwdData, d, s, u.wpart.as<float>(), u.wpart.bytes / 4);
         }
         // tconv backward: weights, bias, gradient at its input (masked by the
         // lower level's ReLU output)
