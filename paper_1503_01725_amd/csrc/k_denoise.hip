@@ -61,6 +61,8 @@ struct GemmArgs {
     int cout_sh;         // log2(cout) (cout is a power of two)
     int relu;
     int k_per_split;     // wgrad: positions per blockIdx.z
+    View pool;           // direct conv fwd: 2x2x2 max-pooled output if pool.p
+    uint8_t* arg;        //   and the index (0-7) of each maximum, [P/8][C]
 };
 
 __device__ __forceinline__ void pos3(int m, int D, int H, int W, int& z, int& y, int& x) {
@@ -295,6 +297,41 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
 
     // epilogue: lane holds rows 4*(lane/16)+e, column lane%16 of each 16x16 tile
+    if constexpr (MODE == kTconvFwd && BM == 64 && BN == 64) {
+        // Transposed convolution: the 64 x 64 tile (bias added, BF16) goes
+        // through LDS (the A operand's buffer, free after the last barrier),
+        // then each lane stores 8 consecutive channels of one child position
+        // (16 bytes) instead of one 2-byte channel.  A tile's 64 columns are
+        // whole 8-channel runs of one child (cout is a multiple of 8).
+        uint16_t (*tile)[kKT + kLdsPad] = As;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ml = wr + 16 * i + 4 * (lane >> 4) + e;
+                    const int nl = wc + 16 * j + (lane & 15);
+                    const int o = (n0 + nl) & (g.cout - 1);
+                    tile[ml][nl] = f2bf(acc[i][j][e] + g.bias[o]);
+                }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int it = t + 256 * k;
+            const int ml = it >> 3, nl = (it & 7) << 3;
+            const int m = m0 + ml, n = n0 + nl;
+            if (m >= g.M || n >= g.N) continue;
+            const int abc = n >> g.cout_sh, o = n & (g.cout - 1);
+            int z, y, x;
+            pos3v(g.a, m, z, y, x);
+            const int cz = 2 * z + (abc >> 2), cy = 2 * y + ((abc >> 1) & 1), cx = 2 * x + (abc & 1);
+            const size_t child = (size_t(cz) * (2 * g.a.H) + cy) * (2 * g.a.W) + cx;
+            *reinterpret_cast<uint4*>(g.b.p + child * g.b.stride + g.b.off + o) =
+                *reinterpret_cast<const uint4*>(&tile[ml][nl]);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -579,6 +616,48 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
                 if (!(bf2f(me[q]) > 0.f)) oe[q] = 0;
         }
         *reinterpret_cast<uint4*>(g.b.p + size_t(m) * g.b.stride + g.b.off + n0 + ch) = o;
+    }
+    if (MODE == kConvFwd && g.pool.p) {
+        // 2x2x2 max pooling of the brick (4^3 coarse positions) from the same
+        // tile: the first maximum in child order (z, y, x bits) wins, as in
+        // k_pool_fwd
+        for (int it = t; it < 64 * kChunks; it += 256) {
+            const int cp = it / kChunks, c8 = (it % kChunks) * 8;
+            const int cz = cp >> 4, cy = (cp >> 2) & 3, cx = cp & 3;
+            float best[8];
+            uint8_t bi[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                best[k] = -INFINITY;
+                bi[k] = 0;
+            }
+#pragma unroll
+            for (int a = 0; a < 8; ++a) {
+                const int fz = 2 * cz + (a >> 2), fy = 2 * cy + ((a >> 1) & 1), fx = 2 * cx + (a & 1);
+                const uint4 fv = *reinterpret_cast<const uint4*>(&tile[((fz * kFB + fy) * kFB + fx) * kTP + c8]);
+                const uint16_t* fe = reinterpret_cast<const uint16_t*>(&fv);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float f = bf2f(fe[k]);
+                    if (f > best[k]) {
+                        best[k] = f;
+                        bi[k] = uint8_t(a);
+                    }
+                }
+            }
+            uint4 po;
+            uint2 ab;
+            uint16_t* pe = reinterpret_cast<uint16_t*>(&po);
+            uint8_t* ae = reinterpret_cast<uint8_t*>(&ab);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                pe[k] = f2bf(best[k]);
+                ae[k] = bi[k];
+            }
+            const int q = ((bz * 4 + cz) * (v.H >> 1) + by * 4 + cy) * (v.W >> 1) + bx * 4 + cx;
+            *reinterpret_cast<uint4*>(g.pool.p + size_t(q) * g.pool.stride + g.pool.off + n0 + c8) = po;
+            *reinterpret_cast<uint2*>(g.arg + size_t(q) * g.b.C + n0 + c8) = ab;
+        }
     }
 }
 
@@ -1174,13 +1253,18 @@ void launch_direct(dim3 grid, int nt, const GemmArgs& g, hipStream_t s) {
 // Convolution GEMM (forward or input gradient): the direct brick kernel
 // where the grid and the channels fit its bricks, else the implicit GEMM.
 // Channel splits use `scratch` (floats) for their partial sums.
-void conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scratch_floats) {
+// With g.pool.p set (forward only), the brick kernel also writes the 2x2x2
+// max pooling of its output when it runs unsplit; the return value says
+// whether it did (else the caller pools).
+bool conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scratch_floats) {
     const View& v = g.a;
     const ConvShape sh = conv_shape(v.D, v.H, v.W, v.C, g.N);
     if (sh.splits == 0 || g.K != 27 * v.C || int64_t(v.D) * v.H * v.W != g.M) {
         gemm_launch(mode, g, s);
-        return;
+        return false;
     }
+    const bool pooled = mode == kConvFwd && g.pool.p && sh.splits == 1;
+    if (!pooled) g.pool.p = nullptr;
     dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / sh.nt, sh.splits);
     if (sh.splits > 1) {
         PSL_CHECK(scratch && scratch_floats >= size_t(sh.splits) * g.M * g.N,
@@ -1207,10 +1291,14 @@ void conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scr
                                sh.splits);
         PSL_HIP(hipGetLastError());
     }
+    return pooled;
 }
 
-// forward conv: in (cin_pad channels view) -> out view, bias, ReLU
-void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t s) {
+// forward conv: in (cin_pad channels view) -> out view, bias, ReLU; with
+// `pool`, also its 2x2x2 max pooling where the kernel can fuse it (returns
+// whether it did)
+bool conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t s,
+              const View* pool = nullptr, uint8_t* arg = nullptr) {
     GemmArgs g{};
     g.a = in;
     g.b = out;
@@ -1222,7 +1310,11 @@ void conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     g.cin = L.cin;
     g.cout = L.cout;
     g.relu = 1;
-    conv_launch(kConvFwd, g, s, u.wpart.as<float>(), u.wpart.bytes / 4);
+    if (pool) {
+        g.pool = *pool;
+        g.arg = arg;
+    }
+    return conv_launch(kConvFwd, g, s, u.wpart.as<float>(), u.wpart.bytes / 4);
 }
 
 // bias gradient over P positions: enough blocks that every thread sums a
@@ -1427,21 +1519,30 @@ void forward(UNet& u, const float* input, hipStream_t s) {
     hipLaunchKernelGGL(k_pack_input, dim3(grid1(P0)), dim3(256), 0, s, input, int(P0),
                        u.x0.as<uint16_t>());
     View h = view(u.x0, u, 0, 8, 8, 0);
+    bool pooled_here = false;   // the previous level's conv wrote this level's pooling
     for (int k = 0; k < kLevels; ++k) {
         const int C = u.ch(k);
         if (k > 0) {
             View pooled = view(u.pooled[k], u, k, u.ch(k - 1), u.ch(k - 1), 0);
-            hipLaunchKernelGGL(k_pool_fwd, dim3(grid1(u.P(k) * u.ch(k - 1) / 8)), dim3(256), 0, s, h,
-                               pooled, u.arg[k].as<uint8_t>());
+            if (!pooled_here)
+                hipLaunchKernelGGL(k_pool_fwd, dim3(grid1(u.P(k) * u.ch(k - 1) / 8)), dim3(256), 0, s,
+                                   h, pooled, u.arg[k].as<uint8_t>());
             h = pooled;
         }
         View a = view(u.enc_a_out[k], u, k, C, C, 0);
         conv_fwd(u, u.enc_a[k], h, a, s);
         // encoder output of levels < 3 goes straight into the first half of the
-        // decoder's concatenation buffer
-        View b = k < kLevels - 1 ? view(u.cat[k], u, k, C, 2 * C, 0) : view(u.bottom_b, u, k, C, C, 0);
-        conv_fwd(u, u.enc_b[k], a, b, s);
-        h = b;
+        // decoder's concatenation buffer (and is pooled for the next level)
+        if (k < kLevels - 1) {
+            View b = view(u.cat[k], u, k, C, 2 * C, 0);
+            View pooled = view(u.pooled[k + 1], u, k + 1, C, C, 0);
+            pooled_here = conv_fwd(u, u.enc_b[k], a, b, s, &pooled, u.arg[k + 1].as<uint8_t>());
+            h = b;
+        } else {
+            View b = view(u.bottom_b, u, k, C, C, 0);
+            conv_fwd(u, u.enc_b[k], a, b, s);
+            h = b;
+        }
     }
     for (int k = kLevels - 2; k >= 0; --k) {
         const int C = u.ch(k);
