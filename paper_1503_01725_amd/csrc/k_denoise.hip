@@ -461,7 +461,9 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         // from holding every item's address across the chunk loop (registers
         // the accumulators need).
         constexpr int kItems = kFHalo * (CC / 8), kPer = (kItems + 255) / 256;
-        constexpr int kBatch = CC == 32 ? kPer / 4 : kPer;
+        // two batches where the registers allow (32 output channels), four
+        // with 64 (its accumulators take the rest)
+        constexpr int kBatch = CC == 32 ? (NT == 32 ? kPer / 2 : kPer / 4) : kPer;
 #pragma unroll
         for (int k0 = 0; k0 < kPer; k0 += kBatch) {
             uint4 stg[kBatch];
@@ -1970,7 +1972,6 @@ extern "C" int psl_dose_gate(const float* cand, const double* plain, const doubl
         PSL_CHECK(block >= 1 && block <= 64, "block edge must lie in [1, 64]");
         PSL_CHECK(cutoff >= 0.0 && cutoff < 1.0, "cutoff must lie in [0, 1)");
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const int64_t n = int64_t(nx) * ny * nz;
         DevBuf part;
         part.alloc(size_t(kGateBlocks) * (1 + kGateSums) * sizeof(double));
         double* pmax = part.as<double>();
