@@ -52,6 +52,7 @@ struct GemmArgs {
     View a;              // conv/tconv input (fwd, wgrad) or output gradient (bwd-data)
     View b;              // output (fwd, bwd-data) or output gradient (wgrad)
     const uint16_t* wt;  // packed weights B^T [N][K] (fwd / bwd-data)
+    const uint16_t* wfrag;   // the same in the brick kernel's operand order (frag_elems)
     const float* bias;   // fwd: [C_out]
     View mask;           // bwd-data: multiply by (mask > 0) if mask.p
     float* wgrad;        // wgrad: FP32 gradient in the reference layout
@@ -447,9 +448,13 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
         tile_pos(w, i, r, z, y, x);
         qrow[i] = ((z + 1) * kFH + y + 1) * kFH + x + 1;
     }
+    // weights in operand order (k_frag): one contiguous 1 KB per wave and K
+    // step, 512 values per step of a 32-row tile
+    const int steps_all = CC == 32 ? (C / 32) * 54 : 15;
     const uint16_t* wrow[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) wrow[j] = g.wt + size_t(n0 + 32 * j + r) * g.K + kc;
+    for (int j = 0; j < NJ; ++j)
+        wrow[j] = g.wfrag + (size_t(n0 / 32 + j) * steps_all) * 512 + lane * 8;
 
     for (int c0 = c_lo; c0 < c_hi; c0 += CC) {
         // stage the halo brick of channels [c0, c0 + 32): item = (position, 8
@@ -509,8 +514,8 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
             return reinterpret_cast<const uint4*>(&halo[(qrow[i] + dq) * kPitch + co]);
         };
         auto w_ptr = [&](int st, int j) {
-            const int co = CC == 32 ? c0 + 16 * (st & 1) : 0;
-            return reinterpret_cast<const uint4*>(wrow[j] + tap_of(st) * C + co);
+            const int gs = CC == 32 ? (c0 / 32) * 54 + st : st;
+            return reinterpret_cast<const uint4*>(wrow[j] + size_t(gs) * 512);
         };
         // the A operand of a step, zero for taps past the 27th (CC = 8)
         auto a_load = [&](int st, int i) {
@@ -1128,6 +1133,42 @@ __global__ void k_pack_conv(const float* w, int cout, int cin, int cin_pad, uint
     }
 }
 
+// Elements of a [N][27 C] weight matrix in the brick kernel's operand order
+// (0 where that kernel does not take it).
+int64_t frag_elems(int N, int C) {
+    if (N % 32 != 0 || !(C == 8 || C % 32 == 0)) return 0;
+    const int64_t steps = C == 8 ? 15 : int64_t(C / 32) * 54;
+    return int64_t(N / 32) * steps * 512;
+}
+
+// [N][27 C] weights (tap-major K) in k_conv_direct's operand order: for each
+// 32-row tile and K step, the 64 lanes' 8 consecutive K values contiguous
+// (lane l: row l % 32, K half l / 32).  C = 32 c: step s of chunk q covers
+// tap s / 2, channels 32 q + 16 (s % 2) ..; C = 8: step s covers taps 2 s
+// (lanes 0-31) and 2 s + 1 (lanes 32-63), clamped to the 27th (its operand
+// is zeroed in the kernel).
+__global__ void k_frag(const uint16_t* src, int N, int C, uint16_t* dst) {
+    const int K = 27 * C;
+    const int steps = C == 8 ? 15 : (C / 32) * 54;
+    const int64_t total = int64_t(N / 32) * steps * 64;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int lane = int(i & 63);
+        const int64_t q = i >> 6;
+        const int st = int(q % steps), nt = int(q / steps);
+        const int n = nt * 32 + (lane & 31), h = lane >> 5;
+        int k;
+        if (C == 8) {
+            k = min(2 * st + h, 26) * 8;
+        } else {
+            const int chunk = st / 54, s = st % 54;
+            k = (s >> 1) * C + chunk * 32 + 16 * (s & 1) + 8 * h;
+        }
+        *reinterpret_cast<uint4*>(dst + i * 8) =
+            *reinterpret_cast<const uint4*>(src + size_t(n) * K + k);
+    }
+}
+
 // tconv weights [c][o][8] -> forward B^T [abc*cout + o][c], backward B^T [c][abc*cout + o]
 __global__ void k_pack_tconv(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb) {
     const int total = cin * cout * 8;
@@ -1152,7 +1193,13 @@ struct UNet {
     int c = 32, D = 0, H = 0, W = 0;
     int64_t n_params = 0;
     // parameter offsets in the flat FP32 arrays (reference order)
-    struct Conv { int64_t w, b; int cin, cout, cin_pad; uint16_t* wf; uint16_t* wb; };
+    // wf / wb: forward [cout][27 cin_pad] and input-gradient [cin][27 cout]
+    // packs; wff / wbf: the same in the brick kernel's operand order (or null)
+    struct Conv {
+        int64_t w, b;
+        int cin, cout, cin_pad;
+        uint16_t *wf, *wb, *wff, *wbf;
+    };
     struct Tconv { int64_t w, b; int cin, cout; uint16_t* wf; uint16_t* wb; };
     Conv enc_a[kLevels], enc_b[kLevels], dec_a[kLevels], dec_b[kLevels];
     Tconv up[kLevels];
@@ -1267,6 +1314,7 @@ bool conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scr
     }
     const bool pooled = mode == kConvFwd && g.pool.p && sh.splits == 1;
     if (!pooled) g.pool.p = nullptr;
+    PSL_CHECK(g.wfrag, "brick convolution without operand-ordered weights");
     dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / sh.nt, sh.splits);
     if (sh.splits > 1) {
         PSL_CHECK(scratch && scratch_floats >= size_t(sh.splits) * g.M * g.N,
@@ -1305,6 +1353,7 @@ bool conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     g.a = in;
     g.b = out;
     g.wt = L.wf;
+    g.wfrag = L.wff;
     g.bias = u.params.as<float>() + L.b;
     g.M = int(int64_t(in.D) * in.H * in.W);
     g.N = L.cout;
@@ -1448,6 +1497,7 @@ void conv_bwd(const UNet& u, const UNet::Conv& L, View in, View gz, View* gin, h
         d.a = gz;
         d.b = *gin;
         d.wt = L.wb;
+        d.wfrag = L.wbf;
         d.mask = in;
         d.M = int(P);
         d.N = L.cin;
@@ -1500,6 +1550,12 @@ void pack_all(UNet& u, hipStream_t s) {
     auto pc = [&](UNet::Conv& L) {
         hipLaunchKernelGGL(k_pack_conv, dim3(grid1(int64_t(L.cout) * L.cin_pad * 27)), dim3(256), 0,
                            s, p + L.w, L.cout, L.cin, L.cin_pad, L.wf, L.wb);
+        if (L.wff)
+            hipLaunchKernelGGL(k_frag, dim3(grid1(frag_elems(L.cout, L.cin_pad) / 8)), dim3(256), 0, s,
+                               L.wf, L.cout, L.cin_pad, L.wff);
+        if (L.wbf)
+            hipLaunchKernelGGL(k_frag, dim3(grid1(frag_elems(L.cin, L.cout) / 8)), dim3(256), 0, s,
+                               L.wb, L.cin, L.cout, L.wbf);
     };
     for (int k = 0; k < kLevels; ++k) {
         pc(u.enc_a[k]);
@@ -1607,6 +1663,8 @@ void backward(UNet& u, const float* input, const float* target, hipStream_t s) {
             d.a = ga;
             d.b = gup;
             d.wt = u.dec_a[k].wb + size_t(C) * 27 * C;   // rows C..2C-1 of the backward pack
+            d.wfrag = u.dec_a[k].wbf ? u.dec_a[k].wbf + size_t(C / 32) * ((C / 32) * 54) * 512
+                                     : nullptr;          // the same rows (32-row tiles C / 32 ..)
             d.M = int(u.P(k));
             d.N = C;
             d.K = 27 * C;
@@ -1823,7 +1881,10 @@ extern "C" int psl_unet_create(int32_t base_width, int32_t d, int32_t h, int32_t
         u->adam_v.alloc(np * 4);
         // packed BF16 weights: forward + backward layouts of every layer
         size_t pk = 0;
-        auto cnt_conv = [&](UNet::Conv& L) { pk += size_t(L.cout) * L.cin_pad * 27 + size_t(L.cin) * 27 * L.cout; };
+        auto cnt_conv = [&](UNet::Conv& L) {
+            pk += size_t(L.cout) * L.cin_pad * 27 + size_t(L.cin) * 27 * L.cout;
+            pk += size_t(frag_elems(L.cout, L.cin_pad)) + size_t(frag_elems(L.cin, L.cout)) + 16;
+        };
         for (int k = 0; k < kLevels; ++k) {
             cnt_conv(u->enc_a[k]);
             cnt_conv(u->enc_b[k]);
@@ -1839,6 +1900,9 @@ extern "C" int psl_unet_create(int32_t base_width, int32_t d, int32_t h, int32_t
         auto place_conv = [&](UNet::Conv& L) {
             L.wf = take(size_t(L.cout) * L.cin_pad * 27);
             L.wb = take(size_t(L.cin) * 27 * L.cout);
+            const int64_t ff = frag_elems(L.cout, L.cin_pad), bf = frag_elems(L.cin, L.cout);
+            L.wff = ff ? take(size_t(ff)) : nullptr;
+            L.wbf = bf ? take(size_t(bf)) : nullptr;
         };
         for (int k = 0; k < kLevels; ++k) {
             place_conv(u->enc_a[k]);
