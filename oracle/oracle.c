@@ -55,8 +55,8 @@ enum { OR_SUB_PRIMARY = 0, OR_SUB_SCATTER = 1, OR_SUB_ELECTRON = 2 };
 enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, L_N };
 /* counters[] slots */
 enum { C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS,
-       C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD,
-       C_PHOTO = 14, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_N = 20 };
+       C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW,
+       C_FOLDS, C_PHOTO = 14, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_MOLLER, C_BREM, C_N = 20 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
@@ -783,7 +783,8 @@ static void gl_init(void)
  * (Slater's rules: 8 - 0.30 and 8 - 2 x 0.85 - 5 x 0.35). */
 #define OR_Z_O_1S 7.70
 #define OR_Z_O_2 4.55
-enum { OR_PHYS_PHOTO = 1, OR_PHYS_RAYLEIGH = 2, OR_PHYS_PAIR = 4 };
+enum { OR_PHYS_PHOTO = 1, OR_PHYS_RAYLEIGH = 2, OR_PHYS_PAIR = 4, OR_PHYS_DELTA = 8,
+       OR_PHYS_BREM = 16 };
 
 /* Photoeffect cross-section (cm^2) of one electron of a hydrogenic K shell of
  * nuclear charge z, in Stobbe's exact non-relativistic form:
@@ -1066,10 +1067,45 @@ double or_s_col_d(double t, int dens)
 }
 double or_s_col(double t) { return or_s_col_d(t, 0); }
 
-static double gl_panel_inv_s(double a, double b, int dens)
+/* Range nodes: T_k log-spaced from t_cut upwards, C_k = int_{t_cut}^{T_k} dT/S. */
+#define OR_RNG_N 4000
+#define OR_RNG_TMAX 30.0
+/* The continuous stopping power S of the range tables: the collision stopping
+ * power (restricted to transfers below the electron cut-off tc when delta
+ * rays are on) plus, with bremsstrahlung on, the radiative loss to photons
+ * below the photon cut-off kc (`soft`, at the nodes; linear in ln T between
+ * them: it is below 1e-3 of S at these cut-offs). */
+typedef struct {
+    double t_cut, ratio, kc;
+    int dens, phys;
+    double t[OR_RNG_N], c[OR_RNG_N], soft[OR_RNG_N];
+} or_range_table;
+
+double or_s_col_restricted(double t, double tc, int dens);
+double or_brem_soft(double t, double kc);
+
+static double rt_soft(const or_range_table* rt, double t)
+{
+    double x = log(t / rt->t_cut) / log(rt->ratio);
+    if (x <= 0.0) return rt->soft[0];
+    if (x >= OR_RNG_N - 1) return rt->soft[OR_RNG_N - 1];
+    int k = (int)x;
+    double f = x - k;
+    return (1.0 - f) * rt->soft[k] + f * rt->soft[k + 1];
+}
+
+static double rt_stop(const or_range_table* rt, double t)
+{
+    double s = (rt->phys & 8) ? or_s_col_restricted(t, rt->t_cut, rt->dens)
+                              : or_s_col_d(t, rt->dens);
+    if (rt->phys & 16) s += rt_soft(rt, t);
+    return s;
+}
+
+static double gl_panel_inv_s(const or_range_table* rt, double a, double b)
 {
     double c = 0.5 * (a + b), h = 0.5 * (b - a), s = 0.0;
-    for (int i = 0; i < OR_GL_N; ++i) s += gl_w[i] / or_s_col_d(c + h * gl_x[i], dens);
+    for (int i = 0; i < OR_GL_N; ++i) s += gl_w[i] / rt_stop(rt, c + h * gl_x[i]);
     return s * h;
 }
 
@@ -1082,38 +1118,34 @@ static double t_of_x(double x)
 
 /* int_a^b dT / S(T); with the density effect the integrand has kinks where
  * delta(T) changes branch (x0, x1), so panels are split there. */
-static double gl_integral_inv_s(double a, double b, int dens)
+static double gl_integral_inv_s(const or_range_table* rt, double a, double b)
 {
-    if (dens) {
+    if (rt->dens) {
         const double knots[2] = {t_of_x(OR_DE_X0), t_of_x(OR_DE_X1)};
         for (int k = 0; k < 2; ++k)
             if (a < knots[k] && knots[k] < b)
-                return gl_integral_inv_s(a, knots[k], dens) + gl_integral_inv_s(knots[k], b, dens);
+                return gl_integral_inv_s(rt, a, knots[k]) + gl_integral_inv_s(rt, knots[k], b);
     }
-    return gl_panel_inv_s(a, b, dens);
+    return gl_panel_inv_s(rt, a, b);
 }
 
-/* Range nodes: T_k log-spaced from t_cut upwards, C_k = int_{t_cut}^{T_k} dT/S. */
-#define OR_RNG_N 4000
-#define OR_RNG_TMAX 30.0
-typedef struct {
-    double t_cut, ratio;
-    int dens, pad;
-    double t[OR_RNG_N], c[OR_RNG_N];
-} or_range_table;
-
-static void range_table_init(or_range_table* rt, double t_cut, int dens)
+/* phys: the OR_PHYS_* bits (only delta rays and bremsstrahlung matter here);
+ * kc: the photon cut-off. */
+static void range_table_init(or_range_table* rt, double t_cut, int dens, int phys, double kc)
 {
     gl_init();
     rt->t_cut = t_cut;
     rt->dens = dens;
+    rt->phys = phys & (8 | 16);
+    rt->kc = kc;
     rt->ratio = pow(OR_RNG_TMAX / t_cut, 1.0 / (OR_RNG_N - 1));
-    rt->t[0] = t_cut;
-    rt->c[0] = 0.0;
-    for (int k = 1; k < OR_RNG_N; ++k) {
+    for (int k = 0; k < OR_RNG_N; ++k) {
         rt->t[k] = t_cut * pow(rt->ratio, (double)k);
-        rt->c[k] = rt->c[k - 1] + gl_integral_inv_s(rt->t[k - 1], rt->t[k], dens);
+        rt->soft[k] = (rt->phys & 16) ? or_brem_soft(rt->t[k], kc) : 0.0;
     }
+    rt->c[0] = 0.0;
+    for (int k = 1; k < OR_RNG_N; ++k)
+        rt->c[k] = rt->c[k - 1] + gl_integral_inv_s(rt, rt->t[k - 1], rt->t[k]);
 }
 
 /* CSDA range above the cut-off: R(T) = int_{t_cut}^{T} dT'/S(T') (g/cm^2). */
@@ -1125,7 +1157,7 @@ static double range_of(const or_range_table* rt, double t)
     if (k > OR_RNG_N - 1) k = OR_RNG_N - 1;
     while (k > 0 && rt->t[k] > t) --k;
     while (k < OR_RNG_N - 1 && rt->t[k + 1] <= t) ++k;
-    return rt->c[k] + gl_integral_inv_s(rt->t[k], t, rt->dens);
+    return rt->c[k] + gl_integral_inv_s(rt, rt->t[k], t);
 }
 
 /* Inverse of range_of by bracketing on the nodes, then safeguarded Newton. */
@@ -1141,9 +1173,9 @@ static double range_inverse(const or_range_table* rt, double rr)
     double a = rt->t[lo], b = rt->t[hi];
     double t = a + (b - a) * (rr - rt->c[lo]) / (rt->c[hi] - rt->c[lo]);
     for (int it = 0; it < 60; ++it) {
-        double f = rt->c[lo] + gl_integral_inv_s(rt->t[lo], t, rt->dens) - rr;
+        double f = rt->c[lo] + gl_integral_inv_s(rt, rt->t[lo], t) - rr;
         if (f > 0.0) b = t; else a = t;
-        double tn = t - f * or_s_col_d(t, rt->dens);
+        double tn = t - f * rt_stop(rt, t);
         if (!(tn > a && tn < b)) tn = 0.5 * (a + b);
         if (fabs(tn - t) <= 1e-15 * t) { t = tn; break; }
         t = tn;
@@ -1153,25 +1185,40 @@ static double range_inverse(const or_range_table* rt, double rr)
 
 /* test hooks */
 static or_range_table g_test_rt;
-static double g_test_rt_cut = -1.0;
-static int g_test_rt_dens = -1;
-static void ensure_test_rt(double t_cut, int dens)
+static double g_test_rt_cut = -1.0, g_test_rt_kc = -1.0;
+static int g_test_rt_dens = -1, g_test_rt_phys = -1;
+static void ensure_test_rt(double t_cut, int dens, int phys, double kc)
 {
-    if (g_test_rt_cut != t_cut || g_test_rt_dens != dens) {
-        range_table_init(&g_test_rt, t_cut, dens);
+    phys &= 8 | 16;
+    if (g_test_rt_cut != t_cut || g_test_rt_dens != dens || g_test_rt_phys != phys ||
+        g_test_rt_kc != kc) {
+        range_table_init(&g_test_rt, t_cut, dens, phys, kc);
         g_test_rt_cut = t_cut;
         g_test_rt_dens = dens;
+        g_test_rt_phys = phys;
+        g_test_rt_kc = kc;
     }
 }
-double or_range_d(double t, double t_cut, int dens)
+double or_range_p(double t, double t_cut, int dens, int phys, double kc)
 {
-    ensure_test_rt(t_cut, dens);
+    ensure_test_rt(t_cut, dens, phys, kc);
     return range_of(&g_test_rt, t);
 }
+double or_range_inv_p(double rr, double t_cut, int dens, int phys, double kc)
+{
+    ensure_test_rt(t_cut, dens, phys, kc);
+    return range_inverse(&g_test_rt, rr);
+}
+/* the continuous stopping power the range tables integrate (MeV cm^2/g) */
+double or_s_cont(double t, double t_cut, int dens, int phys, double kc)
+{
+    ensure_test_rt(t_cut, dens, phys, kc);
+    return rt_stop(&g_test_rt, t);
+}
+double or_range_d(double t, double t_cut, int dens) { return or_range_p(t, t_cut, dens, 0, 0.0); }
 double or_range_inv_d(double rr, double t_cut, int dens)
 {
-    ensure_test_rt(t_cut, dens);
-    return range_inverse(&g_test_rt, rr);
+    return or_range_inv_p(rr, t_cut, dens, 0, 0.0);
 }
 double or_range(double t, double t_cut) { return or_range_d(t, t_cut, 0); }
 double or_range_inv(double rr, double t_cut) { return or_range_inv_d(rr, t_cut, 0); }
@@ -1215,6 +1262,216 @@ void or_ms_sample(double theta0, uint64_t seed, int n, double* theta_out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Electron hard events, each switchable: Moller delta rays (energy transfers */
+/* at or above the electron cut-off tc) and bremsstrahlung photons (at or     */
+/* above the photon cut-off kc).  Below the cut-offs the losses stay           */
+/* continuous: the collision stopping power restricted to transfers below tc  */
+/* and the radiative loss to photons below kc.  The paper's engine has both   */
+/* processes (Sec. 2.3 names its cut-offs only); the forms below are the      */
+/* Moller cross-section and the Bethe-Heitler (Born, unscreened) photon       */
+/* spectrum, formula 3BN of Koch and Motz (1959), with Z(Z+1) for the atomic  */
+/* electrons' share.                                                          */
+/* ------------------------------------------------------------------------ */
+#define OR_ZZ1_WATER 76.0            /* sum of Z (Z + 1) over the atoms of H2O */
+#define OR_MOL_G (1.0 / 18.0153)     /* mol of H2O per gram */
+
+/* Electron density of water per gram (electrons / g). */
+static double ne_per_gram(void) { return OR_NA * OR_ZA_WATER; }
+
+/* Moller differential cross-section per target electron for an electron of
+ * kinetic energy t transferring w (cm^2 / MeV), eps = w / t:
+ *   2 pi re^2 mc^2 / (beta^2 t^2) [1/eps^2 + 1/(1-eps)^2 + (tau/(tau+1))^2
+ *                                 - (2 tau + 1) / (tau+1)^2 / (eps (1-eps))]. */
+double or_moller_dsig(double t, double w)
+{
+    double tau = t / OR_ME, gam = tau + 1.0, beta2 = 1.0 - 1.0 / (gam * gam);
+    double eps = w / t;
+    double a = tau / gam;
+    double br = 1.0 / (eps * eps) + 1.0 / ((1.0 - eps) * (1.0 - eps)) + a * a -
+                (2.0 * tau + 1.0) / (gam * gam) / (eps * (1.0 - eps));
+    return 2.0 * OR_PI * OR_RE * OR_RE * OR_ME / (beta2 * t * t) * br;
+}
+
+/* Its integral over w in [tc, t/2] (the two electrons are identical: the
+ * more energetic one is the primary), per gram of water (cm^2/g); 0 where
+ * t <= 2 tc.  With ec = tc / t, the closed form of the bracket's integral
+ * over eps in [ec, 1/2] is
+ *   1/ec - 1/(1-ec) + (tau/(tau+1))^2 (1/2 - ec) - (2 tau+1)/(tau+1)^2 ln((1-ec)/ec). */
+double or_moller_sigma(double t, double tc)
+{
+    if (!(t > 2.0 * tc)) return 0.0;
+    double tau = t / OR_ME, gam = tau + 1.0, beta2 = 1.0 - 1.0 / (gam * gam);
+    double ec = tc / t, a = tau / gam;
+    double br = 1.0 / ec - 1.0 / (1.0 - ec) + a * a * (0.5 - ec) -
+                (2.0 * tau + 1.0) / (gam * gam) * log((1.0 - ec) / ec);
+    return ne_per_gram() * 2.0 * OR_PI * OR_RE * OR_RE * OR_ME / (beta2 * t) * br;
+}
+
+/* Collision stopping power of water restricted to energy transfers below tc
+ * (ICRU 37, the Rohrlich-Carlson F-(tau, Delta) with Delta = tc / mc^2, at
+ * most tau / 2 where it is the unrestricted one), MeV cm^2/g, less the
+ * density-effect delta(T) when dens is set. */
+double or_s_col_restricted(double t, double tc, int dens)
+{
+    double tau = t / OR_ME, gam = tau + 1.0, beta2 = 1.0 - 1.0 / (gam * gam);
+    double dl = tc / OR_ME;
+    if (dl > 0.5 * tau) dl = 0.5 * tau;
+    double i_rel = OR_I_WATER / OR_ME;
+    double f_minus = -1.0 - beta2 + log((tau - dl) * dl) + tau / (tau - dl) +
+                     (0.5 * dl * dl + (2.0 * tau + 1.0) * log(1.0 - dl / tau)) / (gam * gam);
+    double bracket = log(2.0 * (tau + 2.0) / (i_rel * i_rel)) + f_minus;
+    if (dens) bracket -= or_density_delta(t);
+    return 2.0 * OR_PI * OR_RE * OR_RE * OR_ME * OR_NA * OR_ZA_WATER / beta2 * bracket;
+}
+
+/* Bremsstrahlung: k dsigma/dk of an electron of kinetic energy t emitting a
+ * photon of energy k in water, per gram (cm^2/g), from formula 3BN (energies
+ * in units of mc^2: E0 = 1 + t, E = E0 - k, p the momenta):
+ *   Z^2 alpha re^2 (p/p0) { 4/3 - 2 E0 E (p^2 + p0^2)/(p^2 p0^2) + e0 E/p0^3
+ *     + e E0/p^3 - e e0/(p0 p) + L [8 E0 E/(3 p0 p) + k^2 (E0^2 E^2 + p0^2 p^2)/(p0^3 p^3)
+ *     + k/(2 p0 p) (e0 (E0 E + p0^2)/p0^3 - e (E0 E + p^2)/p^3 + 2 k E0 E/(p^2 p0^2))] }
+ * with L = 2 ln((E0 E + p0 p - 1)/k), e0 = ln((E0+p0)/(E0-p0)), e = ln((E+p)/(E-p)),
+ * and Z^2 -> sum of Z(Z+1) over the molecule.  0 at and beyond the tip. */
+double or_brem_kdsig(double t, double k_mev)
+{
+    double e0t = 1.0 + t / OR_ME, k = k_mev / OR_ME, et = e0t - k;
+    if (!(k > 0.0) || !(et > 1.0)) return 0.0;
+    double p0 = sqrt(e0t * e0t - 1.0), p = sqrt(et * et - 1.0);
+    double L = 2.0 * log((e0t * et + p0 * p - 1.0) / k);
+    double eps0 = log((e0t + p0) / (e0t - p0)), eps = log((et + p) / (et - p));
+    double p02 = p0 * p0, p2 = p * p, p03 = p02 * p0, p3 = p2 * p;
+    double br = 4.0 / 3.0 - 2.0 * e0t * et * (p2 + p02) / (p2 * p02) + eps0 * et / p03 +
+                eps * e0t / p3 - eps * eps0 / (p0 * p) +
+                L * (8.0 * e0t * et / (3.0 * p0 * p) +
+                     k * k * (e0t * e0t * et * et + p02 * p2) / (p03 * p3) +
+                     k / (2.0 * p0 * p) *
+                         (eps0 * (e0t * et + p02) / p03 - eps * (e0t * et + p2) / p3 +
+                          2.0 * k * e0t * et / (p2 * p02)));
+    double v = (p / p0) * br;
+    if (v < 0.0) v = 0.0;
+    return OR_ZZ1_WATER * OR_ALPHA * OR_RE * OR_RE * OR_NA * OR_MOL_G * v;
+}
+
+/* Integrals over ln k by 8-point Gauss-Legendre on n equal panels of [a, b]
+ * (ln k); `weight_k` multiplies the integrand by k (energy moment). */
+static double brem_int_lnk(double t, double lna, double lnb, int n, int weight_k)
+{
+    gl_init();
+    double h = (lnb - lna) / n, s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double c = lna + (i + 0.5) * h;
+        for (int j = 0; j < OR_GL_N; ++j) {
+            double k = exp(c + 0.5 * h * gl_x[j]);
+            s += gl_w[j] * or_brem_kdsig(t, k) * (weight_k ? k : 1.0);
+        }
+    }
+    return 0.5 * h * s;
+}
+
+/* Photons of kc <= k < t, per gram (cm^2/g): the integral of k dsigma/dk
+ * over ln k. */
+double or_brem_sigma(double t, double kc)
+{
+    if (!(t > kc)) return 0.0;
+    return brem_int_lnk(t, log(kc), log(t), 64, 0);
+}
+
+/* Energy radiated in photons below min(kc, t), per gram (MeV cm^2/g): the
+ * integral of k dsigma/dk over k, on ln k from 1e-12 kc (the rest is below
+ * 1e-10 of it). */
+double or_brem_soft(double t, double kc)
+{
+    double top = kc < t ? kc : t;
+    if (!(top > 0.0)) return 0.0;
+    return brem_int_lnk(t, log(top * 1e-12), log(top), 96, 1);
+}
+
+/* Energy transfer of a hard Moller collision (t > 2 tc): eps = w / t from
+ * 1/eps^2 on [ec, 1/2] by inversion, eps = ec / (1 - u (1 - 2 ec)), kept with
+ * probability h(eps) / 2.25 where the differential cross-section is
+ * h(eps) / eps^2 up to a constant,
+ *   h = 1 + (eps/(1-eps))^2 + (tau/(tau+1))^2 eps^2 - (2 tau+1)/(tau+1)^2 eps/(1-eps),
+ * and h <= 2.25 on [0, 1/2].  Two uniforms a trial, at most 1000 trials. */
+static double moller_sample(or_stream* st, double t, double tc)
+{
+    double tau = t / OR_ME, gam = tau + 1.0, a = tau / gam;
+    double c2 = (2.0 * tau + 1.0) / (gam * gam);
+    double ec = tc / t, eps = ec;
+    for (int trial = 0; trial < 1000; ++trial) {
+        double u1 = stream_u01(st), u2 = stream_u01(st);
+        eps = ec / (1.0 - u1 * (1.0 - 2.0 * ec));
+        double r = eps / (1.0 - eps);
+        double h = 1.0 + r * r + a * a * eps * eps - c2 * r;
+        if (u2 * 2.25 <= h) break;
+    }
+    return eps;
+}
+
+/* Photon energy of a hard bremsstrahlung event (kc < t): k = kc (t/kc)^u
+ * (density 1/k), kept with probability k dsigma/dk (t, k) / k dsigma/dk (t,
+ * kc); k dsigma/dk decreases with k on (0, t) (checked in the tests), so the
+ * bound holds.  Two uniforms a trial, at most 1000 trials. */
+static double brem_sample(or_stream* st, double t, double kc)
+{
+    double top = or_brem_kdsig(t, kc), lr = log(t / kc), k = kc;
+    for (int trial = 0; trial < 1000; ++trial) {
+        double u1 = stream_u01(st), u2 = stream_u01(st);
+        k = kc * exp(u1 * lr);
+        if (u2 * top <= or_brem_kdsig(t, k)) break;
+    }
+    return k;
+}
+
+/* test hooks: samples on streams g = i */
+void or_moller_sample(double t, double tc, uint64_t seed, int n, double* eps_out)
+{
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        eps_out[i] = moller_sample(&st, t, tc);
+    }
+}
+void or_brem_sample(double t, double kc, uint64_t seed, int n, double* k_out)
+{
+    for (int i = 0; i < n; ++i) {
+        or_stream st;
+        stream_init(&st, seed, (uint64_t)i, OR_TAG_TR, 0);
+        k_out[i] = brem_sample(&st, t, kc);
+    }
+}
+
+/* Random-number stream of a secondary made in a hard event or by a positron
+ * of a secondary family: the splitmix64 finaliser (Steele, Lea and Flood,
+ * OOPSLA 2014) of the parent's stream (g, sub), the parent's event index j
+ * and the kind (1 delta electron, 2 bremsstrahlung photon, 3 annihilation
+ * photon); the child keeps the history id (low 48 bits of g), takes
+ * 0x8000 | 15 hashed bits as the high 16 bits (disjoint from the annihilation
+ * photons' 2 sub + k of a source photon's family) and 8 hashed bits as its
+ * sub (electrons; photons take sub 0). */
+static uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+void or_child_id(uint64_t g, uint32_t sub, uint32_t j, uint32_t kind, uint64_t* g_out,
+                 uint32_t* sub_out)
+{
+    uint64_t h = mix64(mix64(g) ^ (((uint64_t)sub << 32) | ((uint64_t)j << 8) | (uint64_t)kind));
+    *g_out = (g & 0xFFFFFFFFFFFFull) | ((uint64_t)(0x8000u | (uint32_t)(h & 0x7FFFu)) << 48);
+    *sub_out = (uint32_t)(h >> 16) & 0xFFu;
+}
+
+/* Generations: source photons and source electrons are generation 0; the
+ * electrons a photon sets in motion share its generation; delta electrons,
+ * bremsstrahlung photons and annihilation photons are one above their
+ * parent's.  A particle above OR_GEN_MAX is not followed: its energy (a
+ * positron's plus 2 mc^2) is deposited where it was made (counted as
+ * overflow). */
+#define OR_GEN_MAX 3
+
+/* ------------------------------------------------------------------------ */
 /* Transport and tally                                                        */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -1248,50 +1505,134 @@ static void deposit(or_tracker* T, int64_t v, double e, int32_t tag)
  * Steps end at voxel faces or after a fractional energy loss step_frac;
  * the voxel index is carried explicitly and changes by one at each face. */
 static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
-                             uint64_t seed, uint64_t g, int32_t tag, int secondary);
+                             uint64_t seed, uint64_t g, int32_t tag, int secondary, int gen);
 
-/* A positron that has come to rest at p annihilates into two photons of mc^2
- * each, back to back, the first along an isotropic direction (cos theta =
- * 2u - 1, phi = 2 pi u', two uniforms of the positron's stream).  Each photon
- * is followed as a photon history of its own, id g | (2 sub + k) << 48 (the
- * history ids of a plan stay below 2^48). */
+/* A positron (generation gen) that has come to rest at p annihilates into
+ * two photons of mc^2 each, back to back, the first along an isotropic
+ * direction (cos theta = 2u - 1, phi = 2 pi u', two uniforms of the
+ * positron's stream).  Each photon is followed as a photon history of its
+ * own (generation gen + 1), id g | (2 sub + k) << 48 in a source photon's
+ * family (the history ids of a plan stay below 2^48), else the child stream
+ * of kind 3 with event index k.  Above the generation cap the 2 mc^2 are
+ * deposited at p. */
 static void annihilate(or_tracker* T, or_stream* st, const double p[3], uint64_t seed,
-                       uint64_t g, uint32_t sub, int32_t tag)
+                       uint64_t g, uint32_t sub, int32_t tag, int gen, int64_t v)
 {
     double c = 2.0 * stream_u01(st) - 1.0, phi = 2.0 * OR_PI * stream_u01(st);
     double sn = sqrt(1.0 - c * c);
     double da[3] = {sn * cos(phi), sn * sin(phi), c};
     T->cnt[C_ANNIHIL]++;
+    if (gen + 1 > OR_GEN_MAX) {
+        deposit(T, v, 2.0 * OR_ME, tag);
+        T->cnt[C_OVERFLOW]++;
+        return;
+    }
     for (int k = 0; k < 2; ++k) {
         double pp[3] = {p[0], p[1], p[2]};
         double dd[3] = {k ? -da[0] : da[0], k ? -da[1] : da[1], k ? -da[2] : da[2]};
-        transport_photon(T, pp, dd, OR_ME, seed, g | ((uint64_t)(2u * sub + (uint32_t)k) << 48),
-                         tag, 1);
+        uint64_t gk = g | ((uint64_t)(2u * sub + (uint32_t)k) << 48);
+        if (g >> 48) {
+            uint32_t unused;
+            or_child_id(g, sub, (uint32_t)k, 3u, &gk, &unused);
+        }
+        transport_photon(T, pp, dd, OR_ME, seed, gk, tag, 1, gen + 1);
     }
 }
 
+/* A hard event of an electron (or positron) of kinetic energy *e at p,
+ * direction d, in voxel v, stream st of (g, sub), generation gen, event index
+ * j: the process in proportion to the Moller and bremsstrahlung
+ * cross-sections at *e (one uniform; neither possible: no event).  Moller:
+ * the delta electron takes w = eps *e, the directions from two-body
+ * kinematics, cos = sqrt(w (t + 2 mc^2) / (t (w + 2 mc^2))) for the delta and
+ * the same with t - w for the primary, azimuths phi and phi + pi (one more
+ * uniform).  Bremsstrahlung: the photon takes k along d, the electron keeps
+ * its direction.  The secondary (generation gen + 1) is followed at once, or
+ * deposited at p above the generation cap. */
 static void transport_electron(or_tracker* T, double p[3], double d[3], double e,
-                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag, int positron)
+                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag, int positron,
+                               int gen);
+static void hard_event(or_tracker* T, or_stream* st, const double p[3], double d[3], double* e,
+                       int64_t v, uint64_t seed, uint64_t g, uint32_t sub, int32_t tag, int gen,
+                       uint32_t j)
+{
+    const int32_t phys = T->tp->physics;
+    const double tc = T->tp->e_cut_e, kc = T->tp->e_cut_g;
+    double sm = (phys & OR_PHYS_DELTA) ? or_moller_sigma(*e, tc) : 0.0;
+    double sb = (phys & OR_PHYS_BREM) ? or_brem_sigma(*e, kc) : 0.0;
+    double u = stream_u01(st);
+    if (!(sm + sb > 0.0)) return;
+    uint64_t gc;
+    uint32_t subc;
+    double pp[3] = {p[0], p[1], p[2]};
+    if (u * (sm + sb) < sm) {
+        double t = *e, eps = moller_sample(st, t, tc);
+        double w = eps * t, t1 = t - w;
+        double phi = 2.0 * OR_PI * stream_u01(st);
+        double cd = sqrt(w * (t + 2.0 * OR_ME) / (t * (w + 2.0 * OR_ME)));
+        double cp = sqrt(t1 * (t + 2.0 * OR_ME) / (t * (t1 + 2.0 * OR_ME)));
+        double dd[3] = {d[0], d[1], d[2]};
+        rotate_direction(dd, cd, phi);
+        rotate_direction(d, cp, phi + OR_PI);
+        *e = t1;
+        T->cnt[C_MOLLER]++;
+        if (gen + 1 > OR_GEN_MAX) {
+            deposit(T, v, w, tag);
+            T->cnt[C_OVERFLOW]++;
+            return;
+        }
+        or_child_id(g, sub, j, 1u, &gc, &subc);
+        transport_electron(T, pp, dd, w, seed, gc, subc, tag, 0, gen + 1);
+    } else {
+        double k = brem_sample(st, *e, kc);
+        *e -= k;
+        T->cnt[C_BREM]++;
+        if (gen + 1 > OR_GEN_MAX) {
+            deposit(T, v, k, tag);
+            T->cnt[C_OVERFLOW]++;
+            return;
+        }
+        or_child_id(g, sub, j, 2u, &gc, &subc);
+        double dd[3] = {d[0], d[1], d[2]};
+        transport_photon(T, pp, dd, k, seed, gc, tag, 1, gen + 1);
+    }
+}
+
+/* With delta rays or bremsstrahlung on, the continuous loss is the
+ * restricted one (range tables) and hard events come at a rate sigma_h =
+ * sigma_Moller + sigma_brem per gram taken at the step's initial energy: the
+ * number of mean free paths to the next one, -ln(1 - u), is drawn at the
+ * start and after each event (one uniform), a step ends at the event if it
+ * comes before the face and the energy-loss limit, and the event happens
+ * after that step's continuous loss and deflection (hard_event). */
+static void transport_electron(or_tracker* T, double p[3], double d[3], double e,
+                               uint64_t seed, uint64_t g, uint32_t sub, int32_t tag, int positron,
+                               int gen)
 {
     const or_phantom* ph = T->ph;
     const double tcut = T->tp->e_cut_e, f = T->tp->step_frac;
+    const int32_t phys = T->tp->physics;
+    const int hard = (phys & (OR_PHYS_DELTA | OR_PHYS_BREM)) != 0;
     const int n[3] = {ph->nx, ph->ny, ph->nz};
     int idx[3];
     voxel_clamped(ph, p, idx);
     or_stream st;
     stream_init(&st, seed, g, OR_TAG_TR, sub);
     if (e < tcut) {
-        deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
+        int64_t v0 = ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
+        deposit(T, v0, e, tag);
         T->cnt[C_E_LOCAL]++;
-        if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+        if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v0);
         return;
     }
+    double lam = hard ? -log(1.0 - stream_u01(&st)) : 0.0;
+    uint32_t n_hard = 0;
     for (int step = 0;; ++step) {
         int64_t v = ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
         if (step >= OR_MAX_E_STEPS) {
             deposit(T, v, e, tag);
             T->cnt[C_GUARD]++;
-            if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+            if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v);
             return;
         }
         double rho = (double)ph->density[v];
@@ -1315,12 +1656,46 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
         if (rho > 0.0) sf = (final ? r0 : r0 - range_of(T->rt, e_f)) / rho;
         else sf = OR_INF;
         T->cnt[C_E_STEPS]++;
+        double sig_h = 0.0, sh = OR_INF;
+        if (hard && rho > 0.0) {
+            sig_h = ((phys & OR_PHYS_DELTA) ? or_moller_sigma(e, tcut) : 0.0) +
+                    ((phys & OR_PHYS_BREM) ? or_brem_sigma(e, T->tp->e_cut_g) : 0.0);
+            if (sig_h > 0.0) sh = lam / (rho * sig_h);
+        }
+        if (sh < sf && sh < sb) {
+            /* a hard event ends this step */
+            double e_new = range_inverse(T->rt, r0 - rho * sh);
+            deposit(T, v, e - e_new, tag);
+            for (int a = 0; a < 3; ++a) p[a] += sh * d[a];
+            T->ledger[L_EPATH] += sh;
+            double e_old = e;
+            e = e_new;
+            if (e < tcut) {
+                deposit(T, v, e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v);
+                return;
+            }
+            if (T->tp->ms_enable) {
+                double th0 = or_ms_width(0.5 * (e_old + e), rho, sh);
+                double u1 = stream_u01(&st), u2 = stream_u01(&st);
+                rotate_direction(d, cos(ms_polar(th0, u1)), 2.0 * OR_PI * u2);
+            }
+            hard_event(T, &st, p, d, &e, v, seed, g, sub, tag, gen, n_hard++);
+            if (e < tcut) {
+                deposit(T, v, e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v);
+                return;
+            }
+            lam = -log(1.0 - stream_u01(&st));
+            continue;
+        }
+        lam -= rho * sig_h * (sf <= sb ? sf : sb);
         if (sf <= sb) {
             if (final) {
                 /* the residual range ends inside this voxel */
                 T->ledger[L_EPATH] += sf;
                 deposit(T, v, e, tag);
-                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v);
                 return;
             }
             double e_new = range_inverse(T->rt, r0 - rho * sf);
@@ -1331,7 +1706,7 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
             e = e_new;
             if (e < tcut) {
                 deposit(T, v, e, tag);
-                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v);
                 return;
             }
             if (T->tp->ms_enable) {
@@ -1355,8 +1730,9 @@ static void transport_electron(or_tracker* T, double p[3], double d[3], double e
                 return;
             }
             if (e < tcut) {
-                deposit(T, ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0], e, tag);
-                if (positron) annihilate(T, &st, p, seed, g, sub, tag);
+                int64_t v2 = ((int64_t)idx[2] * ph->ny + idx[1]) * ph->nx + idx[0];
+                deposit(T, v2, e, tag);
+                if (positron) annihilate(T, &st, p, seed, g, sub, tag, gen, v2);
                 return;
             }
             if (T->tp->ms_enable) {
@@ -1391,7 +1767,7 @@ typedef struct { double p[3], d[3], e; uint32_t sub; int positron; } or_electron
  * collision are counted for source photons only (not `secondary` ones, the
  * annihilation photons). */
 static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
-                             uint64_t seed, uint64_t g, int32_t tag, int secondary)
+                             uint64_t seed, uint64_t g, int32_t tag, int secondary, int gen)
 {
     const or_phantom* ph = T->ph;
     const int32_t phys = T->tp->physics;
@@ -1504,7 +1880,7 @@ static void transport_photon(or_tracker* T, double p[3], double d[3], double e,
     }
     for (int i = 0; i < n_e; ++i)
         transport_electron(T, stack[i].p, stack[i].d, stack[i].e, seed, g, stack[i].sub, tag,
-                           stack[i].positron);
+                           stack[i].positron, gen);
 }
 
 static double phantom_rho_max(const or_phantom* ph)
@@ -1556,7 +1932,7 @@ int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_b
     for (int b = 0; b < n_beams; ++b) beam_rotation(&beams[b], R[b]);
     or_sampler S = {m, cdf, plan, beams, R, ph};
     or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
-    range_table_init(rt, tp->e_cut_e, tp->density_effect);
+    range_table_init(rt, tp->e_cut_e, tp->density_effect, tp->physics, tp->e_cut_g);
     double rho_max = phantom_rho_max(ph);
     int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
     int nt = n_threads_of(n_threads);
@@ -1591,9 +1967,9 @@ int or_run(const or_model* m, const or_plan* plan, const or_beam* beams, int n_b
                 T->cnt[C_ENTERED]++;
                 double p[3] = {rec.x, rec.y, rec.z}, d[3] = {rec.u, rec.v, rec.w};
                 if (rec.stype == OR_SUB_ELECTRON)
-                    transport_electron(T, p, d, rec.e, seed, g, 0, rec.tag, 0);
+                    transport_electron(T, p, d, rec.e, seed, g, 0, rec.tag, 0, 0);
                 else
-                    transport_photon(T, p, d, rec.e, seed, g, rec.tag, 0);
+                    transport_photon(T, p, d, rec.e, seed, g, rec.tag, 0, 0);
             }
         }
         for (int64_t c = 0; c < cells; ++c) {
@@ -1638,7 +2014,7 @@ int or_transport(const or_phantom* ph, const or_params* tp, uint64_t seed, int64
 {
     gl_init();
     or_range_table* rt = (or_range_table*)malloc(sizeof(or_range_table));
-    range_table_init(rt, tp->e_cut_e, tp->density_effect);
+    range_table_init(rt, tp->e_cut_e, tp->density_effect, tp->physics, tp->e_cut_g);
     double rho_max = phantom_rho_max(ph);
     int64_t cells = imap ? n_rows * n_cols : (int64_t)ph->nx * ph->ny * ph->nz;
     int nt = n_threads_of(n_threads);
@@ -1660,9 +2036,9 @@ int or_transport(const or_phantom* ph, const or_params* tp, uint64_t seed, int64
             T->cnt[C_HIST]++;
             T->ledger[L_SRC] += e[i];
             if (ptype[i] == 1)
-                transport_electron(T, p, d, e[i], seed, hid[i], 0, tag ? tag[i] : 0, 0);
+                transport_electron(T, p, d, e[i], seed, hid[i], 0, tag ? tag[i] : 0, 0, 0);
             else
-                transport_photon(T, p, d, e[i], seed, hid[i], tag ? tag[i] : 0, 0);
+                transport_photon(T, p, d, e[i], seed, hid[i], tag ? tag[i] : 0, 0, 0);
         }
     }
     for (int64_t c = 0; c < cells; ++c) {

@@ -92,10 +92,13 @@ SAMPLE_REC = np.dtype([("j", "i4"), ("k", "i4"), ("status", "i4"), ("stype", "i4
 LEDGER = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")
 COUNTERS = ("hist", "entered", "wc_steps", "real", "e_pushed", "e_local", "e_steps",
             "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard", "overflow",
-            "folds", "photo", "rayleigh", "pair", "annihil")
+            "folds", "photo", "rayleigh", "pair", "annihil", "moller", "brem")
 N_COUNTERS = 20
 # optional photon processes (bits of params(physics=...))
 PHYS_PHOTO, PHYS_RAYLEIGH, PHYS_PAIR = 1, 2, 4
+# optional electron hard events: Moller delta rays, bremsstrahlung photons
+PHYS_DELTA, PHYS_BREM = 8, 16
+GEN_MAX = 3
 ST_OK, ST_JAW, ST_MISSED, ST_INVALID = 0, 1, 2, 3
 
 
@@ -125,6 +128,31 @@ def _declare(L):
     L.or_mu_total.restype = C.c_double
     L.or_rayleigh_sample_cos.argtypes = [C.c_double, C.c_uint64, C.c_int, dp]
     L.or_pair_share_sample.argtypes = [C.c_uint64, C.c_int, dp]
+    L.or_moller_dsig.argtypes = [C.c_double, C.c_double]
+    L.or_moller_dsig.restype = C.c_double
+    L.or_moller_sigma.argtypes = [C.c_double, C.c_double]
+    L.or_moller_sigma.restype = C.c_double
+    L.or_s_col_restricted.argtypes = [C.c_double, C.c_double, C.c_int]
+    L.or_s_col_restricted.restype = C.c_double
+    L.or_brem_kdsig.argtypes = [C.c_double, C.c_double]
+    L.or_brem_kdsig.restype = C.c_double
+    L.or_brem_sigma.argtypes = [C.c_double, C.c_double]
+    L.or_brem_sigma.restype = C.c_double
+    L.or_brem_soft.argtypes = [C.c_double, C.c_double]
+    L.or_brem_soft.restype = C.c_double
+    L.or_moller_sample.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int, dp]
+    L.or_moller_sample.restype = None
+    L.or_brem_sample.argtypes = [C.c_double, C.c_double, C.c_uint64, C.c_int, dp]
+    L.or_brem_sample.restype = None
+    L.or_child_id.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                              P(C.c_uint64), P(C.c_uint32)]
+    L.or_child_id.restype = None
+    L.or_range_p.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_double]
+    L.or_range_p.restype = C.c_double
+    L.or_range_inv_p.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_double]
+    L.or_range_inv_p.restype = C.c_double
+    L.or_s_cont.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_double]
+    L.or_s_cont.restype = C.c_double
     L.or_s_col.argtypes = [C.c_double]
     L.or_s_col.restype = C.c_double
     L.or_s_col_d.argtypes = [C.c_double, C.c_int]
@@ -483,6 +511,64 @@ def mu_total(e, physics):
     parts = np.zeros(4)
     tot = lib().or_mu_total(e, physics, _ptr(parts, dp))
     return tot, parts
+
+
+def moller_dsig(t, w):
+    """Moller d sigma / dW per target electron (cm^2/MeV)."""
+    return lib().or_moller_dsig(t, w)
+
+
+def moller_sigma(t, tc):
+    """Hard Moller collisions (W >= tc) per gram of water (cm^2/g)."""
+    return lib().or_moller_sigma(t, tc)
+
+
+def s_col_restricted(t, tc, density_effect=False):
+    return lib().or_s_col_restricted(t, tc, 1 if density_effect else 0)
+
+
+def brem_kdsig(t, k):
+    """k d sigma / dk of bremsstrahlung in water (cm^2/g), formula 3BN."""
+    return lib().or_brem_kdsig(t, k)
+
+
+def brem_sigma(t, kc):
+    return lib().or_brem_sigma(t, kc)
+
+
+def brem_soft(t, kc):
+    return lib().or_brem_soft(t, kc)
+
+
+def moller_sample(t, tc, seed, n):
+    out = np.zeros(n)
+    lib().or_moller_sample(t, tc, seed, n, _ptr(out, dp))
+    return out
+
+
+def brem_sample(t, kc, seed, n):
+    out = np.zeros(n)
+    lib().or_brem_sample(t, kc, seed, n, _ptr(out, dp))
+    return out
+
+
+def child_id(g, sub, j, kind):
+    go, so = C.c_uint64(), C.c_uint32()
+    lib().or_child_id(g, sub, j, kind, C.byref(go), C.byref(so))
+    return go.value, so.value
+
+
+def range_p(t, t_cut, physics, kc, density_effect=False):
+    return lib().or_range_p(t, t_cut, 1 if density_effect else 0, int(physics), kc)
+
+
+def range_inv_p(rr, t_cut, physics, kc, density_effect=False):
+    return lib().or_range_inv_p(rr, t_cut, 1 if density_effect else 0, int(physics), kc)
+
+
+def s_cont(t, t_cut, physics, kc, density_effect=False):
+    """The continuous stopping power the range tables integrate (MeV cm^2/g)."""
+    return lib().or_s_cont(t, t_cut, 1 if density_effect else 0, int(physics), kc)
 
 
 def rayleigh_sample_cos(e, seed, n):

@@ -1,0 +1,236 @@
+"""Oracle pins for the optional electron hard events: Moller delta rays above
+the electron cut-off and bremsstrahlung photons above the photon cut-off, the
+continuous losses below them (restricted collision stopping power, soft
+radiative loss), their samplers, the secondaries' random streams and the
+transport with both switched on."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+ME = 0.51099895
+RE = 2.8179403262e-13
+ALPHA = 7.2973525693e-3
+NA = 6.02214076e23
+NE_G = NA * 10.0 / 18.0153          # electrons per gram of water
+MOL_G = NA / 18.0153                # molecules per gram
+ZZ1 = 2 * 1 * 2 + 8 * 9             # sum of Z (Z + 1) over H2O
+TC, KC = 0.2, 0.05                  # the paper's cut-offs (Sec. 2.3)
+DELTA, BREM = 8, 16
+
+
+# ---- Moller ----------------------------------------------------------------
+@pytest.mark.parametrize("t", [0.5, 1.0, 3.0, 6.0, 15.0])
+def test_moller_sigma_is_the_integral_of_its_differential(orc, t):
+    """The closed form of the hard-collision cross-section against a
+    quadrature of the differential cross-section over [tc, t/2]."""
+    num, _ = integrate.quad(lambda w: orc.moller_dsig(t, w), TC, t / 2, epsabs=0, epsrel=1e-12)
+    assert orc.moller_sigma(t, TC) == pytest.approx(NE_G * num, rel=1e-9)
+
+
+def test_moller_below_twice_the_cut_has_no_hard_collision(orc):
+    assert orc.moller_sigma(2 * TC, TC) == 0.0
+    assert orc.moller_sigma(0.39, TC) == 0.0
+    assert orc.moller_sigma(0.41, TC) > 0.0
+
+
+@pytest.mark.parametrize("t", [0.3, 2.0, 8.0])
+def test_moller_symmetric_in_the_two_electrons(orc, t):
+    """Identical particles: the cross-section is symmetric under W <-> t - W."""
+    for w in (0.05 * t, 0.2 * t, 0.37 * t):
+        assert orc.moller_dsig(t, w) == pytest.approx(orc.moller_dsig(t, t - w), rel=1e-12)
+
+
+def test_moller_nonrelativistic_limit_is_mott(orc):
+    """tau -> 0: the bracket tends to Mott's 1/eps^2 + 1/(1-eps)^2 - 1/(eps (1-eps))
+    and the prefactor to 2 pi re^2 mc^2 / (beta^2 t^2) with beta^2 = 2 tau."""
+    t = 1e-7
+    tau = t / ME
+    for eps in (0.1, 0.3, 0.5):
+        mott = 1 / eps ** 2 + 1 / (1 - eps) ** 2 - 1 / (eps * (1 - eps))
+        ref = 2 * math.pi * RE ** 2 * ME / (2 * tau * t * t) * mott
+        assert orc.moller_dsig(t, eps * t) == pytest.approx(ref, rel=1e-5)
+
+
+@pytest.mark.parametrize("t", [0.5, 1.0, 3.0, 6.0, 20.0])
+@pytest.mark.parametrize("dens", [False, True])
+def test_restricted_plus_hard_losses_is_the_bethe_stopping_power(orc, t, dens):
+    """ICRU 37's restricted collision stopping power (Rohrlich-Carlson F-)
+    plus the energy lost in Moller collisions above the cut-off is the
+    unrestricted Bethe stopping power: a relation between two independent
+    formulas (the restricted one and the Moller cross-section)."""
+    hard, _ = integrate.quad(lambda w: w * orc.moller_dsig(t, w), TC, t / 2, epsabs=0,
+                             epsrel=1e-12)
+    full = orc.s_col(t, density_effect=dens)
+    assert orc.s_col_restricted(t, TC, dens) + NE_G * hard == pytest.approx(full, rel=1e-9)
+    # a cut at or above t/2 restricts nothing
+    assert orc.s_col_restricted(t, t, dens) == pytest.approx(full, rel=1e-12)
+
+
+@pytest.mark.parametrize("t", [0.6, 2.0, 6.0])
+def test_moller_sampler_follows_the_cross_section(orc, t):
+    eps = orc.moller_sample(t, TC, 11, 40000)
+    ec = TC / t
+    assert eps.min() >= ec * (1 - 1e-12) and eps.max() <= 0.5 + 1e-12
+    tot, _ = integrate.quad(lambda e: orc.moller_dsig(t, e * t), ec, 0.5, epsrel=1e-11)
+
+    def cdf(x):
+        x = np.atleast_1d(x)
+        return np.array([integrate.quad(lambda e: orc.moller_dsig(t, e * t), ec, min(max(v, ec), 0.5),
+                                        epsrel=1e-10)[0] for v in x]) / tot
+
+    grid = np.linspace(ec, 0.5, 400)
+    c = cdf(grid)
+    assert stats.kstest(eps, lambda x: np.interp(x, grid, c)).pvalue > 1e-3
+
+
+# ---- bremsstrahlung ----------------------------------------------------------
+def _bh_nonrel(t, k):
+    """Bethe-Heitler's non-relativistic (Born) spectrum of one electron on a
+    charge Z = 1, as k dsigma/dk: (16/3) alpha re^2 / p0^2 ln((p0 + p)/(p0 - p)),
+    momenta in units of mc."""
+    e0 = 1 + t / ME
+    e1 = e0 - k / ME
+    p0, p1 = math.sqrt(e0 * e0 - 1), math.sqrt(e1 * e1 - 1)
+    return 16.0 / 3.0 * ALPHA * RE ** 2 / p0 ** 2 * math.log((p0 + p1) / (p0 - p1))
+
+
+@pytest.mark.parametrize("t", [1e-5, 3e-5])
+def test_brem_nonrelativistic_limit(orc, t):
+    """Far below mc^2 the spectrum tends to Bethe-Heitler's non-relativistic one."""
+    for f in (0.1, 0.5, 0.9):
+        ref = _bh_nonrel(t, f * t) * ZZ1 * MOL_G
+        assert orc.brem_kdsig(t, f * t) == pytest.approx(ref, rel=1e-3)
+
+
+def test_brem_high_energy_loss_is_heitlers_unscreened_limit(orc):
+    """Far above mc^2 the radiated energy per unit path, divided by the total
+    energy, tends to Heitler's unscreened 4 Z^2 alpha re^2 (ln(2 E0) - 1/3)."""
+    e0 = 1e4
+    t = (e0 - 1) * ME
+    lo, hi = math.log(t * 1e-12), math.log(t * (1 - 1e-13))
+    rad, _ = integrate.quad(lambda lk: orc.brem_kdsig(t, math.exp(lk)) * math.exp(lk), lo, hi,
+                            limit=400, epsrel=1e-10)
+    ref = 4 * ALPHA * RE ** 2 * ZZ1 * MOL_G * (math.log(2 * e0) - 1.0 / 3.0) * e0 * ME
+    assert rad == pytest.approx(ref, rel=2e-5)
+
+
+@pytest.mark.parametrize("t", [0.3, 1.0, 3.0, 6.0, 20.0])
+def test_brem_spectrum_vanishes_at_the_tip_and_falls_with_k(orc, t):
+    """k dsigma/dk falls monotonically from the photon cut-off to the tip, where
+    the final electron is at rest and the Born spectrum is 0 (the sampler's
+    bound rests on the first property)."""
+    ks = np.geomspace(KC, t * (1 - 1e-9), 500)
+    v = np.array([orc.brem_kdsig(t, k) for k in ks])
+    assert np.all(np.diff(v) <= 0.0)
+    assert orc.brem_kdsig(t, t) == 0.0 and orc.brem_kdsig(t, t * 1.1) == 0.0
+    assert v[-1] < 1e-3 * v[0]
+
+
+@pytest.mark.parametrize("t", [0.3, 1.0, 6.0])
+def test_brem_sigma_and_soft_loss_are_their_integrals(orc, t):
+    hard, _ = integrate.quad(lambda k: orc.brem_kdsig(t, k) / k, KC, t, epsrel=1e-10, limit=200)
+    assert orc.brem_sigma(t, KC) == pytest.approx(hard, rel=1e-6)
+    soft, _ = integrate.quad(lambda k: orc.brem_kdsig(t, k), 0, KC, epsrel=1e-10, limit=200)
+    assert orc.brem_soft(t, KC) == pytest.approx(soft, rel=1e-6)
+    assert orc.brem_sigma(KC * 0.9, KC) == 0.0
+
+
+@pytest.mark.parametrize("t", [0.5, 6.0])
+def test_brem_sampler_follows_the_spectrum(orc, t):
+    k = orc.brem_sample(t, KC, 17, 40000)
+    assert k.min() >= KC * (1 - 1e-12) and k.max() < t
+    grid = np.geomspace(KC, t, 600)
+    dens = np.array([orc.brem_kdsig(t, x) / x for x in grid])
+    c = integrate.cumulative_trapezoid(dens, grid, initial=0.0)
+    c /= c[-1]
+    assert stats.kstest(k, lambda x: np.interp(x, grid, c)).pvalue > 1e-3
+
+
+# ---- continuous loss and range -------------------------------------------------
+@pytest.mark.parametrize("phys", [DELTA, BREM, DELTA | BREM])
+def test_range_is_the_integral_of_the_continuous_stopping_power(orc, phys):
+    s_full = orc.s_col(3.0)
+    s = orc.s_cont(3.0, TC, phys, KC)
+    col = orc.s_col_restricted(3.0, TC, False) if phys & DELTA else s_full
+    rad = orc.brem_soft(3.0, KC) if phys & BREM else 0.0
+    assert s == pytest.approx(col + rad, rel=1e-3)
+    for t in (0.5, 2.0, 6.0):
+        ref, _ = integrate.quad(lambda x: 1.0 / orc.s_cont(x, TC, phys, KC), TC, t, epsrel=1e-10,
+                                limit=200)
+        assert orc.range_p(t, TC, phys, KC) == pytest.approx(ref, rel=1e-6)
+        assert orc.range_inv_p(orc.range_p(t, TC, phys, KC), TC, phys, KC) == pytest.approx(t, rel=1e-9)
+
+
+# ---- secondaries' streams ------------------------------------------------------
+def test_child_streams_keep_the_history_and_leave_the_source_family():
+    from oracle import oracle as orc
+    seen = set()
+    g = (123456789 << 1) | 1
+    for kind in (1, 2, 3):
+        for j in range(50):
+            gc, sc = orc.child_id(g, 7, j, kind)
+            assert gc & ((1 << 48) - 1) == g
+            assert gc >> 63 == 1                    # high 16 bits >= 0x8000
+            assert 0 <= sc < 256
+            seen.add((gc, sc))
+    assert len(seen) == 150
+    assert orc.child_id(g, 7, 3, 1) == orc.child_id(g, 7, 3, 1)
+
+
+# ---- transport ------------------------------------------------------------------
+def _pencil(orc, e, ptype, physics, n=3000, seed=5):
+    from paper_1503_01725_amd import workloads as wl
+    phs = wl.water_phantom(24, 1.0)
+    edep, led, cnt = orc.transport(phs, seed, np.full(n, ptype), np.tile([0.1, -0.2, 0.0], (n, 1)),
+                                   np.tile([0.0, 0.0, 1.0], (n, 1)), np.full(n, e),
+                                   np.arange(n, dtype=np.uint64),
+                                   tparams=orc.params(e_cut_e=TC, e_cut_g=KC, physics=physics))
+    return edep, led, cnt
+
+
+@pytest.mark.parametrize("physics", [DELTA, BREM, DELTA | BREM, DELTA | BREM | 7])
+def test_electron_pencil_conserves_energy(orc, physics):
+    """6 MeV electrons into a 24 cm water cube: every MeV is deposited or
+    escapes, hard events happen at about the rate the cross-sections give, and
+    the generation cap leaves almost nothing unfollowed."""
+    n = 3000
+    edep, led, cnt = _pencil(orc, 6.0, 1, physics, n)
+    src = 6.0 * n
+    assert abs(led["dep"] + led["esc_g"] + led["esc_e"] - src) < 1e-9 * src
+    assert edep.sum() == pytest.approx(led["dep"], rel=1e-12)
+    if physics & DELTA:
+        assert cnt["moller"] > 0.5 * n
+    else:
+        assert cnt["moller"] == 0
+    if physics & BREM:
+        assert cnt["brem"] > 0.2 * n and led["esc_g"] > 0.0
+    else:
+        assert cnt["brem"] == 0
+    assert cnt["overflow"] <= 1e-3 * (cnt["moller"] + cnt["brem"]) + 3
+
+
+def test_moller_event_count_matches_the_cross_section(orc):
+    """With delta rays only and no deflection, a straight 6 MeV electron track
+    meets hard collisions at the rate n_e sigma_Moller(T): the expected count
+    along the CSDA path (its energy lost continuously at the restricted rate,
+    and in each collision by the transfer) is close to the integral of
+    sigma / S_restricted over the energy; compare the source electrons' own
+    events (the delta electrons stay below 2 tc mostly)."""
+    n = 4000
+    _, _, cnt = _pencil(orc, 6.0, 1, DELTA, n)
+    # upper bound: the continuous-loss integral from 6 MeV down to 2 tc
+    ub, _ = integrate.quad(lambda t: orc.moller_sigma(t, TC) / orc.s_col_restricted(t, TC, False),
+                           2 * TC, 6.0, epsrel=1e-8, limit=200)
+    assert cnt["moller"] < 1.25 * ub * n
+    assert cnt["moller"] > 0.6 * ub * n
+
+
+def test_without_the_electron_processes_nothing_changes(orc):
+    """Bits off: the same result as the plain method (same streams, same
+    range tables)."""
+    e1, l1, c1 = _pencil(orc, 6.0, 1, 0, 500)
+    e2, l2, c2 = _pencil(orc, 6.0, 1, 7, 500)   # photon processes only: electrons unchanged
+    assert np.array_equal(e1, e2) and l1 == l2
+    assert c1["moller"] == 0 and c1["brem"] == 0
