@@ -264,8 +264,9 @@ typedef struct {
     int32_t density_effect; /* 1 = collision stopping power less Sternheimer's
                                density-effect correction delta(T) of water;
                                0 = Bethe without it; other values: error */
-    uint32_t physics;       /* optional photon processes, PSL_PHYS_* bits (0 =
-                               Compton only, the plain method's physics)      */
+    uint32_t physics;       /* optional photon processes and electron hard
+                               events, PSL_PHYS_* bits (0 = Compton only and
+                               continuous electron loss, the plain method)   */
 } psl_transport_params;
 
 /* Optional photon processes of psl_transport_params.physics (Sec. 2.3: the
@@ -287,7 +288,27 @@ typedef struct {
  *             mc^2 photons, back to back and isotropic, each followed as a
  *             photon history of its own (id g | (2 sub + k) << 48, history ids
  *             below 2^48), which needs e_cut_electron <= mc^2. */
-enum { PSL_PHYS_PHOTO = 1, PSL_PHYS_RAYLEIGH = 2, PSL_PHYS_PAIR = 4 };
+/* Optional electron hard events (each switchable; the paper's engine has
+ * them, Sec. 2.3), water with density scaling:
+ *   DELTA  Moller collisions transferring at least e_cut_electron (up to half
+ *          the energy) are sampled as events, the delta electron transported
+ *          on its own; below the cut-off the loss is continuous with the
+ *          collision stopping power restricted to smaller transfers (ICRU 37,
+ *          Rohrlich-Carlson F-);
+ *   BREM   bremsstrahlung photons of at least e_cut_photon (Bethe-Heitler Born
+ *          spectrum without screening, formula 3BN of Koch and Motz, with
+ *          Z(Z+1) for the atomic electrons) are sampled as events, the photon
+ *          along the electron and transported; below the cut-off the radiated
+ *          energy is a continuous loss.
+ * Events come at the rate of a step's initial energy: the number of mean free
+ * paths to the next one is drawn at the start and after each event.  Delta
+ * electrons and photons from electrons (bremsstrahlung, annihilation) are one
+ * generation above their parent; generations up to 3 are transported, later
+ * ones deposited where made (counted).  A secondary's random stream is the
+ * splitmix64 hash of its parent's stream, event index and kind (the history
+ * id kept in the low 48 bits, 0x8000 | 15 hashed bits above). */
+enum { PSL_PHYS_PHOTO = 1, PSL_PHYS_RAYLEIGH = 2, PSL_PHYS_PAIR = 4, PSL_PHYS_DELTA = 8,
+       PSL_PHYS_BREM = 16 };
 
 /* A dose tally on `phantom`.  index_map_dev == NULL: one cell per voxel.
  * Otherwise (Sec. 2.2.2) index_map_dev is a device int32 [nz][ny][nx] map,
@@ -335,13 +356,15 @@ int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose
 /* Synchronises with the device and reads the energy ledger (MeV, host double
  * [8]: source, jaw-rejected, missed phantom, invalid, escaped photons, escaped
  * electrons (an escaping positron adds its rest energy 2 mc^2), deposited,
- * electron path length in cm), the event counters (host uint64 [20]:
+ * electron path length in cm), the event counters (host uint64 [24]:
  * histories, entered, Woodcock steps, real interactions, particles pushed by
  * photons, local electron deposits, electron steps, atomic deposits,
  * uncollided escapes of source photons, Kahn trials, electron face crossings,
  * step-guard hits, overflows (a particle stack too small, or a particle column
  * beyond the tally), replicas folded, photoelectric absorptions, Rayleigh
- * scatterings, pair productions, positron annihilations; the rest are zero).
+ * scatterings, pair productions, positron annihilations, hard Moller
+ * collisions, hard bremsstrahlung events, secondaries past the generation cap
+ * (deposited where made); the rest are zero).
  * Returns PSL_EOVERFLOW if an overflow was counted since the last RESET.
  * Either output may be NULL. */
 int psl_tally_stats(psl_tally* tally, double* ledger, uint64_t* counters);

@@ -56,7 +56,8 @@ enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, 
 /* counters[] slots */
 enum { C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS,
        C_DEPOSITS, C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW,
-       C_FOLDS, C_PHOTO = 14, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_MOLLER, C_BREM, C_N = 20 };
+       C_FOLDS, C_PHOTO = 14, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_MOLLER, C_BREM, C_CAPPED,
+       C_N = 24 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as    */
@@ -1466,9 +1467,9 @@ void or_child_id(uint64_t g, uint32_t sub, uint32_t j, uint32_t kind, uint64_t* 
 /* Generations: source photons and source electrons are generation 0; the
  * electrons a photon sets in motion share its generation; delta electrons,
  * bremsstrahlung photons and annihilation photons are one above their
- * parent's.  A particle above OR_GEN_MAX is not followed: its energy (a
- * positron's plus 2 mc^2) is deposited where it was made (counted as
- * overflow). */
+ * parent's.  A particle above OR_GEN_MAX is not followed: its energy (for
+ * annihilation photons the 2 mc^2) is deposited where it was made (counted
+ * as capped). */
 #define OR_GEN_MAX 3
 
 /* ------------------------------------------------------------------------ */
@@ -1524,7 +1525,7 @@ static void annihilate(or_tracker* T, or_stream* st, const double p[3], uint64_t
     T->cnt[C_ANNIHIL]++;
     if (gen + 1 > OR_GEN_MAX) {
         deposit(T, v, 2.0 * OR_ME, tag);
-        T->cnt[C_OVERFLOW]++;
+        T->cnt[C_CAPPED]++;
         return;
     }
     for (int k = 0; k < 2; ++k) {
@@ -1578,7 +1579,7 @@ static void hard_event(or_tracker* T, or_stream* st, const double p[3], double d
         T->cnt[C_MOLLER]++;
         if (gen + 1 > OR_GEN_MAX) {
             deposit(T, v, w, tag);
-            T->cnt[C_OVERFLOW]++;
+            T->cnt[C_CAPPED]++;
             return;
         }
         or_child_id(g, sub, j, 1u, &gc, &subc);
@@ -1589,7 +1590,7 @@ static void hard_event(or_tracker* T, or_stream* st, const double p[3], double d
         T->cnt[C_BREM]++;
         if (gen + 1 > OR_GEN_MAX) {
             deposit(T, v, k, tag);
-            T->cnt[C_OVERFLOW]++;
+            T->cnt[C_CAPPED]++;
             return;
         }
         or_child_id(g, sub, j, 2u, &gc, &subc);

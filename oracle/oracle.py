@@ -92,8 +92,8 @@ SAMPLE_REC = np.dtype([("j", "i4"), ("k", "i4"), ("status", "i4"), ("stype", "i4
 LEDGER = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")
 COUNTERS = ("hist", "entered", "wc_steps", "real", "e_pushed", "e_local", "e_steps",
             "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard", "overflow",
-            "folds", "photo", "rayleigh", "pair", "annihil", "moller", "brem")
-N_COUNTERS = 20
+            "folds", "photo", "rayleigh", "pair", "annihil", "moller", "brem", "capped")
+N_COUNTERS = 24
 # optional photon processes (bits of params(physics=...))
 PHYS_PHOTO, PHYS_RAYLEIGH, PHYS_PAIR = 1, 2, 4
 # optional electron hard events: Moller delta rays, bremsstrahlung photons

@@ -69,7 +69,8 @@ class psl_transport_params(C.Structure):
 
 # optional photon processes (psl_transport_params.physics)
 PSL_PHYS_PHOTO, PSL_PHYS_RAYLEIGH, PSL_PHYS_PAIR = 1, 2, 4
-N_COUNTERS = 20
+PSL_PHYS_DELTA, PSL_PHYS_BREM = 8, 16
+N_COUNTERS = 24
 
 
 class psl_run_opts(C.Structure):

@@ -104,6 +104,10 @@ struct TransportWs {
     // stack of ann_cap entries (x, y, z, u, v, w, E, id, tag, count)
     psl_particles ann{};
     uint32_t ann_cap = 0;
+    // delta electrons (electron hard events on): two electron stacks of
+    // del_cap entries, written by one electron pass and read by the next
+    psl_particles del[2]{};
+    uint32_t del_cap = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -139,7 +143,12 @@ constexpr int INV_TAB_N = 2048;     // T(R) on a uniform R grid
 constexpr int RAY_TAB_N = 1024;     // Rayleigh: cumulative of F^2 over t = (q a0)^2
 
 // Optional photon processes (psl_transport_params.physics bits).
-constexpr uint32_t kPhysPhoto = 1u, kPhysRayleigh = 2u, kPhysPair = 4u;
+constexpr uint32_t kPhysPhoto = 1u, kPhysRayleigh = 2u, kPhysPair = 4u, kPhysDelta = 8u,
+                   kPhysBrem = 16u;
+// Generations of secondaries that are transported (delta electrons,
+// bremsstrahlung and annihilation photons are one above their parent); above
+// it a secondary's energy is deposited where it is made.
+constexpr uint32_t kGenMax = 3u;
 // Particle tag bit 15 marks a positron (tally columns use bits 0-14).
 constexpr uint32_t kPositronBit = 0x8000u;
 constexpr uint32_t kColumnMask = 0x7FFFu;
@@ -163,6 +172,10 @@ struct PhysicsDev {
     float ray_lt1, ray_inv_dlt;     // ln t of node 1, 1 / spacing in ln t
     float ka0_per_mev;              // k a0 per MeV of photon energy
     float photo_bind;               // K binding energy of oxygen (MeV)
+    // optional electron hard events: per unit density (cm^2/g) on the range
+    // table's grid, x = Moller collisions above the electron cut-off, y = x +
+    // bremsstrahlung above the photon cut-off (null when neither is enabled)
+    const float2* hard;
 };
 
 // Energy ledger and counter slots (match psl_tally_stats).
@@ -170,7 +183,7 @@ enum { L_SRC = 0, L_JAW, L_MISSED, L_INVALID, L_ESC_G, L_ESC_E, L_DEP, L_EPATH, 
 enum {
     C_HIST = 0, C_ENTERED, C_WC_STEPS, C_REAL, C_E_PUSHED, C_E_LOCAL, C_E_STEPS, C_DEPOSITS,
     C_ESC_UNCOLLIDED, C_KAHN_TRIALS, C_E_BOUNDARY, C_GUARD, C_OVERFLOW, C_FOLDS,
-    C_PHOTO, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_N = 20
+    C_PHOTO, C_RAYLEIGH, C_PAIR, C_ANNIHIL, C_MOLLER, C_BREM, C_CAPPED, C_N = 24
 };
 
 // Device-side tally state.  `stats` holds kStripes copies of the ledger
@@ -250,6 +263,7 @@ struct psl_phantom {
     float t_cut_tab = -1.f;
     int32_t dens_tab = -1;
     int32_t phys_tab = -1;
+    float kc_tab = -1.f;   // photon cut-off of the bremsstrahlung tables
     uint64_t tab_gen = 0;
     psl::DevBuf tabs;
     psl::PhysicsDev phys{};
@@ -297,7 +311,8 @@ void ensure_device(const psl_plan* p);
 
 // Allocates the scratch for an electron stack of up to perm_cap entries in
 // buf, and a stack of ann_cap annihilation photons (0: none).
-TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap = 0);
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap = 0,
+                               uint32_t del_cap = 0);
 
 
 // Optional HIP events recorded around the transport launches (may be null).
@@ -313,7 +328,7 @@ void launch_sample(const psl_plan* plan, const psl_phantom* ph, uint32_t replica
 void launch_transport(const psl_phantom* ph, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const TransportWs& ws, const psl_transport_params* prm,
                       uint64_t seed, hipStream_t stream, bool sort_electrons, int lane_load,
-                      const PhaseEvents* ev = nullptr);
+                      const PhaseEvents* ev = nullptr, uint32_t grid_items = 0);
 void launch_zero_u32(uint32_t* p, int n, hipStream_t s);
 void launch_fold(psl_tally* t, hipStream_t s);
 }  // namespace psl

@@ -132,6 +132,22 @@ struct PoolStream {
         --cnt;
         return r;
     }
+    // Next uniform for a lane on its own (no wave-wide call): an empty ring
+    // takes the next block of four first.  For rare events whose number of
+    // uniforms is not bounded in advance (rejection loops).
+    __device__ __forceinline__ float next() {
+        if (cnt == 0u) {
+            uint32_t x0 = blk, x1 = tagsub, x2 = g0, x3 = g1;
+            philox4x32_10(x0, x1, x2, x3, k0, k1);
+            ++blk;
+            col[((head + 0u) & (R - 1)) * kLanes] = top24(x0);
+            col[((head + 1u) & (R - 1)) * kLanes] = top24(x1);
+            col[((head + 2u) & (R - 1)) * kLanes] = top24(x2);
+            col[((head + 3u) & (R - 1)) * kLanes] = top24(x3);
+            cnt = 4u;
+        }
+        return pop();
+    }
 };
 
 __device__ __forceinline__ double wave_sum(double v) {

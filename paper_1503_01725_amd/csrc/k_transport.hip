@@ -59,9 +59,15 @@ struct TransportArgs {
     int ms;
     uint32_t seed_lo, seed_hi;
     uint32_t push_chunk;       // electron-stack entries a wave reserves per atomic
-    Stack ann;                 // annihilation photons out of the electron kernel
-                               // (count null: none expected)
-    uint32_t secondary;        // photon kernel: the input holds annihilation photons
+    Stack ann;                 // photons out of the electron kernel: annihilation and
+                               // bremsstrahlung (count null: none expected)
+    uint32_t secondary;        // photon kernel: the input holds secondary photons
+    // electron hard events (kPhysDelta | kPhysBrem bits; 0: none): delta
+    // electrons go to el_next; the pass's generation decides whether its
+    // secondaries are followed (gen + 1 <= kGenMax) or deposited
+    uint32_t hard;
+    uint32_t gen;
+    Stack el_next;
 };
 
 // ---- hardware transcendentals ---------------------------------------------
@@ -780,6 +786,94 @@ __device__ __forceinline__ void face_distance(float p, float d, int i, float o, 
 // Writes the two photons of a positron's annihilation at rest at (x, y, z):
 // mc^2 each, back to back along an isotropic direction (cos theta = 2u - 1,
 // azimuth u' in turns), ids g | (2 sub + k) << 48, the positron's column.
+// ---- electron hard events ----------------------------------------------------
+// Random stream of a secondary from a hard event (kind 1 delta electron, 2
+// bremsstrahlung photon) or an annihilation photon of a secondary family
+// (kind 3): the splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) of
+// the parent's stream (g, sub), its event index j and the kind; the child
+// keeps the history id (low 48 bits), takes 0x8000 | 15 hashed bits as the
+// high 16 bits and 8 hashed bits as its sub (electrons).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ void child_id(uint64_t g, uint32_t sub, uint32_t j, uint32_t kind,
+                                         uint64_t& g_out, uint32_t& sub_out) {
+    const uint64_t h =
+        mix64(mix64(g) ^ ((uint64_t(sub) << 32) | (uint64_t(j) << 8) | uint64_t(kind)));
+    g_out = (g & 0xFFFFFFFFFFFFull) | (uint64_t(0x8000u | uint32_t(h & 0x7FFFu)) << 48);
+    sub_out = uint32_t(h >> 16) & 0xFFu;
+}
+
+// Hard-event cross-sections per unit density (cm^2/g) at kinetic energy t:
+// x Moller (transfers above the electron cut-off), y = x + bremsstrahlung
+// (photons above the photon cut-off); linear in ln T between the range
+// table's nodes.
+__device__ __forceinline__ float2 hard_xs(const PhysicsDev& P, float t) {
+    float x = (hw_log(t) - P.rng_lnt0) * P.rng_inv_dlnt;
+    x = fminf(fmaxf(x, 0.f), float(RNG_TAB_N - 1) - 1e-3f);
+    const int i = int(x);
+    const float f = x - float(i);
+    const float2 a = P.hard[i], b = P.hard[i + 1];
+    return make_float2(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y));
+}
+
+// Moller energy transfer eps = w / t in [tc / t, 1/2]: 1/eps^2 by inversion,
+// kept with probability h(eps) / 2.25 (h = eps^2 times the cross-section's
+// bracket, at most 2.25 on [0, 1/2]); two uniforms a trial.
+template <class St>
+__device__ float moller_eps(St& st, float t, float tc) {
+    const float tau = t * (1.f / kMe), gam = tau + 1.f, a = tau / gam;
+    const float c2 = (2.f * tau + 1.f) / (gam * gam), ec = tc / t;
+    float eps = ec;
+    for (int trial = 0; trial < 1000; ++trial) {
+        const float u1 = st.next(), u2 = st.next();
+        eps = ec / (1.f - u1 * (1.f - 2.f * ec));
+        const float r = eps / (1.f - eps);
+        const float h = 1.f + r * r + a * a * eps * eps - c2 * r;
+        if (u2 * 2.25f <= h) break;
+    }
+    return eps;
+}
+
+// Bremsstrahlung photon spectrum k dsigma/dk up to a constant (Bethe-Heitler,
+// Born, unscreened: formula 3BN of Koch and Motz), FP64: its terms cancel
+// strongly for soft photons.  0 at and beyond the tip.
+__device__ double brem_shape(double t, double km) {
+    constexpr double me = 0.51099895000;
+    const double e0 = 1.0 + t / me, k = km / me, e = e0 - k;
+    if (!(k > 0.0) || !(e > 1.0)) return 0.0;
+    const double p0 = sqrt(e0 * e0 - 1.0), p = sqrt(e * e - 1.0);
+    const double L = 2.0 * log((e0 * e + p0 * p - 1.0) / k);
+    const double l0 = log((e0 + p0) / (e0 - p0)), l = log((e + p) / (e - p));
+    const double p02 = p0 * p0, p2 = p * p, p03 = p02 * p0, p3 = p2 * p;
+    const double br = 4.0 / 3.0 - 2.0 * e0 * e * (p2 + p02) / (p2 * p02) + l0 * e / p03 +
+                      l * e0 / p3 - l * l0 / (p0 * p) +
+                      L * (8.0 * e0 * e / (3.0 * p0 * p) + k * k * (e0 * e0 * e * e + p02 * p2) / (p03 * p3) +
+                           k / (2.0 * p0 * p) *
+                               (l0 * (e0 * e + p02) / p03 - l * (e0 * e + p2) / p3 +
+                                2.0 * k * e0 * e / (p2 * p02)));
+    const double v = (p / p0) * br;
+    return v > 0.0 ? v : 0.0;
+}
+
+// Photon energy of a hard bremsstrahlung event (kc < t): k = kc (t/kc)^u,
+// kept with probability shape(k) / shape(kc) (the spectrum k dsigma/dk falls
+// with k); two uniforms a trial.
+template <class St>
+__device__ float brem_k(St& st, float t, float kc) {
+    const double top = brem_shape(t, kc), lr = log(double(t) / double(kc));
+    double k = kc;
+    for (int trial = 0; trial < 1000; ++trial) {
+        const float u1 = st.next(), u2 = st.next();
+        k = double(kc) * exp(double(u1) * lr);
+        if (double(u2) * top <= brem_shape(t, k)) break;
+    }
+    return float(k);
+}
+
 __device__ __forceinline__ void annihilate(const Stack& ann, float x, float y, float z, float u1,
                                           float u2, uint64_t g, uint32_t sub, uint32_t col,
                                           uint32_t& c_over) {
@@ -800,7 +894,12 @@ __device__ __forceinline__ void annihilate(const Stack& ann, float x, float y, f
         ann.x[i] = x; ann.y[i] = y; ann.z[i] = z;
         ann.u[i] = sg * ux; ann.v[i] = sg * uy; ann.w[i] = sg * c;
         ann.e[i] = kMe;
-        ann.hid[i] = g | (uint64_t(2u * sub + k) << 48);
+        uint64_t gk = g | (uint64_t(2u * sub + k) << 48);
+        if (g >> 48) {
+            uint32_t unused;
+            child_id(g, sub, k, 3u, gk, unused);
+        }
+        ann.hid[i] = gk;
         ann.tag[i] = col;
     }
 }
@@ -822,9 +921,13 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     double &esc_e = ls.l[L_ESC_E], &dep = ls.l[L_DEP], &path = ls.l[L_EPATH];
     uint32_t &c_steps = ls.c[C_E_STEPS], &c_atom = ls.c[C_DEPOSITS], &c_bnd = ls.c[C_E_BOUNDARY],
              &c_guard = ls.c[C_GUARD], &c_local = ls.c[C_E_LOCAL], &c_ann = ls.c[C_ANNIHIL],
-             &c_over = ls.c[C_OVERFLOW];
+             &c_over = ls.c[C_OVERFLOW], &c_moller = ls.c[C_MOLLER], &c_brem = ls.c[C_BREM],
+             &c_capped = ls.c[C_CAPPED];
     (void)c_ann;
     (void)c_over;
+    (void)c_moller;
+    (void)c_brem;
+    (void)c_capped;
     // positrons annihilate where they stop (kFull builds with an annihilation
     // stack; otherwise the flag is not read)
     bool positron = false;
@@ -834,6 +937,10 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
     int ix = 0, iy = 0, iz = 0, cur_v = 0, pend_v = 0, steps = 0;
     uint32_t tag = 0;
     bool alive = false;
+    // hard events (kFull with a.hard): mean free paths left to the next one,
+    // and the electron's event index (its secondaries' streams)
+    float lam = 0.f;
+    uint32_t n_hard = 0;
     WaveQueue wq(n);
     dev::PoolStream<kElectronPool, kBlock> st(s_pool, a.seed_lo, a.seed_hi);
     // Order of an iteration as in k_photon: the CSDA step (deposits
@@ -882,9 +989,22 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                 float sf = INFINITY;
                 if (rho_s > 0.f) sf = (fin ? r0 : r0 - csda_range(P, s_rng, ef)) * hw_rcp(rho_s);
                 ++c_steps;
-                const bool boundary = !(sf <= sb);
-                const float sl = boundary ? sb : sf;
-                if (!boundary && fin) {
+                // hard events: the distance to the next one at the rate of the
+                // step's initial energy; a step ends there if it comes first
+                float sig_h = 0.f, sh = INFINITY;
+                if constexpr (kFull) {
+                    if (a.hard && rho_s > 0.f) {
+                        sig_h = hard_xs(P, t).y;
+                        if (sig_h > 0.f) sh = lam * hw_rcp(rho_s * sig_h);
+                    }
+                }
+                const bool event = sh < sf && sh < sb;
+                const bool boundary = !event && !(sf <= sb);
+                const float sl = event ? sh : (boundary ? sb : sf);
+                if constexpr (kFull) {
+                    if (!event) lam -= rho_s * sig_h * sl;
+                }
+                if (!event && !boundary && fin) {
                     // the residual range ends inside this voxel
                     path += sl;
                     pend_e += t;
@@ -954,22 +1074,126 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                             rotate(dx, dy, dz, __builtin_amdgcn_cosf(th * 0.15915494309189535f),
                                    cphi, sphi);
                         }
+                        if constexpr (kFull) {
+                            if (event && !done) {
+                                // the hard event, after the step's continuous loss and
+                                // deflection: the process in proportion to the
+                                // cross-sections at this energy (one uniform)
+                                // (the table's interpolation is not trusted below the
+                                // thresholds: Moller needs t > 2 tc, a photon of at
+                                // least kc needs t > kc)
+                                const float2 hx = hard_xs(P, t);
+                                const float sm = t > 2.f * tcut ? hx.x : 0.f;
+                                const float stot = sm + (t > a.e_cut_g ? hx.y - hx.x : 0.f);
+                                const float u = st.next();
+                                const uint32_t j = n_hard++;
+                                if (stot > 0.f) {
+                                    const uint64_t gpar = (uint64_t(st.g1) << 32) | st.g0;
+                                    const uint32_t spar = st.tagsub & 0xFFFFu;
+                                    const uint32_t col = tag & kColumnMask;
+                                    const bool follow = a.gen + 1u <= kGenMax;
+                                    uint64_t gc = 0;
+                                    uint32_t sc = 0;
+                                    if (u * stot < sm) {
+                                        // Moller: the delta electron takes w, both
+                                        // directions from two-body kinematics
+                                        const float tt = t;
+                                        const float eps = moller_eps(st, tt, tcut);
+                                        const float w = eps * tt, t1 = tt - w;
+                                        const float up = st.next();
+                                        float sphi, cphi;
+                                        sincos_turn(up, sphi, cphi);
+                                        const float cd = hw_sqrt(w * (tt + 2.f * kMe) /
+                                                                 (tt * (w + 2.f * kMe)));
+                                        const float cp = hw_sqrt(t1 * (tt + 2.f * kMe) /
+                                                                 (tt * (t1 + 2.f * kMe)));
+                                        float ddx = dx, ddy = dy, ddz = dz;
+                                        rotate(ddx, ddy, ddz, cd, cphi, sphi);
+                                        rotate(dx, dy, dz, cp, -cphi, -sphi);
+                                        t = t1;
+                                        ++c_moller;
+                                        bool pushed = false;
+                                        if (follow) {
+                                            child_id(gpar, spar, j, 1u, gc, sc);
+                                            const uint32_t slot = atomicAdd(a.el_next.count, 1u);
+                                            if (slot < a.el_next.capacity) {
+                                                a.el_next.x[slot] = px; a.el_next.y[slot] = py;
+                                                a.el_next.z[slot] = pz;
+                                                a.el_next.u[slot] = ddx; a.el_next.v[slot] = ddy;
+                                                a.el_next.w[slot] = ddz;
+                                                a.el_next.e[slot] = w;
+                                                a.el_next.hid[slot] = gc;
+                                                a.el_next.tag[slot] = col | (sc << 16);
+                                                pushed = true;
+                                            }
+                                        }
+                                        if (!pushed) {
+                                            // past the generation cap, or no room
+                                            pend_e += w;
+                                            dep += w;
+                                            if (follow) ++c_over; else ++c_capped;
+                                        }
+                                    } else {
+                                        // bremsstrahlung: the photon along the electron
+                                        const float k = brem_k(st, t, a.e_cut_g);
+                                        t -= k;
+                                        ++c_brem;
+                                        bool pushed = false;
+                                        if (follow && a.ann.count) {
+                                            child_id(gpar, spar, j, 2u, gc, sc);
+                                            const uint32_t slot = atomicAdd(a.ann.count, 1u);
+                                            if (slot < a.ann.capacity) {
+                                                a.ann.x[slot] = px; a.ann.y[slot] = py;
+                                                a.ann.z[slot] = pz;
+                                                a.ann.u[slot] = dx; a.ann.v[slot] = dy;
+                                                a.ann.w[slot] = dz;
+                                                a.ann.e[slot] = k;
+                                                a.ann.hid[slot] = gc;
+                                                a.ann.tag[slot] = col;
+                                                pushed = true;
+                                            }
+                                        }
+                                        if (!pushed) {
+                                            pend_e += k;
+                                            dep += k;
+                                            if (follow && a.ann.count) ++c_over; else ++c_capped;
+                                        }
+                                    }
+                                }
+                                if (t < tcut) {
+                                    pend_e += t;
+                                    dep += t;
+                                    done = true;
+                                } else {
+                                    lam = -hw_log(1.f - st.next());
+                                }
+                            }
+                        }
                     }
                 }
             }
             if (done) {
-                w_v1 = pend_v;
-                w_e1 = pend_e;
                 alive = false;
                 if constexpr (kFull) {
                     if (positron && !escaped) {
-                        const float u1 = st.pop(), u2 = st.pop();
-                        annihilate(a.ann, px, py, pz, u1, u2,
-                                   (uint64_t(st.g1) << 32) | st.g0, st.tagsub & 0xFFFFu,
-                                   tag & kColumnMask, c_over);
+                        // (next(), not pop(): a hard event may have used the
+                        // uniforms the top-up provided)
+                        const float u1 = st.next(), u2 = st.next();
                         ++c_ann;
+                        if (a.gen + 1u <= kGenMax) {
+                            annihilate(a.ann, px, py, pz, u1, u2,
+                                       (uint64_t(st.g1) << 32) | st.g0, st.tagsub & 0xFFFFu,
+                                       tag & kColumnMask, c_over);
+                        } else {
+                            // above the generation cap: 2 mc^2 where it stops
+                            pend_e += 2.f * kMe;
+                            dep += 2.f * kMe;
+                            ++c_capped;
+                        }
                     }
                 }
+                w_v1 = pend_v;
+                w_e1 = pend_e;
             }
         }
         // refill idle lanes from the wave's chunk of the (band-ordered) stack;
@@ -1034,6 +1258,13 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
                     new_rho = true;
                     steps = 0;
                     alive = true;
+                    if constexpr (kFull) {
+                        if (a.hard) {
+                            // mean free paths to the first hard event
+                            lam = -hw_log(1.f - st.next());
+                            n_hard = 0;
+                        }
+                    }
                 }
             }
         }
@@ -1046,10 +1277,12 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
 }
 
 // ---- small utility kernels (no hipMemsetAsync, so graphs replay cleanly) --
-__global__ void k_reset_queues(uint32_t* el_count, uint32_t* queue, uint32_t* ann_count) {
+__global__ void k_reset_queues(uint32_t* el_count, uint32_t* queue, uint32_t* ann_count,
+                               uint32_t* del_count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (el_count) *el_count = 0u;
         if (ann_count) *ann_count = 0u;
+        if (del_count) *del_count = 0u;
         queue[0] = 0u;
         queue[1] = 0u;
     }
@@ -1154,33 +1387,43 @@ void launch_zero_u32(uint32_t* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, p, n);
 }
 
-TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap) {
+TransportWs alloc_transport_ws(DevBuf& buf, uint32_t perm_cap, uint32_t ann_cap,
+                               uint32_t del_cap) {
     const size_t q = 256, b = size_t(2) * kBands * kSortBlocks * 4, pm = size_t(perm_cap) * 4;
-    // annihilation photons: seven FP32 arrays, the ids, the tags and a count
-    const size_t an = ann_cap ? size_t(ann_cap) * (7 * 4 + 8 + 4) + 256 + 8 * 16 : 0;
-    buf.alloc(q + b + pm + an);
+    // a particle stack: seven FP32 arrays, the ids, the tags and a count
+    auto stack_bytes = [](uint32_t cap) {
+        return cap ? size_t(cap) * (7 * 4 + 8 + 4) + 256 + 8 * 16 : size_t(0);
+    };
+    buf.alloc(q + b + pm + stack_bytes(ann_cap) + 2 * stack_bytes(del_cap));
     TransportWs ws;
     char* base = buf.as<char>();
     ws.queues = reinterpret_cast<uint32_t*>(base);
     ws.bands = reinterpret_cast<uint32_t*>(base + q);
     ws.perm = reinterpret_cast<uint32_t*>(base + q + b);
     ws.perm_cap = perm_cap;
-    if (ann_cap) {
-        size_t off = (q + b + pm + 255) / 256 * 256;
-        auto take = [&](size_t bytes) {
-            void* r = base + off;
-            off += (bytes + 15) / 16 * 16;
-            return r;
-        };
-        psl_particles& p = ws.ann;
+    size_t off = (q + b + pm + 255) / 256 * 256;
+    auto take = [&](size_t bytes) {
+        void* r = base + off;
+        off += (bytes + 15) / 16 * 16;
+        return r;
+    };
+    auto carve_stack = [&](psl_particles& p, uint32_t cap, int32_t ptype) {
         float** f[7] = {&p.x, &p.y, &p.z, &p.u, &p.v, &p.w, &p.e};
-        for (float** fp : f) *fp = static_cast<float*>(take(size_t(ann_cap) * 4));
-        p.hid = static_cast<uint64_t*>(take(size_t(ann_cap) * 8));
-        p.tag = static_cast<uint32_t*>(take(size_t(ann_cap) * 4));
+        for (float** fp : f) *fp = static_cast<float*>(take(size_t(cap) * 4));
+        p.hid = static_cast<uint64_t*>(take(size_t(cap) * 8));
+        p.tag = static_cast<uint32_t*>(take(size_t(cap) * 4));
         p.count = static_cast<uint32_t*>(take(16));
-        p.capacity = ann_cap;
-        p.ptype = 0;
+        p.capacity = cap;
+        p.ptype = ptype;
+    };
+    if (ann_cap) {
+        carve_stack(ws.ann, ann_cap, 0);
         ws.ann_cap = ann_cap;
+    }
+    if (del_cap) {
+        carve_stack(ws.del[0], del_cap, 1);
+        carve_stack(ws.del[1], del_cap, 1);
+        ws.del_cap = del_cap;
     }
     return ws;
 }
@@ -1246,7 +1489,7 @@ void sort_bands(const psl_phantom* ph, const TransportWs& ws, const Stack& estac
 void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_particles* el,
                       psl_tally* tally, const TransportWs& ws, const psl_transport_params* prm,
                       uint64_t seed, hipStream_t stream, bool sort_electrons, int lane_load,
-                      const PhaseEvents* ev) {
+                      const PhaseEvents* ev, uint32_t grid_items) {
     psl_phantom* ph = const_cast<psl_phantom*>(phc);
     const bool full = prm->physics != 0u;
     // positrons (pair production) need a stack for their annihilation photons
@@ -1254,6 +1497,15 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     PSL_CHECK(!pair || ws.ann_cap >= 2u * in->capacity,
               "annihilation photon stack too small (%u for %u photons)", ws.ann_cap,
               in->capacity);
+    // electron hard events: delta electrons into ws.del, bremsstrahlung
+    // photons (with the annihilation photons) into ws.ann
+    const uint32_t hard = prm->physics & (kPhysDelta | kPhysBrem);
+    const bool use_ann = pair || (hard & kPhysBrem) != 0u;
+    const uint32_t e_cap = in->ptype == 0 ? el->capacity : in->capacity;
+    PSL_CHECK(!hard || ws.del_cap >= e_cap, "delta-electron stacks too small (%u for %u)",
+              ws.del_cap, e_cap);
+    PSL_CHECK(!(hard & kPhysBrem) || ws.ann_cap >= e_cap,
+              "secondary photon stack too small (%u for %u)", ws.ann_cap, e_cap);
     TransportArgs a{};
     a.in = to_stack(in);
     a.el = to_stack(el);
@@ -1268,14 +1520,19 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.seed_lo = uint32_t(seed);
     a.seed_hi = uint32_t(seed >> 32);
     a.queue = ws.queues;
-    if (pair) a.ann = to_stack(&ws.ann);
+    if (use_ann) a.ann = to_stack(&ws.ann);
+    a.hard = hard;
+    a.gen = 0u;
+    if (hard) a.el_next = to_stack(&ws.del[0]);
     Stack estack = a.el;
     // The transport kernels are persistent: every lane takes histories from a
     // queue until it is drained.  The grid is sized to the batch (about
     // lane_load histories per lane), not to the stacks, so that a lane works
     // through several histories and a wave is not held up by the one long
-    // history among 64 short ones.
-    const int tg = transport_grid(in->capacity, lane_load);
+    // history among 64 short ones.  The batched runtime sizes it by its batch
+    // size, which its stacks (grown, never shrunk) may exceed.
+    const uint32_t items = grid_items ? std::min(grid_items, in->capacity) : in->capacity;
+    const int tg = transport_grid(items, lane_load);
     // A wave reserves electron-stack entries push_chunk at a time (one
     // returning atomic each); the unused ends of the waves' last chunks
     // (fewer than push_chunk per wave) must fit in the one spare entry per
@@ -1285,7 +1542,7 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     a.push_chunk = waves * 255 <= int64_t(in->capacity) ? 256u : 64u;
     hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream,
                        in->ptype == 0 ? el->count : nullptr, a.queue,
-                       pair ? ws.ann.count : nullptr);
+                       use_ann ? ws.ann.count : nullptr, hard ? ws.del[0].count : nullptr);
     if (in->ptype == 0) {
         if (ev) PSL_HIP(hipEventRecord(ev->photon0, stream));
         photon_kernel(a, full, tg, stream);
@@ -1302,20 +1559,56 @@ void launch_transport(const psl_phantom* phc, const psl_particles* in, psl_parti
     if (ev) PSL_HIP(hipEventRecord(ev->electron0, stream));
     electron_kernel(a, estack, full, tg, stream);
     if (ev) PSL_HIP(hipEventRecord(ev->electron1, stream));
-    if (pair) {
+    if (hard) {
+        // Generations 1 .. kGenMax: the photons the previous electron pass
+        // made (bremsstrahlung, annihilation), whose electrons join that
+        // pass's delta electrons, then those electrons, whose own delta
+        // electrons go to the other stack.  Secondaries of the last
+        // generation are deposited where they are made (in the kernels).
+        Stack cur = to_stack(&ws.del[0]);
+        Stack other = in->ptype == 0 ? a.el : to_stack(&ws.del[1]);
+        const int tg2 = transport_grid(std::min(ws.del_cap, 2u * items), lane_load);
+        const int64_t waves2 = int64_t(tg2) * (kBlock / 64);
+        for (uint32_t gen = 1; gen <= kGenMax; ++gen) {
+            TransportArgs b = a;
+            b.gen = gen;
+            b.in = to_stack(&ws.ann);
+            b.secondary = 1u;
+            b.perm = nullptr;
+            b.el = cur;
+            b.el_next = other;
+            b.push_chunk = waves2 * 255 <= int64_t(cur.capacity) ? 256u : 64u;
+            if (use_ann) {
+                // (without bremsstrahlung or pairs no electron makes photons)
+                hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream, nullptr, b.queue,
+                                   nullptr, nullptr);
+                photon_kernel(b, true, tg2, stream);
+            }
+            // the photons are consumed: the stack takes this pass's new ones
+            hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream, other.count, b.queue,
+                               use_ann ? ws.ann.count : nullptr, nullptr);
+            if (sort_electrons) {
+                sort_bands(ph, ws, cur, stream);
+                b.perm = ws.perm;
+            }
+            electron_kernel(b, cur, true, tg2, stream);
+            std::swap(cur, other);
+        }
+    } else if (pair) {
         // The photons of the positrons' annihilations, as photon histories of
         // their own (mc^2 each: they cannot make pairs, so no further pass),
         // then the electrons they set in motion.
         TransportArgs b = a;
+        b.gen = 1u;
         b.in = to_stack(&ws.ann);
         b.ann = Stack{};
         b.secondary = 1u;
         b.perm = nullptr;
-        const int tg2 = transport_grid(ws.ann_cap, lane_load);
+        const int tg2 = transport_grid(std::min(ws.ann_cap, 2u * items), lane_load);
         const int64_t waves2 = int64_t(tg2) * (kBlock / 64);
         b.push_chunk = waves2 * 255 <= int64_t(ws.ann_cap) ? 256u : 64u;
         hipLaunchKernelGGL(k_reset_queues, dim3(1), dim3(64), 0, stream, el->count, b.queue,
-                           nullptr);
+                           nullptr, nullptr);
         photon_kernel(b, true, tg2, stream);
         if (sort_electrons) {
             sort_bands(ph, ws, estack, stream);
@@ -1452,12 +1745,17 @@ extern "C" int transport_batch(const psl_phantom* phantom, const psl_particles* 
         }
         const psl_particles* es = in->ptype == 0 ? electrons : in;
         ensure_physics(const_cast<psl_phantom*>(phantom), params);
-        const uint32_t ann_need =
+        const bool hard = (params->physics & (kPhysDelta | kPhysBrem)) != 0u;
+        uint32_t ann_need =
             (params->physics & kPhysPair) && in->ptype == 0 ? 2u * in->capacity : 0u;
+        if (params->physics & kPhysBrem) ann_need = std::max(ann_need, es->capacity);
+        const uint32_t del_need = hard ? es->capacity : 0u;
         PSL_CHECK(ann_need == 0 || in->capacity <= (1u << 30), "photon stack too large");
-        if (tally->ws.perm_cap < es->capacity || tally->ws.ann_cap < ann_need)
+        if (tally->ws.perm_cap < es->capacity || tally->ws.ann_cap < ann_need ||
+            tally->ws.del_cap < del_need)
             tally->ws = alloc_transport_ws(tally->ws_mem, std::max(es->capacity, tally->ws.perm_cap),
-                                           std::max(ann_need, tally->ws.ann_cap));
+                                           std::max(ann_need, tally->ws.ann_cap),
+                                           std::max(del_need, tally->ws.del_cap));
         psl_particles dummy = *in;
         launch_transport(phantom, in, in->ptype == 0 ? electrons : &dummy, tally, tally->ws,
                          params, seed, static_cast<hipStream_t>(stream), true, 4);

@@ -9,8 +9,15 @@
 //   * with optional photon processes: the cumulative attenuations (Compton,
 //     + photoelectric, + Rayleigh, + pair) per unit density on the log-E
 //     grid, and the cumulative integral of the molecule's squared form factor
-//     for sampling the Rayleigh angle.
+//     for sampling the Rayleigh angle;
+//   * with optional electron hard events (Moller delta rays, bremsstrahlung):
+//     R(T) of the continuous loss left below the cut-offs (the collision
+//     stopping power restricted to transfers below the electron cut-off, the
+//     radiative loss to photons below the photon cut-off) and the hard-event
+//     cross-sections per unit density on the range table's grid.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.hpp"
 
@@ -66,17 +73,86 @@ double bethe(double t, bool dens) {
     return 2.0 * kPi * kRe * kRe * kMe * kNa * kZoverA * (lg + fm - d) / b2;
 }
 
+// ---- optional electron hard events (water) ------------------------------------
+constexpr double kAlphaFs = 7.2973525693e-3;
+constexpr double kZZ1Water = 76.0;              // sum of Z (Z + 1) over H2O
+
+// Collision stopping power restricted to energy transfers below tc (ICRU 37,
+// the Rohrlich-Carlson F-(tau, Delta), Delta = tc / mc^2 at most tau / 2).
+double bethe_restricted(double t, double tc, bool dens) {
+    const double tau = t / kMe, gamma = 1.0 + tau, b2 = 1.0 - 1.0 / (gamma * gamma);
+    const double ir = kIwater / kMe;
+    const double dl = std::min(tc / kMe, 0.5 * tau);
+    const double fm = -1.0 - b2 + std::log((tau - dl) * dl) + tau / (tau - dl) +
+                      (0.5 * dl * dl + (2.0 * tau + 1.0) * std::log(1.0 - dl / tau)) / (gamma * gamma);
+    const double d = dens ? density_delta(t) : 0.0;
+    return 2.0 * kPi * kRe * kRe * kMe * kNa * kZoverA *
+           (std::log(2.0 * (tau + 2.0) / (ir * ir)) + fm - d) / b2;
+}
+
+// Moller collisions transferring [tc, t/2] per unit density (cm^2/g), the
+// closed form of the Moller cross-section's integral.
+double moller_sigma(double t, double tc) {
+    if (!(t > 2.0 * tc)) return 0.0;
+    const double tau = t / kMe, gamma = 1.0 + tau, b2 = 1.0 - 1.0 / (gamma * gamma);
+    const double ec = tc / t, a = tau / gamma;
+    const double br = 1.0 / ec - 1.0 / (1.0 - ec) + a * a * (0.5 - ec) -
+                      (2.0 * tau + 1.0) / (gamma * gamma) * std::log((1.0 - ec) / ec);
+    return kNa * kZoverA * 2.0 * kPi * kRe * kRe * kMe / (b2 * t) * br;
+}
+
+// k dsigma/dk of bremsstrahlung in water per unit density (cm^2/g): the
+// Bethe-Heitler Born spectrum without screening (Koch and Motz formula 3BN),
+// Z^2 replaced by the molecule's sum of Z (Z + 1); energies in mc^2 inside.
+double brem_kdsig(double t, double k_mev) {
+    const double e0 = 1.0 + t / kMe, k = k_mev / kMe, e = e0 - k;
+    if (!(k > 0.0) || !(e > 1.0)) return 0.0;
+    const double p0 = std::sqrt(e0 * e0 - 1.0), p = std::sqrt(e * e - 1.0);
+    const double L = 2.0 * std::log((e0 * e + p0 * p - 1.0) / k);
+    const double l0 = std::log((e0 + p0) / (e0 - p0)), l = std::log((e + p) / (e - p));
+    const double p02 = p0 * p0, p2 = p * p, p03 = p02 * p0, p3 = p2 * p;
+    const double br = 4.0 / 3.0 - 2.0 * e0 * e * (p2 + p02) / (p2 * p02) + l0 * e / p03 +
+                      l * e0 / p3 - l * l0 / (p0 * p) +
+                      L * (8.0 * e0 * e / (3.0 * p0 * p) + k * k * (e0 * e0 * e * e + p02 * p2) / (p03 * p3) +
+                           k / (2.0 * p0 * p) *
+                               (l0 * (e0 * e + p02) / p03 - l * (e0 * e + p2) / p3 +
+                                2.0 * k * e0 * e / (p2 * p02)));
+    const double v = (p / p0) * br;
+    return v > 0.0 ? kZZ1Water * kAlphaFs * kRe * kRe * kNa / 18.0153 * v : 0.0;
+}
+
+// The continuous stopping power the range tables integrate: Bethe, or with
+// the hard events on, the restricted collision part plus the radiative loss
+// to photons below kc (`soft`, tabulated on log-spaced nodes and linear in
+// ln T between them: at these cut-offs it is below 1e-3 of the total).
+struct ContStop {
+    bool dens = false, restrict_col = false;
+    double tcut = 0.0;
+    std::vector<double> soft;   // at exp(ls0 + i dls)
+    double ls0 = 0.0, dls = 1.0;
+    double operator()(double t) const {
+        double s = restrict_col ? bethe_restricted(t, tcut, dens) : bethe(t, dens);
+        if (!soft.empty()) {
+            double x = (std::log(t) - ls0) / dls;
+            x = std::min(std::max(x, 0.0), double(soft.size() - 1) - 1e-9);
+            const int i = int(x);
+            s += soft[i] + (x - i) * (soft[i + 1] - soft[i]);
+        }
+        return s;
+    }
+};
+
 // Simpson integral of 1/S over [a, b] with m (even) panels; with the density
 // effect the integrand has a kink where delta leaves zero (x0) and another at
 // x1, and an interval across one is split there.
-double inv_s_integral(double a, double b, int m, bool dens) {
-    if (dens) {
+double inv_s_integral(double a, double b, int m, const ContStop& S) {
+    if (S.dens) {
         for (double k : {t_at_x(kX0), t_at_x(kX1)})
-            if (a < k && k < b) return inv_s_integral(a, k, m, dens) + inv_s_integral(k, b, m, dens);
+            if (a < k && k < b) return inv_s_integral(a, k, m, S) + inv_s_integral(k, b, m, S);
     }
     const double h = (b - a) / m;
-    double s = 1.0 / bethe(a, dens) + 1.0 / bethe(b, dens);
-    for (int i = 1; i < m; ++i) s += (i % 2 ? 4.0 : 2.0) / bethe(a + i * h, dens);
+    double s = 1.0 / S(a) + 1.0 / S(b);
+    for (int i = 1; i < m; ++i) s += (i % 2 ? 4.0 : 2.0) / S(a + i * h);
     return s * h / 3.0;
 }
 
@@ -167,13 +243,17 @@ double rayleigh_molecule(double e) {
 void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     PSL_CHECK(p->density_effect == 0 || p->density_effect == 1, "density_effect must be 0 or 1");
     const bool dens = p->density_effect == 1;
-    PSL_CHECK((p->physics & ~(kPhysPhoto | kPhysRayleigh | kPhysPair)) == 0,
+    PSL_CHECK((p->physics & ~(kPhysPhoto | kPhysRayleigh | kPhysPair | kPhysDelta | kPhysBrem)) == 0,
               "physics: unknown process bits 0x%x", p->physics);
+    const uint32_t hard = p->physics & (kPhysDelta | kPhysBrem);
+    PSL_CHECK(!(hard & kPhysBrem) || (p->e_cut_photon > 1e-3f && p->e_cut_photon < p->e_cut_electron * 50.f),
+              "bremsstrahlung needs e_cut_photon in (0.001 MeV, 50 e_cut_electron)");
     PSL_CHECK(!(p->physics & kPhysPair) || p->e_cut_electron <= float(kMe),
               "pair production needs e_cut_electron <= mc^2 (every push then costs the "
               "photon at least the cut-off)");
+    const float kc_key = (hard & kPhysBrem) ? p->e_cut_photon : 0.f;
     if (ph->t_cut_tab == p->e_cut_electron && ph->dens_tab == p->density_effect &&
-        ph->phys_tab == int32_t(p->physics) && ph->tabs.p)
+        ph->phys_tab == int32_t(p->physics) && ph->kc_tab == kc_key && ph->tabs.p)
         return;
     const double tcut = p->e_cut_electron;
     PSL_CHECK(tcut > 2.0e-3 && tcut < 10.0, "e_cut_electron must be in (0.002, 10) MeV");
@@ -187,10 +267,12 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
 
     const uint32_t phys = p->physics;
     // layout: kn, rng, inv, then (optional processes) xs as float4 (kept
-    // 16-byte aligned), ray_t, ray_a
+    // 16-byte aligned), ray_t, ray_a, then (electron hard events) the hard
+    // cross-sections as float2
     const size_t base = size_t(KN_TAB_N) + RNG_TAB_N + INV_TAB_N;
     const size_t extra = phys ? size_t(4) * KN_TAB_N + 2 * RAY_TAB_N : 0;
-    std::vector<float> host(base + extra);
+    const size_t extra_h = hard ? size_t(2) * RNG_TAB_N : 0;
+    std::vector<float> host(base + extra + extra_h);
     float* kn = host.data();
     float* rng = kn + KN_TAB_N;
     float* inv = rng + RNG_TAB_N;
@@ -199,6 +281,22 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     const double le0 = std::log(kEmin), dle = (std::log(kEmax) - le0) / (KN_TAB_N - 1);
     for (int i = 0; i < KN_TAB_N; ++i) kn[i] = float(ne * klein_nishina(std::exp(le0 + i * dle)));
 
+    // the continuous stopping power
+    ContStop S;
+    S.dens = dens;
+    S.restrict_col = (hard & kPhysDelta) != 0u;
+    S.tcut = tcut;
+    const double kc = p->e_cut_photon;
+    if (hard & kPhysBrem) {
+        const int ns = 256;
+        S.ls0 = std::log(tcut);
+        S.dls = (std::log(kTmax) - S.ls0) / (ns - 1);
+        S.soft.resize(ns);
+        for (int i = 0; i < ns; ++i) {
+            const double t = std::exp(S.ls0 + i * S.dls), top = std::min(kc, t);
+            S.soft[i] = log_simpson([&](double k) { return brem_kdsig(t, k); }, top * 1e-12, top, 400);
+        }
+    }
     // fine FP64 range table on a log grid, 16 Simpson panels per interval
     const int fine = 16 * (RNG_TAB_N - 1) + 1;
     const double lt0 = std::log(tcut), dlf = (std::log(kTmax) - lt0) / (fine - 1);
@@ -207,7 +305,7 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     rf[0] = 0.0;
     for (int i = 1; i < fine; ++i) {
         tf[i] = std::exp(lt0 + i * dlf);
-        rf[i] = rf[i - 1] + inv_s_integral(tf[i - 1], tf[i], 8, dens);
+        rf[i] = rf[i - 1] + inv_s_integral(tf[i - 1], tf[i], 8, S);
     }
     for (int i = 0; i < RNG_TAB_N; ++i) rng[i] = float(rf[size_t(i) * 16]);
     // inverse on u = ln(R + R_off): monotone interpolation in the fine table,
@@ -222,8 +320,8 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
         while (k + 1 < size_t(fine) - 1 && rf[k + 1] < r) ++k;
         double t = tf[k] + (tf[k + 1] - tf[k]) * (r - rf[k]) / (rf[k + 1] - rf[k]);
         for (int it = 0; it < 4; ++it) {
-            const double rt = rf[k] + inv_s_integral(tf[k], t, 8, dens);
-            t -= (rt - r) * bethe(t, dens);
+            const double rt = rf[k] + inv_s_integral(tf[k], t, 8, S);
+            t -= (rt - r) * S(t);
         }
         inv[i] = float(t);
     }
@@ -261,6 +359,19 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
             prev = t;
         }
     }
+    if (hard) {
+        // hard-event cross-sections at the range table's nodes
+        float* hx = host.data() + base + extra;
+        for (int i = 0; i < RNG_TAB_N; ++i) {
+            const double t = std::exp(lt0 + i * 16 * dlf);
+            const double sm = (hard & kPhysDelta) ? moller_sigma(t, tcut) : 0.0;
+            const double sbr = (hard & kPhysBrem) && t > kc
+                                   ? log_simpson([&](double k) { return brem_kdsig(t, k) / k; }, kc, t, 400)
+                                   : 0.0;
+            hx[2 * i + 0] = float(sm);
+            hx[2 * i + 1] = float(sm + sbr);
+        }
+    }
     ph->tabs.upload(host);
     PhysicsDev& d = ph->phys;
     d.kn_lne0 = float(le0);
@@ -284,6 +395,8 @@ void ensure_physics(psl_phantom* ph, const psl_transport_params* p) {
     d.ray_inv_dlt = float(1.0 / ray_dlt);
     d.ka0_per_mev = float(kBohr / kHbarC);
     d.photo_bind = float(kZ1s * kZ1s * kRydberg);
+    d.hard = hard ? reinterpret_cast<const float2*>(d.kn + base + extra) : nullptr;
+    ph->kc_tab = kc_key;
     ph->t_cut_tab = p->e_cut_electron;
     ph->dens_tab = p->density_effect;
     ph->phys_tab = int32_t(phys);

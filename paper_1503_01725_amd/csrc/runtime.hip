@@ -128,7 +128,9 @@ struct Runner {
             rep.alloc(256);
         }
     }
-    void ensure_stacks(int n_pipes, uint32_t ph, uint32_t el, bool pair) {
+    void ensure_stacks(int n_pipes, uint32_t ph, uint32_t el, uint32_t physics) {
+        const bool pair = (physics & kPhysPair) != 0u;
+        const bool hard = (physics & (kPhysDelta | kPhysBrem)) != 0u;
         for (int i = 0; i < n_pipes; ++i) {
             Pipe& p = pipes[i];
             if (ph > p.ph_cap) {
@@ -142,11 +144,15 @@ struct Runner {
                 p.el_cap = el;
             }
             const uint32_t need = std::max(p.ph_cap, p.el_cap);
-            const uint32_t ann = pair ? 2u * p.ph_cap : 0u;
-            if (p.ws.perm_cap < need || p.ws.ann_cap < ann) {
+            uint32_t ann = pair ? 2u * p.ph_cap : 0u;
+            // bremsstrahlung photons of an electron pass: at most one stack
+            // entry per electron the pass may hold
+            if (physics & kPhysBrem) ann = std::max(ann, need);
+            const uint32_t del = hard ? need : 0u;
+            if (p.ws.perm_cap < need || p.ws.ann_cap < ann || p.ws.del_cap < del) {
                 drop_graph();
                 p.ws = alloc_transport_ws(p.ws_mem, std::max(need, p.ws.perm_cap),
-                                          std::max(ann, p.ws.ann_cap));
+                                          std::max(ann, p.ws.ann_cap), std::max(del, p.ws.del_cap));
             }
         }
     }
@@ -246,7 +252,7 @@ void enqueue(Runner& R, psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
             }
             launch_transport(ph, &P.phs, &P.els, tally, P.ws, prm, o.seed, q,
                              o.sort_electrons != 0, o.lane_load > 0 ? o.lane_load : 4,
-                             o.timing ? &ev : nullptr);
+                             o.timing ? &ev : nullptr, o.max_batch);
         }
     }
     PSL_HIP(hipGetLastError());
@@ -287,8 +293,7 @@ void run_impl(psl_plan* plan, const psl_phantom* ph, psl_tally* tally,
                   double(plan->n_hist) * double(plan->n_replica) < double(uint64_t(1) << 48),
               "pair production needs history ids below 2^48");
     PSL_CHECK(o.max_batch <= (1u << 30), "max_batch too large");
-    R.ensure_stacks(n_pipes_of(o, plan), o.max_batch, uint32_t(el_need),
-                    (prm->physics & kPhysPair) != 0u);
+    R.ensure_stacks(n_pipes_of(o, plan), o.max_batch, uint32_t(el_need), prm->physics);
     ensure_physics(const_cast<psl_phantom*>(ph), prm);
     ensure_device(plan);
 

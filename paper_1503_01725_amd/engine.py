@@ -191,7 +191,7 @@ class Tally:
         names_l = ("src", "jaw", "missed", "invalid", "esc_g", "esc_e", "dep", "e_path")
         names_c = ("hist", "entered", "wc_steps", "real", "e_pushed", "e_local", "e_steps",
                    "deposits", "esc_uncollided", "kahn_trials", "e_boundary", "guard", "overflow",
-                   "folds", "photo", "rayleigh", "pair", "annihil")
+                   "folds", "photo", "rayleigh", "pair", "annihil", "moller", "brem", "capped")
         out = dict(zip(names_l, led.tolist())), dict(zip(names_c, cnt[:len(names_c)].tolist()))
         if rc != N.PSL_OK:
             raise N.PslError(rc, N.lib().psl_last_error().decode())
@@ -240,7 +240,8 @@ class Particles:
 def transport_params(e_cut_electron=0.2, e_cut_photon=0.01, step_frac=0.1, ms=True,
                      density_effect=False, physics=0):
     """psl_transport_params; physics: PSL_PHYS_* bits of the optional photon
-    processes (photoelectric 1, Rayleigh 2, pair 4; 0 = Compton only)."""
+    processes (photoelectric 1, Rayleigh 2, pair 4) and electron hard events
+    (Moller delta rays 8, bremsstrahlung 16); 0 = the plain method."""
     return N.psl_transport_params(e_cut_electron, e_cut_photon, step_frac, 1 if ms else 0,
                                   1 if density_effect else 0, int(physics))
 

@@ -34,7 +34,8 @@ def _agreement(d1, s1, d2, s2):
     return (np.abs(d1 - d2) < 2 * sd)[hi].mean(), hi.sum()
 
 
-@pytest.mark.parametrize("physics", [1, 2, 4, 7], ids=["photo", "rayleigh", "pair", "all"])
+@pytest.mark.parametrize("physics", [1, 2, 4, 7, 8, 16, 31],
+                         ids=["photo", "rayleigh", "pair", "photons", "delta", "brem", "all"])
 def test_dose_with_process_matches_oracle(eng, orc, wl, physics):
     """The 6 MV-like source on the 60^3 water phantom (1e5 histories in 10
     replicas) with each optional process switched on, and all together."""
@@ -65,12 +66,14 @@ def test_dose_with_process_matches_oracle(eng, orc, wl, physics):
     assert led["dep"] == pytest.approx(led_r["dep"], rel=1e-3)
     frac, nvox = _agreement(d, sg, d_r, sg_r)
     assert nvox > 1000 and frac >= 0.95, frac
-    for k, bit in (("photo", 1), ("rayleigh", 2), ("pair", 4), ("annihil", 4)):
+    for k, bit in (("photo", 1), ("rayleigh", 2), ("pair", 4), ("moller", 8), ("brem", 16)):
         if physics & bit:
             assert cnt_r[k] > 0
             assert _counts_agree(cnt[k], cnt_r[k]), (k, cnt[k], cnt_r[k])
         else:
             assert cnt[k] == 0
+    assert _counts_agree(cnt["annihil"], cnt_r["annihil"]), (cnt["annihil"], cnt_r["annihil"])
+    assert _counts_agree(cnt["capped"], cnt_r["capped"]) and cnt["overflow"] == 0
     assert _counts_agree(cnt["real"], cnt_r["real"], rel=2e-3)
     assert _counts_agree(cnt["e_pushed"], cnt_r["e_pushed"], rel=2e-3)
 
@@ -131,13 +134,15 @@ def test_monoenergetic_pencil_matches_oracle(eng, N, orc, wl, e, physics):
         assert cnt["pair"] > 100 and cnt["annihil"] > 0
 
 
-def test_full_physics_graph_equals_eager(eng, wl):
-    """The batched runtime with every process (annihilation photons in a
-    second photon pass per batch), replayed from a captured graph, gives the
-    eager public-call loop's result."""
+@pytest.mark.parametrize("physics", [7, 31], ids=["photons", "all"])
+def test_full_physics_graph_equals_eager(eng, wl, physics):
+    """The batched runtime with every photon process (annihilation photons in
+    a second photon pass per batch), and with the electron hard events too
+    (three more generations of passes), replayed from a captured graph, gives
+    the eager public-call loop's result."""
     import torch
     W = wl.workload("water60_10x10")
-    prm = eng.transport_params(physics=7)
+    prm = eng.transport_params(physics=physics)
     model = eng.Model(W.model)
     plan = eng.Plan(model, W.beams, 20000, n_replica=2)
     ph = eng.Phantom(W.phantom)
@@ -155,7 +160,8 @@ def test_full_physics_graph_equals_eager(eng, wl):
     torch.cuda.synchronize()
     led2, cnt2 = t2.stats()
     assert abs(_closure(led2)) < 1e-5
-    for k in ("photo", "rayleigh", "pair", "annihil", "real", "e_pushed", "e_steps", "deposits"):
+    for k in ("photo", "rayleigh", "pair", "annihil", "moller", "brem", "capped", "real",
+              "e_pushed", "e_steps", "deposits"):
         assert cnt2[k] == cnt1[k], k
     assert led2["dep"] == pytest.approx(led1["dep"], rel=1e-6)
     hi = d1 > 0.01 * d1.max()
@@ -164,7 +170,8 @@ def test_full_physics_graph_equals_eager(eng, wl):
 
 def test_pair_needs_cutoff_below_electron_mass(eng, N, wl):
     """Pair production with an electron cut-off above mc^2 is refused: every
-    push must cost the photon at least the cut-off for the stack bound."""
+    push must cost the photon at least the cut-off for the stack bound.  An
+    unknown process bit is refused too."""
     ph = eng.Phantom(wl.water_phantom(8, 1.0))
     tally = eng.Tally(ph)
     st = eng.Particles(64)
@@ -176,5 +183,59 @@ def test_pair_needs_cutoff_below_electron_mass(eng, N, wl):
                           eng._stream_ptr())
     assert e.value.code == N.PSL_EINVAL and "pair" in str(e.value)
     with pytest.raises(N.PslError):
-        N.transport_batch(ph.h, st.c, el.c, tally.h, eng.transport_params(physics=8), 1,
+        N.transport_batch(ph.h, st.c, el.c, tally.h, eng.transport_params(physics=32), 1,
                           eng._stream_ptr())
+
+
+def _electron_pencil(eng, n, e, cap):
+    import torch
+    st = eng.Particles(cap)
+    for f, v in (("x", 0.1), ("y", -0.2), ("z", 0.0), ("u", 0.0), ("v", 0.0), ("w", 1.0), ("e", e)):
+        st.t[f][:] = v
+    st.t["hid"][:] = torch.arange(cap)
+    st.t["tag"][:] = 0
+    st.t["count"][:] = n
+    st.c.ptype = 1
+    return st
+
+
+@pytest.mark.parametrize("physics", [8, 16, 24, 31], ids=["delta", "brem", "delta_brem", "all"])
+def test_electron_pencil_hard_events_match_oracle(eng, N, orc, wl, physics):
+    """6 MeV electrons along +z into a 24 cm water cube through
+    transport_batch, with Sec. 2.3's cut-offs (0.2 MeV electrons, 0.05 MeV
+    photons): Moller delta electrons and bremsstrahlung photons followed for
+    three generations.  Ledger, deposited energy and event counts against the
+    oracle on the same streams (the GPU reads cross-sections from FP32
+    tables, so a decision can tip where a uniform falls within table accuracy
+    of its boundary; after that the trajectories are independent samples)."""
+    import torch
+    phs = wl.water_phantom(24, 1.0)
+    n = 20000
+    print(f"[electron physics] oracle 6 MeV electron pencil physics={physics}", flush=True)
+    _, led_r, cnt_r = orc.transport(phs, 9, np.ones(n), np.tile([0.1, -0.2, 0.0], (n, 1)),
+                                    np.tile([0.0, 0.0, 1.0], (n, 1)), np.full(n, 6.0),
+                                    np.arange(n, dtype=np.uint64),
+                                    tparams=orc.params(e_cut_e=0.2, e_cut_g=0.05, physics=physics))
+    print(f"[electron physics] gpu 6 MeV electron pencil physics={physics}", flush=True)
+    ph = eng.Phantom(phs)
+    tally = eng.Tally(ph)
+    # room for the delta electrons of a generation (about one per electron)
+    st = _electron_pencil(eng, n, 6.0, 4 * n)
+    el = eng.Particles(64)
+    N.transport_batch(ph.h, st.c, el.c, tally.h,
+                      eng.transport_params(0.2, 0.05, physics=physics), 9, eng._stream_ptr())
+    torch.cuda.synchronize()
+    led, cnt = tally.stats()
+    print(f"[electron physics] dep {led['dep']:.2f} / {led_r['dep']:.2f} esc_g {led['esc_g']:.2f} / "
+          f"{led_r['esc_g']:.2f}; moller {cnt['moller']} / {cnt_r['moller']}, brem {cnt['brem']} / "
+          f"{cnt_r['brem']}, capped {cnt['capped']} / {cnt_r['capped']}, e_pushed "
+          f"{cnt['e_pushed']} / {cnt_r['e_pushed']}", flush=True)
+    src = 6.0 * n
+    assert abs(led["esc_g"] + led["esc_e"] + led["dep"] - src) < 1e-5 * src
+    assert led["dep"] == pytest.approx(led_r["dep"], rel=3e-3)
+    assert led["esc_g"] == pytest.approx(led_r["esc_g"], rel=0.05, abs=2.0)
+    for k in ("moller", "brem", "capped", "e_pushed", "pair", "annihil", "real"):
+        assert _counts_agree(cnt[k], cnt_r[k], rel=0.02), (k, cnt[k], cnt_r[k])
+    assert (cnt["moller"] > n // 2) == bool(physics & 8)
+    assert (cnt["brem"] > n // 10) == bool(physics & 16)
+    assert cnt["overflow"] == 0
