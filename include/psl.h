@@ -447,8 +447,9 @@ int psl_autotune(psl_plan* plan, const psl_phantom* phantom, psl_tally* tally,
  * ------------------------------------------------------------------------ */
 
 /* FP32 atomic adds of 1.0 (result unused) into grid_dev[addr_dev[i]] for
- * i < n, the instruction the dose tally uses (Sec. 2.1.3: every deposit goes
- * into the shared grid); addresses outside [0, cells) are skipped.  Runs one
+ * i < n, the instruction the dose tally uses (every deposit of the transport
+ * kernels goes into the shared FP32 replica grid; the paper does not
+ * describe its tally); addresses outside [0, cells) are skipped.  Runs one
  * warm-up and `repeats` timed launches on a private stream and writes the
  * average milliseconds per launch to *ms_out.  grid_dev (device FP32
  * [cells]) accumulates every launch.  Synchronous. */
