@@ -36,6 +36,9 @@ def test_graph_run_equals_eager_loop(eng, N, wl):
         assert led["dep"] == pytest.approx(led0["dep"], rel=1e-6)
         hi = d0 > 0.01 * d0.max()
         assert np.allclose(d[hi], d0[hi], rtol=1e-4)
+        # sigma comes from the per-replica folds: each replica's energies
+        # must reach the fold of that replica (two pipelines alternate two grids)
+        assert np.allclose(s[hi], s0[hi], rtol=1e-3)
 
 
 def test_graph_recaptured_after_tables_rebuilt(eng, N, wl):
@@ -115,25 +118,31 @@ def test_grid_size_does_not_change_the_physics(eng, N, wl):
     size (lane_load), the number of concurrent batch pipelines and graph
     replay change which lane runs a history and when, but not what it
     computes: every integer event counter is identical, and the dose agrees to
-    FP32 atomic-add rounding."""
+    FP32 atomic-add rounding.  Five replicas, so that with two pipelines the
+    two replica grids are each reused (replicas 2 and 4 wait for the folds of
+    0 and 2); the standard deviation, which the per-replica folds give, agrees
+    too."""
     import torch
-    W, model, plan, ph, tally = _setup(eng, wl, n_rep=2)
+    W, model, plan, ph, tally = _setup(eng, wl, n_rep=5)
     prm = eng.transport_params()
     out = []
     for ll, pipes, graph in ((1, 1, False), (3, 2, False), (64, 2, True), (3, 1, True)):
+        print(f"[runtime] lane_load {ll} pipelines {pipes} graph {graph}", flush=True)
         tally.op(N.PSL_TALLY_RESET)
         eng.run_plan(plan, ph, tally, prm, eng.run_opts(8192, 4, use_graph=graph, seed=17,
                                                         lane_load=ll, pipelines=pipes))
-        d, _ = tally.finalize(plan)
+        d, sg = tally.finalize(plan)
         torch.cuda.synchronize()
         led, cnt = tally.stats()
-        out.append((d.cpu().numpy(), led, cnt))
-    d0, led0, cnt0 = out[0]
-    for d, led, cnt in out[1:]:
+        out.append((d.cpu().numpy(), sg.cpu().numpy(), led, cnt))
+    d0, s0, led0, cnt0 = out[0]
+    assert cnt0["folds"] == 5
+    for d, sg, led, cnt in out[1:]:
         assert cnt == cnt0
         assert led["dep"] == pytest.approx(led0["dep"], rel=1e-9)
         hi = d0 > 0.05 * d0.max()
         assert np.max(np.abs(d[hi] - d0[hi]) / d0[hi]) < 1e-4
+        assert np.max(np.abs(sg[hi] - s0[hi]) / s0[hi]) < 1e-2
 
 
 @pytest.mark.parametrize("seed", [0, 1])
