@@ -22,7 +22,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--hist-per-basis", type=int, default=10 ** 6)
     ap.add_argument("--noise", type=float, default=0.005)
-    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--max-iter", type=int, default=200000)
     ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
 
@@ -67,8 +67,13 @@ def main():
     Au = Af[:, used]
     x_true, b = wl.commissioning_target(Au, W.seed, noise_rel=args.noise)
     scale = float(b.max())
+    # the solver sees unit-norm columns (y = x |A_j|, an exact change of
+    # variables that keeps y >= 0): the basis doses span orders of magnitude,
+    # and gradient projection on the unscaled matrix is far slower
+    cn = np.linalg.norm(Au, axis=0)
     t0 = time.perf_counter()
-    x, rep = eng.commission_nnls(Au / scale, b / scale, max_iter=args.max_iter)
+    y, rep = eng.commission_nnls(Au / cn, b / scale, x0=cn / scale, max_iter=args.max_iter)
+    x = y * scale / cn
     t_nnls = time.perf_counter() - t0
     fit = Au @ x
     out = {"histories": int(plan.n_hist), "rows": int(Af.shape[0]), "bases": int(used.sum()),

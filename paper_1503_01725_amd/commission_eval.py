@@ -248,9 +248,9 @@ def basis_doses(eng, model_src, fields, hist_per_basis, seed, phantom, opts, prm
 
 
 def scaled_system(A: np.ndarray, b: np.ndarray, D=None, smooth: float = 0.0):
-    """The least-squares system the solver sees: used columns (some row sees
-    them) scaled to unit norm and b by its maximum, so y = x * cn over the used
-    bases.  With smooth > 0 the rows sqrt(smooth) * D follow; an unused basis
+    """The least-squares system the solver sees: the used columns (some row
+    sees them) scaled to unit norm, then the whole system divided by b's
+    maximum, so y = x * cn over the used bases.  With smooth > 0 the rows sqrt(smooth) * D follow; an unused basis
     keeps its factor 1, which moves to the right-hand side.  Then
     |A1 y - b1|^2 = |A x - b|^2 / scale^2 + smooth |D x|^2."""
     used = np.abs(A).max(axis=0) > 0
@@ -276,7 +276,7 @@ def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int, D=None, smooth: float 
     return x, used, rep
 
 
-def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_iter=100000,
+def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_iter=300000,
              seed=20150306, smooth=0.0, log=print) -> dict:
     """The whole experiment; returns the result dictionary printed by main()."""
     from . import engine as eng
@@ -360,7 +360,7 @@ def main():
                     help="histories per field of the reference and commissioned models")
     ap.add_argument("--hist-measured", type=float, default=1e10,
                     help="histories per field of the measured beam")
-    ap.add_argument("--max-iter", type=int, default=100000)
+    ap.add_argument("--max-iter", type=int, default=300000)
     ap.add_argument("--seed", type=int, default=20150306)
     ap.add_argument("--smooth", type=float, default=0.0,
                     help="weight of the ring-to-ring smoothness term of the fit (0 = Eq. 8 alone)")
