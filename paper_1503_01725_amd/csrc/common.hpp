@@ -89,7 +89,7 @@ struct DevBuf {
 
 // Scratch of one transport pipeline: the two work-queue heads, the band
 // counters / offsets of the electron energy sort and the electron order.
-constexpr int kSortBands = 32;      // electron energy bands of the counting sort
+constexpr int kSortBands = 8;       // electron energy bands of the counting sort
 constexpr int kSortBlocks = 1024;   // fixed grid of the counting sort
 // Histories per entry of a plan's chunk index (the sampling kernel's search
 // starts from it).

@@ -253,16 +253,24 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct WaveQueue {
     uint32_t base, left, dyn0;   // dyn0: first entry of the dynamic part
+    uint32_t wave, waves, share;
     bool drained;
     __device__ explicit WaveQueue(uint32_t n) {
         const uint32_t per_block = blockDim.x >> 6;
-        const uint32_t waves = gridDim.x * per_block;
-        const uint32_t w = blockIdx.x * per_block + (threadIdx.x >> 6);
-        const uint32_t share = uint32_t(uint64_t(n) * 3u / 4u / waves);
-        base = w * share;
+        waves = gridDim.x * per_block;
+        wave = blockIdx.x * per_block + (threadIdx.x >> 6);
+        share = uint32_t(uint64_t(n) * 3u / 4u / waves);
+        base = wave * share;
         left = share;
         dyn0 = waves * share;
         drained = false;
+    }
+    // Stack position of queue entry q when the stack is ordered longest work
+    // first: the static shares interleave (the wave's t-th entry is position
+    // t * waves + wave), so that every wave gets the same mix and starts with
+    // its longest histories; the dynamic part keeps its order.
+    __device__ __forceinline__ uint32_t strided(uint32_t q) const {
+        return q < dyn0 ? (q - wave * share) * waves + wave : q;
     }
 };
 
@@ -1206,7 +1214,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
             const unsigned long long idle = __ballot(!alive);
             const bool refill = __popcll(idle) >= kRefillLanes || idle == ~0ull;
             const uint32_t q = refill ? take_work(!alive, wq, a.queue + 1, n) : kNone;
-            const uint32_t i = q != kNone ? (a.perm ? a.perm[q] : q) : 0u;
+            const uint32_t i = q != kNone ? (a.perm ? a.perm[wq.strided(q)] : q) : 0u;
             uint32_t tg = 1u << 24;
             float nx = 0.f, ny = 0.f, nz = 0.f, nu = 0.f, nv = 0.f, nw = 0.f, ne = 0.f;
             uint64_t g = 0;
