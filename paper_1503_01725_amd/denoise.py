@@ -356,6 +356,62 @@ def bench_unet(width=32, n=128, iters=10, log=print):
     return out
 
 
+def measure_time_to_1pct(k, n=128, n_high=1e9, n0=1e6, log=None):
+    """The plain engine's time to 1 % sigma, run rather than extrapolated, on
+    the first k test cases: sigma_rel at n0 histories predicts
+    N = n0 (sigma_rel / 0.01)^2; the engine then runs N histories (4
+    replicas, timed after a warm-up run of the same plan) and sigma_rel is
+    measured on that dose; while it is still above 1 %, N grows by the same
+    rule with a 2 % margin (at most two more runs).  Also the RMS error (% of Dmax, all voxels) of that dose
+    against an n_high reference."""
+    import torch
+    log = log or (lambda m: print(m, file=sys.stderr, flush=True))
+    from . import engine as eng
+    model_src = wl.psr_model(20150306)
+    rows = []
+    for s in range(5000, 5000 + k):
+        ph, beam = case_geometry(s, n)
+        E = DoseEngine(model_src, ph, beam, s)
+        d0, s0 = E.dose(int(n0), n_rep=4, seed_offset=3)
+        n_pred = n0 * (sigma_rel(d0.cpu().numpy(), s0.cpu().numpy()) / 0.01) ** 2
+        runs = []
+        n_run = int(math.ceil(n_pred))
+        for attempt in range(3):
+            per = max(1, n_run // 4)
+            plan = eng.Plan(E.model, [beam], per, n_replica=4)
+            tally = eng.Tally(E.phantom)
+            opts = eng.run_opts(1 << 22, 24, use_graph=False, seed=s * 1000003 + 17,
+                                lane_load=32, pipelines=2, sort_electrons=False)
+            eng.run_plan(plan, E.phantom, tally, E.prm, opts)      # warm-up
+            torch.cuda.synchronize()
+            tally.op(eng.N.PSL_TALLY_RESET)
+            t0 = time.perf_counter()
+            eng.run_plan(plan, E.phantom, tally, E.prm, opts)
+            d, sd = tally.finalize(plan)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            dn, sdn = d.float().cpu().numpy(), sd.float().cpu().numpy()
+            sr = sigma_rel(dn, sdn)
+            runs.append({"histories": per * 4, "sigma_rel": sr, "seconds": t})
+            if sr <= 0.01:
+                break
+            n_run = int(math.ceil(per * 4 * (sr / 0.01) ** 2 * 1.02))
+        ref = E.dose(int(n_high), n_rep=1, seed_offset=9)[0].cpu().numpy()
+        row = {"seed": s, "predicted_histories": n_pred, "runs": runs,
+               "rms_percent_dmax": rms_percent(dn, ref),
+               "met": runs[-1]["sigma_rel"] <= 0.01}
+        rows.append(row)
+        log(f"[time-to-1%] case {s}: " + json.dumps(row))
+    last = [r["runs"][-1] for r in rows]
+    return {"cases": rows,
+            "mean_histories": float(np.mean([r["histories"] for r in last])),
+            "mean_seconds": float(np.mean([r["seconds"] for r in last])),
+            "mean_sigma_rel": float(np.mean([r["sigma_rel"] for r in last])),
+            "mean_rms_percent_dmax": float(np.mean([r["rms_percent_dmax"] for r in rows])),
+            "met": int(sum(r["met"] for r in rows)),
+            "mean_predicted_histories": float(np.mean([r["predicted_histories"] for r in rows]))}
+
+
 def rms_percent_region(d, ref, cutoff=GATE_CUTOFF):
     """Eq. (10) over the voxels where the reference exceeds `cutoff` of its
     maximum, in % of that maximum (the region and scale the gate judges)."""
@@ -383,9 +439,14 @@ def main():
     ap.add_argument("--bench", action="store_true",
                     help="only time forward / training step at --width, --n")
     ap.add_argument("--iters", type=int, default=10, help="timed repetitions of --bench")
+    ap.add_argument("--time-to-1pct", type=int, default=0, metavar="K",
+                    help="only measure the plain engine's time to 1 %% sigma on K test cases")
     args = ap.parse_args()
     if args.bench:
         print(json.dumps(bench_unet(args.width, args.n, args.iters)))
+        return
+    if args.time_to_1pct:
+        print(json.dumps(measure_time_to_1pct(args.time_to_1pct, args.n, args.n_high)))
         return
 
     def log(m):
