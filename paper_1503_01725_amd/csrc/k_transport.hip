@@ -253,7 +253,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 
 struct WaveQueue {
     uint32_t base, left, dyn0;   // dyn0: first entry of the dynamic part
-    uint32_t wave, waves, share;
+    uint32_t wave, waves, share, slot;
     bool drained;
     __device__ explicit WaveQueue(uint32_t n) {
         const uint32_t per_block = blockDim.x >> 6;
@@ -264,13 +264,22 @@ struct WaveQueue {
         left = share;
         dyn0 = waves * share;
         drained = false;
+        // the wave's place in the interleave: workgroups go to the eight
+        // XCDs in turn, so the waves of one XCD take neighbouring positions
+        // and share cache lines in that XCD's L2 (a bijection of the waves
+        // whatever the placement)
+        slot = wave;
+        if ((gridDim.x & 7u) == 0u) {
+            const uint32_t xcd = blockIdx.x & 7u, per_xcd = (gridDim.x >> 3) * per_block;
+            slot = xcd * per_xcd + (blockIdx.x >> 3) * per_block + (threadIdx.x >> 6);
+        }
     }
-    // Stack position of queue entry q when the stack is ordered longest work
-    // first: the static shares interleave (the wave's t-th entry is position
-    // t * waves + wave), so that every wave gets the same mix and starts with
-    // its longest histories; the dynamic part keeps its order.
+    // Stack position of queue entry q for a stack ordered roughly longest
+    // work first: the static shares interleave (the wave's t-th entry is
+    // position t * waves + slot), so that every wave gets the same mix and
+    // starts with its longest histories; the dynamic part keeps its order.
     __device__ __forceinline__ uint32_t strided(uint32_t q) const {
-        return q < dyn0 ? (q - wave * share) * waves + wave : q;
+        return q < dyn0 ? (q - wave * share) * waves + slot : q;
     }
 };
 
@@ -1214,7 +1223,7 @@ __global__ void __launch_bounds__(kBlock) k_electron(TransportArgs a, Stack s) {
             const unsigned long long idle = __ballot(!alive);
             const bool refill = __popcll(idle) >= kRefillLanes || idle == ~0ull;
             const uint32_t q = refill ? take_work(!alive, wq, a.queue + 1, n) : kNone;
-            const uint32_t i = q != kNone ? (a.perm ? a.perm[wq.strided(q)] : q) : 0u;
+            const uint32_t i = q != kNone ? (a.perm ? a.perm[wq.strided(q)] : wq.strided(q)) : 0u;
             uint32_t tg = 1u << 24;
             float nx = 0.f, ny = 0.f, nz = 0.f, nu = 0.f, nv = 0.f, nw = 0.f, ne = 0.f;
             uint64_t g = 0;
