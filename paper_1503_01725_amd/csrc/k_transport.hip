@@ -364,9 +364,9 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
     // earlier, rather than those just made.
     for (;;) {
         if (__ballot(alive) == 0ull && wq.drained && wq.left == 0) break;
-        // a flight and its collision test (2), two Kahn trials (6) and the
+        // a flight and its collision test (2), three Kahn trials (9) and the
         // azimuth (1) fit in one iteration
-        st.topup(alive, kFull ? 10 : 9, 12);
+        st.topup(alive, kFull ? 13 : 12, 13);
         // this step's writes, deferred: one deposit, one electron
         int w_v = -1;
         float w_e = 0.f;
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
         }
         if (alive && phase == kKahn) {
             // Kahn's method for x = E/E' in [1, 1 + 2k], three uniforms a
-            // trial, at most two trials per iteration (a photon that needs
+            // trial, at most three trials per iteration (a photon that needs
             // more goes on in the next one, so that the wavefront does not
             // loop for its few unlucky lanes).  Both proposals come from one
             // reciprocal and the lane selects, so the two branches of the
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(kBlock) k_photon(TransportArgs a) {
             const float ik = kMe * hw_rcp(e);
             const float p_a = (1.f + k2) * hw_rcp(9.f + k2);
             const float i1k2 = hw_rcp(1.f + k2);
-            for (int tr = 0; tr < 2 && st.cnt >= 3u; ++tr) {
+            for (int tr = 0; tr < 3 && st.cnt >= 3u; ++tr) {
                 const float r1 = st.pop(), r2 = st.pop(), r3 = st.pop();
                 ++c_kahn;
                 ++trials;
