@@ -547,7 +547,9 @@ int psl_unet_set_params(psl_unet* net, const float* host);
 int psl_unet_get_params(const psl_unet* net, float* host);
 
 /* input_dev: device FP32 [2][d][h][w] (dose scaled by its maximum, density);
- * pred_dev: device FP32 [d][h][w] (scaled dose).  Asynchronous. */
+ * pred_dev: device FP32 [d][h][w] (scaled dose), written directly, must not
+ * overlap input_dev.  Inference only: the last layer's activations, which
+ * only the backward pass reads, are not kept.  Asynchronous. */
 int psl_unet_forward(psl_unet* net, const float* input_dev, float* pred_dev, void* stream);
 
 /* Forward + backward + one Adam step (beta 0.9 / 0.999, eps 1e-8) at learning

@@ -64,6 +64,14 @@ struct GemmArgs {
     int k_per_split;     // wgrad: positions per blockIdx.z
     View pool;           // direct conv fwd: 2x2x2 max-pooled output if pool.p
     uint8_t* arg;        //   and the index (0-7) of each maximum, [P/8][C]
+    // direct conv fwd, one workgroup over all output channels: the 1x1x1 head
+    // pred = dose + head_b + head_w . out per position if head_out (FP32 [P]);
+    // with skip_store the layer's own output is not written
+    const float* head_w;
+    const float* head_b;
+    const float* head_dose;
+    float* head_out;
+    int skip_store;
 };
 
 __device__ __forceinline__ void pos3(int m, int D, int H, int W, int& z, int& y, int& x) {
@@ -605,6 +613,23 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
             }
     }
     __syncthreads();
+    if (MODE == kConvFwd && g.head_out) {
+        // the head from the tile: channels in ascending order, as k_head_fwd
+        for (int p = t; p < 512; p += 256) {
+            const int z = p >> 6, y = (p >> 3) & 7, x = p & 7;
+            const int m = ((bz * kFB + z) * v.H + by * kFB + y) * v.W + bx * kFB + x;
+            float sum = g.head_b[0] + g.head_dose[m];
+#pragma unroll
+            for (int c8 = 0; c8 < NT; c8 += 8) {
+                const uint4 hv = *reinterpret_cast<const uint4*>(&tile[p * kTP + c8]);
+                const uint16_t* he = reinterpret_cast<const uint16_t*>(&hv);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sum += g.head_w[c8 + k] * bf2f(he[k]);
+            }
+            g.head_out[m] = sum;
+        }
+        if (g.skip_store) return;
+    }
     constexpr int kChunks = NT / 8;                 // 16-byte chunks per position
     constexpr int kOut = 512 * kChunks / 256;       // per thread
     const int ch = (t % kChunks) * 8;
@@ -1314,6 +1339,12 @@ bool conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scr
     }
     const bool pooled = mode == kConvFwd && g.pool.p && sh.splits == 1;
     if (!pooled) g.pool.p = nullptr;
+    // the head needs every output channel of a position in one workgroup
+    const bool headed = mode == kConvFwd && g.head_out && sh.splits == 1 && sh.nt == g.N;
+    if (!headed) {
+        g.head_out = nullptr;
+        g.skip_store = 0;
+    }
     PSL_CHECK(g.wfrag, "brick convolution without operand-ordered weights");
     dim3 grid((v.D / kFB) * (v.H / kFB) * (v.W / kFB), g.N / sh.nt, sh.splits);
     if (sh.splits > 1) {
@@ -1341,14 +1372,22 @@ bool conv_launch(int mode, GemmArgs g, hipStream_t s, float* scratch, size_t scr
                                sh.splits);
         PSL_HIP(hipGetLastError());
     }
-    return pooled;
+    return pooled || headed;
 }
 
 // forward conv: in (cin_pad channels view) -> out view, bias, ReLU; with
 // `pool`, also its 2x2x2 max pooling where the kernel can fuse it (returns
 // whether it did)
+struct HeadArgs {
+    const float* w;
+    const float* b;
+    const float* dose;
+    float* out;
+    bool skip_store;
+};
+
 bool conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t s,
-              const View* pool = nullptr, uint8_t* arg = nullptr) {
+              const View* pool = nullptr, uint8_t* arg = nullptr, const HeadArgs* head = nullptr) {
     GemmArgs g{};
     g.a = in;
     g.b = out;
@@ -1364,6 +1403,13 @@ bool conv_fwd(const UNet& u, const UNet::Conv& L, View in, View out, hipStream_t
     if (pool) {
         g.pool = *pool;
         g.arg = arg;
+    }
+    if (head) {
+        g.head_w = head->w;
+        g.head_b = head->b;
+        g.head_dose = head->dose;
+        g.head_out = head->out;
+        g.skip_store = head->skip_store ? 1 : 0;
     }
     return conv_launch(kConvFwd, g, s, u.wpart.as<float>(), u.wpart.bytes / 4);
 }
@@ -1571,8 +1617,11 @@ void pack_all(UNet& u, hipStream_t s) {
     PSL_HIP(hipGetLastError());
 }
 
-// input [2][P0] FP32 -> pred [P0] FP32 (activations kept for the backward pass)
-void forward(UNet& u, const float* input, hipStream_t s) {
+// input [2][P0] FP32 -> pred [P0] FP32 (activations kept for the backward
+// pass unless keep is false: then the last layer's output, which only the
+// head reads, is not written where the head is fused into its convolution)
+void forward(UNet& u, const float* input, hipStream_t s, bool keep = true, float* pred = nullptr) {
+    float* const pred_out = pred ? pred : u.pred.as<float>();
     const int64_t P0 = u.P(0);
     hipLaunchKernelGGL(k_pack_input, dim3(grid1(P0)), dim3(256), 0, s, input, int(P0),
                        u.x0.as<uint16_t>());
@@ -1620,12 +1669,19 @@ void forward(UNet& u, const float* input, hipStream_t s) {
         View a = view(u.dec_a_out[k], u, k, C, C, 0);
         conv_fwd(u, u.dec_a[k], catv, a, s);
         View b = view(u.dec_b_out[k], u, k, C, C, 0);
-        conv_fwd(u, u.dec_b[k], a, b, s);
+        if (k == 0) {
+            // the head in the last convolution's epilogue where it can go
+            const HeadArgs head{u.params.as<float>() + u.head_w, u.params.as<float>() + u.head_b,
+                                input, pred_out, !keep};
+            if (!conv_fwd(u, u.dec_b[k], a, b, s, nullptr, nullptr, &head))
+                hipLaunchKernelGGL(k_head_fwd, dim3(grid1(P0)), dim3(256), 0, s, b,
+                                   u.params.as<float>() + u.head_w,
+                                   u.params.as<float>() + u.head_b, input, int(P0), pred_out);
+        } else {
+            conv_fwd(u, u.dec_b[k], a, b, s);
+        }
         h = b;
     }
-    hipLaunchKernelGGL(k_head_fwd, dim3(grid1(P0)), dim3(256), 0, s, h,
-                       u.params.as<float>() + u.head_w, u.params.as<float>() + u.head_b, input,
-                       int(P0), u.pred.as<float>());
     PSL_HIP(hipGetLastError());
 }
 
@@ -1980,8 +2036,9 @@ extern "C" int psl_unet_forward(psl_unet* net, const float* input, float* pred, 
         PSL_CHECK(net && input && pred, "null argument");
         UNet& u = *unet_cast(net);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        forward(u, input, s);
-        PSL_HIP(hipMemcpyAsync(pred, u.pred.p, size_t(u.P(0)) * 4, hipMemcpyDeviceToDevice, s));
+        // inference only: the prediction straight into the caller's buffer,
+        // the last layer's activations (read only by the backward pass) not kept
+        forward(u, input, s, false, pred);
     });
 }
 
