@@ -362,8 +362,8 @@ def measure_time_to_1pct(k, n=128, n_high=1e9, n0=1e6, log=None):
     N = n0 (sigma_rel / 0.01)^2; the engine then runs N histories (4
     replicas, timed after a warm-up run of the same plan) and sigma_rel is
     measured on that dose; while it is still above 1 %, N grows by the same
-    rule with a 2 % margin (at most two more runs).  Also the RMS error (% of Dmax, all voxels) of that dose
-    against an n_high reference."""
+    rule with a 2 % margin (at most two more runs).  Also the RMS error (% of
+    Dmax, all voxels) of that dose against an n_high reference."""
     import torch
     log = log or (lambda m: print(m, file=sys.stderr, flush=True))
     from . import engine as eng
@@ -376,7 +376,7 @@ def measure_time_to_1pct(k, n=128, n_high=1e9, n0=1e6, log=None):
         n_pred = n0 * (sigma_rel(d0.cpu().numpy(), s0.cpu().numpy()) / 0.01) ** 2
         runs = []
         n_run = int(math.ceil(n_pred))
-        for attempt in range(3):
+        for _ in range(3):
             per = max(1, n_run // 4)
             plan = eng.Plan(E.model, [beam], per, n_replica=4)
             tally = eng.Tally(E.phantom)
