@@ -433,6 +433,8 @@ def main():
     ap.add_argument("--n-high", type=float, default=1e9)
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-decay", type=float, default=0.5,
+                    help="learning rate at the last epoch as a fraction of --lr (geometric)")
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--out", default="out/denoise.json")
     ap.add_argument("--save", default="")
@@ -462,7 +464,7 @@ def main():
     from .unet_init import init_params
     net.set_params(init_params(7, args.width, net.n_params))
     t0 = time.perf_counter()
-    hist = train(net, train_pairs, args.epochs, args.lr, log)
+    hist = train(net, train_pairs, args.epochs, args.lr, log, lr_decay=args.lr_decay)
     t_train = time.perf_counter() - t0
     del train_pairs
     if args.save:
