@@ -247,17 +247,24 @@ def basis_doses(eng, model_src, fields, hist_per_basis, seed, phantom, opts, prm
     return A, rows, plan.n_hist, time.perf_counter() - t0
 
 
-def scaled_system(A: np.ndarray, b: np.ndarray, D=None, smooth: float = 0.0):
-    """The least-squares system the solver sees: the used columns (some row
-    sees them) scaled to unit norm, then the whole system divided by b's
-    maximum, so y = x * cn over the used bases.  With smooth > 0 the rows sqrt(smooth) * D follow; an unused basis
-    keeps its factor 1, which moves to the right-hand side.  Then
+def scaled_system(A: np.ndarray, b: np.ndarray, D=None, smooth: float = 0.0,
+                  min_sens: float = 0.0):
+    """The least-squares system the solver sees: the used columns scaled to
+    unit norm, then the whole system divided by b's maximum, so y = x * cn
+    over the used bases.  A column is used if some row sees it and, with
+    min_sens > 0, if its norm is at least min_sens times the median norm of
+    the seen columns (the data barely constrain the others); an unused basis
+    keeps its factor 1, and its dose moves to the right-hand side.  With
+    smooth > 0 the rows sqrt(smooth) * D follow.  Then
     |A1 y - b1|^2 = |A x - b|^2 / scale^2 + smooth |D x|^2."""
-    used = np.abs(A).max(axis=0) > 0
+    norms = np.linalg.norm(A, axis=0)
+    used = norms > 0
+    if min_sens > 0.0:
+        used = norms > min_sens * float(np.median(norms[used]))
     Au = A[:, used]
-    cn = np.linalg.norm(Au, axis=0)
+    cn = norms[used]
     scale = float(np.abs(b).max())
-    A1, b1 = Au / cn / scale, b / scale
+    A1, b1 = Au / cn / scale, (b - A[:, ~used].sum(axis=1)) / scale
     if D is not None and smooth > 0.0:
         keep = np.abs(D[:, used]).sum(axis=1) > 0
         w = np.sqrt(smooth)
@@ -266,10 +273,11 @@ def scaled_system(A: np.ndarray, b: np.ndarray, D=None, smooth: float = 0.0):
     return A1, b1, used, cn, scale
 
 
-def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int, D=None, smooth: float = 0.0):
+def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int, D=None, smooth: float = 0.0,
+        min_sens: float = 0.0):
     """Eq. (8) on the scaled system (plus the smoothness rows when smooth > 0);
-    bases that no row sees keep their factor 1."""
-    A1, b1, used, cn, _ = scaled_system(A, b, D, smooth)
+    bases left out of it keep their factor 1."""
+    A1, b1, used, cn, _ = scaled_system(A, b, D, smooth, min_sens)
     y, rep = eng.commission_nnls(A1, b1, x0=np.ones(int(used.sum())) * cn, max_iter=max_iter)
     x = np.ones(A.shape[1])
     x[used] = y / cn
@@ -277,7 +285,7 @@ def fit(eng, A: np.ndarray, b: np.ndarray, max_iter: int, D=None, smooth: float 
 
 
 def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_iter=300000,
-             seed=20150306, smooth=0.0, log=print) -> dict:
+             seed=20150306, smooth=0.0, log=print, min_sens=0.0) -> dict:
     """The whole experiment; returns the result dictionary printed by main()."""
     from . import engine as eng
     from . import workloads as wl
@@ -312,7 +320,7 @@ def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_ite
             bvec.append(meas[s][name])
     As, bs = np.vstack(blocks), np.concatenate(bvec)
     t0 = time.perf_counter()
-    x, used, rep = fit(eng, As, bs, max_iter, smoothness_rows(src), smooth)
+    x, used, rep = fit(eng, As, bs, max_iter, smoothness_rows(src), smooth, min_sens)
     t_fit = time.perf_counter() - t0
     log(f"[commission_eval] NNLS: {rep['iters']} iterations, {t_fit:.2f} s")
     # 4. the commissioned model on every field
@@ -341,7 +349,7 @@ def evaluate(hist_per_basis=1e7, hist_per_field=3e9, hist_measured=1e10, max_ite
     fitted = As @ x
     result.update({
         "bases": int(nb), "bases_used": int(used.sum()), "rows": int(As.shape[0]),
-        "smooth": float(smooth),
+        "smooth": float(smooth), "min_sensitivity": float(min_sens),
         "basis_histories": int(n_a), "t_basis_doses_s": t_a,
         "hist_per_field": int(hist_per_field), "hist_measured": int(hist_measured),
         "nnls": {"iters": rep["iters"], "converged": rep["converged"], "t_s": t_fit,
@@ -364,13 +372,17 @@ def main():
     ap.add_argument("--seed", type=int, default=20150306)
     ap.add_argument("--smooth", type=float, default=0.0,
                     help="weight of the ring-to-ring smoothness term of the fit (0 = Eq. 8 alone)")
+    ap.add_argument("--min-sensitivity", type=float, default=0.0,
+                    help="fit only bases whose dose column is at least this fraction of the "
+                         "median column (0 = every basis some row sees)")
     args = ap.parse_args()
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
     print(json.dumps(evaluate(args.hist_per_basis, args.hist_per_field, args.hist_measured,
-                              args.max_iter, args.seed, smooth=args.smooth, log=log)))
+                              args.max_iter, args.seed, smooth=args.smooth, log=log,
+                              min_sens=args.min_sensitivity)))
 
 
 if __name__ == "__main__":

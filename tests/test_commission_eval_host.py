@@ -146,3 +146,24 @@ def test_scaled_system_adds_the_smoothness_term():
         rhs = np.sum((A @ x - b) ** 2) / scale ** 2 + lam * np.sum((D @ x) ** 2)
         assert lhs == pytest.approx(rhs, rel=1e-12)
     assert A1.shape[0] == 30 + 10                  # the row of unused bases 7 and 8 is dropped
+
+
+def test_scaled_system_leaves_weakly_seen_bases_at_one():
+    """With a sensitivity threshold, bases whose dose column falls below it
+    are not fitted: they keep the factor 1, their dose moves to the
+    right-hand side, and |A1 y - b1|^2 = |A x - b|^2 / scale^2 still holds."""
+    from paper_1503_01725_amd import commission_eval as ce
+    rng = np.random.default_rng(12)
+    A = rng.uniform(0, 1, (30, 12))
+    A[:, 3] = 0.0                              # a basis no row sees
+    A[:, 5] *= 1e-6                            # a basis the rows barely see
+    b = rng.uniform(0, 2, 30)
+    A1, b1, used, cn, scale = ce.scaled_system(A, b, min_sens=1e-3)
+    assert not used[3] and not used[5] and used.sum() == 10
+    x = rng.uniform(0, 2, 12)
+    x[~used] = 1.0
+    y = x[used] * cn
+    lhs = np.sum((A1 @ y - b1) ** 2)
+    assert lhs == pytest.approx(np.sum((A @ x - b) ** 2) / scale ** 2, rel=1e-12)
+    A1_0, b1_0, used_0, _, _ = ce.scaled_system(A, b)
+    assert used_0[5] and not used_0[3] and used_0.sum() == 11
