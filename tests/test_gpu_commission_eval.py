@@ -94,3 +94,20 @@ def test_commissioning_experiment_with_ring_smoothness(eng):
     assert n["rel_residual"] <= n["rel_residual_uncommissioned"] * (1 + 1e-9)
     for d in r["fields"].values():
         assert all(v is None or math.isfinite(v) for v in d["commissioned"]["pdd"].values())
+
+
+def test_commissioning_experiment_with_sensitivity_threshold(eng):
+    """Bases below the sensitivity threshold are left out of the fit (fewer
+    bases fitted than without it); the start point is the uncommissioned model
+    and the solver only descends, so the residual cannot rise above it."""
+    from paper_1503_01725_amd import commission_eval as ce
+    kw = dict(hist_per_basis=2e4, hist_per_field=2e7, hist_measured=4e7, max_iter=300,
+              log=lambda m: print(m, flush=True))
+    r = ce.evaluate(min_sens=1e-2, **kw)
+    assert r["min_sensitivity"] == 1e-2
+    r0 = ce.evaluate(**kw)
+    assert 0 < r["bases_used"] < r0["bases_used"]
+    n = r["nnls"]
+    assert n["rel_residual"] <= n["rel_residual_uncommissioned"] * (1 + 1e-9)
+    for d in r["fields"].values():
+        assert all(v is None or math.isfinite(v) for v in d["commissioned"]["pdd"].values())
