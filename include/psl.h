@@ -164,7 +164,9 @@ void psl_plan_free(psl_plan* plan);
 /* ------------------------------------------------------------------------
  * Phantom
  * ------------------------------------------------------------------------ */
-/* density_dev: device float32 [nz][ny][nx] mass densities (water-like medium
+/* The voxel phantom the dose is computed in (Sec. 2.3 and Sec. 3.1: a water
+ * phantom, and patient CT volumes as densities of a water-like medium).
+ * density_dev: device float32 [nz][ny][nx] mass densities (water-like medium
  * scaled by density), x fastest; must stay valid while the phantom is used.
  * vox: voxel size (cm); origin: patient coordinates of the outer corner of
  * voxel (0,0,0).  The maximum density is found on the device.  Synchronous. */
@@ -346,9 +348,11 @@ enum {
 
 /* Tally operations, applied in the order RESET, FOLD, FINALIZE when several
  * bits are set.  FINALIZE writes dose_dev and sigma_dev (device FP64, one per
- * cell) in Gy per model particle: mean over folded replicas of
- * 1.602176634e-10 * E / (rho V) * (column weight of `plan`), and the standard
- * error of that mean.  plan, dose_dev and sigma_dev may be NULL without
+ * cell) in Gy per model particle, an absolute dose as the commissioning of
+ * Sec. 2.2.2 needs it: mean over folded replicas of
+ * 1.602176634e-10 * E / (rho V) * (column weight of `plan`: the Eq. (3)
+ * normaliser over the histories of the column), and the standard error of
+ * that mean.  plan, dose_dev and sigma_dev may be NULL without
  * FINALIZE. */
 int tally_dose(psl_tally* tally, int32_t ops, const psl_plan* plan, double* dose_dev,
                double* sigma_dev, void* stream);
