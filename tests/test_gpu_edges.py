@@ -1,7 +1,7 @@
 """Edge cases of the dose path on the GPU: empty particle stacks, plans of one
 or a few histories per replica (single-history batches, more pipelines asked
-for than batches, ragged batch ends) against the oracle, and the launch
-limits the runtime refuses before any device work."""
+for than batches, ragged batch ends) against the oracle, and the launch and
+size limits the library refuses before any device work."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -89,3 +89,22 @@ def test_run_limits_are_refused(eng, N, wl):
             eng.run_plan(plan, ph, tally, prm, eng.run_opts(use_graph=False, seed=1, **kw))
     led, cnt = tally.stats()
     assert cnt["hist"] == 0
+
+
+def test_size_limits_are_refused(eng, N):
+    """Phantoms of 2^31 voxels or more, empty phantom axes, U-Net volumes that
+    four levels cannot halve (not multiples of 8) or that exceed its index
+    range, and unsupported widths are refused with an error before any device
+    memory is touched or allocated."""
+    import ctypes as C
+    import torch
+    buf = torch.zeros(64, dtype=torch.float32, device="cuda")
+    for nx, ny, nz in ((2048, 2048, 512), (0, 4, 4)):
+        print(f"[edges] refused phantom {nx} x {ny} x {nz}", flush=True)
+        with pytest.raises(N.PslError):
+            N.psl_phantom_create(buf.data_ptr(), nx, ny, nz, (0.1, 0.1, 0.1), (0.0, 0.0, 0.0))
+    out = C.c_void_p()
+    for c, d, h, w in ((8, 12, 16, 16), (8, 16, 16, 4), (8, 1024, 1024, 512), (24, 16, 16, 16)):
+        print(f"[edges] refused U-Net width {c} at {d} x {h} x {w}", flush=True)
+        assert N.lib().psl_unet_create(c, d, h, w, C.byref(out)) == N.PSL_EINVAL
+    assert not out.value
