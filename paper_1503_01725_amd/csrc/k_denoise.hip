@@ -418,7 +418,7 @@ __device__ __forceinline__ void tile_pos(int w, int i, int row, int& z, int& y, 
 // chip: each split writes its FP32 partial sums and k_conv_split_reduce adds
 // them in split order and applies the epilogue.
 template <int MODE, int NT, int CC>
-__global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
+__global__ void __launch_bounds__(256, CC == 8 && NT == 32 ? 3 : 2) k_conv_direct(GemmArgs g) {
     static_assert(NT == 32 || NT == 64, "32 or 64 output channels per workgroup");
     static_assert(CC == 32 || CC == 8, "32 or 8 channels per staged chunk");
     constexpr int NJ = NT / 32;
@@ -439,8 +439,11 @@ __global__ void __launch_bounds__(256, 2) k_conv_direct(GemmArgs g) {
     // independent accumulation chains: a 32x32x16 MFMA's result is not
     // ready for a dependent MFMA until several others have issued, so with
     // one column tile the even and odd K steps accumulate separately (eight
-    // chains per wave either way), summed in the epilogue
-    constexpr int KS = NJ == 1 ? 2 : 1;
+    // chains per wave either way), summed in the epilogue.  The 8-channel
+    // input layer keeps four chains per wave instead: its 150 registers let
+    // three workgroups share a CU (launch bounds above), whose staging and
+    // stores then overlap more MFMA work than two could
+    constexpr int KS = NJ == 1 && CC == 32 ? 2 : 1;
     floatx16 acc[4][NJ * KS];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
