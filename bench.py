@@ -463,7 +463,7 @@ def main():
             "plain_histories": n1, "plain_s": n1 / value,
             "plain_s_graph": n1 / graph_replay["value"] if graph_replay else None,
             "denoised_s": None,
-            "denoised_note": "no denoised time: the denoiser's error floor (0.50 % of Dmax RMS on "
+            "denoised_note": "no denoised time: the denoiser's error floor (0.49 % of Dmax RMS on "
                              "its held-out cases) lies above a plain dose's error at 1 % sigma "
                              "(0.25 %)"}
     out["entered_per_s"] = cnt["entered"] * args.steps / elapsed
